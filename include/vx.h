@@ -1,0 +1,171 @@
+/*
+ * vx.h -- C ABI of the MI355X VaultX plotter hot path (libvx.so).
+ *
+ * What is computed (VaultxGPU paper, sections I-A, II-B, III-A, III-B):
+ *   Table 1: every nonce n in [0, 2^k) is hashed with keyed BLAKE3 under the
+ *            256-bit plot key; the first 8 output bytes, read big-endian,
+ *            form key64(n).  Records (key64, n) are filed into 2^24 buckets
+ *            by the 24-bit prefix key64 >> 40 and each bucket is sorted by
+ *            hash value, ties by nonce.
+ *   Table 2: inside each bucket, every pair i < j (Table-1 order) with
+ *            key64[j] - key64[i] < T is hashed with keyed BLAKE3 over
+ *            LE32(nonce_i) || LE32(nonce_j) into a 16-byte record.
+ * Readings of what the paper leaves open: nonce = 4-byte little-endian u32;
+ * hash kept = 8 bytes, big-endian u64; default T = 2^(64-k), the expected
+ * gap between neighbouring keys; strict "<"; pairs never cross buckets;
+ * Table 2 in order of i, then j.
+ *
+ * Conventions for every call:
+ *  - Pointers named d_* are DEVICE pointers owned by the caller; the library
+ *    never frees them and keeps none after the enqueued work completes.
+ *    Host pointers (params, buffers, tuning structs) are read during the
+ *    call only.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Every call only
+ *    enqueues work on it and returns; outputs are valid once the stream has
+ *    reached that point.
+ *  - Argument and size errors are returned synchronously and enqueue
+ *    nothing.  A failed HIP launch returns VX_ERR_DEVICE.  vx_last_error()
+ *    gives a message for the calling thread's last failure.
+ *  - Data-dependent conditions are reported on the device: Table-2 overflow
+ *    as *d_t2_count > t2_capacity (records past the capacity are not
+ *    written), and degenerate inputs the sort cannot place (see
+ *    vx_read_status) in a status word at the start of the workspace.
+ *  - Outputs are deterministic and bit-exact: they do not depend on tuning,
+ *    on the stream, or on other work running at the same time.
+ *  - Sizes: k in [1, 31]; 2^k records; offsets have 2^24 + 1 entries.
+ */
+#ifndef VX_H
+#define VX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VX_OK = 0,
+    VX_ERR_INVALID_ARG = 1,   /* bad k, bucket_bits, null or misaligned pointer */
+    VX_ERR_WORKSPACE = 2,     /* workspace smaller than vx_workspace_bytes() */
+    VX_ERR_DEVICE = 3,        /* a HIP call failed; see vx_last_error() */
+    VX_ERR_OUT_OF_MEMORY = 4, /* reserved for callers that allocate through the library */
+    VX_ERR_UNSUPPORTED = 5,   /* a tuning value outside its supported range */
+} vx_status;
+
+/* Device status word bits (vx_read_status). */
+#define VX_DEV_STATUS_GROUP_TOO_LARGE 0x1u /* a sort group exceeded the fallback limit */
+
+#define VX_BUCKET_BITS 24
+#define VX_NUM_BUCKETS (1u << VX_BUCKET_BITS)
+
+/* One plot.  key: the 256-bit plot key (paper sec. III-B), used as eight
+ * little-endian words.  k: log2 of the number of nonces.  bucket_bits: must
+ * be 24 (2^24 buckets, paper sec. I-A).  match_threshold: T of the match
+ * predicate; vx_default_threshold(k) gives the paper-scale default. */
+typedef struct {
+    uint8_t key[32];
+    uint32_t k;
+    uint32_t bucket_bits;
+    uint64_t match_threshold;
+} vx_plot_params;
+
+/* One Table-2 record, 16 bytes, little-endian fields. */
+typedef struct {
+    uint32_t nonce_a; /* nonce of the earlier record in Table-1 order */
+    uint32_t nonce_b; /* nonce of the later record */
+    uint64_t hash2;   /* BE64 of the first 8 bytes of keyed BLAKE3(LE32 a || LE32 b) */
+} vx_t2_record;
+
+/* Buffers of a whole plot (vx_plot).  All device pointers, caller-owned:
+ *  t1_keys[2^k] (u64, 8-byte aligned), t1_nonces[2^k] (u32),
+ *  bucket_offsets[2^24 + 1] (u32; offsets[b] = index of the first Table-1
+ *  record of bucket b, offsets[2^24] = 2^k),
+ *  t2[t2_capacity] records (16-byte aligned), t2_count: one device u64 that
+ *  receives |Table 2| (which may exceed t2_capacity),
+ *  workspace: at least vx_workspace_bytes(params, VX_CALL_PLOT, tuning)
+ *  bytes, 256-byte aligned. */
+typedef struct {
+    uint64_t *t1_keys;
+    uint32_t *t1_nonces;
+    uint32_t *bucket_offsets;
+    vx_t2_record *t2;
+    uint64_t t2_capacity;
+    uint64_t *t2_count;
+    void *workspace;
+    size_t workspace_bytes;
+} vx_plot_buffers;
+
+/* Implementation parameters.  None of them changes any output; they only
+ * move work between kernels.  Zero in any field selects the built-in
+ * default for the plot's k. */
+typedef struct {
+    uint32_t group_bits;   /* sort groups = 2^group_bits key prefixes, 1..24 */
+    uint32_t pass1_bits;   /* digit bits of the first partition pass, 1..11 */
+    uint32_t group_cap;    /* records a group may hold in LDS, 64..8192 */
+    uint32_t h1_tiles;     /* work-groups of the hash + first partition pass */
+    uint32_t match_bits;   /* match work groups = 2^match_bits key prefixes, 0..24 */
+    uint32_t reserved[3];
+} vx_tuning;
+
+enum { VX_CALL_BUCKET_SORT = 1, VX_CALL_MATCH = 2, VX_CALL_PLOT = 3 };
+
+/* 2^(64-k): the expected gap between neighbouring keys of a k-plot. */
+uint64_t vx_default_threshold(uint32_t k);
+
+/* Workspace bytes a call needs for these params and tuning (tuning may be
+ * NULL).  Returns 0 for invalid params. */
+size_t vx_workspace_bytes(const vx_plot_params *params, int which_call, const vx_tuning *tuning);
+
+/* A Table-2 capacity that holds |Table 2| of a k-plot with threshold T with
+ * overwhelming probability (expectation plus a generous margin). */
+uint64_t vx_t2_capacity_hint(uint32_t k, uint64_t threshold);
+
+/* Table-1 hashing (paper sec. III-A, III-B: one hash per nonce, all 2^k
+ * nonces): d_keys[n] = key64(n) for n in [0, 2^k), in nonce order. */
+vx_status vx_hash_table1(const vx_plot_params *params, uint64_t *d_keys, void *stream);
+
+/* Bucketing and in-bucket sort (paper sec. III-A, III-B; sort by hash value
+ * inside each of the 2^24 buckets): from nonce-order hashes d_keys[2^k]
+ * (record n has nonce n) to Table 1 sorted by (key64, nonce) in
+ * d_t1_keys / d_t1_nonces, and d_offsets[2^24 + 1].  d_keys is read only and
+ * must not overlap the outputs. */
+vx_status vx_bucket_sort(const vx_plot_params *params, const uint64_t *d_keys,
+                         uint64_t *d_t1_keys, uint32_t *d_t1_nonces, uint32_t *d_offsets,
+                         void *d_workspace, size_t workspace_bytes, const vx_tuning *tuning,
+                         void *stream);
+
+/* Match and Table-2 hashing (paper sec. II-B, III-A: pairs within the
+ * threshold, hashed into Table-2 records) over a sorted Table 1 with its
+ * offsets.  Writes min(|T2|, t2_capacity) records in canonical order and
+ * |T2| to *d_t2_count. */
+vx_status vx_match_table2(const vx_plot_params *params, const uint64_t *d_t1_keys,
+                          const uint32_t *d_t1_nonces, const uint32_t *d_offsets,
+                          vx_t2_record *d_t2, uint64_t t2_capacity, uint64_t *d_t2_count,
+                          void *d_workspace, size_t workspace_bytes, const vx_tuning *tuning,
+                          void *stream);
+
+/* Whole plot (paper sec. III-A pipeline without the host copy and disk
+ * write): the same outputs as vx_match_table2(vx_bucket_sort(
+ * vx_hash_table1())). */
+vx_status vx_plot(const vx_plot_params *params, const vx_plot_buffers *buffers,
+                  const vx_tuning *tuning, void *stream);
+
+/* n independent plots (params[i], buffers[i]) enqueued on one stream; each
+ * output equals vx_plot(params[i], buffers[i]).  tuning may be NULL (built-in
+ * defaults per k) or an array of n entries. */
+vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buffers,
+                        uint32_t n, const vx_tuning *tuning, void *stream);
+
+/* Copies the device status word at the start of a workspace used by
+ * vx_bucket_sort or vx_plot to *h_status (synchronising `stream`). */
+vx_status vx_read_status(const void *d_workspace, uint32_t *h_status, void *stream);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char *vx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VX_H */

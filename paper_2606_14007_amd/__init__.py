@@ -1,0 +1,19 @@
+"""MI355X-native VaultX plotter hot path (arxiv 2606.14007, "VaultxGPU").
+
+The computation lives in libvx.so (hand-written HIP for gfx950 behind the C
+ABI in include/vx.h).  This package is its Python binding:
+
+  * `_native`  -- ctypes declarations, same names as the C ABI;
+  * `plotter`  -- torch-allocated device buffers and one-call helpers.
+"""
+from ._native import (VX_BUCKET_BITS, VX_CALL_BUCKET_SORT, VX_CALL_MATCH, VX_CALL_PLOT,
+                      VX_DEV_STATUS_GROUP_TOO_LARGE, VX_NUM_BUCKETS, VxError, VxPlotBuffers,
+                      VxPlotParams, VxT2Record, VxTuning, lib, make_params, make_tuning,
+                      vx_bucket_sort, vx_default_threshold, vx_hash_table1, vx_last_error,
+                      vx_match_table2, vx_plot, vx_plot_batch, vx_read_status,
+                      vx_t2_capacity_hint, vx_workspace_bytes)
+from .plotter import (T2_DTYPE, PlotBuffers, alloc_plot, bucket_sort, device_status,
+                      footprint_bytes, hash_table1, match_table2, plot, t2_count, t2_records,
+                      u32, u64)
+
+__all__ = [n for n in dir() if not n.startswith("_")]

@@ -1,0 +1,360 @@
+// C ABI of libvx (declared in include/vx.h): argument checks, the per-plot
+// plan (partition digits, group sizes, tile counts), the workspace layout,
+// and the launch sequence of each call.  No call allocates device memory.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "kernels.h"
+#include "vx.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+vx_status fail(vx_status st, const char *msg) {
+    snprintf(g_err, sizeof(g_err), "%s", msg);
+    return st;
+}
+
+vx_status fail_hip(hipError_t e, const char *where) {
+    snprintf(g_err, sizeof(g_err), "%s: %s", where, hipGetErrorString(e));
+    return VX_ERR_DEVICE;
+}
+
+#define VX_HIP(call, where)                              \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return fail_hip(e_, where); \
+    } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// How one plot is cut into kernels.  Every field only moves work around;
+// outputs never depend on it.
+struct Plan {
+    uint32_t k = 0;
+    uint64_t n = 0;          // 2^k records
+    uint32_t key_words[8] = {};
+    uint64_t T = 0;
+    uint32_t G = 0;          // sort groups = 2^G leading-bit prefixes
+    uint32_t D1 = 0;         // digit bits of partition pass 1
+    uint32_t D2 = 0;         // digit bits of partition pass 2 (0 = one pass)
+    uint32_t W = 0;          // tiles of hash + pass 1
+    uint64_t chunk1 = 0;     // records per pass-1 tile
+    uint32_t Q = 0;          // pass-2 tiles per pass-1 segment
+    uint32_t cap = 0;        // LDS capacity of a sort group
+    uint32_t Gm = 0;         // match groups = 2^Gm prefixes
+};
+
+uint32_t clampu(int64_t v, int64_t lo, int64_t hi) {
+    return (uint32_t)(v < lo ? lo : (v > hi ? hi : v));
+}
+
+vx_status check_params(const vx_plot_params *p) {
+    if (!p) return fail(VX_ERR_INVALID_ARG, "params is NULL");
+    if (p->k < 1 || p->k > 31) return fail(VX_ERR_INVALID_ARG, "k must be in [1, 31]");
+    if (p->bucket_bits != VX_BUCKET_BITS) return fail(VX_ERR_INVALID_ARG, "bucket_bits must be 24");
+    return VX_OK;
+}
+
+vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl) {
+    vx_status st = check_params(p);
+    if (st != VX_OK) return st;
+    Plan P;
+    P.k = p->k;
+    P.n = 1ull << p->k;
+    for (int i = 0; i < 8; ++i)
+        P.key_words[i] = (uint32_t)p->key[4 * i] | ((uint32_t)p->key[4 * i + 1] << 8) |
+                         ((uint32_t)p->key[4 * i + 2] << 16) | ((uint32_t)p->key[4 * i + 3] << 24);
+    P.T = p->match_threshold;
+    vx_tuning z;
+    memset(&z, 0, sizeof(z));
+    if (!t) t = &z;
+    // Sort groups of about 4096 records.
+    P.G = t->group_bits ? t->group_bits : clampu((int64_t)p->k - 12, 1, 19);
+    if (P.G < 1 || P.G > 24) return fail(VX_ERR_UNSUPPORTED, "group_bits must be in [1, 24]");
+    P.D1 = t->pass1_bits ? t->pass1_bits : (P.G < 8 ? P.G : 8);
+    if (P.D1 < 1 || P.D1 > (uint32_t)vxk::kMaxDigitBits || P.D1 > P.G)
+        return fail(VX_ERR_UNSUPPORTED, "pass1_bits must be in [1, min(11, group_bits)]");
+    P.D2 = P.G - P.D1;
+    if (P.D2 > (uint32_t)vxk::kMaxDigitBits)
+        return fail(VX_ERR_UNSUPPORTED, "group_bits - pass1_bits must be at most 11");
+    P.W = t->h1_tiles ? t->h1_tiles : clampu((int64_t)(P.n >> 14), 1, 2048);
+    if (P.W < 1 || P.W > 65536) return fail(VX_ERR_UNSUPPORTED, "h1_tiles must be in [1, 65536]");
+    P.chunk1 = (P.n + P.W - 1) / P.W;
+    P.Q = clampu((int64_t)((P.n >> P.D1) >> 19), 1, 16);
+    P.cap = t->group_cap ? t->group_cap : (uint32_t)vxk::kGroupCapMax;
+    if (P.cap < 64 || P.cap > (uint32_t)vxk::kGroupCapMax)
+        return fail(VX_ERR_UNSUPPORTED, "group_cap must be in [64, 8192]");
+    P.Gm = t->match_bits ? t->match_bits : clampu((int64_t)p->k - 11, 0, 20);
+    if (P.Gm > (uint32_t)vxk::kMatchBitsMax) return fail(VX_ERR_UNSUPPORTED, "match_bits must be at most 24");
+    *pl = P;
+    return VX_OK;
+}
+
+// Workspace regions (byte offsets from the workspace start, 256-aligned).
+struct Layout {
+    size_t header = 0;        // u32 words: [0] status, [1] overflow count
+    size_t keys_no = 0;       // u64[n] nonce-order hashes (plot only)
+    size_t scr_keys = 0;      // u64[n] partition scratch
+    size_t scr_nonces = 0;    // u32[n]
+    size_t hist1 = 0, off1 = 0;   // u32[W][2^D1]
+    size_t gstart1 = 0;           // u32[2^D1 + 1]
+    size_t hist2 = 0, off2 = 0;   // u32[2^D1 * Q][2^D2]
+    size_t gstart = 0;            // u32[2^G + 1]
+    size_t ovf_list = 0;          // u32[2^G]
+    size_t mcount = 0, mbase = 0; // u64[2^Gm]
+    size_t mpart = 0;             // u64[scan parts]
+    size_t total = 0;
+};
+
+constexpr uint32_t kHeaderWords = 64;
+
+Layout layout(const Plan &P, int which) {
+    Layout L;
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = at;
+        at = align_up(at + bytes, 256);
+        return o;
+    };
+    L.header = take(kHeaderWords * 4);
+    const bool sort = which == VX_CALL_BUCKET_SORT || which == VX_CALL_PLOT;
+    const bool match = which == VX_CALL_MATCH || which == VX_CALL_PLOT;
+    if (which == VX_CALL_PLOT) L.keys_no = take(P.n * 8);
+    if (sort) {
+        L.scr_keys = take(P.n * 8);
+        L.scr_nonces = take(P.n * 4);
+        L.hist1 = take((size_t)P.W * (1u << P.D1) * 4);
+        L.off1 = take((size_t)P.W * (1u << P.D1) * 4);
+        L.gstart1 = take(((size_t)(1u << P.D1) + 1) * 4);
+        if (P.D2) {
+            L.hist2 = take((size_t)(1u << P.D1) * P.Q * (1u << P.D2) * 4);
+            L.off2 = take((size_t)(1u << P.D1) * P.Q * (1u << P.D2) * 4);
+        }
+        L.gstart = take(((size_t)(1u << P.G) + 1) * 4);
+        L.ovf_list = take((size_t)(1u << P.G) * 4);
+    }
+    if (match) {
+        L.mcount = take((size_t)(1u << P.Gm) * 8);
+        L.mbase = take((size_t)(1u << P.Gm) * 8);
+        L.mpart = take((size_t)vxk::scan_parts(1u << P.Gm) * 8);
+    }
+    L.total = at;
+    return L;
+}
+
+template <typename T>
+T *at(void *ws, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// Hash + the pass-1 histogram (plot) or the pass-1 histogram of caller keys.
+// Then the partition passes and the group sort; Table 1 ends in t1_*.
+vx_status run_bucket_sort(const Plan &P, const Layout &L, void *ws, const uint64_t *keys_no,
+                          bool hist_done, uint64_t *t1_keys, uint32_t *t1_nonces,
+                          uint32_t *offsets, hipStream_t s) {
+    uint32_t *hdr = at<uint32_t>(ws, L.header);
+    uint32_t *hist1 = at<uint32_t>(ws, L.hist1), *off1 = at<uint32_t>(ws, L.off1);
+    uint32_t *gstart1 = at<uint32_t>(ws, L.gstart1), *gstart = at<uint32_t>(ws, L.gstart);
+    uint64_t *scr_k = at<uint64_t>(ws, L.scr_keys);
+    uint32_t *scr_n = at<uint32_t>(ws, L.scr_nonces);
+    const uint32_t nd1 = 1u << P.D1;
+    if (!hist_done)
+        VX_HIP(vxk::launch_hist_chunks(keys_no, P.n, P.W, P.chunk1, 64 - P.D1, P.D1, hist1, s),
+               "pass-1 histogram");
+    // Pass 1 writes into Table 1 directly when it is the only pass.
+    uint64_t *p1k = P.D2 ? scr_k : t1_keys;
+    uint32_t *p1n = P.D2 ? scr_n : t1_nonces;
+    uint32_t *g1 = P.D2 ? gstart1 : gstart;
+    VX_HIP(vxk::launch_colscan(hist1, off1, 1, P.W, nd1, nullptr, g1, nd1, (uint32_t)P.n, s),
+           "pass-1 scan");
+    VX_HIP(vxk::launch_scatter_chunks(keys_no, nullptr, p1k, p1n, off1, P.n, P.W, P.chunk1, 64 - P.D1,
+                                      P.D1, s),
+           "pass-1 scatter");
+    if (P.D2) {
+        uint32_t *hist2 = at<uint32_t>(ws, L.hist2), *off2 = at<uint32_t>(ws, L.off2);
+        const uint32_t nd2 = 1u << P.D2;
+        const uint32_t shift2 = 64 - P.D1 - P.D2;
+        VX_HIP(vxk::launch_hist_segments(p1k, gstart1, nd1, P.Q, shift2, P.D2, hist2, s),
+               "pass-2 histogram");
+        VX_HIP(vxk::launch_colscan(hist2, off2, nd1, P.Q, nd2, gstart1, gstart, 1u << P.G,
+                                   (uint32_t)P.n, s),
+               "pass-2 scan");
+        VX_HIP(vxk::launch_scatter_segments(p1k, p1n, t1_keys, t1_nonces, off2, gstart1, nd1, P.Q,
+                                            shift2, P.D2, s),
+               "pass-2 scatter");
+    }
+    VX_HIP(vxk::launch_groupsort(t1_keys, t1_nonces, gstart, P.G, P.cap, offsets, (uint32_t)P.n,
+                                 hdr + 1, at<uint32_t>(ws, L.ovf_list), s),
+           "group sort");
+    VX_HIP(vxk::launch_group_fallback(t1_keys, t1_nonces, scr_k, scr_n, gstart, P.G, offsets, hdr + 1,
+                                      at<uint32_t>(ws, L.ovf_list), hdr, s),
+           "group sort fallback");
+    return VX_OK;
+}
+
+vx_status run_match(const Plan &P, const Layout &L, void *ws, const uint64_t *t1_keys,
+                    const uint32_t *t1_nonces, const uint32_t *offsets, vx_t2_record *t2,
+                    uint64_t cap, uint64_t *t2_count, hipStream_t s) {
+    uint64_t *cnt = at<uint64_t>(ws, L.mcount), *base = at<uint64_t>(ws, L.mbase);
+    uint64_t *part = at<uint64_t>(ws, L.mpart);
+    VX_HIP(vxk::launch_match_count(t1_keys, offsets, P.Gm, P.T, (uint32_t)P.n, cnt, s), "match count");
+    VX_HIP(vxk::launch_scan_u64(cnt, 1u << P.Gm, base, part, t2_count, s), "match scan");
+    VX_HIP(vxk::launch_match_emit(P.key_words, t1_keys, t1_nonces, offsets, P.Gm, P.T, (uint32_t)P.n, base,
+                                   t2, cap, s),
+           "match emit");
+    return VX_OK;
+}
+
+vx_status check_ws(const Layout &L, const void *ws, size_t bytes) {
+    if (!ws) return fail(VX_ERR_INVALID_ARG, "workspace is NULL");
+    if (!aligned(ws, 256)) return fail(VX_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (bytes < L.total) return fail(VX_ERR_WORKSPACE, "workspace smaller than vx_workspace_bytes()");
+    return VX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t vx_default_threshold(uint32_t k) {
+    if (k < 1 || k > 63) return 0;
+    return 1ull << (64 - k);
+}
+
+size_t vx_workspace_bytes(const vx_plot_params *params, int which_call, const vx_tuning *tuning) {
+    Plan P;
+    if (which_call < VX_CALL_BUCKET_SORT || which_call > VX_CALL_PLOT) return 0;
+    if (make_plan(params, tuning, &P) != VX_OK) return 0;
+    return layout(P, which_call).total;
+}
+
+uint64_t vx_t2_capacity_hint(uint32_t k, uint64_t threshold) {
+    if (k < 1 || k > 31) return 0;
+    // Expected pairs per record for uniform keys: neighbours within T inside
+    // the record's bucket.  With lambda = 2^(k-24) records per bucket and
+    // bucket width W = 2^40, a record sees on average lambda * min(T, W) / W
+    // later neighbours within T (at most lambda / 2 counting all pairs once).
+    const double n = (double)(1ull << k);
+    const double lam = n / (double)VX_NUM_BUCKETS;
+    const double w = (double)(1ull << 40);
+    const double t = threshold >= (1ull << 40) ? w : (double)threshold;
+    double per = lam * (t / w) * (1.0 - 0.5 * t / w);
+    double expect = n * per;
+    double cap = expect * 1.05 + 8.0 * __builtin_sqrt(expect + 1.0) + 4096.0;
+    return (uint64_t)cap;
+}
+
+const char *vx_last_error(void) { return g_err; }
+
+vx_status vx_hash_table1(const vx_plot_params *params, uint64_t *d_keys, void *stream) {
+    Plan P;
+    vx_status st = make_plan(params, nullptr, &P);
+    if (st != VX_OK) return st;
+    if (!d_keys || !aligned(d_keys, 8)) return fail(VX_ERR_INVALID_ARG, "d_keys must be 8-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    VX_HIP(vxk::launch_hash_table1(P.key_words, P.n, P.W, P.chunk1, d_keys, nullptr, 0, s), "hash");
+    g_err[0] = 0;
+    return VX_OK;
+}
+
+vx_status vx_bucket_sort(const vx_plot_params *params, const uint64_t *d_keys, uint64_t *d_t1_keys,
+                         uint32_t *d_t1_nonces, uint32_t *d_offsets, void *d_workspace,
+                         size_t workspace_bytes, const vx_tuning *tuning, void *stream) {
+    Plan P;
+    vx_status st = make_plan(params, tuning, &P);
+    if (st != VX_OK) return st;
+    if (!d_keys || !d_t1_keys || !d_t1_nonces || !d_offsets)
+        return fail(VX_ERR_INVALID_ARG, "NULL buffer");
+    if (!aligned(d_keys, 8) || !aligned(d_t1_keys, 8) || !aligned(d_t1_nonces, 4) || !aligned(d_offsets, 4))
+        return fail(VX_ERR_INVALID_ARG, "misaligned buffer");
+    Layout L = layout(P, VX_CALL_BUCKET_SORT);
+    if ((st = check_ws(L, d_workspace, workspace_bytes)) != VX_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    VX_HIP(vxk::launch_reset(at<uint32_t>(d_workspace, L.header), kHeaderWords, s), "reset");
+    st = run_bucket_sort(P, L, d_workspace, d_keys, false, d_t1_keys, d_t1_nonces, d_offsets, s);
+    if (st == VX_OK) g_err[0] = 0;
+    return st;
+}
+
+vx_status vx_match_table2(const vx_plot_params *params, const uint64_t *d_t1_keys,
+                          const uint32_t *d_t1_nonces, const uint32_t *d_offsets, vx_t2_record *d_t2,
+                          uint64_t t2_capacity, uint64_t *d_t2_count, void *d_workspace,
+                          size_t workspace_bytes, const vx_tuning *tuning, void *stream) {
+    Plan P;
+    vx_status st = make_plan(params, tuning, &P);
+    if (st != VX_OK) return st;
+    if (!d_t1_keys || !d_t1_nonces || !d_offsets || !d_t2_count || (t2_capacity && !d_t2))
+        return fail(VX_ERR_INVALID_ARG, "NULL buffer");
+    if (!aligned(d_t1_keys, 8) || !aligned(d_t2_count, 8) || (d_t2 && !aligned(d_t2, 16)))
+        return fail(VX_ERR_INVALID_ARG, "misaligned buffer");
+    Layout L = layout(P, VX_CALL_MATCH);
+    if ((st = check_ws(L, d_workspace, workspace_bytes)) != VX_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = run_match(P, L, d_workspace, d_t1_keys, d_t1_nonces, d_offsets, d_t2, t2_capacity, d_t2_count, s);
+    if (st == VX_OK) g_err[0] = 0;
+    return st;
+}
+
+vx_status vx_plot(const vx_plot_params *params, const vx_plot_buffers *b, const vx_tuning *tuning,
+                  void *stream) {
+    Plan P;
+    vx_status st = make_plan(params, tuning, &P);
+    if (st != VX_OK) return st;
+    if (!b) return fail(VX_ERR_INVALID_ARG, "buffers is NULL");
+    if (!b->t1_keys || !b->t1_nonces || !b->bucket_offsets || !b->t2_count || (b->t2_capacity && !b->t2))
+        return fail(VX_ERR_INVALID_ARG, "NULL buffer");
+    if (!aligned(b->t1_keys, 8) || !aligned(b->t1_nonces, 4) || !aligned(b->bucket_offsets, 4) ||
+        !aligned(b->t2_count, 8) || (b->t2 && !aligned(b->t2, 16)))
+        return fail(VX_ERR_INVALID_ARG, "misaligned buffer");
+    Layout L = layout(P, VX_CALL_PLOT);
+    if ((st = check_ws(L, b->workspace, b->workspace_bytes)) != VX_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    void *ws = b->workspace;
+    uint64_t *keys_no = at<uint64_t>(ws, L.keys_no);
+    VX_HIP(vxk::launch_reset(at<uint32_t>(ws, L.header), kHeaderWords, s), "reset");
+    VX_HIP(vxk::launch_hash_table1(P.key_words, P.n, P.W, P.chunk1, keys_no, at<uint32_t>(ws, L.hist1),
+                                   P.D1, s),
+           "hash");
+    st = run_bucket_sort(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, b->bucket_offsets, s);
+    if (st != VX_OK) return st;
+    st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, b->t2, b->t2_capacity,
+                   b->t2_count, s);
+    if (st == VX_OK) g_err[0] = 0;
+    return st;
+}
+
+vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buffers, uint32_t n,
+                        const vx_tuning *tuning, void *stream) {
+    if (n && (!params || !buffers)) return fail(VX_ERR_INVALID_ARG, "NULL params or buffers");
+    // Validate everything before enqueuing anything.
+    for (uint32_t i = 0; i < n; ++i) {
+        Plan P;
+        vx_status st = make_plan(&params[i], tuning ? &tuning[i] : nullptr, &P);
+        if (st != VX_OK) return st;
+        Layout L = layout(P, VX_CALL_PLOT);
+        if ((st = check_ws(L, buffers[i].workspace, buffers[i].workspace_bytes)) != VX_OK) return st;
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+        vx_status st = vx_plot(&params[i], &buffers[i], tuning ? &tuning[i] : nullptr, stream);
+        if (st != VX_OK) return st;
+    }
+    g_err[0] = 0;
+    return VX_OK;
+}
+
+vx_status vx_read_status(const void *d_workspace, uint32_t *h_status, void *stream) {
+    if (!d_workspace || !h_status) return fail(VX_ERR_INVALID_ARG, "NULL pointer");
+    hipStream_t s = (hipStream_t)stream;
+    VX_HIP(hipMemcpyAsync(h_status, d_workspace, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "status copy");
+    VX_HIP(hipStreamSynchronize(s), "status sync");
+    g_err[0] = 0;
+    return VX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,53 @@
+// Launchers of the plotter kernels (defined in kernels.hip).  Internal to
+// libvx; the public boundary is include/vx.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define VXK_BUCKET_BITS 24
+#define VXK_NUM_BUCKETS (1u << VXK_BUCKET_BITS)
+#define VXK_DEV_STATUS_GROUP_TOO_LARGE 0x1u
+
+namespace vxk {
+
+constexpr int kMaxDigitBits = 11;     // widest partition digit (LDS histograms)
+constexpr int kGroupCapMax = 8192;    // records a sort group may hold in LDS
+constexpr uint32_t kFallbackMax = 1u << 20;  // largest group the fallback sorts
+constexpr int kMatchBitsMax = 24;
+
+hipError_t launch_reset(uint32_t *words, uint32_t n, hipStream_t s);
+hipError_t launch_hash_table1(const uint32_t key_words[8], uint64_t n, uint32_t tiles, uint64_t chunk,
+                              uint64_t *keys, uint32_t *hist, uint32_t hist_bits, hipStream_t s);
+hipError_t launch_hist_chunks(const uint64_t *keys, uint64_t n, uint32_t tiles, uint64_t chunk,
+                              uint32_t shift, uint32_t bits, uint32_t *hist, hipStream_t s);
+hipError_t launch_hist_segments(const uint64_t *keys, const uint32_t *seg, uint32_t nseg, uint32_t q,
+                                uint32_t shift, uint32_t bits, uint32_t *hist, hipStream_t s);
+hipError_t launch_colscan(const uint32_t *hist, uint32_t *off, uint32_t nseg, uint32_t rps,
+                          uint32_t ncol, const uint32_t *seg_base, uint32_t *gstart, uint32_t n_groups,
+                          uint32_t n_total, hipStream_t s);
+hipError_t launch_scatter_chunks(const uint64_t *in_keys, const uint32_t *in_nonces,
+                                 uint64_t *out_keys, uint32_t *out_nonces, const uint32_t *off,
+                                 uint64_t n, uint32_t tiles, uint64_t chunk, uint32_t shift,
+                                 uint32_t bits, hipStream_t s);
+hipError_t launch_scatter_segments(const uint64_t *in_keys, const uint32_t *in_nonces,
+                                   uint64_t *out_keys, uint32_t *out_nonces, const uint32_t *off,
+                                   const uint32_t *seg, uint32_t nseg, uint32_t q, uint32_t shift,
+                                   uint32_t bits, hipStream_t s);
+hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint32_t *gstart, uint32_t G,
+                            uint32_t cap, uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count,
+                            uint32_t *ovf_list, hipStream_t s);
+hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, uint64_t *scr_keys,
+                                 uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G,
+                                 uint32_t *offsets, const uint32_t *ovf_count, const uint32_t *ovf_list,
+                                 uint32_t *status, hipStream_t s);
+hipError_t launch_match_count(const uint64_t *keys, const uint32_t *offsets, uint32_t Gm, uint64_t T,
+                              uint32_t n_total, uint64_t *counts, hipStream_t s);
+hipError_t launch_scan_u64(const uint64_t *in, uint32_t n, uint64_t *out, uint64_t *part,
+                           uint64_t *total, hipStream_t s);
+uint32_t scan_parts(uint32_t n);
+hipError_t launch_match_emit(const uint32_t key_words[8], const uint64_t *keys, const uint32_t *nonces,
+                             const uint32_t *offsets, uint32_t Gm, uint64_t T, uint32_t n_total,
+                             const uint64_t *group_base, void *t2, uint64_t cap, hipStream_t s);
+
+}  // namespace vxk

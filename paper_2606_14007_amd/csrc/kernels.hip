@@ -1,0 +1,736 @@
+// HIP kernels of the VaultX plotter hot path for gfx950 (MI355X).
+//
+// Stages (paper sec. III-A): hash every nonce into Table 1, file records into
+// 2^24 buckets by hash prefix, sort inside buckets, then match neighbours
+// below the threshold and hash each pair into Table 2.
+//
+// How the work maps onto CDNA4 (the paper's atomic slot claim into fixed-size
+// buckets and its one-thread insertion sort are replaced):
+//  * hash: one nonce per lane, BLAKE3 held in VGPRs, key in SGPRs; the same
+//    kernel counts the first partition digit in an LDS histogram;
+//  * bucketing: one or two MSD partition passes over the leading key bits
+//    (histogram per tile -> column scan -> LDS-ranked scatter that writes
+//    each digit's run contiguously), so that every "group" of keys sharing
+//    the leading G bits is contiguous and small enough for LDS;
+//  * sort: one work-group per group: LDS counting sort on the next 12 bits,
+//    then an exact rank inside each (tiny) sub-bin; bucket offsets come from
+//    a binary search of the sorted group;
+//  * match + Table-2 hash: one work-group per group of buckets, per-record
+//    pair counts, a work-group scan and a device scan give every pair its
+//    canonical slot; pairs are expanded into an LDS list and hashed one pair
+//    per lane.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "block_scan.h"
+#include "blake3_device.h"
+#include "kernels.h"
+
+namespace vxk {
+
+using vxd::Key;
+
+constexpr int kMaxDigits = 1 << kMaxDigitBits;
+
+struct TileGeom {
+    // mode 0: tile t covers [t * chunk, min((t + 1) * chunk, n)).
+    // mode 1: tile t is part (t % q) of q equal parts of segment s = t / q,
+    //         which covers [seg[s], seg[s + 1]).
+    uint32_t mode;
+    uint32_t q;
+    uint64_t chunk;
+    uint64_t n;
+    const uint32_t *seg;
+};
+
+__device__ __forceinline__ void tile_range(const TileGeom &g, uint32_t t, uint64_t &lo,
+                                           uint64_t &hi) {
+    if (g.mode == 0) {
+        lo = (uint64_t)t * g.chunk;
+        hi = lo + g.chunk;
+        if (lo > g.n) lo = g.n;
+        if (hi > g.n) hi = g.n;
+    } else {
+        const uint32_t s = t / g.q, part = t % g.q;
+        const uint64_t a = g.seg[s], b = g.seg[s + 1], len = b - a;
+        lo = a + len * part / g.q;
+        hi = a + len * (part + 1) / g.q;
+    }
+}
+
+__device__ __forceinline__ bool rec_less(uint64_t ka, uint32_t na, uint64_t kb, uint32_t nb) {
+    return ka < kb || (ka == kb && na < nb);
+}
+
+// ---------------------------------------------------------------------------
+// Table-1 hash (+ first-digit histogram)
+// ---------------------------------------------------------------------------
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_hash_table1(Key key, uint64_t n, uint64_t chunk,
+                                                       uint64_t *__restrict__ keys,
+                                                       uint32_t *__restrict__ hist,
+                                                       uint32_t hist_bits) {
+    __shared__ uint32_t s_hist[kMaxDigits];
+    const uint32_t nd = hist ? (1u << hist_bits) : 0u;
+    for (uint32_t i = threadIdx.x; i < nd; i += BLOCK) s_hist[i] = 0;
+    __syncthreads();
+    uint64_t lo = (uint64_t)blockIdx.x * chunk;
+    uint64_t hi = lo + chunk;
+    if (hi > n) hi = n;
+    const uint32_t shift = 64u - hist_bits;
+    uint64_t i = lo + threadIdx.x;
+    for (; i + BLOCK < hi; i += 2 * BLOCK) {
+        const uint64_t a = vxd::h1(key, (uint32_t)i);
+        const uint64_t b = vxd::h1(key, (uint32_t)(i + BLOCK));
+        keys[i] = a;
+        keys[i + BLOCK] = b;
+        if (hist) {
+            atomicAdd(&s_hist[a >> shift], 1u);
+            atomicAdd(&s_hist[b >> shift], 1u);
+        }
+    }
+    if (i < hi) {
+        const uint64_t a = vxd::h1(key, (uint32_t)i);
+        keys[i] = a;
+        if (hist) atomicAdd(&s_hist[a >> shift], 1u);
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < nd; d += BLOCK) hist[(uint64_t)blockIdx.x * nd + d] = s_hist[d];
+}
+
+// ---------------------------------------------------------------------------
+// Digit histogram per tile
+// ---------------------------------------------------------------------------
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_digit_hist(const uint64_t *__restrict__ keys,
+                                                      TileGeom geom, uint32_t shift,
+                                                      uint32_t bits, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t s_hist[kMaxDigits];
+    const uint32_t nd = 1u << bits, mask = nd - 1u;
+    for (uint32_t i = threadIdx.x; i < nd; i += BLOCK) s_hist[i] = 0;
+    __syncthreads();
+    uint64_t lo, hi;
+    tile_range(geom, blockIdx.x, lo, hi);
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += BLOCK)
+        atomicAdd(&s_hist[(uint32_t)(keys[i] >> shift) & mask], 1u);
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < nd; d += BLOCK) hist[(uint64_t)blockIdx.x * nd + d] = s_hist[d];
+}
+
+// ---------------------------------------------------------------------------
+// Segmented column scan of per-tile digit histograms.
+// hist/off are [rows][ncol]; segment s (one work-group) owns rows
+// [s * rps, (s + 1) * rps) and starts at record seg_base[s] (0 if NULL).
+// off[r][c] = seg_base + sum_{c' < c} total(s, c') + sum_{rows r' < r of s} hist[r'][c]
+// gstart[s * ncol + c] = seg_base + sum_{c' < c} total(s, c'); the last
+// work-group also writes gstart[n_groups] = n_total.
+// ---------------------------------------------------------------------------
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_colscan(const uint32_t *__restrict__ hist,
+                                                   uint32_t *__restrict__ off, uint32_t rps,
+                                                   uint32_t ncol,
+                                                   const uint32_t *__restrict__ seg_base,
+                                                   uint32_t *__restrict__ gstart,
+                                                   uint32_t n_groups, uint32_t n_total) {
+    __shared__ uint32_t s_part[BLOCK];
+    __shared__ uint32_t s_col[kMaxDigits];
+    __shared__ uint32_t s_wave[BLOCK / 64 + 1];
+    const uint32_t s = blockIdx.x;
+    const uint32_t base = seg_base ? seg_base[s] : 0u;
+    const uint64_t r0 = (uint64_t)s * rps;
+    const uint32_t tid = threadIdx.x;
+    if (ncol < BLOCK) {
+        // R row slices per column, one column per thread.
+        const uint32_t R = BLOCK / ncol;
+        const uint32_t c = tid % ncol, q = tid / ncol;
+        const uint32_t a = (uint32_t)((uint64_t)rps * q / R), b = (uint32_t)((uint64_t)rps * (q + 1) / R);
+        uint32_t sum = 0;
+#pragma unroll 8
+        for (uint32_t r = a; r < b; ++r) sum += hist[(r0 + r) * ncol + c];
+        s_part[tid] = sum;
+        __syncthreads();
+        if (tid < ncol) {
+            uint32_t run = 0;
+            for (uint32_t qq = 0; qq < R; ++qq) {
+                const uint32_t v = s_part[qq * ncol + tid];
+                s_part[qq * ncol + tid] = run;
+                run += v;
+            }
+            s_col[tid] = run;
+        }
+        __syncthreads();
+        vxd::lds_exclusive_scan<BLOCK>(s_col, (int)ncol, s_wave);
+        for (uint32_t cc = tid; cc < ncol; cc += BLOCK) gstart[(uint64_t)s * ncol + cc] = base + s_col[cc];
+        uint32_t run = base + s_col[c] + s_part[tid];
+#pragma unroll 8
+        for (uint32_t r = a; r < b; ++r) {
+            const uint64_t ix = (r0 + r) * ncol + c;
+            const uint32_t v = hist[ix];
+            off[ix] = run;
+            run += v;
+        }
+    } else {
+        // ncol >= BLOCK: several columns per thread, every row.
+        for (uint32_t c = tid; c < ncol; c += BLOCK) {
+            uint32_t sum = 0;
+            for (uint32_t r = 0; r < rps; ++r) sum += hist[(r0 + r) * ncol + c];
+            s_col[c] = sum;
+        }
+        __syncthreads();
+        vxd::lds_exclusive_scan<BLOCK>(s_col, (int)ncol, s_wave);
+        for (uint32_t c = tid; c < ncol; c += BLOCK) {
+            gstart[(uint64_t)s * ncol + c] = base + s_col[c];
+            uint32_t run = base + s_col[c];
+            for (uint32_t r = 0; r < rps; ++r) {
+                const uint64_t ix = (r0 + r) * ncol + c;
+                const uint32_t v = hist[ix];
+                off[ix] = run;
+                run += v;
+            }
+        }
+    }
+    if (s == gridDim.x - 1 && tid == 0) gstart[n_groups] = n_total;
+}
+
+// ---------------------------------------------------------------------------
+// Partition scatter: each tile streams its records in sub-tiles, ranks them
+// by digit in LDS and writes every digit's run contiguously at the tile's
+// running cursor for that digit.
+// ---------------------------------------------------------------------------
+
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ in_keys,
+                                                   const uint32_t *__restrict__ in_nonces,
+                                                   uint64_t *__restrict__ out_keys,
+                                                   uint32_t *__restrict__ out_nonces,
+                                                   const uint32_t *__restrict__ off, TileGeom geom,
+                                                   uint32_t shift, uint32_t bits) {
+    constexpr int SUB = BLOCK * ITEMS;
+    __shared__ uint64_t s_keys[SUB];
+    __shared__ uint32_t s_nonces[SUB];
+    __shared__ uint32_t s_cursor[kMaxDigits];
+    __shared__ uint32_t s_start[kMaxDigits + 1];
+    __shared__ uint32_t s_wave[BLOCK / 64 + 1];
+    const uint32_t nd = 1u << bits, mask = nd - 1u;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t d = tid; d < nd; d += BLOCK) s_cursor[d] = off[(uint64_t)blockIdx.x * nd + d];
+    uint64_t lo, hi;
+    tile_range(geom, blockIdx.x, lo, hi);
+    for (uint64_t base = lo; base < hi; base += SUB) {
+        for (uint32_t d = tid; d < nd; d += BLOCK) s_start[d] = 0;
+        __syncthreads();
+        uint64_t k[ITEMS];
+        uint32_t nn[ITEMS], slot[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint64_t idx = base + (uint64_t)j * BLOCK + tid;
+            if (idx < hi) {
+                k[j] = in_keys[idx];
+                nn[j] = in_nonces ? in_nonces[idx] : (uint32_t)idx;
+                slot[j] = atomicAdd(&s_start[(uint32_t)(k[j] >> shift) & mask], 1u);
+            }
+        }
+        __syncthreads();
+        const uint32_t total = vxd::lds_exclusive_scan<BLOCK>(s_start, (int)nd, s_wave);
+        if (tid == 0) s_start[nd] = total;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint64_t idx = base + (uint64_t)j * BLOCK + tid;
+            if (idx < hi) {
+                const uint32_t p = s_start[(uint32_t)(k[j] >> shift) & mask] + slot[j];
+                s_keys[p] = k[j];
+                s_nonces[p] = nn[j];
+            }
+        }
+        __syncthreads();
+        for (uint32_t e = tid; e < total; e += BLOCK) {
+            const uint64_t kk = s_keys[e];
+            const uint32_t d = (uint32_t)(kk >> shift) & mask;
+            const uint64_t g = (uint64_t)s_cursor[d] + (e - s_start[d]);
+            out_keys[g] = kk;
+            out_nonces[g] = s_nonces[e];
+        }
+        __syncthreads();
+        for (uint32_t d = tid; d < nd; d += BLOCK) s_cursor[d] += s_start[d + 1] - s_start[d];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Group sort in LDS (in place on Table 1) + bucket offsets of the group.
+// ---------------------------------------------------------------------------
+
+constexpr int kSubBinBits = 12;
+constexpr int kSubBins = 1 << kSubBinBits;
+
+template <int BLOCK, int CAPMAX>
+__global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys,
+                                                     uint32_t *__restrict__ nonces,
+                                                     const uint32_t *__restrict__ gstart,
+                                                     uint32_t G, uint32_t cap,
+                                                     uint32_t *__restrict__ offsets,
+                                                     uint32_t n_total,
+                                                     uint32_t *__restrict__ ovf_count,
+                                                     uint32_t *__restrict__ ovf_list) {
+    constexpr int ITEMS = CAPMAX / BLOCK;
+    __shared__ uint64_t s_keys[CAPMAX];
+    __shared__ uint32_t s_nonces[CAPMAX];
+    __shared__ uint32_t s_start[kSubBins + 1];
+    __shared__ uint32_t s_wave[BLOCK / 64 + 1];
+    const uint32_t g = blockIdx.x, tid = threadIdx.x;
+    const uint32_t lo = gstart[g], hi = gstart[g + 1], n = hi - lo;
+    if (g == gridDim.x - 1 && tid == 0) offsets[VXK_NUM_BUCKETS] = n_total;
+    if (n > cap) {
+        if (tid == 0) {
+            const uint32_t i = atomicAdd(ovf_count, 1u);
+            ovf_list[i] = g;
+        }
+        return;
+    }
+    for (uint32_t i = tid; i < kSubBins; i += BLOCK) s_start[i] = 0;
+    __syncthreads();
+    const uint32_t sb_shift = 64u - G - kSubBinBits;
+    uint64_t k[ITEMS];
+    uint32_t nn[ITEMS], slot[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t e = j * BLOCK + tid;
+        if (e < n) {
+            k[j] = keys[lo + e];
+            nn[j] = nonces[lo + e];
+            slot[j] = atomicAdd(&s_start[(uint32_t)(k[j] >> sb_shift) & (kSubBins - 1)], 1u);
+        }
+    }
+    __syncthreads();
+    vxd::lds_exclusive_scan<BLOCK>(s_start, kSubBins, s_wave);
+    if (tid == 0) s_start[kSubBins] = n;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t e = j * BLOCK + tid;
+        if (e < n) {
+            const uint32_t p = s_start[(uint32_t)(k[j] >> sb_shift) & (kSubBins - 1)] + slot[j];
+            s_keys[p] = k[j];
+            s_nonces[p] = nn[j];
+        }
+    }
+    __syncthreads();
+    // Exact rank inside the sub-bin; slot[] is reused for the final position.
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t e = j * BLOCK + tid;
+        if (e < n) {
+            const uint32_t sb = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
+            const uint32_t b0 = s_start[sb], b1 = s_start[sb + 1];
+            uint32_t r = 0;
+            for (uint32_t x = b0; x < b1; ++x) r += rec_less(s_keys[x], s_nonces[x], k[j], nn[j]);
+            slot[j] = b0 + r;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t e = j * BLOCK + tid;
+        if (e < n) {
+            s_keys[slot[j]] = k[j];
+            s_nonces[slot[j]] = nn[j];
+        }
+    }
+    __syncthreads();
+    for (uint32_t e = tid; e < n; e += BLOCK) {
+        keys[lo + e] = s_keys[e];
+        nonces[lo + e] = s_nonces[e];
+    }
+    // offsets[b] for the group's buckets: first record with bucket >= b.
+    const uint32_t nbg = 1u << (VXK_BUCKET_BITS - G);
+    const uint32_t bfirst = g << (VXK_BUCKET_BITS - G);
+    for (uint32_t bl = tid; bl < nbg; bl += BLOCK) {
+        const uint32_t b = bfirst + bl;
+        uint32_t a = 0, c = n;
+        while (a < c) {
+            const uint32_t mid = (a + c) >> 1;
+            if ((uint32_t)(s_keys[mid] >> 40) < b) a = mid + 1; else c = mid;
+        }
+        offsets[b] = lo + a;
+    }
+}
+
+// Groups larger than the LDS capacity: rank sort against LDS-staged tiles of
+// the group (copied to scratch first), then bucket offsets by binary search
+// in global memory.  Groups above fb_max set a status bit and stay unsorted.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_group_fallback(
+    uint64_t *__restrict__ keys, uint32_t *__restrict__ nonces, uint64_t *__restrict__ scr_keys,
+    uint32_t *__restrict__ scr_nonces, const uint32_t *__restrict__ gstart, uint32_t G,
+    uint32_t *__restrict__ offsets, const uint32_t *__restrict__ ovf_count,
+    const uint32_t *__restrict__ ovf_list, uint32_t fb_max, uint32_t *__restrict__ status) {
+    __shared__ uint64_t s_k[BLOCK];
+    __shared__ uint32_t s_n[BLOCK];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t cnt = *ovf_count;
+    for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const uint32_t g = ovf_list[i];
+        const uint32_t lo = gstart[g], hi = gstart[g + 1], n = hi - lo;
+        if (n > fb_max) {
+            if (tid == 0) atomicOr(status, (uint32_t)VXK_DEV_STATUS_GROUP_TOO_LARGE);
+            continue;
+        }
+        for (uint32_t e = tid; e < n; e += BLOCK) {
+            scr_keys[lo + e] = keys[lo + e];
+            scr_nonces[lo + e] = nonces[lo + e];
+        }
+        __syncthreads();
+        for (uint32_t e0 = 0; e0 < n; e0 += BLOCK) {
+            const uint32_t e = e0 + tid;
+            const bool valid = e < n;
+            uint64_t mk = 0;
+            uint32_t mn = 0, r = 0;
+            if (valid) {
+                mk = scr_keys[lo + e];
+                mn = scr_nonces[lo + e];
+            }
+            for (uint32_t t0 = 0; t0 < n; t0 += BLOCK) {
+                __syncthreads();
+                if (t0 + tid < n) {
+                    s_k[tid] = scr_keys[lo + t0 + tid];
+                    s_n[tid] = scr_nonces[lo + t0 + tid];
+                }
+                __syncthreads();
+                const uint32_t m = min((uint32_t)BLOCK, n - t0);
+                if (valid)
+                    for (uint32_t x = 0; x < m; ++x) r += rec_less(s_k[x], s_n[x], mk, mn);
+            }
+            if (valid) {
+                keys[lo + r] = mk;
+                nonces[lo + r] = mn;
+            }
+        }
+        __syncthreads();
+        const uint32_t nbg = 1u << (VXK_BUCKET_BITS - G);
+        const uint32_t bfirst = g << (VXK_BUCKET_BITS - G);
+        for (uint32_t bl = tid; bl < nbg; bl += BLOCK) {
+            const uint32_t b = bfirst + bl;
+            uint32_t a = 0, c = n;
+            while (a < c) {
+                const uint32_t mid = (a + c) >> 1;
+                if ((uint32_t)(keys[lo + mid] >> 40) < b) a = mid + 1; else c = mid;
+            }
+            offsets[b] = lo + a;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Match: pair count per match group (buckets [g << (24-Gm), (g+1) << (24-Gm))).
+// ---------------------------------------------------------------------------
+
+template <int BLOCK, int MCAP>
+__global__ __launch_bounds__(BLOCK) void k_match_count(const uint64_t *__restrict__ keys,
+                                                       const uint32_t *__restrict__ offsets,
+                                                       uint32_t Gm, uint64_t T, uint32_t n_total,
+                                                       uint64_t *__restrict__ counts) {
+    __shared__ uint64_t s_keys[MCAP];
+    __shared__ uint64_t s_wave[BLOCK / 64 + 1];
+    const uint32_t g = blockIdx.x, tid = threadIdx.x;
+    const uint32_t sh = VXK_BUCKET_BITS - Gm;
+    // Offsets come from the caller: clamp so that a malformed table cannot
+    // send reads outside [0, n_total).
+    const uint32_t hi = min(offsets[(g + 1) << sh], n_total);
+    const uint32_t lo = min(offsets[g << sh], hi);
+    uint64_t total = 0;
+    for (uint32_t c = lo; c < hi; c += MCAP) {
+        const uint32_t m = min((uint32_t)MCAP, hi - c);
+        for (uint32_t e = tid; e < m; e += BLOCK) s_keys[e] = keys[c + e];
+        __syncthreads();
+        for (uint32_t e = tid; e < m; e += BLOCK) {
+            const uint64_t ki = s_keys[e];
+            const uint32_t bi = (uint32_t)(ki >> 40);
+            for (uint32_t j = c + e + 1; j < hi; ++j) {
+                const uint64_t kj = (j - c < m) ? s_keys[j - c] : keys[j];
+                if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
+                ++total;
+            }
+        }
+        __syncthreads();
+    }
+    total = vxd::block_sum<BLOCK>(total, s_wave);
+    if (tid == 0) counts[g] = total;
+}
+
+// Match + Table-2 hash.  Per chunk of the match group: each record's pair
+// count goes through a work-group scan into LDS offsets (u64, so degenerate
+// inputs cannot overflow); then every lane takes pair slots p = tid, tid +
+// BLOCK, ..., finds the record owning slot p by binary search of the
+// offsets, and hashes that pair.  Slots are in canonical order, so the
+// Table-2 index is group base + chunk base + p.
+template <int BLOCK, int MCAP>
+__global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *__restrict__ keys,
+                                                      const uint32_t *__restrict__ nonces,
+                                                      const uint32_t *__restrict__ offsets,
+                                                      uint32_t Gm, uint64_t T, uint32_t n_total,
+                                                      const uint64_t *__restrict__ group_base,
+                                                      uint4 *__restrict__ t2, uint64_t cap) {
+    constexpr int ITEMS = MCAP / BLOCK;
+    __shared__ uint64_t s_keys[MCAP];
+    __shared__ uint32_t s_nonces[MCAP];
+    __shared__ uint64_t s_off[MCAP + 1];
+    __shared__ uint64_t s_wave[BLOCK / 64 + 1];
+    const uint32_t g = blockIdx.x, tid = threadIdx.x;
+    const uint32_t sh = VXK_BUCKET_BITS - Gm;
+    const uint32_t hi = min(offsets[(g + 1) << sh], n_total);
+    const uint32_t lo = min(offsets[g << sh], hi);
+    uint64_t base = group_base[g];
+    for (uint32_t c = lo; c < hi; c += MCAP) {
+        const uint32_t m = min((uint32_t)MCAP, hi - c);
+        for (uint32_t e = tid; e < m; e += BLOCK) {
+            s_keys[e] = keys[c + e];
+            s_nonces[e] = nonces[c + e];
+        }
+        __syncthreads();
+        // Pair counts of this thread's contiguous records, kept in s_off.
+        uint64_t mine = 0;
+        const uint32_t e0 = tid * ITEMS;
+#pragma unroll 1
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t e = e0 + i;
+            uint32_t cnt = 0;
+            if (e < m) {
+                const uint64_t ki = s_keys[e];
+                const uint32_t bi = (uint32_t)(ki >> 40);
+                for (uint32_t j = c + e + 1; j < hi; ++j) {
+                    const uint64_t kj = (j - c < m) ? s_keys[j - c] : keys[j];
+                    if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
+                    ++cnt;
+                }
+            }
+            s_off[e] = cnt;
+            mine += cnt;
+        }
+        uint64_t ctot;
+        uint64_t run = vxd::block_exclusive_scan<BLOCK>(mine, s_wave, &ctot);
+#pragma unroll 1
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t e = e0 + i;
+            const uint64_t cnt = s_off[e];
+            s_off[e] = run;
+            run += cnt;
+        }
+        if (tid == 0) s_off[MCAP] = ctot;
+        __syncthreads();
+        // Records past m own no slots (count 0), so the search over all MCAP
+        // entries stays inside [0, m).
+#pragma unroll 1
+        for (uint64_t p = tid; p < ctot; p += BLOCK) {
+            uint32_t a = 0, b = MCAP;  // largest e with s_off[e] <= p
+            while (b - a > 1) {
+                const uint32_t mid = (a + b) >> 1;
+                if (s_off[mid] <= p) a = mid; else b = mid;
+            }
+            const uint32_t e = a;
+            const uint32_t j = c + e + 1 + (uint32_t)(p - s_off[e]);
+            const uint32_t na = s_nonces[e];
+            const uint32_t nb = (j - c < m) ? s_nonces[j - c] : nonces[j];
+            const uint64_t h = vxd::h2(key, na, nb);
+            const uint64_t idx = base + p;
+            if (idx < cap) t2[idx] = make_uint4(na, nb, (uint32_t)h, (uint32_t)(h >> 32));
+        }
+        base += ctot;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan of u64 (pair counts -> Table-2 bases).
+// ---------------------------------------------------------------------------
+
+constexpr int kScanBlock = 1024;
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kScanBlock * kScanPer;
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const uint64_t *__restrict__ in,
+                                                           uint32_t n, uint64_t *__restrict__ part) {
+    __shared__ uint64_t s_wave[kScanBlock / 64 + 1];
+    const uint64_t t0 = (uint64_t)blockIdx.x * kScanTile;
+    uint64_t sum = 0;
+    for (int i = 0; i < kScanPer; ++i) {
+        const uint64_t ix = t0 + (uint64_t)i * kScanBlock + threadIdx.x;
+        if (ix < n) sum += in[ix];
+    }
+    sum = vxd::block_sum<kScanBlock>(sum, s_wave);
+    if (threadIdx.x == 0) part[blockIdx.x] = sum;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_partials(uint64_t *__restrict__ part,
+                                                             uint32_t nparts,
+                                                             uint64_t *__restrict__ total_out) {
+    __shared__ uint64_t s[kScanTile];
+    __shared__ uint64_t s_wave[kScanBlock / 64 + 1];
+    for (uint32_t i = threadIdx.x; i < nparts; i += kScanBlock) s[i] = part[i];
+    __syncthreads();
+    const uint64_t total = vxd::lds_exclusive_scan<kScanBlock>(s, (int)nparts, s_wave);
+    for (uint32_t i = threadIdx.x; i < nparts; i += kScanBlock) part[i] = s[i];
+    if (threadIdx.x == 0 && total_out) *total_out = total;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(const uint64_t *__restrict__ in, uint32_t n,
+                                                          const uint64_t *__restrict__ part,
+                                                          uint64_t *__restrict__ out) {
+    __shared__ uint64_t s[kScanTile];
+    __shared__ uint64_t s_wave[kScanBlock / 64 + 1];
+    const uint64_t t0 = (uint64_t)blockIdx.x * kScanTile;
+    const uint32_t m = (uint32_t)min((uint64_t)kScanTile, (uint64_t)n - t0);
+    for (uint32_t i = threadIdx.x; i < m; i += kScanBlock) s[i] = in[t0 + i];
+    __syncthreads();
+    vxd::lds_exclusive_scan<kScanBlock>(s, (int)m, s_wave);
+    const uint64_t base = part[blockIdx.x];
+    for (uint32_t i = threadIdx.x; i < m; i += kScanBlock) out[t0 + i] = base + s[i];
+}
+
+__global__ void k_reset_words(uint32_t *__restrict__ p, uint32_t n) {
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+// ---------------------------------------------------------------------------
+
+static TileGeom geom_chunks(uint64_t n, uint64_t chunk) {
+    TileGeom g;
+    g.mode = 0;
+    g.q = 1;
+    g.chunk = chunk;
+    g.n = n;
+    g.seg = nullptr;
+    return g;
+}
+
+static TileGeom geom_segments(const uint32_t *seg, uint32_t q) {
+    TileGeom g;
+    g.mode = 1;
+    g.q = q;
+    g.chunk = 0;
+    g.n = 0;
+    g.seg = seg;
+    return g;
+}
+
+constexpr int kHashBlock = 256;
+constexpr int kHistBlock = 256;
+constexpr int kColBlock = 1024;
+constexpr int kScatterBlock = 256;
+constexpr int kScatterItems = 16;
+constexpr int kSortBlock = 512;
+constexpr int kFallbackBlock = 1024;
+constexpr int kFallbackGrid = 256;
+constexpr int kMatchBlock = 256;
+constexpr int kMatchCap = 2048;
+
+hipError_t launch_reset(uint32_t *words, uint32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_words, dim3(1), dim3(256), 0, s, words, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_table1(const uint32_t key_words[8], uint64_t n, uint32_t tiles, uint64_t chunk,
+                              uint64_t *keys, uint32_t *hist, uint32_t hist_bits, hipStream_t s) {
+    Key key;
+    for (int i = 0; i < 8; ++i) key.w[i] = key_words[i];
+    hipLaunchKernelGGL(k_hash_table1<kHashBlock>, dim3(tiles), dim3(kHashBlock), 0, s, key, n, chunk,
+                       keys, hist, hist_bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist_chunks(const uint64_t *keys, uint64_t n, uint32_t tiles, uint64_t chunk,
+                              uint32_t shift, uint32_t bits, uint32_t *hist, hipStream_t s) {
+    hipLaunchKernelGGL(k_digit_hist<kHistBlock>, dim3(tiles), dim3(kHistBlock), 0, s, keys,
+                       geom_chunks(n, chunk), shift, bits, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist_segments(const uint64_t *keys, const uint32_t *seg, uint32_t nseg, uint32_t q,
+                                uint32_t shift, uint32_t bits, uint32_t *hist, hipStream_t s) {
+    hipLaunchKernelGGL(k_digit_hist<kHistBlock>, dim3(nseg * q), dim3(kHistBlock), 0, s, keys,
+                       geom_segments(seg, q), shift, bits, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_colscan(const uint32_t *hist, uint32_t *off, uint32_t nseg, uint32_t rps,
+                          uint32_t ncol, const uint32_t *seg_base, uint32_t *gstart, uint32_t n_groups,
+                          uint32_t n_total, hipStream_t s) {
+    hipLaunchKernelGGL(k_colscan<kColBlock>, dim3(nseg), dim3(kColBlock), 0, s, hist, off, rps, ncol,
+                       seg_base, gstart, n_groups, n_total);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_chunks(const uint64_t *in_keys, const uint32_t *in_nonces,
+                                 uint64_t *out_keys, uint32_t *out_nonces, const uint32_t *off,
+                                 uint64_t n, uint32_t tiles, uint64_t chunk, uint32_t shift,
+                                 uint32_t bits, hipStream_t s) {
+    hipLaunchKernelGGL((k_scatter<kScatterBlock, kScatterItems>), dim3(tiles), dim3(kScatterBlock), 0,
+                       s, in_keys, in_nonces, out_keys, out_nonces, off, geom_chunks(n, chunk), shift,
+                       bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_segments(const uint64_t *in_keys, const uint32_t *in_nonces,
+                                   uint64_t *out_keys, uint32_t *out_nonces, const uint32_t *off,
+                                   const uint32_t *seg, uint32_t nseg, uint32_t q, uint32_t shift,
+                                   uint32_t bits, hipStream_t s) {
+    hipLaunchKernelGGL((k_scatter<kScatterBlock, kScatterItems>), dim3(nseg * q), dim3(kScatterBlock),
+                       0, s, in_keys, in_nonces, out_keys, out_nonces, off, geom_segments(seg, q),
+                       shift, bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint32_t *gstart, uint32_t G,
+                            uint32_t cap, uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count,
+                            uint32_t *ovf_list, hipStream_t s) {
+    hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapMax>), dim3(1u << G), dim3(kSortBlock), 0, s,
+                       keys, nonces, gstart, G, cap, offsets, n_total, ovf_count, ovf_list);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, uint64_t *scr_keys,
+                                 uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G,
+                                 uint32_t *offsets, const uint32_t *ovf_count, const uint32_t *ovf_list,
+                                 uint32_t *status, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_fallback<kFallbackBlock>, dim3(kFallbackGrid), dim3(kFallbackBlock), 0,
+                       s, keys, nonces, scr_keys, scr_nonces, gstart, G, offsets, ovf_count, ovf_list,
+                       (uint32_t)kFallbackMax, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_match_count(const uint64_t *keys, const uint32_t *offsets, uint32_t Gm, uint64_t T,
+                              uint32_t n_total, uint64_t *counts, hipStream_t s) {
+    hipLaunchKernelGGL((k_match_count<kMatchBlock, kMatchCap>), dim3(1u << Gm), dim3(kMatchBlock), 0, s,
+                       keys, offsets, Gm, T, n_total, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_u64(const uint64_t *in, uint32_t n, uint64_t *out, uint64_t *part,
+                           uint64_t *total, hipStream_t s) {
+    const uint32_t nparts = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nparts), dim3(kScanBlock), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanBlock), 0, s, part, nparts, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nparts), dim3(kScanBlock), 0, s, in, n, part, out);
+    return hipGetLastError();
+}
+
+uint32_t scan_parts(uint32_t n) { return (n + kScanTile - 1) / kScanTile; }
+
+hipError_t launch_match_emit(const uint32_t key_words[8], const uint64_t *keys, const uint32_t *nonces,
+                             const uint32_t *offsets, uint32_t Gm, uint64_t T, uint32_t n_total,
+                             const uint64_t *group_base, void *t2, uint64_t cap, hipStream_t s) {
+    Key key;
+    for (int i = 0; i < 8; ++i) key.w[i] = key_words[i];
+    hipLaunchKernelGGL((k_match_emit<kMatchBlock, kMatchCap>), dim3(1u << Gm),
+                       dim3(kMatchBlock), 0, s, key, keys, nonces, offsets, Gm, T, n_total,
+                       group_base, (uint4 *)t2, cap);
+    return hipGetLastError();
+}
+
+}  // namespace vxk

@@ -1,0 +1,178 @@
+"""Device buffers for plots (torch tensors as HIP memory) and one-call helpers
+around the C ABI.  Every computation runs in libvx's kernels; this module only
+allocates memory, passes pointers and copies results back for inspection."""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+T2_DTYPE = np.dtype([("nonce_a", "<u4"), ("nonce_b", "<u4"), ("hash2", "<u8")])
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dev(device):
+    return torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+
+
+def _need_cuda(t: torch.Tensor, name: str, nbytes: int) -> int:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{name} holds fewer than {nbytes} bytes")
+    return t.data_ptr()
+
+
+@dataclass
+class PlotBuffers:
+    """All device memory of one plot at size k (caller-owned, reusable)."""
+    k: int
+    t1_keys: torch.Tensor        # int64[2^k], read as u64
+    t1_nonces: torch.Tensor      # int32[2^k], read as u32
+    bucket_offsets: torch.Tensor  # int32[2^24 + 1], read as u32
+    t2: torch.Tensor             # int64[cap, 2] = 16-byte records
+    t2_count: torch.Tensor       # int64[1], read as u64
+    workspace: torch.Tensor      # uint8[workspace_bytes]
+
+    @property
+    def t2_capacity(self) -> int:
+        return self.t2.shape[0]
+
+    def native(self) -> N.VxPlotBuffers:
+        b = N.VxPlotBuffers()
+        b.t1_keys = self.t1_keys.data_ptr()
+        b.t1_nonces = self.t1_nonces.data_ptr()
+        b.bucket_offsets = self.bucket_offsets.data_ptr()
+        b.t2 = self.t2.data_ptr() if self.t2_capacity else None
+        b.t2_capacity = self.t2_capacity
+        b.t2_count = self.t2_count.data_ptr()
+        b.workspace = self.workspace.data_ptr()
+        b.workspace_bytes = self.workspace.numel()
+        return b
+
+    def nbytes(self) -> int:
+        return sum(t.numel() * t.element_size() for t in
+                   (self.t1_keys, self.t1_nonces, self.bucket_offsets, self.t2, self.t2_count,
+                    self.workspace))
+
+
+def footprint_bytes(k: int, threshold: int | None = None, t2_capacity: int | None = None,
+                    tuning: N.VxTuning | None = None) -> int:
+    """Device bytes alloc_plot(k) takes: Table 1, offsets, Table 2, workspace."""
+    p = N.make_params(bytes(32), k, threshold)
+    cap = N.vx_t2_capacity_hint(k, p.match_threshold) if t2_capacity is None else t2_capacity
+    n = 1 << k
+    return (n * 12 + (N.VX_NUM_BUCKETS + 1) * 4 + cap * 16 + 8 +
+            N.vx_workspace_bytes(p, N.VX_CALL_PLOT, tuning))
+
+
+def alloc_plot(k: int, threshold: int | None = None, t2_capacity: int | None = None,
+               tuning: N.VxTuning | None = None, device=None) -> PlotBuffers:
+    dev = _dev(device)
+    p = N.make_params(bytes(32), k, threshold)
+    cap = N.vx_t2_capacity_hint(k, p.match_threshold) if t2_capacity is None else int(t2_capacity)
+    ws = N.vx_workspace_bytes(p, N.VX_CALL_PLOT, tuning)
+    if ws == 0:
+        raise ValueError("invalid plot parameters or tuning")
+    n = 1 << k
+    return PlotBuffers(
+        k=k,
+        t1_keys=torch.empty(n, dtype=torch.int64, device=dev),
+        t1_nonces=torch.empty(n, dtype=torch.int32, device=dev),
+        bucket_offsets=torch.empty(N.VX_NUM_BUCKETS + 1, dtype=torch.int32, device=dev),
+        t2=torch.empty((cap, 2), dtype=torch.int64, device=dev),
+        t2_count=torch.zeros(1, dtype=torch.int64, device=dev),
+        workspace=torch.empty(ws, dtype=torch.uint8, device=dev),
+    )
+
+
+def plot(key: bytes, k: int, threshold: int | None = None, buffers: PlotBuffers | None = None,
+         tuning: N.VxTuning | None = None, stream=None) -> PlotBuffers:
+    """Enqueue one whole plot (vx_plot); returns the buffers holding it."""
+    p = N.make_params(key, k, threshold)
+    if buffers is None:
+        buffers = alloc_plot(k, p.match_threshold, tuning=tuning)
+    if buffers.k != k:
+        raise ValueError("buffers were allocated for another k")
+    N.vx_plot(p, buffers.native(), tuning, _stream(stream))
+    return buffers
+
+
+def hash_table1(key: bytes, k: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    p = N.make_params(key, k)
+    n = 1 << k
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=_dev(None))
+    N.vx_hash_table1(p, _need_cuda(out, "out", n * 8), _stream(stream))
+    return out
+
+
+def bucket_sort(key: bytes, k: int, keys: torch.Tensor, tuning: N.VxTuning | None = None,
+                stream=None):
+    """Returns (t1_keys, t1_nonces, offsets, workspace) device tensors."""
+    p = N.make_params(key, k)
+    n = 1 << k
+    dev = keys.device
+    t1k = torch.empty(n, dtype=torch.int64, device=dev)
+    t1n = torch.empty(n, dtype=torch.int32, device=dev)
+    off = torch.empty(N.VX_NUM_BUCKETS + 1, dtype=torch.int32, device=dev)
+    wsb = N.vx_workspace_bytes(p, N.VX_CALL_BUCKET_SORT, tuning)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    N.vx_bucket_sort(p, _need_cuda(keys, "keys", n * 8), t1k.data_ptr(), t1n.data_ptr(),
+                     off.data_ptr(), ws.data_ptr(), wsb, tuning, _stream(stream))
+    return t1k, t1n, off, ws
+
+
+def match_table2(key: bytes, k: int, t1_keys, t1_nonces, offsets, threshold: int | None = None,
+                 t2_capacity: int | None = None, tuning: N.VxTuning | None = None, stream=None):
+    """Returns (t2 int64[cap, 2], t2_count int64[1]) device tensors."""
+    p = N.make_params(key, k, threshold)
+    dev = t1_keys.device
+    cap = N.vx_t2_capacity_hint(k, p.match_threshold) if t2_capacity is None else int(t2_capacity)
+    t2 = torch.empty((max(cap, 1), 2), dtype=torch.int64, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    wsb = N.vx_workspace_bytes(p, N.VX_CALL_MATCH, tuning)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    n = 1 << k
+    N.vx_match_table2(p, _need_cuda(t1_keys, "t1_keys", n * 8),
+                      _need_cuda(t1_nonces, "t1_nonces", n * 4),
+                      _need_cuda(offsets, "offsets", (N.VX_NUM_BUCKETS + 1) * 4),
+                      t2.data_ptr(), cap, cnt.data_ptr(), ws.data_ptr(), wsb, tuning,
+                      _stream(stream))
+    return t2, cnt
+
+
+# ---- host views (for checks and export) -----------------------------------
+
+def u64(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+def u32(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def t2_records(t2: torch.Tensor, count: int) -> np.ndarray:
+    n = min(int(count), t2.shape[0])
+    return t2[:n].detach().cpu().numpy().view(T2_DTYPE).reshape(-1)
+
+
+def t2_count(buffers_or_tensor) -> int:
+    t = buffers_or_tensor.t2_count if isinstance(buffers_or_tensor, PlotBuffers) else buffers_or_tensor
+    return int(t.item())
+
+
+def device_status(workspace: torch.Tensor, stream=None) -> int:
+    return N.vx_read_status(workspace.data_ptr(), _stream(stream))

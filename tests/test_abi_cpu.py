@@ -1,0 +1,80 @@
+"""The C-ABI library on the CPU: it loads, exports every function that
+include/vx.h declares, and its host-only calls (sizes, thresholds,
+argument checks) behave as documented.  No kernel is launched."""
+import os
+import re
+
+import pytest
+
+import paper_2606_14007_amd as vx
+from paper_2606_14007_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "vx.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^[\w\s\*]*?\b(vx_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    names = _declared_functions()
+    assert len(names) >= 10
+    L = vx.lib()
+    bound = {n for n, _, _ in N.SYMBOLS}
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in bound, n
+        assert hasattr(vx, n), n
+
+
+def test_default_threshold():
+    for k in (1, 20, 27, 31):
+        assert vx.vx_default_threshold(k) == 1 << (64 - k)
+    assert vx.vx_default_threshold(0) == 0
+
+
+def test_capacity_hint_covers_expectation():
+    # E|T2| = 2^k * lam * t * (1 - t/2), lam = 2^(k-24), t = min(T, 2^40) / 2^40
+    for k in (10, 20, 27, 31):
+        T = 1 << (64 - k)
+        lam = 2.0 ** (k - 24)
+        t = min(T, 1 << 40) / float(1 << 40)
+        expect = (1 << k) * lam * t * (1 - t / 2)
+        cap = vx.vx_t2_capacity_hint(k, T)
+        assert cap >= expect * 1.04 + 4096
+        assert cap <= expect * 1.2 + 1e6
+
+
+def test_workspace_sizes_and_validation():
+    p = vx.make_params(bytes(32), 20)
+    a = vx.vx_workspace_bytes(p, vx.VX_CALL_BUCKET_SORT)
+    b = vx.vx_workspace_bytes(p, vx.VX_CALL_MATCH)
+    c = vx.vx_workspace_bytes(p, vx.VX_CALL_PLOT)
+    assert a > 12 << 20 and b > 0 and c >= a + (8 << 20)
+    assert vx.vx_workspace_bytes(p, 9) == 0
+    bad = vx.make_params(bytes(32), 20)
+    bad.k = 32
+    assert vx.vx_workspace_bytes(bad, vx.VX_CALL_PLOT) == 0
+    assert vx.vx_workspace_bytes(p, vx.VX_CALL_PLOT, vx.make_tuning(group_bits=25)) == 0
+    assert vx.vx_workspace_bytes(p, vx.VX_CALL_PLOT, vx.make_tuning(group_cap=10)) == 0
+
+
+@pytest.mark.parametrize("field,value", [("k", 0), ("k", 32), ("bucket_bits", 16)])
+def test_invalid_params_fail_before_any_device_work(field, value):
+    p = vx.make_params(bytes(32), 12)
+    setattr(p, field, value)
+    with pytest.raises(vx.VxError) as e:
+        vx.vx_hash_table1(p, 0)
+    assert e.value.status == N.VX_ERR_INVALID_ARG
+    assert vx.vx_last_error()
+
+
+def test_workspace_too_small_is_rejected_on_host():
+    p = vx.make_params(bytes(32), 12)
+    need = vx.vx_workspace_bytes(p, vx.VX_CALL_BUCKET_SORT)
+    with pytest.raises(vx.VxError) as e:
+        # fake, aligned device addresses: rejected before anything is enqueued
+        vx.vx_bucket_sort(p, 256, 512, 1024, 2048, 4096, need - 1)
+    assert e.value.status == N.VX_ERR_WORKSPACE

@@ -1,0 +1,177 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, bit-exact.
+
+Every input is seeded (vx_inputs) and every expected value comes from the
+oracle.  Sizes span one to many tiles, groups and match chunks with ragged
+tails; tunings that force the oversized-group fallback are included.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from vx_inputs import derive_key
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+KEY0 = derive_key(0)
+
+
+@pytest.fixture(scope="module")
+def vx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_14007_amd as m
+    m.lib()
+    return m
+
+
+def _crowded_keys(k, nbuckets, seed, ties=0):
+    rng = np.random.default_rng(seed)
+    n = 1 << k
+    prefixes = rng.choice(1 << 24, size=nbuckets, replace=False).astype(np.uint64)
+    low = rng.integers(0, 1 << 40, size=n, dtype=np.uint64)
+    keys = (prefixes[rng.integers(0, nbuckets, size=n)] << np.uint64(40)) | low
+    if ties:
+        keys[rng.integers(0, n, size=ties)] = keys[rng.integers(0, n, size=ties)]
+    return keys
+
+
+def _to_dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a).view(dtype)).cuda()
+
+
+def _assert_plot_equal(vx, b, ref):
+    torch.cuda.synchronize()
+    assert vx.device_status(b.workspace) == 0
+    assert np.array_equal(vx.u64(b.t1_keys), ref.t1_keys)
+    assert np.array_equal(vx.u32(b.t1_nonces), ref.t1_nonces)
+    assert np.array_equal(vx.u32(b.bucket_offsets), ref.offsets)
+    cnt = vx.t2_count(b)
+    assert cnt == len(ref.t2)
+    assert np.array_equal(vx.t2_records(b.t2, cnt), ref.t2)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 8, 12, 13, 14, 16])
+def test_hash_table1_small(vx, k):
+    out = vx.hash_table1(KEY0, k)
+    torch.cuda.synchronize()
+    assert np.array_equal(vx.u64(out), oracle.hash_table1(KEY0, k))
+
+
+def test_hash_table1_k20_several_keys(vx):
+    for seed in (0, 1, 77):
+        key = derive_key(seed)
+        out = vx.hash_table1(key, 20)
+        torch.cuda.synchronize()
+        assert np.array_equal(vx.u64(out), oracle.hash_table1(key, 20, threads=8))
+
+
+@pytest.mark.parametrize("k", [1, 3, 9, 12, 13, 15, 17, 20])
+def test_plot_default_threshold(vx, k):
+    b = vx.plot(KEY0, k)
+    _assert_plot_equal(vx, b, oracle.plot(KEY0, k, threads=8))
+
+
+@pytest.mark.parametrize("k,T", [(14, 1 << 44), (16, 1 << 42), (18, 1 << 41), (12, 0),
+                                 (16, (1 << 64) - 1)])
+def test_plot_thresholds(vx, k, T):
+    b = vx.plot(KEY0, k, threshold=T)
+    _assert_plot_equal(vx, b, oracle.plot(KEY0, k, threshold=T, threads=8))
+
+
+TUNINGS = [
+    dict(group_bits=4),                       # big groups -> LDS path near capacity / fallback
+    dict(group_bits=10, pass1_bits=3),        # two passes with a narrow first digit
+    dict(group_bits=12, pass1_bits=11),       # wide first digit
+    dict(group_cap=64),                       # almost every group takes the fallback
+    dict(group_cap=200, match_bits=3),        # fallback + long match chunks
+    dict(match_bits=0),                       # one match group for the whole table
+    dict(match_bits=20, h1_tiles=7),          # tiny match groups, ragged hash tiles
+]
+
+
+@pytest.mark.parametrize("tun", TUNINGS, ids=[str(t) for t in TUNINGS])
+def test_plot_tunings_do_not_change_outputs(vx, tun):
+    k, T = 16, 1 << 44
+    ref = oracle.plot(KEY0, k, threshold=T, threads=8)
+    t = vx.make_tuning(**tun)
+    b = vx.plot(KEY0, k, threshold=T, tuning=t)
+    _assert_plot_equal(vx, b, ref)
+
+
+@pytest.mark.parametrize("T", [0, 1 << 34, 1 << 37, 1 << 40, (1 << 64) - 1])
+def test_bucket_sort_and_match_crowded(vx, T):
+    """Caller-supplied keys crowded into few buckets: oversized groups, long
+    equal-prefix runs, duplicate keys (nonce tie-break), many pairs."""
+    k = 14
+    keys = _crowded_keys(k, nbuckets=9, seed=5, ties=40)
+    ref_t1k, ref_t1n, ref_off = oracle.bucket_sort(k, keys)
+    ref_t2, ref_cnt = oracle.match_table2(KEY0, T, ref_t1k, ref_t1n, ref_off, threads=8)
+    dkeys = _to_dev(keys, np.int64)
+    t1k, t1n, off, ws = vx.bucket_sort(KEY0, k, dkeys)
+    torch.cuda.synchronize()
+    assert vx.device_status(ws) == 0
+    assert np.array_equal(vx.u64(t1k), ref_t1k)
+    assert np.array_equal(vx.u32(t1n), ref_t1n)
+    assert np.array_equal(vx.u32(off), ref_off)
+    t2, cnt = vx.match_table2(KEY0, k, t1k, t1n, off, threshold=T, t2_capacity=ref_cnt + 5)
+    torch.cuda.synchronize()
+    assert vx.t2_count(cnt) == ref_cnt
+    assert np.array_equal(vx.t2_records(t2, ref_cnt), ref_t2)
+
+
+def test_match_from_oracle_table1(vx):
+    """vx_match_table2 on an oracle-built Table 1."""
+    k = 18
+    T = 1 << 43
+    ref = oracle.plot(KEY0, k, threshold=T, threads=8)
+    t2, cnt = vx.match_table2(KEY0, k, _to_dev(ref.t1_keys, np.int64),
+                              _to_dev(ref.t1_nonces, np.int32), _to_dev(ref.offsets, np.int32),
+                              threshold=T)
+    torch.cuda.synchronize()
+    assert vx.t2_count(cnt) == len(ref.t2)
+    assert np.array_equal(vx.t2_records(t2, len(ref.t2)), ref.t2)
+
+
+def test_t2_capacity_overflow_is_reported_not_written(vx):
+    k, T = 16, 1 << 44
+    ref = oracle.plot(KEY0, k, threshold=T, threads=8)
+    cap = len(ref.t2) // 3
+    b = vx.alloc_plot(k, T, t2_capacity=cap + 8)
+    sentinel = torch.full((8, 2), -1, dtype=torch.int64, device=b.t2.device)
+    b.t2[cap:].copy_(sentinel)
+    b2 = vx.PlotBuffers(k, b.t1_keys, b.t1_nonces, b.bucket_offsets, b.t2[:cap], b.t2_count,
+                        b.workspace)
+    vx.plot(KEY0, k, threshold=T, buffers=b2)
+    torch.cuda.synchronize()
+    assert vx.t2_count(b2) == len(ref.t2)
+    assert np.array_equal(vx.t2_records(b2.t2, cap), ref.t2[:cap])
+    assert torch.equal(b.t2[cap:], sentinel)
+
+
+def test_repeat_runs_are_identical(vx):
+    k = 20
+    a = vx.plot(KEY0, k)
+    b = vx.plot(KEY0, k)
+    torch.cuda.synchronize()
+    assert torch.equal(a.t1_keys, b.t1_keys) and torch.equal(a.t1_nonces, b.t1_nonces)
+    n = vx.t2_count(a)
+    assert n == vx.t2_count(b) and torch.equal(a.t2[:n], b.t2[:n])
+
+
+def test_invalid_arguments_raise(vx):
+    with pytest.raises(ValueError):
+        vx.make_params(bytes(31), 10)
+    p = vx.make_params(KEY0, 0)
+    with pytest.raises(vx.VxError):
+        vx.vx_hash_table1(p, 0)
+    p = vx.make_params(KEY0, 10)
+    p.bucket_bits = 20
+    with pytest.raises(vx.VxError):
+        vx.vx_hash_table1(p, 0)
+    with pytest.raises(ValueError):
+        vx.plot(KEY0, 10, tuning=vx.make_tuning(group_cap=8))
+    b = vx.alloc_plot(10)
+    with pytest.raises(vx.VxError):
+        vx.plot(KEY0, 10, buffers=b, tuning=vx.make_tuning(group_cap=8))
