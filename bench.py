@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark: one whole k=31 VaultX plot on one MI355X (K=31 plot seconds).
+
+A step is one vx_plot over the seeded k=31 workload (key from SplitMix64
+seed 0, 2^31 nonces, default threshold 2^33): keyed BLAKE3 of every nonce,
+bucketing by the 24-bit prefix, in-bucket sort, match, Table-2 hashing.  All
+buffers are allocated before the timed region.  Stage times come from HIP
+events recorded by the library on the plot's stream during the timed steps.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+STAGES = ["hash", "partition1", "partition2", "group_sort", "match_count", "match_emit"]
+KERNEL_OF_STAGE = {"hash": "k_hash_table1", "match_emit": "k_match_emit",
+                   "group_sort": "k_groupsort", "partition1": "k_scatter (pass 1)",
+                   "partition2": "k_scatter (pass 2)", "match_count": "k_match_count"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "blake3_device.h", "block_scan.h", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2606_14007_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, k: int):
+    """HBM bytes per launch of `kernel` at size k, from the committed
+    rocprofv3 counter summary, or None when absent or taken on other code."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for ln in open(path):
+        ln = ln.strip()
+        if not ln or ln.startswith("#"):
+            continue
+        parts = ln.split()
+        if len(parts) >= 5 and parts[0] == kernel and parts[1] == f"k={k}":
+            rec = {"sha": parts[2], "fetch": float(parts[3]), "write": float(parts[4])}
+    if not rec or rec["sha"] != source_digest():
+        return None
+    return rec["fetch"] + rec["write"]
+
+
+def cpu_baseline(k_sample: int, target_k: int):
+    import oracle
+    from vx_inputs import derive_key
+    log(f"cpu baseline: plain oracle, full k={k_sample} plot, 1 thread ...")
+    t0 = time.perf_counter()
+    secs, t2n = oracle.plot_timed(derive_key(0), k_sample, threads=1)
+    wall = time.perf_counter() - t0
+    scale = 2.0 ** (target_k - k_sample)
+    est = sum(secs) * scale
+    log(f"cpu baseline: stages {['%.2f' % s for s in secs]} s, |T2|={t2n}, "
+        f"scaled x{scale:.0f} -> {est:.1f} s per k={target_k} plot")
+    return {
+        "value": round(est, 2), "unit": "s", "cores": 1, "kind": "oracle",
+        "sample": (f"full k={k_sample} plot of the same seeded key on 1 host thread "
+                   f"({wall:.1f} s wall: hash {secs[0]:.2f} s, bucket+sort {secs[1]:.2f} s, "
+                   f"match+H2 {secs[2]:.2f} s); each stage scaled by 2^{target_k - k_sample} "
+                   f"to k={target_k} (linear; the in-bucket insertion sort grows faster, so "
+                   f"this favours the CPU)"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--k", type=int, default=31)
+    ap.add_argument("--cpu-sample-k", type=int, default=25)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 2 GiB device-to-device copy (known bytes) so that "
+                         "HBM byte counters can be scaled against it")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only: a plot runs on one MI355X and this build has no "
+              f"multi-GPU path (asked for --gpus {args.gpus}, WORLD_SIZE={world}).",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2606_14007_amd as vx
+    from paper_2606_14007_amd import opcount
+    from vx_inputs import derive_key
+
+    k = args.k
+    key = derive_key(0)
+    T = vx.vx_default_threshold(k)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log(f"device: {torch.cuda.get_device_name(0)}; k={k}; allocating "
+        f"{vx.footprint_bytes(k, T) / 2**30:.1f} GiB")
+    bufs = vx.alloc_plot(k, T, device=dev)
+    params = vx.make_params(key, k, T)
+    nb = bufs.native()
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+
+    if args.calibrate_copy:
+        src = torch.empty(1 << 31, dtype=torch.uint8, device=dev).fill_(7)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 2 GiB read + 2 GiB written")
+        del src, dst
+
+    for i in range(args.warmup):
+        vx.vx_plot(params, nb, None, sh)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    status = vx.device_status(bufs.workspace)
+    if status:
+        raise RuntimeError(f"device status {status:#x}")
+
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(vx.VX_PLOT_EVENTS)]
+              for _ in range(args.steps)]
+    for row in events:
+        for e in row:
+            e.record(stream)  # materialise the hipEvent_t handles
+    torch.cuda.synchronize()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for row in events:
+        vx.vx_plot_with_events(params, nb, [e.cuda_event for e in row], None, sh)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    log(f"timed {args.steps} plots in {t1 - t0:.3f} s")
+
+    t2n = vx.t2_count(bufs)
+    if t2n > bufs.t2_capacity:
+        raise RuntimeError(f"Table 2 overflow: {t2n} > {bufs.t2_capacity}")
+    n = 1 << k
+    stage_ms = {s: 0.0 for s in STAGES}
+    for row in events:
+        for i, s in enumerate(STAGES):
+            stage_ms[s] += row[i].elapsed_time(row[i + 1]) / args.steps
+    event_total = sum(stage_ms.values())
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    plot_s = ms_per_step / 1000.0
+
+    # Rooflines per stage (algorithmic work per launch / event-measured time).
+    h1_ops = opcount.valu_per_h1() * n
+    h2_ops = opcount.valu_per_h2() * t2n
+    valu_peak = opcount.MI355X_VALU_LANE_OPS_PER_S
+    hbm_peak = opcount.MI355X_HBM_BYTES_PER_S
+    algo_bytes = {
+        "partition1": n * (8 + 12) + 2 * 0,      # read key, write key+nonce
+        "partition2": n * (12 + 12),             # read and write key+nonce
+        "group_sort": n * (12 + 12) + (vx.VX_NUM_BUCKETS + 1) * 4,
+        "match_count": n * 8,                    # read keys
+    }
+    stages = {}
+    for s in STAGES:
+        sec = stage_ms[s] / 1000.0
+        ent = {"ms": round(stage_ms[s], 3), "kernel": KERNEL_OF_STAGE[s]}
+        if sec > 0:
+            if s == "hash":
+                ent.update(bound="alu", achieved=h1_ops / sec / 1e12, peak=valu_peak / 1e12,
+                           unit="T lane-ops/s")
+            elif s == "match_emit":
+                ent.update(bound="alu", achieved=h2_ops / sec / 1e12, peak=valu_peak / 1e12,
+                           unit="T lane-ops/s")
+            else:
+                ent.update(bound="hbm", achieved=algo_bytes[s] / sec / 1e9, peak=hbm_peak / 1e9,
+                           unit="GB/s")
+            ent["frac"] = round(ent["achieved"] / ent["peak"], 4)
+            ent["achieved"] = round(ent["achieved"], 2)
+        stages[s] = ent
+    dom = max(STAGES, key=lambda s: stage_ms[s])
+    d = stages[dom]
+    traffic = load_traffic(KERNEL_OF_STAGE[dom], k)
+    roofline = {"bound": d.get("bound"), "achieved": d.get("achieved"), "peak": d.get("peak"),
+                "unit": "TOP/s" if d.get("bound") == "alu" else "GB/s",
+                "frac": d.get("frac"), "traffic": traffic, "kernel": d["kernel"], "stage": dom,
+                "work_per_launch": (h1_ops if dom == "hash" else h2_ops if dom == "match_emit"
+                                    else algo_bytes.get(dom)),
+                "work_unit": ("VALU lane-instructions (%d per hash)" % opcount.valu_per_h1()
+                              if d.get("bound") == "alu" else "bytes")}
+
+    out = {
+        "metric": "K=31 plot seconds" if k == 31 else f"K={k} plot seconds",
+        "value": round(plot_s, 5),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"k={k} single plot", "k": k, "nonces": n, "key_seed": 0,
+                   "threshold": f"2^{64 - k}", "buckets": 1 << 24,
+                   "parallelism": "single GPU"},
+        "blake3_hashes_per_s": round((n + t2n) / plot_s, 1),
+        "plots_per_hour": round(3600.0 / plot_s, 1),
+        "table2_records": t2n,
+        "stage_ms": {s: stages[s]["ms"] for s in STAGES},
+        "event_total_ms": round(event_total, 3),
+        "stages": stages,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_k, k)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

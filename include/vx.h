@@ -151,6 +151,19 @@ vx_status vx_match_table2(const vx_plot_params *params, const uint64_t *d_t1_key
 vx_status vx_plot(const vx_plot_params *params, const vx_plot_buffers *buffers,
                   const vx_tuning *tuning, void *stream);
 
+/* Number of events vx_plot_with_events records. */
+#define VX_PLOT_EVENTS 7
+
+/* vx_plot that also records caller-created hipEvent_t handles on `stream`
+ * at its stage boundaries, for per-stage timing: events[0] before the hash
+ * kernel (after the small workspace-header reset); events[1] after the Table-1 hash; [2] after partition pass 1;
+ * [3] after partition pass 2 (no kernels between [2] and [3] when the plot
+ * needs one pass); [4] after the in-group sort; [5] after the match count
+ * and its scan; [6] after the match and Table-2 hash.  Outputs and errors
+ * are those of vx_plot; events must not be NULL. */
+vx_status vx_plot_with_events(const vx_plot_params *params, const vx_plot_buffers *buffers,
+                              const vx_tuning *tuning, void *const *events, void *stream);
+
 /* n independent plots (params[i], buffers[i]) enqueued on one stream; each
  * output equals vx_plot(params[i], buffers[i]).  tuning may be NULL (built-in
  * defaults per k) or an array of n entries. */

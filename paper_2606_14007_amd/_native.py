@@ -69,6 +69,8 @@ SYMBOLS = [
                                   C.POINTER(VxTuning), C.c_void_p]),
     ("vx_plot", C.c_int, [C.POINTER(VxPlotParams), C.POINTER(VxPlotBuffers), C.POINTER(VxTuning),
                           C.c_void_p]),
+    ("vx_plot_with_events", C.c_int, [C.POINTER(VxPlotParams), C.POINTER(VxPlotBuffers),
+                                      C.POINTER(VxTuning), C.POINTER(C.c_void_p), C.c_void_p]),
     ("vx_plot_batch", C.c_int, [C.POINTER(VxPlotParams), C.POINTER(VxPlotBuffers), C.c_uint32,
                                 C.POINTER(VxTuning), C.c_void_p]),
     ("vx_read_status", C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.c_void_p]),
@@ -156,6 +158,19 @@ def vx_match_table2(params, d_t1_keys, d_t1_nonces, d_offsets, d_t2, t2_capacity
 
 def vx_plot(params: VxPlotParams, buffers: VxPlotBuffers, tuning=None, stream: int = 0) -> None:
     _check(lib().vx_plot(C.byref(params), C.byref(buffers), _tref(tuning), stream), "vx_plot")
+
+
+VX_PLOT_EVENTS = 7
+
+
+def vx_plot_with_events(params: VxPlotParams, buffers: VxPlotBuffers, events, tuning=None,
+                        stream: int = 0) -> None:
+    """events: VX_PLOT_EVENTS raw hipEvent_t handles (ints)."""
+    if len(events) != VX_PLOT_EVENTS:
+        raise ValueError(f"need {VX_PLOT_EVENTS} events")
+    arr = (C.c_void_p * VX_PLOT_EVENTS)(*events)
+    _check(lib().vx_plot_with_events(C.byref(params), C.byref(buffers), _tref(tuning), arr, stream),
+           "vx_plot_with_events")
 
 
 def vx_plot_batch(params_list, buffers_list, tunings=None, stream: int = 0) -> None:

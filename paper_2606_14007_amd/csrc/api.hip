@@ -146,6 +146,11 @@ Layout layout(const Plan &P, int which) {
     return L;
 }
 
+// Records ev[i] on s when an event array is given (stage timing).
+inline hipError_t mark(hipEvent_t *ev, int i, hipStream_t s) {
+    return ev ? hipEventRecord(ev[i], s) : hipSuccess;
+}
+
 template <typename T>
 T *at(void *ws, size_t off) {
     return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
@@ -157,7 +162,7 @@ bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 // Then the partition passes and the group sort; Table 1 ends in t1_*.
 vx_status run_bucket_sort(const Plan &P, const Layout &L, void *ws, const uint64_t *keys_no,
                           bool hist_done, uint64_t *t1_keys, uint32_t *t1_nonces,
-                          uint32_t *offsets, hipStream_t s) {
+                          uint32_t *offsets, hipStream_t s, hipEvent_t *ev = nullptr) {
     uint32_t *hdr = at<uint32_t>(ws, L.header);
     uint32_t *hist1 = at<uint32_t>(ws, L.hist1), *off1 = at<uint32_t>(ws, L.off1);
     uint32_t *gstart1 = at<uint32_t>(ws, L.gstart1), *gstart = at<uint32_t>(ws, L.gstart);
@@ -176,6 +181,7 @@ vx_status run_bucket_sort(const Plan &P, const Layout &L, void *ws, const uint64
     VX_HIP(vxk::launch_scatter_chunks(keys_no, nullptr, p1k, p1n, off1, P.n, P.W, P.chunk1, 64 - P.D1,
                                       P.D1, s),
            "pass-1 scatter");
+    VX_HIP(mark(ev, 2, s), "event");
     if (P.D2) {
         uint32_t *hist2 = at<uint32_t>(ws, L.hist2), *off2 = at<uint32_t>(ws, L.off2);
         const uint32_t nd2 = 1u << P.D2;
@@ -189,25 +195,29 @@ vx_status run_bucket_sort(const Plan &P, const Layout &L, void *ws, const uint64
                                             shift2, P.D2, s),
                "pass-2 scatter");
     }
+    VX_HIP(mark(ev, 3, s), "event");
     VX_HIP(vxk::launch_groupsort(t1_keys, t1_nonces, gstart, P.G, P.cap, offsets, (uint32_t)P.n,
                                  hdr + 1, at<uint32_t>(ws, L.ovf_list), s),
            "group sort");
     VX_HIP(vxk::launch_group_fallback(t1_keys, t1_nonces, scr_k, scr_n, gstart, P.G, offsets, hdr + 1,
                                       at<uint32_t>(ws, L.ovf_list), hdr, s),
            "group sort fallback");
+    VX_HIP(mark(ev, 4, s), "event");
     return VX_OK;
 }
 
 vx_status run_match(const Plan &P, const Layout &L, void *ws, const uint64_t *t1_keys,
                     const uint32_t *t1_nonces, const uint32_t *offsets, vx_t2_record *t2,
-                    uint64_t cap, uint64_t *t2_count, hipStream_t s) {
+                    uint64_t cap, uint64_t *t2_count, hipStream_t s, hipEvent_t *ev = nullptr) {
     uint64_t *cnt = at<uint64_t>(ws, L.mcount), *base = at<uint64_t>(ws, L.mbase);
     uint64_t *part = at<uint64_t>(ws, L.mpart);
     VX_HIP(vxk::launch_match_count(t1_keys, offsets, P.Gm, P.T, (uint32_t)P.n, cnt, s), "match count");
     VX_HIP(vxk::launch_scan_u64(cnt, 1u << P.Gm, base, part, t2_count, s), "match scan");
+    VX_HIP(mark(ev, 5, s), "event");
     VX_HIP(vxk::launch_match_emit(P.key_words, t1_keys, t1_nonces, offsets, P.Gm, P.T, (uint32_t)P.n, base,
                                    t2, cap, s),
            "match emit");
+    VX_HIP(mark(ev, 6, s), "event");
     return VX_OK;
 }
 
@@ -301,8 +311,12 @@ vx_status vx_match_table2(const vx_plot_params *params, const uint64_t *d_t1_key
     return st;
 }
 
-vx_status vx_plot(const vx_plot_params *params, const vx_plot_buffers *b, const vx_tuning *tuning,
-                  void *stream) {
+}  // extern "C"
+
+namespace {
+
+vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, const vx_tuning *tuning,
+                    hipEvent_t *ev, void *stream) {
     Plan P;
     vx_status st = make_plan(params, tuning, &P);
     if (st != VX_OK) return st;
@@ -318,15 +332,37 @@ vx_status vx_plot(const vx_plot_params *params, const vx_plot_buffers *b, const 
     void *ws = b->workspace;
     uint64_t *keys_no = at<uint64_t>(ws, L.keys_no);
     VX_HIP(vxk::launch_reset(at<uint32_t>(ws, L.header), kHeaderWords, s), "reset");
+    VX_HIP(mark(ev, 0, s), "event");
     VX_HIP(vxk::launch_hash_table1(P.key_words, P.n, P.W, P.chunk1, keys_no, at<uint32_t>(ws, L.hist1),
                                    P.D1, s),
            "hash");
-    st = run_bucket_sort(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, b->bucket_offsets, s);
+    VX_HIP(mark(ev, 1, s), "event");
+    st = run_bucket_sort(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, b->bucket_offsets, s, ev);
     if (st != VX_OK) return st;
     st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, b->t2, b->t2_capacity,
-                   b->t2_count, s);
+                   b->t2_count, s, ev);
     if (st == VX_OK) g_err[0] = 0;
     return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+vx_status vx_plot(const vx_plot_params *params, const vx_plot_buffers *b, const vx_tuning *tuning,
+                  void *stream) {
+    return plot_impl(params, b, tuning, nullptr, stream);
+}
+
+vx_status vx_plot_with_events(const vx_plot_params *params, const vx_plot_buffers *b,
+                              const vx_tuning *tuning, void *const *events, void *stream) {
+    if (!events) return fail(VX_ERR_INVALID_ARG, "events is NULL");
+    hipEvent_t ev[VX_PLOT_EVENTS];
+    for (int i = 0; i < VX_PLOT_EVENTS; ++i) {
+        if (!events[i]) return fail(VX_ERR_INVALID_ARG, "NULL event");
+        ev[i] = (hipEvent_t)events[i];
+    }
+    return plot_impl(params, b, tuning, ev, stream);
 }
 
 vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buffers, uint32_t n,
