@@ -98,14 +98,16 @@ typedef struct {
 
 /* Implementation parameters.  None of them changes any output; they only
  * move work between kernels.  Zero in any field selects the built-in
- * default for the plot's k. */
+ * default for the plot's k.  The group_bits leading key bits are split over
+ * at most three partition passes of at most 11 bits each. */
 typedef struct {
     uint32_t group_bits;   /* sort groups = 2^group_bits key prefixes, 1..24 */
     uint32_t pass1_bits;   /* digit bits of the first partition pass, 1..11 */
-    uint32_t group_cap;    /* records a group may hold in LDS, 64..8192 */
+    uint32_t group_cap;    /* records a group may hold in LDS, 64..4096 */
     uint32_t h1_tiles;     /* work-groups of the hash + first partition pass */
-    uint32_t match_bits;   /* match work groups = 2^match_bits key prefixes, 0..24 */
-    uint32_t reserved[3];
+    uint32_t match_chunk_bits; /* match works on chunks of 2^bits Table-1 records, 6..11 */
+    uint32_t pass2_bits;   /* digit bits of the second pass (a third takes the rest) */
+    uint32_t reserved[2];
 } vx_tuning;
 
 enum { VX_CALL_BUCKET_SORT = 1, VX_CALL_MATCH = 2, VX_CALL_PLOT = 3 };
@@ -136,9 +138,10 @@ vx_status vx_bucket_sort(const vx_plot_params *params, const uint64_t *d_keys,
                          void *stream);
 
 /* Match and Table-2 hashing (paper sec. II-B, III-A: pairs within the
- * threshold, hashed into Table-2 records) over a sorted Table 1 with its
- * offsets.  Writes min(|T2|, t2_capacity) records in canonical order and
- * |T2| to *d_t2_count. */
+ * threshold, hashed into Table-2 records) over a sorted Table 1.  Writes
+ * min(|T2|, t2_capacity) records in canonical order and |T2| to
+ * *d_t2_count.  d_offsets must be the table's bucket offsets (it is checked
+ * for NULL; bucket boundaries are read from the keys themselves). */
 vx_status vx_match_table2(const vx_plot_params *params, const uint64_t *d_t1_keys,
                           const uint32_t *d_t1_nonces, const uint32_t *d_offsets,
                           vx_t2_record *d_t2, uint64_t t2_capacity, uint64_t *d_t2_count,

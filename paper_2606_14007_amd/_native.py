@@ -46,7 +46,8 @@ class VxPlotBuffers(C.Structure):
 
 class VxTuning(C.Structure):
     _fields_ = [("group_bits", C.c_uint32), ("pass1_bits", C.c_uint32), ("group_cap", C.c_uint32),
-                ("h1_tiles", C.c_uint32), ("match_bits", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+                ("h1_tiles", C.c_uint32), ("match_chunk_bits", C.c_uint32), ("pass2_bits", C.c_uint32),
+                ("reserved", C.c_uint32 * 2)]
 
 
 class VxError(RuntimeError):
@@ -114,10 +115,11 @@ def make_params(key: bytes, k: int, threshold: int | None = None) -> VxPlotParam
     return p
 
 
-def make_tuning(group_bits=0, pass1_bits=0, group_cap=0, h1_tiles=0, match_bits=0) -> VxTuning:
+def make_tuning(group_bits=0, pass1_bits=0, group_cap=0, h1_tiles=0, match_chunk_bits=0,
+                pass2_bits=0) -> VxTuning:
     t = VxTuning()
     t.group_bits, t.pass1_bits, t.group_cap = group_bits, pass1_bits, group_cap
-    t.h1_tiles, t.match_bits = h1_tiles, match_bits
+    t.h1_tiles, t.match_chunk_bits, t.pass2_bits = h1_tiles, match_chunk_bits, pass2_bits
     return t
 
 

@@ -33,19 +33,22 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // How one plot is cut into kernels.  Every field only moves work around;
 // outputs never depend on it.
+constexpr int kMaxPasses = 3;
+
 struct Plan {
     uint32_t k = 0;
     uint64_t n = 0;          // 2^k records
     uint32_t key_words[8] = {};
     uint64_t T = 0;
     uint32_t G = 0;          // sort groups = 2^G leading-bit prefixes
-    uint32_t D1 = 0;         // digit bits of partition pass 1
-    uint32_t D2 = 0;         // digit bits of partition pass 2 (0 = one pass)
-    uint32_t W = 0;          // tiles of hash + pass 1
-    uint64_t chunk1 = 0;     // records per pass-1 tile
-    uint32_t Q = 0;          // pass-2 tiles per pass-1 segment
+    uint32_t npass = 0;      // MSD partition passes over those G bits
+    uint32_t D[kMaxPasses] = {};   // digit bits per pass
+    uint32_t pre[kMaxPasses] = {}; // bits consumed before each pass
+    uint32_t Q[kMaxPasses] = {};   // tiles per input segment (passes >= 1)
+    uint32_t W = 0;          // tiles of hash + pass 0
+    uint64_t chunk1 = 0;     // records per pass-0 tile
     uint32_t cap = 0;        // LDS capacity of a sort group
-    uint32_t Gm = 0;         // match groups = 2^Gm prefixes
+    uint32_t cb = 0;         // match chunk = 2^cb consecutive Table-1 records
 };
 
 uint32_t clampu(int64_t v, int64_t lo, int64_t hi) {
@@ -72,24 +75,53 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl) {
     vx_tuning z;
     memset(&z, 0, sizeof(z));
     if (!t) t = &z;
-    // Sort groups of about 4096 records.
-    P.G = t->group_bits ? t->group_bits : clampu((int64_t)p->k - 12, 1, 19);
+    // Sort groups of about 2048 records (half the LDS capacity).
+    P.G = t->group_bits ? t->group_bits : clampu((int64_t)p->k - 11, 1, 20);
     if (P.G < 1 || P.G > 24) return fail(VX_ERR_UNSUPPORTED, "group_bits must be in [1, 24]");
-    P.D1 = t->pass1_bits ? t->pass1_bits : (P.G < 8 ? P.G : 8);
-    if (P.D1 < 1 || P.D1 > (uint32_t)vxk::kMaxDigitBits || P.D1 > P.G)
-        return fail(VX_ERR_UNSUPPORTED, "pass1_bits must be in [1, min(11, group_bits)]");
-    P.D2 = P.G - P.D1;
-    if (P.D2 > (uint32_t)vxk::kMaxDigitBits)
-        return fail(VX_ERR_UNSUPPORTED, "group_bits - pass1_bits must be at most 11");
+    // Split G into passes of at most 9 bits so every digit's run per sub-tile
+    // spans whole cache lines.
+    uint32_t d0, d1, d2;
+    if (P.G <= 9) {
+        d0 = P.G; d1 = 0; d2 = 0;
+    } else if (P.G <= 17) {
+        d0 = (P.G + 1) / 2; d1 = P.G - d0; d2 = 0;
+    } else {
+        d0 = 8; d1 = (P.G - 8 + 1) / 2; d2 = P.G - 8 - d1;
+    }
+    if (t->pass1_bits || t->pass2_bits) {
+        d0 = t->pass1_bits ? t->pass1_bits : d0;
+        if (d0 > P.G) return fail(VX_ERR_UNSUPPORTED, "pass1_bits must be at most group_bits");
+        const uint32_t rest = P.G - d0;
+        d1 = t->pass2_bits ? t->pass2_bits : (rest <= (uint32_t)vxk::kMaxDigitBits ? rest : (rest + 1) / 2);
+        if (d1 > rest) return fail(VX_ERR_UNSUPPORTED, "pass1_bits + pass2_bits must be at most group_bits");
+        d2 = rest - d1;
+    }
+    const uint32_t ds[kMaxPasses] = {d0, d1, d2};
+    P.npass = 0;
+    uint32_t used = 0;
+    for (int i = 0; i < kMaxPasses; ++i) {
+        if (ds[i] == 0) {
+            if (i == 0) return fail(VX_ERR_UNSUPPORTED, "pass1_bits must be at least 1");
+            continue;
+        }
+        if (ds[i] > (uint32_t)vxk::kMaxDigitBits)
+            return fail(VX_ERR_UNSUPPORTED, "a partition pass may take at most 11 bits");
+        P.D[P.npass] = ds[i];
+        P.pre[P.npass] = used;
+        used += ds[i];
+        P.npass++;
+    }
     P.W = t->h1_tiles ? t->h1_tiles : clampu((int64_t)(P.n >> 14), 1, 2048);
     if (P.W < 1 || P.W > 65536) return fail(VX_ERR_UNSUPPORTED, "h1_tiles must be in [1, 65536]");
     P.chunk1 = (P.n + P.W - 1) / P.W;
-    P.Q = clampu((int64_t)((P.n >> P.D1) >> 19), 1, 16);
+    for (uint32_t i = 1; i < P.npass; ++i)  // about 2^17 records per tile
+        P.Q[i] = clampu((int64_t)((P.n >> P.pre[i]) >> 17), 1, 64);
     P.cap = t->group_cap ? t->group_cap : (uint32_t)vxk::kGroupCapMax;
     if (P.cap < 64 || P.cap > (uint32_t)vxk::kGroupCapMax)
-        return fail(VX_ERR_UNSUPPORTED, "group_cap must be in [64, 8192]");
-    P.Gm = t->match_bits ? t->match_bits : clampu((int64_t)p->k - 11, 0, 20);
-    if (P.Gm > (uint32_t)vxk::kMatchBitsMax) return fail(VX_ERR_UNSUPPORTED, "match_bits must be at most 24");
+        return fail(VX_ERR_UNSUPPORTED, "group_cap must be in [64, 4096]");
+    P.cb = t->match_chunk_bits ? t->match_chunk_bits : (uint32_t)vxk::kMatchChunkBitsMax;
+    if (P.cb < 6 || P.cb > (uint32_t)vxk::kMatchChunkBitsMax)
+        return fail(VX_ERR_UNSUPPORTED, "match_chunk_bits must be in [6, 11]");
     *pl = P;
     return VX_OK;
 }
@@ -100,17 +132,21 @@ struct Layout {
     size_t keys_no = 0;       // u64[n] nonce-order hashes (plot only)
     size_t scr_keys = 0;      // u64[n] partition scratch
     size_t scr_nonces = 0;    // u32[n]
-    size_t hist1 = 0, off1 = 0;   // u32[W][2^D1]
-    size_t gstart1 = 0;           // u32[2^D1 + 1]
-    size_t hist2 = 0, off2 = 0;   // u32[2^D1 * Q][2^D2]
-    size_t gstart = 0;            // u32[2^G + 1]
+    size_t hist[kMaxPasses] = {}, off[kMaxPasses] = {};  // u32[tiles][2^D]
+    size_t gstart[kMaxPasses] = {};  // u32[2^(pre + D) + 1] group starts after each pass
     size_t ovf_list = 0;          // u32[2^G]
-    size_t mcount = 0, mbase = 0; // u64[2^Gm]
+    size_t mcount = 0, mbase = 0; // u64[match chunks]: pair counts, Table-2 bases
     size_t mpart = 0;             // u64[scan parts]
     size_t total = 0;
 };
 
 constexpr uint32_t kHeaderWords = 64;
+
+uint32_t match_chunks(const Plan &P) { return (uint32_t)((P.n + (1ull << P.cb) - 1) >> P.cb); }
+
+uint32_t pass_tiles(const Plan &P, uint32_t i) {
+    return i == 0 ? P.W : (1u << P.pre[i]) * P.Q[i];
+}
 
 Layout layout(const Plan &P, int which) {
     Layout L;
@@ -127,20 +163,19 @@ Layout layout(const Plan &P, int which) {
     if (sort) {
         L.scr_keys = take(P.n * 8);
         L.scr_nonces = take(P.n * 4);
-        L.hist1 = take((size_t)P.W * (1u << P.D1) * 4);
-        L.off1 = take((size_t)P.W * (1u << P.D1) * 4);
-        L.gstart1 = take(((size_t)(1u << P.D1) + 1) * 4);
-        if (P.D2) {
-            L.hist2 = take((size_t)(1u << P.D1) * P.Q * (1u << P.D2) * 4);
-            L.off2 = take((size_t)(1u << P.D1) * P.Q * (1u << P.D2) * 4);
+        for (uint32_t i = 0; i < P.npass; ++i) {
+            const size_t cells = (size_t)pass_tiles(P, i) << P.D[i];
+            L.hist[i] = take(cells * 4);
+            L.off[i] = take(cells * 4);
+            L.gstart[i] = take((((size_t)1 << (P.pre[i] + P.D[i])) + 1) * 4);
         }
-        L.gstart = take(((size_t)(1u << P.G) + 1) * 4);
         L.ovf_list = take((size_t)(1u << P.G) * 4);
     }
     if (match) {
-        L.mcount = take((size_t)(1u << P.Gm) * 8);
-        L.mbase = take((size_t)(1u << P.Gm) * 8);
-        L.mpart = take((size_t)vxk::scan_parts(1u << P.Gm) * 8);
+        const uint32_t nch = match_chunks(P);
+        L.mcount = take((size_t)nch * 8);
+        L.mbase = take((size_t)nch * 8);
+        L.mpart = take((size_t)vxk::scan_parts(nch) * 8);
     }
     L.total = at;
     return L;
@@ -158,64 +193,80 @@ T *at(void *ws, size_t off) {
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-// Hash + the pass-1 histogram (plot) or the pass-1 histogram of caller keys.
-// Then the partition passes and the group sort; Table 1 ends in t1_*.
+// Partition passes and the group sort.  Pass 0 reads the nonce-order keys
+// (its histogram comes from the hash kernel in a plot, or from a histogram
+// pass over caller keys); passes alternate between Table 1 and the scratch
+// arrays so that the last one lands in Table 1, where groups are sorted in
+// place.  chunk_count (may be NULL) receives the Table-2 pair count of each
+// match chunk of the sorted table.
 vx_status run_bucket_sort(const Plan &P, const Layout &L, void *ws, const uint64_t *keys_no,
                           bool hist_done, uint64_t *t1_keys, uint32_t *t1_nonces,
-                          uint32_t *offsets, hipStream_t s, hipEvent_t *ev = nullptr) {
+                          uint32_t *offsets, uint64_t *chunk_count, hipStream_t s,
+                          hipEvent_t *ev = nullptr) {
     uint32_t *hdr = at<uint32_t>(ws, L.header);
-    uint32_t *hist1 = at<uint32_t>(ws, L.hist1), *off1 = at<uint32_t>(ws, L.off1);
-    uint32_t *gstart1 = at<uint32_t>(ws, L.gstart1), *gstart = at<uint32_t>(ws, L.gstart);
     uint64_t *scr_k = at<uint64_t>(ws, L.scr_keys);
     uint32_t *scr_n = at<uint32_t>(ws, L.scr_nonces);
-    const uint32_t nd1 = 1u << P.D1;
-    if (!hist_done)
-        VX_HIP(vxk::launch_hist_chunks(keys_no, P.n, P.W, P.chunk1, 64 - P.D1, P.D1, hist1, s),
-               "pass-1 histogram");
-    // Pass 1 writes into Table 1 directly when it is the only pass.
-    uint64_t *p1k = P.D2 ? scr_k : t1_keys;
-    uint32_t *p1n = P.D2 ? scr_n : t1_nonces;
-    uint32_t *g1 = P.D2 ? gstart1 : gstart;
-    VX_HIP(vxk::launch_colscan(hist1, off1, 1, P.W, nd1, nullptr, g1, nd1, (uint32_t)P.n, s),
-           "pass-1 scan");
-    VX_HIP(vxk::launch_scatter_chunks(keys_no, nullptr, p1k, p1n, off1, P.n, P.W, P.chunk1, 64 - P.D1,
-                                      P.D1, s),
-           "pass-1 scatter");
-    VX_HIP(mark(ev, 2, s), "event");
-    if (P.D2) {
-        uint32_t *hist2 = at<uint32_t>(ws, L.hist2), *off2 = at<uint32_t>(ws, L.off2);
-        const uint32_t nd2 = 1u << P.D2;
-        const uint32_t shift2 = 64 - P.D1 - P.D2;
-        VX_HIP(vxk::launch_hist_segments(p1k, gstart1, nd1, P.Q, shift2, P.D2, hist2, s),
-               "pass-2 histogram");
-        VX_HIP(vxk::launch_colscan(hist2, off2, nd1, P.Q, nd2, gstart1, gstart, 1u << P.G,
-                                   (uint32_t)P.n, s),
-               "pass-2 scan");
-        VX_HIP(vxk::launch_scatter_segments(p1k, p1n, t1_keys, t1_nonces, off2, gstart1, nd1, P.Q,
-                                            shift2, P.D2, s),
-               "pass-2 scatter");
+    const uint64_t *in_k = keys_no;
+    const uint32_t *in_n = nullptr;
+    for (uint32_t i = 0; i < P.npass; ++i) {
+        const bool to_t1 = ((P.npass - 1 - i) % 2) == 0;
+        uint64_t *out_k = to_t1 ? t1_keys : scr_k;
+        uint32_t *out_n = to_t1 ? t1_nonces : scr_n;
+        uint32_t *hist = at<uint32_t>(ws, L.hist[i]), *off = at<uint32_t>(ws, L.off[i]);
+        uint32_t *gst = at<uint32_t>(ws, L.gstart[i]);
+        const uint32_t nd = 1u << P.D[i];
+        const uint32_t shift = 64 - P.pre[i] - P.D[i];
+        const uint32_t ngroups = 1u << (P.pre[i] + P.D[i]);
+        if (i == 0) {
+            if (!hist_done)
+                VX_HIP(vxk::launch_hist_chunks(in_k, P.n, P.W, P.chunk1, shift, P.D[0], hist, s),
+                       "pass-0 histogram");
+            VX_HIP(vxk::launch_colscan(hist, off, 1, P.W, nd, nullptr, gst, ngroups, (uint32_t)P.n, s),
+                   "pass-0 scan");
+            VX_HIP(vxk::launch_scatter_chunks(in_k, nullptr, out_k, out_n, off, P.n, P.W, P.chunk1,
+                                              shift, P.D[0], s),
+                   "pass-0 scatter");
+        } else {
+            const uint32_t nseg = 1u << P.pre[i];
+            const uint32_t *seg = at<uint32_t>(ws, L.gstart[i - 1]);
+            VX_HIP(vxk::launch_hist_segments(in_k, seg, nseg, P.Q[i], shift, P.D[i], hist, s),
+                   "pass histogram");
+            VX_HIP(vxk::launch_colscan(hist, off, nseg, P.Q[i], nd, seg, gst, ngroups, (uint32_t)P.n, s),
+                   "pass scan");
+            VX_HIP(vxk::launch_scatter_segments(in_k, in_n, out_k, out_n, off, seg, nseg, P.Q[i], shift,
+                                                P.D[i], s),
+                   "pass scatter");
+        }
+        VX_HIP(mark(ev, i == 0 ? 2 : 3, s), "event");
+        in_k = out_k;
+        in_n = out_n;
     }
-    VX_HIP(mark(ev, 3, s), "event");
+    if (P.npass == 1) VX_HIP(mark(ev, 3, s), "event");
+    const uint32_t *gstart = at<uint32_t>(ws, L.gstart[P.npass - 1]);
+    if (chunk_count) VX_HIP(vxk::launch_zero_u64(chunk_count, match_chunks(P), s), "zero counts");
     VX_HIP(vxk::launch_groupsort(t1_keys, t1_nonces, gstart, P.G, P.cap, offsets, (uint32_t)P.n,
-                                 hdr + 1, at<uint32_t>(ws, L.ovf_list), s),
+                                 hdr + 1, at<uint32_t>(ws, L.ovf_list), P.T, chunk_count, P.cb, s),
            "group sort");
     VX_HIP(vxk::launch_group_fallback(t1_keys, t1_nonces, scr_k, scr_n, gstart, P.G, offsets, hdr + 1,
-                                      at<uint32_t>(ws, L.ovf_list), hdr, s),
+                                      at<uint32_t>(ws, L.ovf_list), hdr, P.T, chunk_count, P.cb, s),
            "group sort fallback");
     VX_HIP(mark(ev, 4, s), "event");
     return VX_OK;
 }
 
+// Match and Table-2 hashing over fixed chunks of Table 1.  counted: the
+// per-chunk pair counts are already in the workspace (the sort produced
+// them); otherwise they are counted here.
 vx_status run_match(const Plan &P, const Layout &L, void *ws, const uint64_t *t1_keys,
-                    const uint32_t *t1_nonces, const uint32_t *offsets, vx_t2_record *t2,
-                    uint64_t cap, uint64_t *t2_count, hipStream_t s, hipEvent_t *ev = nullptr) {
+                    const uint32_t *t1_nonces, vx_t2_record *t2, uint64_t cap, uint64_t *t2_count,
+                    bool counted, hipStream_t s, hipEvent_t *ev = nullptr) {
     uint64_t *cnt = at<uint64_t>(ws, L.mcount), *base = at<uint64_t>(ws, L.mbase);
     uint64_t *part = at<uint64_t>(ws, L.mpart);
-    VX_HIP(vxk::launch_match_count(t1_keys, offsets, P.Gm, P.T, (uint32_t)P.n, cnt, s), "match count");
-    VX_HIP(vxk::launch_scan_u64(cnt, 1u << P.Gm, base, part, t2_count, s), "match scan");
+    if (!counted)
+        VX_HIP(vxk::launch_match_count(t1_keys, (uint32_t)P.n, P.cb, P.T, cnt, s), "match count");
+    VX_HIP(vxk::launch_scan_u64(cnt, match_chunks(P), base, part, t2_count, s), "match scan");
     VX_HIP(mark(ev, 5, s), "event");
-    VX_HIP(vxk::launch_match_emit(P.key_words, t1_keys, t1_nonces, offsets, P.Gm, P.T, (uint32_t)P.n, base,
-                                   t2, cap, s),
+    VX_HIP(vxk::launch_match_emit(P.key_words, t1_keys, t1_nonces, (uint32_t)P.n, P.cb, P.T, base, t2, cap, s),
            "match emit");
     VX_HIP(mark(ev, 6, s), "event");
     return VX_OK;
@@ -287,7 +338,7 @@ vx_status vx_bucket_sort(const vx_plot_params *params, const uint64_t *d_keys, u
     if ((st = check_ws(L, d_workspace, workspace_bytes)) != VX_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     VX_HIP(vxk::launch_reset(at<uint32_t>(d_workspace, L.header), kHeaderWords, s), "reset");
-    st = run_bucket_sort(P, L, d_workspace, d_keys, false, d_t1_keys, d_t1_nonces, d_offsets, s);
+    st = run_bucket_sort(P, L, d_workspace, d_keys, false, d_t1_keys, d_t1_nonces, d_offsets, nullptr, s);
     if (st == VX_OK) g_err[0] = 0;
     return st;
 }
@@ -306,7 +357,8 @@ vx_status vx_match_table2(const vx_plot_params *params, const uint64_t *d_t1_key
     Layout L = layout(P, VX_CALL_MATCH);
     if ((st = check_ws(L, d_workspace, workspace_bytes)) != VX_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    st = run_match(P, L, d_workspace, d_t1_keys, d_t1_nonces, d_offsets, d_t2, t2_capacity, d_t2_count, s);
+    (void)d_offsets;  // validated above; the match walks Table 1 itself
+    st = run_match(P, L, d_workspace, d_t1_keys, d_t1_nonces, d_t2, t2_capacity, d_t2_count, false, s);
     if (st == VX_OK) g_err[0] = 0;
     return st;
 }
@@ -333,14 +385,15 @@ vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, cons
     uint64_t *keys_no = at<uint64_t>(ws, L.keys_no);
     VX_HIP(vxk::launch_reset(at<uint32_t>(ws, L.header), kHeaderWords, s), "reset");
     VX_HIP(mark(ev, 0, s), "event");
-    VX_HIP(vxk::launch_hash_table1(P.key_words, P.n, P.W, P.chunk1, keys_no, at<uint32_t>(ws, L.hist1),
-                                   P.D1, s),
+    VX_HIP(vxk::launch_hash_table1(P.key_words, P.n, P.W, P.chunk1, keys_no, at<uint32_t>(ws, L.hist[0]),
+                                   P.D[0], s),
            "hash");
     VX_HIP(mark(ev, 1, s), "event");
-    st = run_bucket_sort(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, b->bucket_offsets, s, ev);
+    // The sort counts each match chunk's pairs while the groups are in LDS.
+    st = run_bucket_sort(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, b->bucket_offsets,
+                         at<uint64_t>(ws, L.mcount), s, ev);
     if (st != VX_OK) return st;
-    st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, b->t2, b->t2_capacity,
-                   b->t2_count, s, ev);
+    st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, true, s, ev);
     if (st == VX_OK) g_err[0] = 0;
     return st;
 }

@@ -12,9 +12,9 @@
 namespace vxk {
 
 constexpr int kMaxDigitBits = 11;     // widest partition digit (LDS histograms)
-constexpr int kGroupCapMax = 8192;    // records a sort group may hold in LDS
+constexpr int kGroupCapMax = 4096;    // records a sort group may hold in LDS
 constexpr uint32_t kFallbackMax = 1u << 20;  // largest group the fallback sorts
-constexpr int kMatchBitsMax = 24;
+constexpr int kMatchChunkBitsMax = 11;  // match chunk = 2^bits records (LDS capacity 2048)
 
 hipError_t launch_reset(uint32_t *words, uint32_t n, hipStream_t s);
 hipError_t launch_hash_table1(const uint32_t key_words[8], uint64_t n, uint32_t tiles, uint64_t chunk,
@@ -36,18 +36,21 @@ hipError_t launch_scatter_segments(const uint64_t *in_keys, const uint32_t *in_n
                                    uint32_t bits, hipStream_t s);
 hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint32_t *gstart, uint32_t G,
                             uint32_t cap, uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count,
-                            uint32_t *ovf_list, hipStream_t s);
+                            uint32_t *ovf_list, uint64_t T, uint64_t *chunk_count, uint32_t chunk_bits,
+                            hipStream_t s);
 hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, uint64_t *scr_keys,
                                  uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G,
                                  uint32_t *offsets, const uint32_t *ovf_count, const uint32_t *ovf_list,
-                                 uint32_t *status, hipStream_t s);
-hipError_t launch_match_count(const uint64_t *keys, const uint32_t *offsets, uint32_t Gm, uint64_t T,
-                              uint32_t n_total, uint64_t *counts, hipStream_t s);
+                                 uint32_t *status, uint64_t T, uint64_t *chunk_count,
+                                 uint32_t chunk_bits, hipStream_t s);
+hipError_t launch_match_count(const uint64_t *keys, uint32_t n_total, uint32_t chunk_bits, uint64_t T,
+                              uint64_t *counts, hipStream_t s);
+hipError_t launch_zero_u64(uint64_t *p, uint32_t n, hipStream_t s);
 hipError_t launch_scan_u64(const uint64_t *in, uint32_t n, uint64_t *out, uint64_t *part,
                            uint64_t *total, hipStream_t s);
 uint32_t scan_parts(uint32_t n);
 hipError_t launch_match_emit(const uint32_t key_words[8], const uint64_t *keys, const uint32_t *nonces,
-                             const uint32_t *offsets, uint32_t Gm, uint64_t T, uint32_t n_total,
-                             const uint64_t *group_base, void *t2, uint64_t cap, hipStream_t s);
+                             uint32_t n_total, uint32_t chunk_bits, uint64_t T, const uint64_t *chunk_base,
+                             void *t2, uint64_t cap, hipStream_t s);
 
 }  // namespace vxk

@@ -196,9 +196,11 @@ __global__ __launch_bounds__(BLOCK) void k_colscan(const uint32_t *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Partition scatter: each tile streams its records in sub-tiles, ranks them
-// by digit in LDS and writes every digit's run contiguously at the tile's
-// running cursor for that digit.
+// Partition scatter: each tile streams its records in sub-tiles of
+// BLOCK * ITEMS, ranks them by digit in LDS and writes every digit's run
+// contiguously at the tile's running cursor for that digit.  The next
+// sub-tile's loads are issued before the current one's LDS work and stores,
+// so a lone work-group per CU still keeps HBM reads in flight.
 // ---------------------------------------------------------------------------
 
 template <int BLOCK, int ITEMS>
@@ -219,18 +221,39 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ 
     for (uint32_t d = tid; d < nd; d += BLOCK) s_cursor[d] = off[(uint64_t)blockIdx.x * nd + d];
     uint64_t lo, hi;
     tile_range(geom, blockIdx.x, lo, hi);
+    uint64_t nk[ITEMS];
+    uint32_t nn[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint64_t idx = lo + (uint64_t)j * BLOCK + tid;
+        if (idx < hi) {
+            nk[j] = in_keys[idx];
+            nn[j] = in_nonces ? in_nonces[idx] : (uint32_t)idx;
+        }
+    }
     for (uint64_t base = lo; base < hi; base += SUB) {
+        uint64_t k[ITEMS];
+        uint32_t n[ITEMS], slot[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            k[j] = nk[j];
+            n[j] = nn[j];
+        }
         for (uint32_t d = tid; d < nd; d += BLOCK) s_start[d] = 0;
         __syncthreads();
-        uint64_t k[ITEMS];
-        uint32_t nn[ITEMS], slot[ITEMS];
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const uint64_t idx = base + (uint64_t)j * BLOCK + tid;
+            if (idx < hi) slot[j] = atomicAdd(&s_start[(uint32_t)(k[j] >> shift) & mask], 1u);
+        }
+        // Prefetch the next sub-tile.
+        const uint64_t nbase = base + SUB;
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint64_t idx = nbase + (uint64_t)j * BLOCK + tid;
             if (idx < hi) {
-                k[j] = in_keys[idx];
+                nk[j] = in_keys[idx];
                 nn[j] = in_nonces ? in_nonces[idx] : (uint32_t)idx;
-                slot[j] = atomicAdd(&s_start[(uint32_t)(k[j] >> shift) & mask], 1u);
             }
         }
         __syncthreads();
@@ -243,7 +266,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ 
             if (idx < hi) {
                 const uint32_t p = s_start[(uint32_t)(k[j] >> shift) & mask] + slot[j];
                 s_keys[p] = k[j];
-                s_nonces[p] = nn[j];
+                s_nonces[p] = n[j];
             }
         }
         __syncthreads();
@@ -261,11 +284,47 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Group sort in LDS (in place on Table 1) + bucket offsets of the group.
+// Group sort in LDS (in place on Table 1), bucket offsets of the group, and
+// (optionally) the group's Table-2 pair count.
 // ---------------------------------------------------------------------------
 
 constexpr int kSubBinBits = 12;
 constexpr int kSubBins = 1 << kSubBinBits;
+
+// Pairs owned by record e of a sorted run keys[0..n): later records of the
+// same bucket whose key is less than T above keys[e].  The run must end at a
+// bucket boundary (a group always does).
+__device__ __forceinline__ uint32_t pairs_after(const uint64_t *keys, uint32_t e, uint32_t n,
+                                                uint64_t T) {
+    const uint64_t ki = keys[e];
+    const uint32_t bi = (uint32_t)(ki >> 40);
+    uint32_t c = 0;
+    for (uint32_t j = e + 1; j < n; ++j) {
+        const uint64_t kj = keys[j];
+        if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
+        ++c;
+    }
+    return c;
+}
+
+// Adds the Table-2 pairs owned by the sorted run keys[0..n) (global records
+// [lo, lo + n)) to the counters of the fixed match chunks those records fall
+// in (chunk = record index >> chunk_bits).  Integer sums, so the order of the
+// atomic adds does not matter.
+template <int BLOCK>
+__device__ __forceinline__ void add_chunk_pairs(const uint64_t *keys, uint32_t lo, uint32_t n,
+                                                uint64_t T, uint64_t *chunk_count,
+                                                uint32_t chunk_bits, uint64_t *s_wave) {
+    const uint32_t c0 = lo >> chunk_bits, c1 = (lo + n - 1) >> chunk_bits;
+    for (uint32_t c = c0; c <= c1; ++c) {
+        const uint32_t a = max(c << chunk_bits, lo) - lo;
+        const uint32_t b = min((c + 1) << chunk_bits, lo + n) - lo;
+        uint64_t mine = 0;
+        for (uint32_t e = a + threadIdx.x; e < b; e += BLOCK) mine += pairs_after(keys, e, n, T);
+        mine = vxd::block_sum<BLOCK>(mine, s_wave);
+        if (threadIdx.x == 0 && mine) atomicAdd((unsigned long long *)&chunk_count[c], (unsigned long long)mine);
+    }
+}
 
 template <int BLOCK, int CAPMAX>
 __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys,
@@ -275,12 +334,15 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys
                                                      uint32_t *__restrict__ offsets,
                                                      uint32_t n_total,
                                                      uint32_t *__restrict__ ovf_count,
-                                                     uint32_t *__restrict__ ovf_list) {
+                                                     uint32_t *__restrict__ ovf_list, uint64_t T,
+                                                     uint64_t *__restrict__ chunk_count,
+                                                     uint32_t chunk_bits) {
     constexpr int ITEMS = CAPMAX / BLOCK;
     __shared__ uint64_t s_keys[CAPMAX];
     __shared__ uint32_t s_nonces[CAPMAX];
     __shared__ uint32_t s_start[kSubBins + 1];
-    __shared__ uint32_t s_wave[BLOCK / 64 + 1];
+    __shared__ uint64_t s_wave[BLOCK / 64 + 1];
+    uint32_t *s_wave32 = reinterpret_cast<uint32_t *>(s_wave);
     const uint32_t g = blockIdx.x, tid = threadIdx.x;
     const uint32_t lo = gstart[g], hi = gstart[g + 1], n = hi - lo;
     if (g == gridDim.x - 1 && tid == 0) offsets[VXK_NUM_BUCKETS] = n_total;
@@ -306,7 +368,7 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys
         }
     }
     __syncthreads();
-    vxd::lds_exclusive_scan<BLOCK>(s_start, kSubBins, s_wave);
+    vxd::lds_exclusive_scan<BLOCK>(s_start, kSubBins, s_wave32);
     if (tid == 0) s_start[kSubBins] = n;
     __syncthreads();
 #pragma unroll
@@ -357,19 +419,23 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys
         }
         offsets[b] = lo + a;
     }
+    if (chunk_count && n) add_chunk_pairs<BLOCK>(s_keys, lo, n, T, chunk_count, chunk_bits, s_wave);
 }
 
 // Groups larger than the LDS capacity: rank sort against LDS-staged tiles of
 // the group (copied to scratch first), then bucket offsets by binary search
-// in global memory.  Groups above fb_max set a status bit and stay unsorted.
+// and the pair count in global memory.  Groups above fb_max set a status bit
+// and stay unsorted.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_group_fallback(
     uint64_t *__restrict__ keys, uint32_t *__restrict__ nonces, uint64_t *__restrict__ scr_keys,
     uint32_t *__restrict__ scr_nonces, const uint32_t *__restrict__ gstart, uint32_t G,
     uint32_t *__restrict__ offsets, const uint32_t *__restrict__ ovf_count,
-    const uint32_t *__restrict__ ovf_list, uint32_t fb_max, uint32_t *__restrict__ status) {
+    const uint32_t *__restrict__ ovf_list, uint32_t fb_max, uint32_t *__restrict__ status,
+    uint64_t T, uint64_t *__restrict__ chunk_count, uint32_t chunk_bits) {
     __shared__ uint64_t s_k[BLOCK];
     __shared__ uint32_t s_n[BLOCK];
+    __shared__ uint64_t s_wave[BLOCK / 64 + 1];
     const uint32_t tid = threadIdx.x;
     const uint32_t cnt = *ovf_count;
     for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
@@ -421,126 +487,162 @@ __global__ __launch_bounds__(BLOCK) void k_group_fallback(
             }
             offsets[b] = lo + a;
         }
+        if (chunk_count && n) add_chunk_pairs<BLOCK>(keys + lo, lo, n, T, chunk_count, chunk_bits, s_wave);
         __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// Match: pair count per match group (buckets [g << (24-Gm), (g+1) << (24-Gm))).
+// Match over fixed chunks of Table 1 (chunk c = records [c << cb, (c+1) << cb)).
+// A record's pairs are owned by its chunk even when the partner lies in the
+// next chunk; pairs never cross a bucket, so the forward scan stops at the
+// bucket's end.
 // ---------------------------------------------------------------------------
 
+// Pair count per chunk (used when the sort did not provide it).
 template <int BLOCK, int MCAP>
 __global__ __launch_bounds__(BLOCK) void k_match_count(const uint64_t *__restrict__ keys,
-                                                       const uint32_t *__restrict__ offsets,
-                                                       uint32_t Gm, uint64_t T, uint32_t n_total,
+                                                       uint32_t n_total, uint32_t cb, uint64_t T,
                                                        uint64_t *__restrict__ counts) {
     __shared__ uint64_t s_keys[MCAP];
     __shared__ uint64_t s_wave[BLOCK / 64 + 1];
-    const uint32_t g = blockIdx.x, tid = threadIdx.x;
-    const uint32_t sh = VXK_BUCKET_BITS - Gm;
-    // Offsets come from the caller: clamp so that a malformed table cannot
-    // send reads outside [0, n_total).
-    const uint32_t hi = min(offsets[(g + 1) << sh], n_total);
-    const uint32_t lo = min(offsets[g << sh], hi);
-    uint64_t total = 0;
-    for (uint32_t c = lo; c < hi; c += MCAP) {
-        const uint32_t m = min((uint32_t)MCAP, hi - c);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nchunks = (n_total + (1u << cb) - 1) >> cb;
+    for (uint32_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {
+        const uint32_t c = ci << cb;
+        const uint32_t m = min(1u << cb, n_total - c);
         for (uint32_t e = tid; e < m; e += BLOCK) s_keys[e] = keys[c + e];
         __syncthreads();
+        uint64_t total = 0;
         for (uint32_t e = tid; e < m; e += BLOCK) {
             const uint64_t ki = s_keys[e];
             const uint32_t bi = (uint32_t)(ki >> 40);
-            for (uint32_t j = c + e + 1; j < hi; ++j) {
+            for (uint32_t j = c + e + 1; j < n_total; ++j) {
                 const uint64_t kj = (j - c < m) ? s_keys[j - c] : keys[j];
                 if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
                 ++total;
             }
         }
-        __syncthreads();
+        total = vxd::block_sum<BLOCK>(total, s_wave);
+        if (tid == 0) counts[ci] = total;
     }
-    total = vxd::block_sum<BLOCK>(total, s_wave);
-    if (tid == 0) counts[g] = total;
 }
 
-// Match + Table-2 hash.  Per chunk of the match group: each record's pair
-// count goes through a work-group scan into LDS offsets (u64, so degenerate
-// inputs cannot overflow); then every lane takes pair slots p = tid, tid +
-// BLOCK, ..., finds the record owning slot p by binary search of the
-// offsets, and hashes that pair.  Slots are in canonical order, so the
-// Table-2 index is group base + chunk base + p.
-template <int BLOCK, int MCAP>
+// Match + Table-2 hash.  A persistent work-group walks chunks ci =
+// blockIdx.x, blockIdx.x + gridDim.x, ...  Per chunk: each thread counts the
+// pairs of its ITEMS consecutive records, a work-group scan turns the counts
+// into canonical slots, and the pairs are expanded into an LDS list of
+// (nonce_a, nonce_b) in slot order, PW slots at a time, which is hashed one
+// pair per lane -- every lane does the same BLAKE3 work whatever the pair
+// distribution.  Table-2 index = chunk base + slot.  The next chunk's
+// records are loaded into registers while the current one is worked on.
+template <int BLOCK, int MCAP, int PW>
 __global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *__restrict__ keys,
                                                       const uint32_t *__restrict__ nonces,
-                                                      const uint32_t *__restrict__ offsets,
-                                                      uint32_t Gm, uint64_t T, uint32_t n_total,
-                                                      const uint64_t *__restrict__ group_base,
+                                                      uint32_t n_total, uint32_t cb, uint64_t T,
+                                                      const uint64_t *__restrict__ chunk_base,
                                                       uint4 *__restrict__ t2, uint64_t cap) {
     constexpr int ITEMS = MCAP / BLOCK;
     __shared__ uint64_t s_keys[MCAP];
     __shared__ uint32_t s_nonces[MCAP];
-    __shared__ uint64_t s_off[MCAP + 1];
+    __shared__ uint32_t s_pa[PW];
+    __shared__ uint32_t s_pb[PW];
     __shared__ uint64_t s_wave[BLOCK / 64 + 1];
-    const uint32_t g = blockIdx.x, tid = threadIdx.x;
-    const uint32_t sh = VXK_BUCKET_BITS - Gm;
-    const uint32_t hi = min(offsets[(g + 1) << sh], n_total);
-    const uint32_t lo = min(offsets[g << sh], hi);
-    uint64_t base = group_base[g];
-    for (uint32_t c = lo; c < hi; c += MCAP) {
-        const uint32_t m = min((uint32_t)MCAP, hi - c);
-        for (uint32_t e = tid; e < m; e += BLOCK) {
-            s_keys[e] = keys[c + e];
-            s_nonces[e] = nonces[c + e];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t csize = 1u << cb;  // <= MCAP
+    const uint32_t nchunks = (n_total + csize - 1) >> cb;
+    uint32_t ci = blockIdx.x;
+    if (ci >= nchunks) return;
+    uint64_t pk[ITEMS];
+    uint32_t pn[ITEMS];
+    {
+        const uint32_t c = ci << cb, m = min(csize, n_total - c);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t e = tid + i * BLOCK;
+            if (e < m) {
+                pk[i] = keys[c + e];
+                pn[i] = nonces[c + e];
+            }
         }
+    }
+    while (true) {
+        const uint32_t c = ci << cb, m = min(csize, n_total - c);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t e = tid + i * BLOCK;
+            if (e < m) {
+                s_keys[e] = pk[i];
+                s_nonces[e] = pn[i];
+            }
+        }
+        const uint32_t nci = ci + gridDim.x;
+        const bool more = nci < nchunks;
+        if (more) {
+            const uint32_t nc = nci << cb, nm = min(csize, n_total - nc);
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t e = tid + i * BLOCK;
+                if (e < nm) {
+                    pk[i] = keys[nc + e];
+                    pn[i] = nonces[nc + e];
+                }
+            }
+        }
+        const uint64_t base = chunk_base[ci];
         __syncthreads();
-        // Pair counts of this thread's contiguous records, kept in s_off.
-        uint64_t mine = 0;
         const uint32_t e0 = tid * ITEMS;
-#pragma unroll 1
+        uint32_t cnt[ITEMS];
+        uint64_t mine = 0;
+#pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t e = e0 + i;
-            uint32_t cnt = 0;
+            uint32_t cc = 0;
             if (e < m) {
                 const uint64_t ki = s_keys[e];
                 const uint32_t bi = (uint32_t)(ki >> 40);
-                for (uint32_t j = c + e + 1; j < hi; ++j) {
+                for (uint32_t j = c + e + 1; j < n_total; ++j) {
                     const uint64_t kj = (j - c < m) ? s_keys[j - c] : keys[j];
                     if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
-                    ++cnt;
+                    ++cc;
                 }
             }
-            s_off[e] = cnt;
-            mine += cnt;
+            cnt[i] = cc;
+            mine += cc;
         }
         uint64_t ctot;
-        uint64_t run = vxd::block_exclusive_scan<BLOCK>(mine, s_wave, &ctot);
-#pragma unroll 1
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t e = e0 + i;
-            const uint64_t cnt = s_off[e];
-            s_off[e] = run;
-            run += cnt;
-        }
-        if (tid == 0) s_off[MCAP] = ctot;
-        __syncthreads();
-        // Records past m own no slots (count 0), so the search over all MCAP
-        // entries stays inside [0, m).
-#pragma unroll 1
-        for (uint64_t p = tid; p < ctot; p += BLOCK) {
-            uint32_t a = 0, b = MCAP;  // largest e with s_off[e] <= p
-            while (b - a > 1) {
-                const uint32_t mid = (a + b) >> 1;
-                if (s_off[mid] <= p) a = mid; else b = mid;
+        const uint64_t my_off = vxd::block_exclusive_scan<BLOCK>(mine, s_wave, &ctot);
+        for (uint64_t w = 0; w < ctot; w += PW) {
+            uint64_t off = my_off;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint64_t pend = off + cnt[i];
+                if (pend > w && off < w + PW) {
+                    const uint32_t e = e0 + i;
+                    const uint32_t na = s_nonces[e];
+                    const uint64_t p0 = off > w ? off : w;
+                    const uint64_t p1 = pend < w + PW ? pend : w + PW;
+                    for (uint64_t p = p0; p < p1; ++p) {
+                        const uint32_t j = c + e + 1 + (uint32_t)(p - off);
+                        s_pa[p - w] = na;
+                        s_pb[p - w] = (j - c < m) ? s_nonces[j - c] : nonces[j];
+                    }
+                }
+                off = pend;
             }
-            const uint32_t e = a;
-            const uint32_t j = c + e + 1 + (uint32_t)(p - s_off[e]);
-            const uint32_t na = s_nonces[e];
-            const uint32_t nb = (j - c < m) ? s_nonces[j - c] : nonces[j];
-            const uint64_t h = vxd::h2(key, na, nb);
-            const uint64_t idx = base + p;
-            if (idx < cap) t2[idx] = make_uint4(na, nb, (uint32_t)h, (uint32_t)(h >> 32));
+            __syncthreads();
+            const uint32_t lim = (uint32_t)((ctot - w) < PW ? (ctot - w) : PW);
+#pragma unroll 1
+            for (uint32_t p = tid; p < lim; p += BLOCK) {
+                const uint32_t a = s_pa[p], b = s_pb[p];
+                const uint64_t h = vxd::h2(key, a, b);
+                const uint64_t idx = base + w + p;
+                if (idx < cap) t2[idx] = make_uint4(a, b, (uint32_t)h, (uint32_t)(h >> 32));
+            }
+            __syncthreads();
         }
-        base += ctot;
-        __syncthreads();
+        if (!more) break;
+        ci = nci;
     }
 }
 
@@ -591,6 +693,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const uint64_t *__res
     for (uint32_t i = threadIdx.x; i < m; i += kScanBlock) out[t0 + i] = base + s[i];
 }
 
+__global__ void k_zero_u64(uint64_t *__restrict__ p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
 __global__ void k_reset_words(uint32_t *__restrict__ p, uint32_t n) {
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
@@ -622,13 +728,13 @@ static TileGeom geom_segments(const uint32_t *seg, uint32_t q) {
 constexpr int kHashBlock = 256;
 constexpr int kHistBlock = 256;
 constexpr int kColBlock = 1024;
-constexpr int kScatterBlock = 256;
-constexpr int kScatterItems = 16;
 constexpr int kSortBlock = 512;
 constexpr int kFallbackBlock = 1024;
 constexpr int kFallbackGrid = 256;
-constexpr int kMatchBlock = 256;
+constexpr int kMatchBlock = 512;
 constexpr int kMatchCap = 2048;
+constexpr int kMatchWindow = 2048;
+constexpr int kMatchGrid = 256 * 2 * 2;  // persistent: two rounds of two work-groups per CU
 
 hipError_t launch_reset(uint32_t *words, uint32_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_words, dim3(1), dim3(256), 0, s, words, n);
@@ -666,48 +772,61 @@ hipError_t launch_colscan(const uint32_t *hist, uint32_t *off, uint32_t nseg, ui
     return hipGetLastError();
 }
 
+// Wide digits get big sub-tiles (8192 records: 16+ records per digit run for
+// up to 512 digits, one work-group per CU); narrow digits get 4096-record
+// sub-tiles and more work-groups per CU.
+template <typename... A>
+static hipError_t launch_scatter_cfg(uint32_t bits, uint32_t grid, hipStream_t s, A... args) {
+    if (bits >= 7)
+        hipLaunchKernelGGL((k_scatter<1024, 8>), dim3(grid), dim3(1024), 0, s, args...);
+    else
+        hipLaunchKernelGGL((k_scatter<512, 8>), dim3(grid), dim3(512), 0, s, args...);
+    return hipGetLastError();
+}
+
 hipError_t launch_scatter_chunks(const uint64_t *in_keys, const uint32_t *in_nonces,
                                  uint64_t *out_keys, uint32_t *out_nonces, const uint32_t *off,
                                  uint64_t n, uint32_t tiles, uint64_t chunk, uint32_t shift,
                                  uint32_t bits, hipStream_t s) {
-    hipLaunchKernelGGL((k_scatter<kScatterBlock, kScatterItems>), dim3(tiles), dim3(kScatterBlock), 0,
-                       s, in_keys, in_nonces, out_keys, out_nonces, off, geom_chunks(n, chunk), shift,
-                       bits);
-    return hipGetLastError();
+    return launch_scatter_cfg(bits, tiles, s, in_keys, in_nonces, out_keys, out_nonces, off,
+                              geom_chunks(n, chunk), shift, bits);
 }
 
 hipError_t launch_scatter_segments(const uint64_t *in_keys, const uint32_t *in_nonces,
                                    uint64_t *out_keys, uint32_t *out_nonces, const uint32_t *off,
                                    const uint32_t *seg, uint32_t nseg, uint32_t q, uint32_t shift,
                                    uint32_t bits, hipStream_t s) {
-    hipLaunchKernelGGL((k_scatter<kScatterBlock, kScatterItems>), dim3(nseg * q), dim3(kScatterBlock),
-                       0, s, in_keys, in_nonces, out_keys, out_nonces, off, geom_segments(seg, q),
-                       shift, bits);
-    return hipGetLastError();
+    return launch_scatter_cfg(bits, nseg * q, s, in_keys, in_nonces, out_keys, out_nonces, off,
+                              geom_segments(seg, q), shift, bits);
 }
 
 hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint32_t *gstart, uint32_t G,
                             uint32_t cap, uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count,
-                            uint32_t *ovf_list, hipStream_t s) {
+                            uint32_t *ovf_list, uint64_t T, uint64_t *chunk_count, uint32_t chunk_bits,
+                            hipStream_t s) {
     hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapMax>), dim3(1u << G), dim3(kSortBlock), 0, s,
-                       keys, nonces, gstart, G, cap, offsets, n_total, ovf_count, ovf_list);
+                       keys, nonces, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T,
+                       chunk_count, chunk_bits);
     return hipGetLastError();
 }
 
 hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, uint64_t *scr_keys,
                                  uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G,
                                  uint32_t *offsets, const uint32_t *ovf_count, const uint32_t *ovf_list,
-                                 uint32_t *status, hipStream_t s) {
+                                 uint32_t *status, uint64_t T, uint64_t *chunk_count,
+                                 uint32_t chunk_bits, hipStream_t s) {
     hipLaunchKernelGGL(k_group_fallback<kFallbackBlock>, dim3(kFallbackGrid), dim3(kFallbackBlock), 0,
                        s, keys, nonces, scr_keys, scr_nonces, gstart, G, offsets, ovf_count, ovf_list,
-                       (uint32_t)kFallbackMax, status);
+                       (uint32_t)kFallbackMax, status, T, chunk_count, chunk_bits);
     return hipGetLastError();
 }
 
-hipError_t launch_match_count(const uint64_t *keys, const uint32_t *offsets, uint32_t Gm, uint64_t T,
-                              uint32_t n_total, uint64_t *counts, hipStream_t s) {
-    hipLaunchKernelGGL((k_match_count<kMatchBlock, kMatchCap>), dim3(1u << Gm), dim3(kMatchBlock), 0, s,
-                       keys, offsets, Gm, T, n_total, counts);
+hipError_t launch_match_count(const uint64_t *keys, uint32_t n_total, uint32_t chunk_bits, uint64_t T,
+                              uint64_t *counts, hipStream_t s) {
+    const uint32_t nchunks = (n_total + (1u << chunk_bits) - 1) >> chunk_bits;
+    const uint32_t grid = min(nchunks, (uint32_t)kMatchGrid * 4);
+    hipLaunchKernelGGL((k_match_count<kMatchBlock, kMatchCap>), dim3(grid), dim3(kMatchBlock), 0, s,
+                       keys, n_total, chunk_bits, T, counts);
     return hipGetLastError();
 }
 
@@ -723,13 +842,19 @@ hipError_t launch_scan_u64(const uint64_t *in, uint32_t n, uint64_t *out, uint64
 uint32_t scan_parts(uint32_t n) { return (n + kScanTile - 1) / kScanTile; }
 
 hipError_t launch_match_emit(const uint32_t key_words[8], const uint64_t *keys, const uint32_t *nonces,
-                             const uint32_t *offsets, uint32_t Gm, uint64_t T, uint32_t n_total,
-                             const uint64_t *group_base, void *t2, uint64_t cap, hipStream_t s) {
+                             uint32_t n_total, uint32_t chunk_bits, uint64_t T, const uint64_t *chunk_base,
+                             void *t2, uint64_t cap, hipStream_t s) {
     Key key;
     for (int i = 0; i < 8; ++i) key.w[i] = key_words[i];
-    hipLaunchKernelGGL((k_match_emit<kMatchBlock, kMatchCap>), dim3(1u << Gm),
-                       dim3(kMatchBlock), 0, s, key, keys, nonces, offsets, Gm, T, n_total,
-                       group_base, (uint4 *)t2, cap);
+    const uint32_t nchunks = (n_total + (1u << chunk_bits) - 1) >> chunk_bits;
+    const uint32_t grid = min(nchunks, (uint32_t)kMatchGrid);
+    hipLaunchKernelGGL((k_match_emit<kMatchBlock, kMatchCap, kMatchWindow>), dim3(grid), dim3(kMatchBlock),
+                       0, s, key, keys, nonces, n_total, chunk_bits, T, chunk_base, (uint4 *)t2, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(uint64_t *p, uint32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(min((n + 1023) / 1024, 4096u)), dim3(1024), 0, s, p, n);
     return hipGetLastError();
 }
 

@@ -81,13 +81,15 @@ def test_plot_thresholds(vx, k, T):
 
 
 TUNINGS = [
-    dict(group_bits=4),                       # big groups -> LDS path near capacity / fallback
+    dict(group_bits=4),                       # groups near LDS capacity -> many take the fallback
     dict(group_bits=10, pass1_bits=3),        # two passes with a narrow first digit
-    dict(group_bits=12, pass1_bits=11),       # wide first digit
+    dict(group_bits=12, pass1_bits=11),       # wide first digit, 1-bit second pass
+    dict(group_bits=15, pass1_bits=5, pass2_bits=5),  # three passes
+    dict(group_bits=18),                      # three default passes, tiny groups
     dict(group_cap=64),                       # almost every group takes the fallback
-    dict(group_cap=200, match_bits=3),        # fallback + long match chunks
-    dict(match_bits=0),                       # one match group for the whole table
-    dict(match_bits=20, h1_tiles=7),          # tiny match groups, ragged hash tiles
+    dict(group_cap=200, match_chunk_bits=7),  # fallback + small match chunks
+    dict(match_chunk_bits=6),                 # smallest match chunks
+    dict(match_chunk_bits=9, h1_tiles=7),     # ragged hash tiles
 ]
 
 
