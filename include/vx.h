@@ -55,6 +55,7 @@ typedef enum {
 
 /* Device status word bits (vx_read_status). */
 #define VX_DEV_STATUS_GROUP_TOO_LARGE 0x1u /* a sort group exceeded the fallback limit */
+#define VX_DEV_STATUS_LOOKBACK_TIMEOUT 0x2u /* vx_plot: a Table-2 base wait hit its bound */
 
 #define VX_BUCKET_BITS 24
 #define VX_NUM_BUCKETS (1u << VX_BUCKET_BITS)
@@ -107,7 +108,8 @@ typedef struct {
     uint32_t h1_tiles;     /* work-groups of the hash + first partition pass */
     uint32_t match_chunk_bits; /* match works on chunks of 2^bits Table-1 records, 6..11 */
     uint32_t pass2_bits;   /* digit bits of the second pass (a third takes the rest) */
-    uint32_t reserved[2];
+    uint32_t fused_sort_match; /* plot: nonzero runs sort, match and Table-2 hash as one kernel */
+    uint32_t reserved;
 } vx_tuning;
 
 enum { VX_CALL_BUCKET_SORT = 1, VX_CALL_MATCH = 2, VX_CALL_PLOT = 3 };

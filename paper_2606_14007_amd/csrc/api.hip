@@ -49,6 +49,7 @@ struct Plan {
     uint64_t chunk1 = 0;     // records per pass-0 tile
     uint32_t cap = 0;        // LDS capacity of a sort group
     uint32_t cb = 0;         // match chunk = 2^cb consecutive Table-1 records
+    bool fused = false;      // plot: one fused sort + match kernel instead of two
 };
 
 uint32_t clampu(int64_t v, int64_t lo, int64_t hi) {
@@ -78,8 +79,8 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl) {
     // Sort groups of about 2048 records (half the LDS capacity).
     P.G = t->group_bits ? t->group_bits : clampu((int64_t)p->k - 11, 1, 20);
     if (P.G < 1 || P.G > 24) return fail(VX_ERR_UNSUPPORTED, "group_bits must be in [1, 24]");
-    // Split G into passes of at most 9 bits so every digit's run per sub-tile
-    // spans whole cache lines.
+    // Split G into passes of at most 9 bits (8-6-6 at k=31) so that every
+    // digit's run per sub-tile spans whole cache lines.
     uint32_t d0, d1, d2;
     if (P.G <= 9) {
         d0 = P.G; d1 = 0; d2 = 0;
@@ -122,6 +123,7 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl) {
     P.cb = t->match_chunk_bits ? t->match_chunk_bits : (uint32_t)vxk::kMatchChunkBitsMax;
     if (P.cb < 6 || P.cb > (uint32_t)vxk::kMatchChunkBitsMax)
         return fail(VX_ERR_UNSUPPORTED, "match_chunk_bits must be in [6, 11]");
+    P.fused = t->fused_sort_match != 0;
     *pl = P;
     return VX_OK;
 }
@@ -135,12 +137,14 @@ struct Layout {
     size_t hist[kMaxPasses] = {}, off[kMaxPasses] = {};  // u32[tiles][2^D]
     size_t gstart[kMaxPasses] = {};  // u32[2^(pre + D) + 1] group starts after each pass
     size_t ovf_list = 0;          // u32[2^G]
+    size_t lbwords = 0;           // u64[2^G] look-back words of the fused sort + match
     size_t mcount = 0, mbase = 0; // u64[match chunks]: pair counts, Table-2 bases
     size_t mpart = 0;             // u64[scan parts]
     size_t total = 0;
 };
 
-constexpr uint32_t kHeaderWords = 64;
+constexpr uint32_t kHeaderWords = 64;  // [0] status, [1] overflow count, [2] sort+match ticket
+constexpr uint32_t kLookbackSpinLimit = 1u << 20;
 
 uint32_t match_chunks(const Plan &P) { return (uint32_t)((P.n + (1ull << P.cb) - 1) >> P.cb); }
 
@@ -170,6 +174,7 @@ Layout layout(const Plan &P, int which) {
             L.gstart[i] = take((((size_t)1 << (P.pre[i] + P.D[i])) + 1) * 4);
         }
         L.ovf_list = take((size_t)(1u << P.G) * 4);
+        if (which == VX_CALL_PLOT) L.lbwords = take((size_t)(1u << P.G) * 8);
     }
     if (match) {
         const uint32_t nch = match_chunks(P);
@@ -193,17 +198,13 @@ T *at(void *ws, size_t off) {
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-// Partition passes and the group sort.  Pass 0 reads the nonce-order keys
-// (its histogram comes from the hash kernel in a plot, or from a histogram
-// pass over caller keys); passes alternate between Table 1 and the scratch
-// arrays so that the last one lands in Table 1, where groups are sorted in
-// place.  chunk_count (may be NULL) receives the Table-2 pair count of each
-// match chunk of the sorted table.
-vx_status run_bucket_sort(const Plan &P, const Layout &L, void *ws, const uint64_t *keys_no,
-                          bool hist_done, uint64_t *t1_keys, uint32_t *t1_nonces,
-                          uint32_t *offsets, uint64_t *chunk_count, hipStream_t s,
-                          hipEvent_t *ev = nullptr) {
-    uint32_t *hdr = at<uint32_t>(ws, L.header);
+// Partition passes.  Pass 0 reads the nonce-order keys (its histogram comes
+// from the hash kernel in a plot, or from a histogram pass over caller
+// keys); passes alternate between Table 1 and the scratch arrays so that the
+// last one lands in Table 1, where groups are then sorted in place.
+vx_status run_partition(const Plan &P, const Layout &L, void *ws, const uint64_t *keys_no,
+                        bool hist_done, uint64_t *t1_keys, uint32_t *t1_nonces, hipStream_t s,
+                        hipEvent_t *ev) {
     uint64_t *scr_k = at<uint64_t>(ws, L.scr_keys);
     uint32_t *scr_n = at<uint32_t>(ws, L.scr_nonces);
     const uint64_t *in_k = keys_no;
@@ -242,12 +243,23 @@ vx_status run_bucket_sort(const Plan &P, const Layout &L, void *ws, const uint64
         in_n = out_n;
     }
     if (P.npass == 1) VX_HIP(mark(ev, 3, s), "event");
+    return VX_OK;
+}
+
+// In-place group sort of the partitioned Table 1 (+ oversized groups), with
+// bucket offsets.  chunk_count (may be NULL) receives the Table-2 pair count
+// of each match chunk of the sorted table.
+vx_status run_group_sort(const Plan &P, const Layout &L, void *ws, uint64_t *t1_keys,
+                         uint32_t *t1_nonces, uint32_t *offsets, uint64_t *chunk_count, hipStream_t s,
+                         hipEvent_t *ev) {
+    uint32_t *hdr = at<uint32_t>(ws, L.header);
     const uint32_t *gstart = at<uint32_t>(ws, L.gstart[P.npass - 1]);
     if (chunk_count) VX_HIP(vxk::launch_zero_u64(chunk_count, match_chunks(P), s), "zero counts");
     VX_HIP(vxk::launch_groupsort(t1_keys, t1_nonces, gstart, P.G, P.cap, offsets, (uint32_t)P.n,
                                  hdr + 1, at<uint32_t>(ws, L.ovf_list), P.T, chunk_count, P.cb, s),
            "group sort");
-    VX_HIP(vxk::launch_group_fallback(t1_keys, t1_nonces, scr_k, scr_n, gstart, P.G, offsets, hdr + 1,
+    VX_HIP(vxk::launch_group_fallback(t1_keys, t1_nonces, at<uint64_t>(ws, L.scr_keys),
+                                      at<uint32_t>(ws, L.scr_nonces), gstart, P.G, offsets, hdr + 1,
                                       at<uint32_t>(ws, L.ovf_list), hdr, P.T, chunk_count, P.cb, s),
            "group sort fallback");
     VX_HIP(mark(ev, 4, s), "event");
@@ -338,7 +350,9 @@ vx_status vx_bucket_sort(const vx_plot_params *params, const uint64_t *d_keys, u
     if ((st = check_ws(L, d_workspace, workspace_bytes)) != VX_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     VX_HIP(vxk::launch_reset(at<uint32_t>(d_workspace, L.header), kHeaderWords, s), "reset");
-    st = run_bucket_sort(P, L, d_workspace, d_keys, false, d_t1_keys, d_t1_nonces, d_offsets, nullptr, s);
+    st = run_partition(P, L, d_workspace, d_keys, false, d_t1_keys, d_t1_nonces, s, nullptr);
+    if (st == VX_OK)
+        st = run_group_sort(P, L, d_workspace, d_t1_keys, d_t1_nonces, d_offsets, nullptr, s, nullptr);
     if (st == VX_OK) g_err[0] = 0;
     return st;
 }
@@ -389,11 +403,28 @@ vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, cons
                                    P.D[0], s),
            "hash");
     VX_HIP(mark(ev, 1, s), "event");
-    // The sort counts each match chunk's pairs while the groups are in LDS.
-    st = run_bucket_sort(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, b->bucket_offsets,
-                         at<uint64_t>(ws, L.mcount), s, ev);
+    st = run_partition(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, s, ev);
     if (st != VX_OK) return st;
-    st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, true, s, ev);
+    if (!P.fused) {
+        // Separate kernels: the sort counts each match chunk's pairs while the
+        // groups are in LDS, then the match kernel re-reads Table 1.
+        st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets,
+                            at<uint64_t>(ws, L.mcount), s, ev);
+        if (st != VX_OK) return st;
+        st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, true, s, ev);
+    } else {
+        uint32_t *hdr = at<uint32_t>(ws, L.header);
+        uint64_t *words = at<uint64_t>(ws, L.lbwords);
+        VX_HIP(vxk::launch_zero_u64(words, 1u << P.G, s), "zero look-back words");
+        VX_HIP(mark(ev, 4, s), "event");
+        VX_HIP(mark(ev, 5, s), "event");
+        VX_HIP(vxk::launch_sort_match(P.key_words, b->t1_keys, b->t1_nonces, at<uint64_t>(ws, L.scr_keys),
+                                      at<uint32_t>(ws, L.scr_nonces), at<uint32_t>(ws, L.gstart[P.npass - 1]),
+                                      P.G, P.cap, b->bucket_offsets, (uint32_t)P.n, P.T, hdr + 2, words, hdr,
+                                      b->t2, b->t2_capacity, b->t2_count, kLookbackSpinLimit, s),
+               "sort + match");
+        VX_HIP(mark(ev, 6, s), "event");
+    }
     if (st == VX_OK) g_err[0] = 0;
     return st;
 }

@@ -8,6 +8,7 @@
 #define VXK_BUCKET_BITS 24
 #define VXK_NUM_BUCKETS (1u << VXK_BUCKET_BITS)
 #define VXK_DEV_STATUS_GROUP_TOO_LARGE 0x1u
+#define VXK_DEV_STATUS_LOOKBACK_TIMEOUT 0x2u
 
 namespace vxk {
 
@@ -46,6 +47,11 @@ hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, uint64_t *scr
 hipError_t launch_match_count(const uint64_t *keys, uint32_t n_total, uint32_t chunk_bits, uint64_t T,
                               uint64_t *counts, hipStream_t s);
 hipError_t launch_zero_u64(uint64_t *p, uint32_t n, hipStream_t s);
+hipError_t launch_sort_match(const uint32_t key_words[8], uint64_t *keys, uint32_t *nonces, uint64_t *scr_keys,
+                             uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G, uint32_t cap,
+                             uint32_t *offsets, uint32_t n_total, uint64_t T, uint32_t *ticket,
+                             uint64_t *words, uint32_t *dev_status, void *t2, uint64_t t2cap,
+                             uint64_t *t2_count, uint32_t spin_limit, hipStream_t s);
 hipError_t launch_scan_u64(const uint64_t *in, uint32_t n, uint64_t *out, uint64_t *part,
                            uint64_t *total, hipStream_t s);
 uint32_t scan_parts(uint32_t n);

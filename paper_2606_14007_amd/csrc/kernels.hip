@@ -79,19 +79,13 @@ __global__ __launch_bounds__(BLOCK) void k_hash_table1(Key key, uint64_t n, uint
     uint64_t hi = lo + chunk;
     if (hi > n) hi = n;
     const uint32_t shift = 64u - hist_bits;
-    uint64_t i = lo + threadIdx.x;
-    for (; i + BLOCK < hi; i += 2 * BLOCK) {
-        const uint64_t a = vxd::h1(key, (uint32_t)i);
-        const uint64_t b = vxd::h1(key, (uint32_t)(i + BLOCK));
-        keys[i] = a;
-        keys[i + BLOCK] = b;
-        if (hist) {
-            atomicAdd(&s_hist[a >> shift], 1u);
-            atomicAdd(&s_hist[b >> shift], 1u);
-        }
-    }
-    if (i < hi) {
-        const uint64_t a = vxd::h1(key, (uint32_t)i);
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += BLOCK) {
+        // The empty asm hides that the nonce is the loop counter: otherwise
+        // the optimiser strength-reduces "uniform + nonce" sums inside the
+        // rounds into extra per-iteration adds (about 70 VALU per hash).
+        uint32_t nonce = (uint32_t)i;
+        asm volatile("" : "+v"(nonce));
+        const uint64_t a = vxd::h1(key, nonce);
         keys[i] = a;
         if (hist) atomicAdd(&s_hist[a >> shift], 1u);
     }
@@ -203,7 +197,7 @@ __global__ __launch_bounds__(BLOCK) void k_colscan(const uint32_t *__restrict__ 
 // so a lone work-group per CU still keeps HBM reads in flight.
 // ---------------------------------------------------------------------------
 
-template <int BLOCK, int ITEMS>
+template <int BLOCK, int ITEMS, int MAXD>
 __global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ in_keys,
                                                    const uint32_t *__restrict__ in_nonces,
                                                    uint64_t *__restrict__ out_keys,
@@ -213,8 +207,8 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ 
     constexpr int SUB = BLOCK * ITEMS;
     __shared__ uint64_t s_keys[SUB];
     __shared__ uint32_t s_nonces[SUB];
-    __shared__ uint32_t s_cursor[kMaxDigits];
-    __shared__ uint32_t s_start[kMaxDigits + 1];
+    __shared__ uint32_t s_cursor[MAXD];
+    __shared__ uint32_t s_start[MAXD + 1];
     __shared__ uint32_t s_wave[BLOCK / 64 + 1];
     const uint32_t nd = 1u << bits, mask = nd - 1u;
     const uint32_t tid = threadIdx.x;
@@ -647,6 +641,312 @@ __global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *_
 }
 
 // ---------------------------------------------------------------------------
+// Fused group sort + match + Table-2 hash (the plot path).
+//
+// A persistent work-group takes sort groups in increasing order from a
+// ticket counter.  For each group it sorts the records in LDS (as
+// k_groupsort), writes them to Table 1 with the group's bucket offsets,
+// counts every record's pairs, and obtains the group's Table-2 base with a
+// decoupled look-back over the groups before it (single-pass scan, Merrill
+// and Garland 2016): it publishes its own count first, then sums published
+// counts backwards until it meets a published inclusive prefix.  Tickets are
+// handed out in order to running work-groups and every work-group publishes
+// its count before it waits, so the waits always end; the wait is still
+// bounded and sets a status bit if the bound is hit.  Then the group's pairs
+// are expanded into an LDS list and hashed one pair per lane.  Sorting and
+// hashing of different work-groups overlap on each CU, and Table 1 is read
+// once.  Groups above the LDS capacity are sorted and matched from global
+// memory by the same work-group (slow path, never taken by BLAKE3 keys).
+// ---------------------------------------------------------------------------
+
+constexpr uint64_t kLbAgg = 1ull << 62;     // word holds the group's own count
+constexpr uint64_t kLbPrefix = 2ull << 62;  // word holds the inclusive prefix
+constexpr uint64_t kLbValue = (1ull << 62) - 1;
+
+__device__ __forceinline__ uint64_t lb_load(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Run by the whole work-group.  Returns (in every thread) the sum of the
+// counts of groups [0, g).  Thread t inspects group j - t, so one round
+// covers BLOCK predecessors -- about the number of groups in flight, which is
+// how far back the nearest published inclusive prefix usually is.  A round
+// consumes the window up to the first group that is not yet published or
+// that carries an inclusive prefix.
+template <int BLOCK>
+__device__ uint64_t lookback(const uint64_t *words, uint32_t g, uint32_t spin_limit,
+                             uint32_t *dev_status, uint32_t *s_first, uint64_t *s_wave) {
+    constexpr int NW = BLOCK / 64;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid / 64u;
+    uint64_t prefix = 0;
+    int64_t j = (int64_t)g - 1;
+    uint32_t spins = 0;
+    while (j >= 0) {
+        const int64_t idx = j - (int64_t)tid;
+        const uint64_t v = idx >= 0 ? lb_load(&words[idx]) : kLbPrefix;
+        const uint64_t flag = v & ~kLbValue;
+        const uint64_t not_ready = __ballot(flag == 0);
+        const uint64_t pref = __ballot(flag == kLbPrefix);
+        if (lane == 0) {
+            s_first[wid] = not_ready ? (uint32_t)__builtin_ctzll(not_ready) : 64u;
+            s_first[NW + wid] = pref ? (uint32_t)__builtin_ctzll(pref) : 64u;
+        }
+        __syncthreads();
+        uint32_t first_nr = BLOCK, first_pf = BLOCK;
+#pragma unroll
+        for (int w = NW - 1; w >= 0; --w) {
+            if (s_first[w] < 64u) first_nr = w * 64 + s_first[w];
+            if (s_first[NW + w] < 64u) first_pf = w * 64 + s_first[NW + w];
+        }
+        const uint32_t take = first_pf < first_nr ? first_pf + 1 : first_nr;
+        prefix += vxd::block_sum<BLOCK>(tid < take ? (uint64_t)(v & kLbValue) : (uint64_t)0, s_wave);
+        if (first_pf < first_nr) break;
+        j -= take;
+        if (take == 0) {
+            // Bounded wait.  After any timeout every later look-back gives up
+            // at once, so one failure cannot chain into long waits.
+            const uint32_t st = __hip_atomic_load(dev_status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (++spins > spin_limit || (st & VXK_DEV_STATUS_LOOKBACK_TIMEOUT)) {
+                if (tid == 0) atomicOr(dev_status, (uint32_t)VXK_DEV_STATUS_LOOKBACK_TIMEOUT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    return prefix;
+}
+
+// Writes the pairs of records [e0, e0 + ITEMS) of a sorted LDS run that fall
+// in slots [w, w + PW) into the pair list (slot - w); my_off is the slot of
+// the first pair of record e0.  Partners are found by the same forward scan
+// that counted them.
+template <int ITEMS>
+__device__ __forceinline__ void expand_pairs(const uint64_t *s_keys, const uint32_t *s_nonces, uint32_t e0,
+                                             uint32_t n, uint64_t T, uint64_t my_off, uint64_t w,
+                                             uint32_t PW, uint32_t *s_pa, uint32_t *s_pb) {
+    uint64_t off = my_off;
+    for (uint32_t e = e0; e < min(e0 + ITEMS, n) && off < w + PW; ++e) {
+        const uint64_t ki = s_keys[e];
+        const uint32_t bi = (uint32_t)(ki >> 40);
+        const uint32_t na = s_nonces[e];
+        uint32_t j = e + 1;
+        for (; j < n; ++j) {
+            const uint64_t kj = s_keys[j];
+            if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
+            const uint64_t q = off + (j - e - 1);
+            if (q >= w && q < w + PW) {
+                s_pa[q - w] = na;
+                s_pb[q - w] = s_nonces[j];
+            }
+        }
+        off += j - e - 1;
+    }
+}
+
+template <int BLOCK, int CAPMAX, int PW>
+__global__ __launch_bounds__(BLOCK) void k_sort_match(
+    Key key, uint64_t *__restrict__ keys, uint32_t *__restrict__ nonces,
+    uint64_t *__restrict__ scr_keys, uint32_t *__restrict__ scr_nonces,
+    const uint32_t *__restrict__ gstart, uint32_t G, uint32_t cap,
+    uint32_t *__restrict__ offsets, uint32_t n_total, uint64_t T, uint32_t *__restrict__ ticket,
+    uint64_t *__restrict__ words, uint32_t *__restrict__ dev_status, uint4 *__restrict__ t2,
+    uint64_t t2cap, uint64_t *__restrict__ t2_count, uint32_t spin_limit, uint32_t fb_max) {
+    constexpr int ITEMS = CAPMAX / BLOCK;
+    static_assert(kSubBins * 4 >= PW * 8, "pair list reuses the sub-bin area");
+    static_assert(CAPMAX >= PW, "hashes of one window reuse the key area");
+    __shared__ uint64_t s_keys[CAPMAX];
+    __shared__ uint32_t s_nonces[CAPMAX];
+    __shared__ uint32_t s_start[kSubBins + 1];
+    __shared__ uint64_t s_wave[BLOCK / 64 + 1];
+    __shared__ uint32_t s_first[2 * (BLOCK / 64)];
+    __shared__ uint32_t s_g;
+    uint32_t *s_wave32 = reinterpret_cast<uint32_t *>(s_wave);
+    uint32_t *s_pa = s_start;
+    uint32_t *s_pb = s_start + PW;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t ngroups = 1u << G;
+    const uint32_t sb_shift = 64u - G - kSubBinBits;
+    const uint32_t nbg = 1u << (VXK_BUCKET_BITS - G);
+    while (true) {
+        if (tid == 0) s_g = atomicAdd(ticket, 1u);
+        __syncthreads();
+        const uint32_t g = s_g;
+        if (g >= ngroups) break;
+        const uint32_t lo = gstart[g], hi = gstart[g + 1], n = hi - lo;
+        const bool fast = n <= cap;
+        if (g == ngroups - 1 && tid == 0) offsets[VXK_NUM_BUCKETS] = n_total;
+        const uint32_t bfirst = g << (VXK_BUCKET_BITS - G);
+        if (fast) {
+            for (uint32_t i = tid; i < kSubBins; i += BLOCK) s_start[i] = 0;
+            __syncthreads();
+            uint64_t k[ITEMS];
+            uint32_t nn[ITEMS], slot[ITEMS];
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t e = j * BLOCK + tid;
+                if (e < n) {
+                    k[j] = keys[lo + e];
+                    nn[j] = nonces[lo + e];
+                    slot[j] = atomicAdd(&s_start[(uint32_t)(k[j] >> sb_shift) & (kSubBins - 1)], 1u);
+                }
+            }
+            __syncthreads();
+            vxd::lds_exclusive_scan<BLOCK>(s_start, kSubBins, s_wave32);
+            if (tid == 0) s_start[kSubBins] = n;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t e = j * BLOCK + tid;
+                if (e < n) {
+                    const uint32_t q = s_start[(uint32_t)(k[j] >> sb_shift) & (kSubBins - 1)] + slot[j];
+                    s_keys[q] = k[j];
+                    s_nonces[q] = nn[j];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t e = j * BLOCK + tid;
+                if (e < n) {
+                    const uint32_t sb = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
+                    const uint32_t b0 = s_start[sb], b1 = s_start[sb + 1];
+                    uint32_t r = 0;
+                    for (uint32_t x = b0; x < b1; ++x) r += rec_less(s_keys[x], s_nonces[x], k[j], nn[j]);
+                    slot[j] = b0 + r;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t e = j * BLOCK + tid;
+                if (e < n) {
+                    s_keys[slot[j]] = k[j];
+                    s_nonces[slot[j]] = nn[j];
+                }
+            }
+            __syncthreads();
+            for (uint32_t e = tid; e < n; e += BLOCK) {
+                keys[lo + e] = s_keys[e];
+                nonces[lo + e] = s_nonces[e];
+            }
+            for (uint32_t bl = tid; bl < nbg; bl += BLOCK) {
+                uint32_t a = 0, c = n;
+                while (a < c) {
+                    const uint32_t mid = (a + c) >> 1;
+                    if ((uint32_t)(s_keys[mid] >> 40) < bfirst + bl) a = mid + 1; else c = mid;
+                }
+                offsets[bfirst + bl] = lo + a;
+            }
+        } else if (n <= fb_max) {
+            // Slow path: rank sort through scratch, all in global memory.
+            for (uint32_t e = tid; e < n; e += BLOCK) {
+                scr_keys[lo + e] = keys[lo + e];
+                scr_nonces[lo + e] = nonces[lo + e];
+            }
+            __syncthreads();
+            for (uint32_t e = tid; e < n; e += BLOCK) {
+                const uint64_t mk = scr_keys[lo + e];
+                const uint32_t mn = scr_nonces[lo + e];
+                uint32_t r = 0;
+                for (uint32_t x = 0; x < n; ++x) r += rec_less(scr_keys[lo + x], scr_nonces[lo + x], mk, mn);
+                keys[lo + r] = mk;
+                nonces[lo + r] = mn;
+            }
+            __syncthreads();
+            for (uint32_t bl = tid; bl < nbg; bl += BLOCK) {
+                uint32_t a = 0, c = n;
+                while (a < c) {
+                    const uint32_t mid = (a + c) >> 1;
+                    if ((uint32_t)(keys[lo + mid] >> 40) < bfirst + bl) a = mid + 1; else c = mid;
+                }
+                offsets[bfirst + bl] = lo + a;
+            }
+        } else {
+            if (tid == 0) atomicOr(dev_status, (uint32_t)VXK_DEV_STATUS_GROUP_TOO_LARGE);
+        }
+        const bool counted = fast || n <= fb_max;
+        // Pair counts.  Fast path: this thread owns records [e0, e0 + ITEMS)
+        // of the sorted group in LDS; slow path: records tid, tid + BLOCK, ...
+        const uint32_t e0 = tid * ITEMS;
+        uint64_t mine = 0;
+        if (fast) {
+            for (uint32_t e = e0; e < min(e0 + ITEMS, n); ++e) mine += pairs_after(s_keys, e, n, T);
+        } else if (counted) {
+            for (uint32_t e = tid; e < n; e += BLOCK) mine += pairs_after(keys + lo, e, n, T);
+        }
+        uint64_t ctot;
+        const uint64_t my_off = vxd::block_exclusive_scan<BLOCK>(mine, s_wave, &ctot);
+        // Publish this group's count at once, so that later groups can pass
+        // it in their look-back while this one keeps working.
+        if (tid == 0) lb_store(&words[g], kLbAgg | ctot);
+        if (fast && ctot <= PW) {
+            // Common case, one window: expand and hash the pairs into LDS
+            // first (the hashes overwrite the key area, no longer needed),
+            // then look back -- by now the groups before this one have
+            // published -- and write the records out.
+            expand_pairs<ITEMS>(s_keys, s_nonces, tid * ITEMS, n, T, my_off, 0, PW, s_pa, s_pb);
+            __syncthreads();
+            uint64_t *s_h = s_keys;
+#pragma unroll 1
+            for (uint32_t q = tid; q < (uint32_t)ctot; q += BLOCK) s_h[q] = vxd::h2(key, s_pa[q], s_pb[q]);
+            __syncthreads();  // hashes visible to the writers below (the look-back may not sync)
+            const uint64_t base = lookback<BLOCK>(words, g, spin_limit, dev_status, s_first, s_wave);
+            if (tid == 0) {
+                lb_store(&words[g], kLbPrefix | (base + ctot));
+                if (g == ngroups - 1) *t2_count = base + ctot;
+            }
+            for (uint32_t q = tid; q < (uint32_t)ctot; q += BLOCK) {
+                const uint64_t idx = base + q;
+                const uint64_t h = s_h[q];
+                if (idx < t2cap) t2[idx] = make_uint4(s_pa[q], s_pb[q], (uint32_t)h, (uint32_t)(h >> 32));
+            }
+        } else {
+        const uint64_t base = lookback<BLOCK>(words, g, spin_limit, dev_status, s_first, s_wave);
+        if (tid == 0) {
+            lb_store(&words[g], kLbPrefix | (base + ctot));
+            if (g == ngroups - 1) *t2_count = base + ctot;
+        }
+        if (fast) {
+            for (uint64_t w = 0; w < ctot; w += PW) {
+                expand_pairs<ITEMS>(s_keys, s_nonces, tid * ITEMS, n, T, my_off, w, PW, s_pa, s_pb);
+                __syncthreads();
+                const uint32_t lim = (uint32_t)((ctot - w) < PW ? (ctot - w) : PW);
+#pragma unroll 1
+                for (uint32_t q = tid; q < lim; q += BLOCK) {
+                    const uint32_t a = s_pa[q], b = s_pb[q];
+                    const uint64_t h = vxd::h2(key, a, b);
+                    const uint64_t idx = base + w + q;
+                    if (idx < t2cap) t2[idx] = make_uint4(a, b, (uint32_t)h, (uint32_t)(h >> 32));
+                }
+                __syncthreads();
+            }
+        } else if (counted) {
+            // Slow path: one thread per record, pairs in canonical order by a
+            // sequential walk of the records (rare; correctness only).
+            __syncthreads();
+            if (tid == 0) {
+                uint64_t idx = base;
+                for (uint32_t e = 0; e < n; ++e) {
+                    const uint32_t c = pairs_after(keys + lo, e, n, T);
+                    for (uint32_t q = 0; q < c; ++q) {
+                        const uint32_t a = nonces[lo + e], b = nonces[lo + e + 1 + q];
+                        const uint64_t h = vxd::h2(key, a, b);
+                        if (idx < t2cap) t2[idx] = make_uint4(a, b, (uint32_t)h, (uint32_t)(h >> 32));
+                        ++idx;
+                    }
+                }
+            }
+        }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Device-wide exclusive scan of u64 (pair counts -> Table-2 bases).
 // ---------------------------------------------------------------------------
 
@@ -735,6 +1035,7 @@ constexpr int kMatchBlock = 512;
 constexpr int kMatchCap = 2048;
 constexpr int kMatchWindow = 2048;
 constexpr int kMatchGrid = 256 * 2 * 2;  // persistent: two rounds of two work-groups per CU
+constexpr int kSortMatchGrid = 256 * 2;  // persistent: two work-groups per CU
 
 hipError_t launch_reset(uint32_t *words, uint32_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_words, dim3(1), dim3(256), 0, s, words, n);
@@ -772,15 +1073,18 @@ hipError_t launch_colscan(const uint32_t *hist, uint32_t *off, uint32_t nseg, ui
     return hipGetLastError();
 }
 
-// Wide digits get big sub-tiles (8192 records: 16+ records per digit run for
-// up to 512 digits, one work-group per CU); narrow digits get 4096-record
-// sub-tiles and more work-groups per CU.
+// Digits of 7 to 9 bits use 8192-record sub-tiles (16+ records per digit run,
+// one 1024-thread work-group per CU); narrower digits use 4096-record
+// sub-tiles with several work-groups per CU; wider ones (tunings only) the
+// big tile with room for 2048 digits.
 template <typename... A>
 static hipError_t launch_scatter_cfg(uint32_t bits, uint32_t grid, hipStream_t s, A... args) {
-    if (bits >= 7)
-        hipLaunchKernelGGL((k_scatter<1024, 8>), dim3(grid), dim3(1024), 0, s, args...);
+    if (bits <= 6)
+        hipLaunchKernelGGL((k_scatter<512, 8, 64>), dim3(grid), dim3(512), 0, s, args...);
+    else if (bits <= 9)
+        hipLaunchKernelGGL((k_scatter<1024, 8, 512>), dim3(grid), dim3(1024), 0, s, args...);
     else
-        hipLaunchKernelGGL((k_scatter<512, 8>), dim3(grid), dim3(512), 0, s, args...);
+        hipLaunchKernelGGL((k_scatter<1024, 8, kMaxDigits>), dim3(grid), dim3(1024), 0, s, args...);
     return hipGetLastError();
 }
 
@@ -850,6 +1154,21 @@ hipError_t launch_match_emit(const uint32_t key_words[8], const uint64_t *keys, 
     const uint32_t grid = min(nchunks, (uint32_t)kMatchGrid);
     hipLaunchKernelGGL((k_match_emit<kMatchBlock, kMatchCap, kMatchWindow>), dim3(grid), dim3(kMatchBlock),
                        0, s, key, keys, nonces, n_total, chunk_bits, T, chunk_base, (uint4 *)t2, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_match(const uint32_t key_words[8], uint64_t *keys, uint32_t *nonces, uint64_t *scr_keys,
+                             uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G, uint32_t cap,
+                             uint32_t *offsets, uint32_t n_total, uint64_t T, uint32_t *ticket,
+                             uint64_t *words, uint32_t *dev_status, void *t2, uint64_t t2cap,
+                             uint64_t *t2_count, uint32_t spin_limit, hipStream_t s) {
+    Key key;
+    for (int i = 0; i < 8; ++i) key.w[i] = key_words[i];
+    const uint32_t grid = min(1u << G, (uint32_t)kSortMatchGrid);
+    hipLaunchKernelGGL((k_sort_match<kSortBlock, kGroupCapMax, kMatchWindow>), dim3(grid), dim3(kSortBlock),
+                       0, s, key, keys, nonces, scr_keys, scr_nonces, gstart, G, cap, offsets, n_total, T,
+                       ticket, words, dev_status, (uint4 *)t2, t2cap, t2_count, spin_limit,
+                       (uint32_t)kFallbackMax);
     return hipGetLastError();
 }
 

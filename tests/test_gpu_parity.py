@@ -90,6 +90,10 @@ TUNINGS = [
     dict(group_cap=200, match_chunk_bits=7),  # fallback + small match chunks
     dict(match_chunk_bits=6),                 # smallest match chunks
     dict(match_chunk_bits=9, h1_tiles=7),     # ragged hash tiles
+    dict(fused_sort_match=1),                 # one fused sort + match kernel (look-back bases)
+    dict(fused_sort_match=1, group_cap=64),   # fused kernel, most groups on its slow path
+    dict(fused_sort_match=1, group_bits=3),   # fused kernel, few large groups
+    dict(group_bits=20, pass1_bits=10),       # a 10-bit pass (wide-digit scatter)
 ]
 
 
