@@ -305,6 +305,27 @@ __device__ __forceinline__ uint32_t pairs_after(const uint64_t *keys, uint32_t e
 // [lo, lo + n)) to the counters of the fixed match chunks those records fall
 // in (chunk = record index >> chunk_bits).  Integer sums, so the order of the
 // atomic adds does not matter.
+// Pairs owned by records [e_lo, e_hi) of a sorted run keys[0..n) (the run
+// ends at a bucket boundary), counted with a two-pointer walk: the last
+// partner of a record never precedes the previous record's last partner.
+__device__ __forceinline__ uint64_t pairs_in_range(const uint64_t *keys, uint32_t e_lo, uint32_t e_hi,
+                                                   uint32_t n, uint64_t T) {
+    uint64_t total = 0;
+    uint32_t reach = e_lo;
+    for (uint32_t e = e_lo; e < e_hi; ++e) {
+        const uint64_t ki = keys[e];
+        const uint32_t bi = (uint32_t)(ki >> 40);
+        if (reach < e) reach = e;
+        while (reach + 1 < n) {
+            const uint64_t kj = keys[reach + 1];
+            if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
+            ++reach;
+        }
+        total += reach - e;
+    }
+    return total;
+}
+
 template <int BLOCK>
 __device__ __forceinline__ void add_chunk_pairs(const uint64_t *keys, uint32_t lo, uint32_t n,
                                                 uint64_t T, uint64_t *chunk_count,
@@ -313,8 +334,9 @@ __device__ __forceinline__ void add_chunk_pairs(const uint64_t *keys, uint32_t l
     for (uint32_t c = c0; c <= c1; ++c) {
         const uint32_t a = max(c << chunk_bits, lo) - lo;
         const uint32_t b = min((c + 1) << chunk_bits, lo + n) - lo;
-        uint64_t mine = 0;
-        for (uint32_t e = a + threadIdx.x; e < b; e += BLOCK) mine += pairs_after(keys, e, n, T);
+        const uint32_t per = (b - a + BLOCK - 1) / BLOCK;
+        const uint32_t r0 = min(a + per * threadIdx.x, b), r1 = min(r0 + per, b);
+        uint64_t mine = pairs_in_range(keys, r0, r1, n, T);
         mine = vxd::block_sum<BLOCK>(mine, s_wave);
         if (threadIdx.x == 0 && mine) atomicAdd((unsigned long long *)&chunk_count[c], (unsigned long long)mine);
     }
@@ -523,14 +545,18 @@ __global__ __launch_bounds__(BLOCK) void k_match_count(const uint64_t *__restric
 }
 
 // Match + Table-2 hash.  A persistent work-group walks chunks ci =
-// blockIdx.x, blockIdx.x + gridDim.x, ...  Per chunk: each thread counts the
-// pairs of its ITEMS consecutive records, a work-group scan turns the counts
-// into canonical slots, and the pairs are expanded into an LDS list of
-// (nonce_a, nonce_b) in slot order, PW slots at a time, which is hashed one
-// pair per lane -- every lane does the same BLAKE3 work whatever the pair
-// distribution.  Table-2 index = chunk base + slot.  The next chunk's
-// records are loaded into registers while the current one is worked on.
-template <int BLOCK, int MCAP, int PW>
+// blockIdx.x, blockIdx.x + gridDim.x, ...  Per chunk:
+//  * each thread counts the pairs of its ITEMS consecutive records with a
+//    two-pointer walk (a record's last partner never precedes the previous
+//    record's), so no lane waits on another's long partner list;
+//  * a work-group scan turns the counts into canonical Table-2 slots, and the
+//    first slot of every record is kept in LDS;
+//  * each thread then takes an equal run of consecutive slots, finds the
+//    record of its first slot by binary search and walks on, hashing one pair
+//    per slot -- equal BLAKE3 work per lane whatever the pair distribution.
+// Table-2 index = chunk base + slot.  The next chunk's records are loaded
+// into registers while the current one is worked on.
+template <int BLOCK, int MCAP>
 __global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *__restrict__ keys,
                                                       const uint32_t *__restrict__ nonces,
                                                       uint32_t n_total, uint32_t cb, uint64_t T,
@@ -539,8 +565,7 @@ __global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *_
     constexpr int ITEMS = MCAP / BLOCK;
     __shared__ uint64_t s_keys[MCAP];
     __shared__ uint32_t s_nonces[MCAP];
-    __shared__ uint32_t s_pa[PW];
-    __shared__ uint32_t s_pb[PW];
+    __shared__ uint64_t s_off[MCAP + 1];
     __shared__ uint64_t s_wave[BLOCK / 64 + 1];
     const uint32_t tid = threadIdx.x;
     const uint32_t csize = 1u << cb;  // <= MCAP
@@ -585,9 +610,12 @@ __global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *_
         }
         const uint64_t base = chunk_base[ci];
         __syncthreads();
+        // Two-pointer count over records [e0, e0 + ITEMS); reach = index of
+        // the last partner found so far (relative to c; may pass m).
         const uint32_t e0 = tid * ITEMS;
         uint32_t cnt[ITEMS];
         uint64_t mine = 0;
+        uint32_t reach = e0;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t e = e0 + i;
@@ -595,46 +623,55 @@ __global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *_
             if (e < m) {
                 const uint64_t ki = s_keys[e];
                 const uint32_t bi = (uint32_t)(ki >> 40);
-                for (uint32_t j = c + e + 1; j < n_total; ++j) {
-                    const uint64_t kj = (j - c < m) ? s_keys[j - c] : keys[j];
+                if (reach < e) reach = e;
+                while (c + reach + 1 < n_total) {
+                    const uint32_t j = reach + 1;
+                    const uint64_t kj = j < m ? s_keys[j] : keys[c + j];
                     if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
-                    ++cc;
+                    reach = j;
                 }
+                cc = reach - e;
             }
             cnt[i] = cc;
             mine += cc;
         }
         uint64_t ctot;
-        const uint64_t my_off = vxd::block_exclusive_scan<BLOCK>(mine, s_wave, &ctot);
-        for (uint64_t w = 0; w < ctot; w += PW) {
-            uint64_t off = my_off;
+        uint64_t run = vxd::block_exclusive_scan<BLOCK>(mine, s_wave, &ctot);
 #pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const uint64_t pend = off + cnt[i];
-                if (pend > w && off < w + PW) {
-                    const uint32_t e = e0 + i;
-                    const uint32_t na = s_nonces[e];
-                    const uint64_t p0 = off > w ? off : w;
-                    const uint64_t p1 = pend < w + PW ? pend : w + PW;
-                    for (uint64_t p = p0; p < p1; ++p) {
-                        const uint32_t j = c + e + 1 + (uint32_t)(p - off);
-                        s_pa[p - w] = na;
-                        s_pb[p - w] = (j - c < m) ? s_nonces[j - c] : nonces[j];
-                    }
-                }
-                off = pend;
-            }
-            __syncthreads();
-            const uint32_t lim = (uint32_t)((ctot - w) < PW ? (ctot - w) : PW);
-#pragma unroll 1
-            for (uint32_t p = tid; p < lim; p += BLOCK) {
-                const uint32_t a = s_pa[p], b = s_pb[p];
-                const uint64_t h = vxd::h2(key, a, b);
-                const uint64_t idx = base + w + p;
-                if (idx < cap) t2[idx] = make_uint4(a, b, (uint32_t)h, (uint32_t)(h >> 32));
-            }
-            __syncthreads();
+        for (int i = 0; i < ITEMS; ++i) {
+            if (e0 + i < MCAP) s_off[e0 + i] = run;
+            run += cnt[i];
         }
+        if (tid == 0) s_off[MCAP] = ctot;
+        __syncthreads();
+        // Slots [q0, q1) of this thread.
+        const uint64_t per = (ctot + BLOCK - 1) / BLOCK;
+        const uint64_t q0 = per * tid < ctot ? per * tid : ctot;
+        const uint64_t q1 = q0 + per < ctot ? q0 + per : ctot;
+        if (q0 < q1) {
+            uint32_t lo_e = 0, hi_e = MCAP;  // largest e with s_off[e] <= q0
+            while (hi_e - lo_e > 1) {
+                const uint32_t mid = (lo_e + hi_e) >> 1;
+                if (s_off[mid] <= q0) lo_e = mid; else hi_e = mid;
+            }
+            uint32_t e = lo_e;
+            uint64_t e_end = s_off[e + 1];
+            uint32_t na = s_nonces[e];
+            uint4 *out = t2 + base;
+#pragma unroll 1
+            for (uint64_t q = q0; q < q1; ++q) {
+                while (q >= e_end) {  // next record with pairs
+                    ++e;
+                    e_end = s_off[e + 1];
+                    na = s_nonces[e];
+                }
+                const uint32_t j = e + 1 + (uint32_t)(q - s_off[e]);
+                const uint32_t nb = j < m ? s_nonces[j] : nonces[c + j];
+                const uint64_t h = vxd::h2(key, na, nb);
+                if (base + q < cap) out[q] = make_uint4(na, nb, (uint32_t)h, (uint32_t)(h >> 32));
+            }
+        }
+        __syncthreads();
         if (!more) break;
         ci = nci;
     }
@@ -1152,7 +1189,7 @@ hipError_t launch_match_emit(const uint32_t key_words[8], const uint64_t *keys, 
     for (int i = 0; i < 8; ++i) key.w[i] = key_words[i];
     const uint32_t nchunks = (n_total + (1u << chunk_bits) - 1) >> chunk_bits;
     const uint32_t grid = min(nchunks, (uint32_t)kMatchGrid);
-    hipLaunchKernelGGL((k_match_emit<kMatchBlock, kMatchCap, kMatchWindow>), dim3(grid), dim3(kMatchBlock),
+    hipLaunchKernelGGL((k_match_emit<kMatchBlock, kMatchCap>), dim3(grid), dim3(kMatchBlock),
                        0, s, key, keys, nonces, n_total, chunk_bits, T, chunk_base, (uint4 *)t2, cap);
     return hipGetLastError();
 }
