@@ -80,6 +80,131 @@ def cpu_baseline(k_sample: int, target_k: int):
     }
 
 
+def bench_batched(args) -> dict:
+    """32 plots, k uniform in 22..29, independent keys (SplitMix64 seed 4):
+    plots/hour of one batched launch (eager, and replayed as a HIP graph)
+    against the same plots one at a time through vx_plot."""
+    import torch
+    import paper_2606_14007_amd as vx
+    from paper_2606_14007_amd import autotune, batch as B
+    from vx_inputs import batched_plan
+
+    specs = batched_plan(32)
+    tunings = None
+    if args.autotune:
+        cache = autotune.load_cache()
+        tun = [autotune.tuned(s.k, cache) for s in specs]
+        tunings = [autotune.to_native(t) if t else vx.make_tuning() for t in tun]
+        log(f"autotuned plots: {sum(t is not None for t in tun)}/{len(tun)}")
+    bt = B.alloc_batch(specs, tunings=tunings)
+    log(f"batched: {len(specs)} plots, k={sorted(s.k for s in specs)}, "
+        f"{bt.footprint_bytes() / 2**30:.1f} GiB on the device")
+    sh = torch.cuda.current_stream().cuda_stream
+    params = bt.params
+    nbs = [b.native() for b in bt.plots]
+
+    def sequential():
+        for p, nb in zip(params, nbs):
+            vx.vx_plot(p, nb, None, sh)   # plain path, default tuning, one at a time
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    reps = max(1, args.steps)
+    t_seq = timed(sequential, reps)
+    log(f"sequential: {t_seq * 1e3:.1f} ms for {len(specs)} plots")
+    t_bat = timed(lambda: B.plot_batch(bt), reps)
+    log(f"batched (eager): {t_bat * 1e3:.1f} ms")
+    B.capture(bt)
+    t_graph = timed(lambda: B.replay(bt), reps)
+    log(f"batched (graph replay): {t_graph * 1e3:.1f} ms")
+    for b in bt.plots:
+        if vx.t2_count(b) > b.t2_capacity:
+            raise RuntimeError("Table 2 overflow in batch")
+    n = len(specs)
+    best = min(t_bat, t_graph)
+    return {
+        "metric": "mixed-k plots/hour batched vs plain",
+        "value": round(n * 3600.0 / best, 1),
+        "unit": "plots/h",
+        "n_gpus": 1, "steps": reps, "warmup": 1,
+        "ms_per_step": round(best * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "batched: 32 plots, k uniform in 22..29, keys from SplitMix64 "
+                               "seed 4, default thresholds", "ks": [s.k for s in specs],
+                   "lanes": B.LANES, "autotuned": bool(args.autotune),
+                   "parallelism": "single GPU"},
+        "sequential_plots_per_hour": round(n * 3600.0 / t_seq, 1),
+        "batched_eager_plots_per_hour": round(n * 3600.0 / t_bat, 1),
+        "batched_graph_plots_per_hour": round(n * 3600.0 / t_graph, 1),
+        "speedup_vs_sequential": round(t_seq / best, 3),
+        "records": sum(1 << s.k for s in specs),
+    }
+
+
+def bench_serving(args) -> dict:
+    """Poisson plot requests (SplitMix64 seed 5), k uniform in 22..30, at
+    about 80% of the plain one-at-a-time service rate; continuous batching
+    (4 slots, HBM-footprint admission) against a FIFO one-at-a-time server on
+    the same arrivals."""
+    import torch
+    from paper_2606_14007_amd import serve
+    from vx_inputs import serving_arrivals
+
+    k_lo, k_hi = 22, 30
+    per_k = serve.measure_plain_times(range(k_lo, k_hi + 1), reps=2)
+    torch.cuda.empty_cache()
+    mean_t = serve.expected_service_time(k_lo, k_hi, per_k)
+    rate = 0.8 / mean_t
+    log("plain service time per k (ms): " + ", ".join(f"{k}:{t * 1e3:.2f}" for k, t in per_k.items()))
+    log(f"mean service time {mean_t * 1e3:.2f} ms -> arrival rate {rate:.1f}/s (80% load)")
+    arrivals = serving_arrivals(args.requests, rate)
+    budget = int(args.budget_gb * 2**30)
+
+    def run(slots, max_bypass):
+        ex = serve.GpuExecutor(slots=slots, budget_bytes=budget)
+        st = serve.Server(ex, budget, slots=slots, max_bypass=max_bypass).run(
+            serve.jobs_from_arrivals(arrivals))
+        del ex
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return st
+
+    cb = run(4, 8)
+    log(f"continuous batching: p50 {cb.percentile(50) * 1e3:.1f} ms, p99 {cb.percentile(99) * 1e3:.1f} ms, "
+        f"{cb.plots_per_hour():.0f} plots/h, peak resident {cb.max_resident / 2**30:.1f} GiB")
+    fifo = run(1, 0)
+    log(f"FIFO one at a time:  p50 {fifo.percentile(50) * 1e3:.1f} ms, p99 {fifo.percentile(99) * 1e3:.1f} ms, "
+        f"{fifo.plots_per_hour():.0f} plots/h")
+    return {
+        "metric": "plot serving plots/hour (continuous batching, p50/p99 latency) vs FIFO",
+        "value": round(cb.plots_per_hour(), 1),
+        "unit": "plots/h",
+        "n_gpus": 1, "steps": args.requests, "warmup": 0,
+        "ms_per_step": round(cb.makespan * 1e3 / args.requests, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"serving: {args.requests} Poisson requests (seed 5), k uniform in "
+                               f"{k_lo}..{k_hi}, rate {rate:.1f}/s = 80% of the plain service rate",
+                   "slots": 4, "budget_gib": args.budget_gb, "parallelism": "single GPU"},
+        "p50_latency_ms": round(cb.percentile(50) * 1e3, 2),
+        "p99_latency_ms": round(cb.percentile(99) * 1e3, 2),
+        "fifo_p50_latency_ms": round(fifo.percentile(50) * 1e3, 2),
+        "fifo_p99_latency_ms": round(fifo.percentile(99) * 1e3, 2),
+        "fifo_plots_per_hour": round(fifo.plots_per_hour(), 1),
+        "peak_resident_gib": round(cb.max_resident / 2**30, 2),
+        "max_concurrent": cb.max_concurrent,
+        "plain_ms_per_k": {k: round(t * 1e3, 3) for k, t in per_k.items()},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +213,13 @@ def main() -> int:
     ap.add_argument("--k", type=int, default=31)
     ap.add_argument("--cpu-sample-k", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["k31", "batched", "serving"], default="k31",
+                    help="k31: one whole plot (the default line); batched: the 32-plot mix; "
+                         "serving: Poisson requests through the continuous-batching server")
+    ap.add_argument("--requests", type=int, default=400, help="serving: number of requests")
+    ap.add_argument("--budget-gb", type=float, default=250.0, help="serving: HBM budget (GiB)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batched: use the cached autotuned tuning per k")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 2 GiB device-to-device copy (known bytes) so that "
                          "HBM byte counters can be scaled against it")
@@ -99,6 +231,13 @@ def main() -> int:
               f"multi-GPU path (asked for --gpus {args.gpus}, WORLD_SIZE={world}).",
               file=sys.stderr)
         return 2
+
+    if args.workload in ("batched", "serving"):
+        import torch
+        torch.cuda.set_device(0)
+        fn = bench_batched if args.workload == "batched" else bench_serving
+        print(json.dumps(fn(args)), flush=True)
+        return 0
 
     import torch
     import paper_2606_14007_amd as vx

@@ -169,9 +169,17 @@ vx_status vx_plot(const vx_plot_params *params, const vx_plot_buffers *buffers,
 vx_status vx_plot_with_events(const vx_plot_params *params, const vx_plot_buffers *buffers,
                               const vx_tuning *tuning, void *const *events, void *stream);
 
-/* n independent plots (params[i], buffers[i]) enqueued on one stream; each
- * output equals vx_plot(params[i], buffers[i]).  tuning may be NULL (built-in
- * defaults per k) or an array of n entries. */
+/* n independent plots (params[i], buffers[i]) as one unit of work on
+ * `stream`: the call forks the stream into a few internal lane streams, runs
+ * each lane's plots in order, and joins the lanes back into `stream`, so
+ * that kernels of different plots overlap on the device and a caller can
+ * capture the whole batch into one HIP graph.  Plots whose buffers share the
+ * same workspace run one after another in list order (so one workspace per
+ * lane suffices); other buffers must not overlap.  Each output equals
+ * vx_plot(params[i], buffers[i]).  tuning is NULL (built-in defaults per k)
+ * or an array of n entries.  All plots are validated before anything is
+ * enqueued.  The lane streams are shared per device: batches on one device
+ * must not be captured from two threads at once. */
 vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buffers,
                         uint32_t n, const vx_tuning *tuning, void *stream);
 

@@ -6,6 +6,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
 #include "kernels.h"
 #include "vx.h"
 
@@ -381,6 +385,41 @@ vx_status vx_match_table2(const vx_plot_params *params, const uint64_t *d_t1_key
 
 namespace {
 
+// Internal streams for vx_plot_batch, created once per device at default
+// priority, with the events that fork from and join into the caller's
+// stream.  The mutex serialises enqueuing from different host threads.
+constexpr int kBatchLanes = 4;
+
+struct Lanes {
+    std::mutex mu;
+    bool ready = false;
+    hipStream_t s[kBatchLanes] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kBatchLanes] = {};
+};
+
+constexpr int kMaxDevices = 64;
+Lanes g_lanes[kMaxDevices];
+std::mutex g_lanes_mu;
+
+vx_status lanes_for_current_device(Lanes **out) {
+    int dev = 0;
+    VX_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(VX_ERR_UNSUPPORTED, "device index out of range");
+    Lanes &L = g_lanes[dev];
+    std::lock_guard<std::mutex> guard(g_lanes_mu);
+    if (!L.ready) {
+        for (int l = 0; l < kBatchLanes; ++l) {
+            VX_HIP(hipStreamCreateWithFlags(&L.s[l], hipStreamNonBlocking), "batch stream");
+            VX_HIP(hipEventCreateWithFlags(&L.join[l], hipEventDisableTiming), "batch event");
+        }
+        VX_HIP(hipEventCreateWithFlags(&L.fork, hipEventDisableTiming), "batch event");
+        L.ready = true;
+    }
+    *out = &L;
+    return VX_OK;
+}
+
 vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, const vx_tuning *tuning,
                     hipEvent_t *ev, void *stream) {
     Plan P;
@@ -453,19 +492,69 @@ vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buf
                         const vx_tuning *tuning, void *stream) {
     if (n && (!params || !buffers)) return fail(VX_ERR_INVALID_ARG, "NULL params or buffers");
     // Validate everything before enqueuing anything.
+    std::vector<uint64_t> work(n);
     for (uint32_t i = 0; i < n; ++i) {
         Plan P;
         vx_status st = make_plan(&params[i], tuning ? &tuning[i] : nullptr, &P);
         if (st != VX_OK) return st;
         Layout L = layout(P, VX_CALL_PLOT);
         if ((st = check_ws(L, buffers[i].workspace, buffers[i].workspace_bytes)) != VX_OK) return st;
+        work[i] = P.n;
     }
+    if (n == 0) return VX_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Lanes *ln = nullptr;
+    vx_status st = lanes_for_current_device(&ln);
+    if (st != VX_OK) return st;
+    // Plots that share a workspace form one chain (run in list order); chains
+    // go, largest first, to the least loaded lane.
+    std::vector<int> chain_of(n, -1);
+    std::vector<const void *> chain_ws;
+    std::vector<uint64_t> chain_work;
     for (uint32_t i = 0; i < n; ++i) {
-        vx_status st = vx_plot(&params[i], &buffers[i], tuning ? &tuning[i] : nullptr, stream);
-        if (st != VX_OK) return st;
+        int c = -1;
+        for (size_t j = 0; j < chain_ws.size(); ++j)
+            if (chain_ws[j] == buffers[i].workspace) c = (int)j;
+        if (c < 0) {
+            c = (int)chain_ws.size();
+            chain_ws.push_back(buffers[i].workspace);
+            chain_work.push_back(0);
+        }
+        chain_of[i] = c;
+        chain_work[c] += work[i];
     }
-    g_err[0] = 0;
-    return VX_OK;
+    std::vector<int> order(chain_ws.size());
+    for (size_t j = 0; j < order.size(); ++j) order[j] = (int)j;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return chain_work[x] > chain_work[y]; });
+    std::vector<int> lane_of_chain(chain_ws.size(), 0);
+    uint64_t load[kBatchLanes] = {};
+    for (int c : order) {
+        int best = 0;
+        for (int l = 1; l < kBatchLanes; ++l)
+            if (load[l] < load[best]) best = l;
+        lane_of_chain[c] = best;
+        load[best] += chain_work[c];
+    }
+    std::lock_guard<std::mutex> guard(ln->mu);
+    VX_HIP(hipEventRecord(ln->fork, s), "batch fork");
+    bool used[kBatchLanes] = {};
+    for (uint32_t i = 0; i < n; ++i) used[lane_of_chain[chain_of[i]]] = true;
+    for (int l = 0; l < kBatchLanes; ++l)
+        if (used[l]) VX_HIP(hipStreamWaitEvent(ln->s[l], ln->fork, 0), "batch fork wait");
+    for (uint32_t i = 0; i < n; ++i) {
+        const int l = lane_of_chain[chain_of[i]];
+        st = plot_impl(&params[i], &buffers[i], tuning ? &tuning[i] : nullptr, nullptr, ln->s[l]);
+        if (st != VX_OK) break;
+    }
+    // Join every used lane back into the caller's stream, also on failure, so
+    // the caller's stream never runs ahead of work already enqueued.
+    for (int l = 0; l < kBatchLanes; ++l) {
+        if (!used[l]) continue;
+        VX_HIP(hipEventRecord(ln->join[l], ln->s[l]), "batch join");
+        VX_HIP(hipStreamWaitEvent(s, ln->join[l], 0), "batch join wait");
+    }
+    if (st == VX_OK) g_err[0] = 0;
+    return st;
 }
 
 vx_status vx_read_status(const void *d_workspace, uint32_t *h_status, void *stream) {

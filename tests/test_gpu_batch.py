@@ -1,0 +1,97 @@
+"""Batched plots (vx_plot_batch) and their HIP-graph replay, against the
+oracle and against solo vx_plot runs -- bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+from vx_inputs import PlotSpec, batched_plan, derive_key
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_14007_amd as m
+    m.lib()
+    return m
+
+
+def _specs():
+    # uneven k, independent keys, one threshold widened so Table 2 is busy
+    ks = [16, 10, 18, 13, 17, 12, 15, 14]
+    out = [PlotSpec(k=k, key=derive_key(100 + i)) for i, k in enumerate(ks)]
+    return out
+
+
+def _check(vx, b, ref):
+    assert np.array_equal(vx.u64(b.t1_keys), ref.t1_keys)
+    assert np.array_equal(vx.u32(b.t1_nonces), ref.t1_nonces)
+    assert np.array_equal(vx.u32(b.bucket_offsets), ref.offsets)
+    cnt = vx.t2_count(b)
+    assert cnt == len(ref.t2)
+    assert np.array_equal(vx.t2_records(b.t2, cnt), ref.t2)
+
+
+@pytest.fixture(scope="module")
+def refs():
+    return [oracle.plot(s.key, s.k, threads=8) for s in _specs()]
+
+
+def test_batch_equals_oracle(vx, refs):
+    from paper_2606_14007_amd import batch as B
+    bt = B.alloc_batch(_specs())
+    assert len(set(w.data_ptr() for w in bt.workspaces)) <= B.LANES
+    B.plot_batch(bt)
+    torch.cuda.synchronize()
+    for b, ref in zip(bt.plots, refs):
+        _check(vx, b, ref)
+
+
+def test_batch_with_tunings_and_two_lanes(vx, refs):
+    from paper_2606_14007_amd import batch as B
+    specs = _specs()
+    tun = [vx.make_tuning(group_cap=128) if i % 2 else vx.make_tuning(match_chunk_bits=7)
+           for i in range(len(specs))]
+    bt = B.alloc_batch(specs, tunings=tun, lanes=2)
+    B.plot_batch(bt)
+    torch.cuda.synchronize()
+    for b, ref in zip(bt.plots, refs):
+        _check(vx, b, ref)
+
+
+def test_batch_equals_solo_plots(vx):
+    from paper_2606_14007_amd import batch as B
+    specs = [PlotSpec(k=s.k, key=s.key) for s in batched_plan(6, k_lo=14, k_hi=20)]
+    bt = B.alloc_batch(specs)
+    B.plot_batch(bt)
+    solo = [vx.plot(s.key, s.k) for s in specs]
+    torch.cuda.synchronize()
+    for a, b in zip(bt.plots, solo):
+        assert torch.equal(a.t1_keys, b.t1_keys) and torch.equal(a.t1_nonces, b.t1_nonces)
+        assert torch.equal(a.bucket_offsets, b.bucket_offsets)
+        n = vx.t2_count(b)
+        assert vx.t2_count(a) == n and torch.equal(a.t2[:n], b.t2[:n])
+
+
+def test_graph_replay_recomputes_every_time(vx, refs):
+    """Capture once, then replay three times; before each replay the outputs
+    are wiped and unrelated eager work runs, and every replay is checked."""
+    from paper_2606_14007_amd import batch as B
+    bt = B.capture(B.alloc_batch(_specs()))
+    for r in range(3):
+        for b in bt.plots:
+            b.t1_keys.fill_(-1)
+            b.t1_nonces.fill_(-1)
+            b.t2.fill_(-1)
+            b.t2_count.zero_()
+        other = vx.plot(derive_key(900 + r), 12)  # eager work between replays
+        torch.cuda.synchronize()
+        B.replay(bt)
+        torch.cuda.synchronize()
+        for b, ref in zip(bt.plots, refs):
+            _check(vx, b, ref)
+        assert vx.t2_count(other) >= 0

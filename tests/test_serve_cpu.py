@@ -1,0 +1,127 @@
+"""The serving scheduler on the CPU, with a simulated executor and a
+virtual clock: admission by footprint, budget, ordering, bounded backfill,
+latency statistics.  No GPU."""
+import math
+
+import pytest
+
+from paper_2606_14007_amd.serve import Executor, Job, Server, Stats, jobs_from_arrivals
+from vx_inputs import serving_arrivals
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def now(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-5)
+
+
+class FakeExecutor(Executor):
+    """Job of size k takes 2^(k-20) ms of device time; running jobs share the
+    device (processor sharing) up to `parallel` at full speed each."""
+
+    def __init__(self, clock, parallel=2.0, fp_per_record=48):
+        self.clock = clock
+        self.parallel = parallel
+        self.fp = fp_per_record
+        self.running = {}
+        self.resident = 0
+        self.peak = 0
+        self.order = []
+
+    def footprint(self, k):
+        return (1 << k) * self.fp
+
+    def _advance(self):
+        now = self.clock.now()
+        dt = now - getattr(self, "_last", now)
+        self._last = now
+        if self.running:
+            rate = min(1.0, self.parallel / len(self.running))
+            for h in self.running:
+                self.running[h] -= dt * rate
+
+    def submit(self, job, slot):
+        self._advance()
+        h = object()
+        self.running[h] = 2.0 ** (job.k - 20) * 1e-3
+        self.resident += self.footprint(job.k)
+        self.peak = max(self.peak, self.resident)
+        self.order.append(job.jid)
+        return h
+
+    def poll(self, h):
+        self._advance()
+        if self.running[h] <= 0:
+            del self.running[h]
+            return True
+        return False
+
+    def release(self, job):
+        self.resident -= self.footprint(job.k)
+
+
+def _run(jobs, slots, budget, **kw):
+    c = Clock()
+    ex = FakeExecutor(c)
+    srv = Server(ex, budget, slots=slots, clock=c.now, sleep=c.sleep, **kw)
+    return srv.run(jobs), ex
+
+
+def test_all_jobs_complete_and_respect_arrival_and_budget():
+    arr = serving_arrivals(200, rate_per_s=300.0, k_lo=18, k_hi=24)
+    jobs = jobs_from_arrivals(arr)
+    budget = (1 << 24) * 48 * 3
+    st, ex = _run(jobs, slots=4, budget=budget)
+    assert len(st.jobs) == 200
+    assert all(j.admitted >= j.arrival - 1e-9 and j.finished >= j.admitted for j in st.jobs)
+    assert ex.peak <= budget and st.max_resident <= budget
+    assert st.max_concurrent <= 4
+
+
+def test_single_slot_is_fifo():
+    jobs = jobs_from_arrivals(serving_arrivals(60, rate_per_s=500.0, k_lo=18, k_hi=22))
+    st, ex = _run(jobs, slots=1, budget=1 << 40, max_bypass=0)
+    assert ex.order == sorted(ex.order)
+    assert st.max_concurrent == 1
+
+
+def test_continuous_batching_beats_fifo_latency():
+    arr = serving_arrivals(300, rate_per_s=400.0, k_lo=18, k_hi=23)
+    fifo, _ = _run(jobs_from_arrivals(arr), slots=1, budget=1 << 40, max_bypass=0)
+    cb, _ = _run(jobs_from_arrivals(arr), slots=4, budget=1 << 40)
+    assert cb.percentile(50) < fifo.percentile(50)
+    assert cb.percentile(99) < fifo.percentile(99)
+    assert cb.plots_per_hour() >= fifo.plots_per_hour()
+
+
+def test_backfill_is_bounded_so_big_jobs_do_not_starve():
+    big = Job(0, 24, b"\x00" * 32, 0.0)
+    small = [Job(i, 18, b"\x01" * 32, 0.0001 * i) for i in range(1, 200)]
+    filler = Job(999, 23, b"\x02" * 32, 0.0)
+    budget = ((1 << 24) + (1 << 23)) * 48 - 1  # big + filler do not fit together
+    st, ex = _run([filler, big] + small, slots=3, budget=budget, max_bypass=5)
+    pos = ex.order.index(0)
+    assert big.bypassed <= 5
+    assert pos <= 2 + 5 + 3  # admitted soon after the filler leaves
+
+
+def test_job_larger_than_budget_is_rejected():
+    with pytest.raises(ValueError):
+        _run([Job(0, 25, b"\x00" * 32, 0.0)], slots=1, budget=1000)
+
+
+def test_percentiles():
+    jobs = []
+    for i in range(100):
+        j = Job(i, 10, b"", 0.0)
+        j.finished = (i + 1) / 100.0
+        jobs.append(j)
+    st = Stats(jobs, makespan=1.0, max_resident=0, max_concurrent=1)
+    assert math.isclose(st.percentile(50), 0.50)
+    assert math.isclose(st.percentile(99), 0.99)
+    assert math.isclose(st.plots_per_hour(), 360000.0)
