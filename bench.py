@@ -202,6 +202,8 @@ def bench_serving(args) -> dict:
         "peak_resident_gib": round(cb.max_resident / 2**30, 2),
         "max_concurrent": cb.max_concurrent,
         "plain_ms_per_k": {k: round(t * 1e3, 3) for k, t in per_k.items()},
+        "p50_ms_per_k": {k: round(v["p50_ms"], 2) for k, v in cb.by_k().items()},
+        "fifo_p50_ms_per_k": {k: round(v["p50_ms"], 2) for k, v in fifo.by_k().items()},
     }
 
 

@@ -5,11 +5,13 @@ order as soon as an execution slot is free and the job's device footprint
 (Table 1 + Table 2 capacity + offsets + workspace) fits the HBM budget next
 to everything resident.  Each admitted job runs on its own stream, so jobs
 overlap on the device; finished jobs keep their tables on the device until
-their result is consumed, and then their buffers return to a per-k pool
-for reuse.  If the oldest waiting job does not fit, later jobs that do fit
-may go first ("backfill"), which keeps the GPU busy without letting a large
-job starve: a job that has been passed over `max_bypass` times blocks
-backfill until it runs.
+their result is consumed, and then their memory is returned.  On the GPU
+all plot buffers are carved from one arena allocated up front, so serving
+never allocates or frees device memory (a free would synchronise every
+stream).  If the oldest waiting job does not fit, later jobs that do fit may
+go first ("backfill"), which keeps the GPU busy without letting a large job
+starve: a job that has been passed over `max_bypass` times blocks backfill
+until it runs.
 
 The scheduler is written against a small executor interface (footprint /
 submit / poll / release) so that the same loop drives the GPU executor
@@ -17,7 +19,6 @@ below or a simulated one in CPU tests.
 """
 from __future__ import annotations
 
-import heapq
 import math
 import time
 from dataclasses import dataclass, field
@@ -57,6 +58,10 @@ class Executor:
     def release(self, job: Job) -> None:
         raise NotImplementedError
 
+    def can_admit(self, k: int, resident: int, budget: int) -> bool:
+        """Whether a job of size k may start now (default: bytes fit the budget)."""
+        return resident + self.footprint(k) <= budget
+
 
 @dataclass
 class Stats:
@@ -77,6 +82,12 @@ class Stats:
 
     def plots_per_hour(self) -> float:
         return len(self.jobs) * 3600.0 / self.makespan if self.makespan > 0 else float("nan")
+
+    def by_k(self) -> Dict[int, Dict[str, float]]:
+        out: Dict[int, list] = {}
+        for j in self.jobs:
+            out.setdefault(j.k, []).append(j.latency)
+        return {k: {"n": len(v), "p50_ms": sorted(v)[len(v) // 2] * 1e3} for k, v in sorted(out.items())}
 
 
 class Server:
@@ -132,7 +143,7 @@ class Server:
             while free_slots and i < len(waiting):
                 job = waiting[i]
                 need = self.ex.footprint(job.k)
-                if resident + need <= self.budget:
+                if self.ex.can_admit(job.k, resident, self.budget):
                     slot = free_slots.pop(0)
                     job.admitted = self.clock() - t0
                     job.handle = self.ex.submit(job, slot)
@@ -147,7 +158,7 @@ class Server:
                 if job.bypassed >= self.max_bypass:
                     break
                 for later in waiting[i + 1:]:
-                    if resident + self.ex.footprint(later.k) <= self.budget:
+                    if self.ex.can_admit(later.k, resident, self.budget):
                         job.bypassed += 1
                         break
                 i += 1
@@ -165,63 +176,124 @@ class Server:
 # GPU executor
 # ---------------------------------------------------------------------------
 
+class Arena:
+    """First-fit sub-allocator over one preallocated device byte range, with
+    coalescing of free neighbours.  Host-side bookkeeping only: serving never
+    calls the device allocator, so no allocation or free can stall streams."""
+
+    ALIGN = 2 << 20
+
+    def __init__(self, size: int):
+        self.size = size // self.ALIGN * self.ALIGN
+        self.free = [(0, self.size)]      # sorted (offset, length)
+
+    def alloc(self, nbytes: int) -> Optional[int]:
+        n = -(-nbytes // self.ALIGN) * self.ALIGN
+        for i, (off, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (off + n, ln - n)
+                return off
+        return None
+
+    def can_alloc(self, nbytes: int) -> bool:
+        n = -(-nbytes // self.ALIGN) * self.ALIGN
+        return any(ln >= n for _, ln in self.free)
+
+    def release(self, off: int, nbytes: int) -> None:
+        n = -(-nbytes // self.ALIGN) * self.ALIGN
+        self.free.append((off, n))
+        self.free.sort()
+        merged = []
+        for o, ln in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((o, ln))
+        self.free = merged
+
+
 class GpuExecutor(Executor):
-    """Runs each job as one vx_plot on the stream of its slot.  Buffers come
-    from a per-k pool; idle pooled buffers count against the budget only
-    while they exist, and are dropped (largest first) when a new allocation
-    would not fit."""
+    """Runs each job as one vx_plot on the stream of its slot.  All plot
+    buffers are carved from one device arena allocated up front (the HBM
+    budget), so admission is "a contiguous block of the job's footprint is
+    free", and finished jobs' tables stay in place until released."""
 
     def __init__(self, slots: int, budget_bytes: int, tuning_for_k=None, device=None):
         import torch
         from . import plotter as P
+        from . import _native as N
         self.torch = torch
         self.P = P
+        self.N = N
         self.device = P._dev(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
-        self.budget = budget_bytes
-        self.pool: Dict[int, list] = {}
+        self.arena = Arena(budget_bytes)
+        self.mem = torch.empty(self.arena.size, dtype=torch.uint8, device=self.device)
         self.tuning_for_k = tuning_for_k or (lambda k: None)
         self._fp: Dict[int, int] = {}
+        self._layout: Dict[int, tuple] = {}
+
+    def _plan(self, k: int):
+        if k not in self._layout:
+            N = self.N
+            p = N.make_params(bytes(32), k)
+            cap = N.vx_t2_capacity_hint(k, p.match_threshold)
+            ws = N.vx_workspace_bytes(p, N.VX_CALL_PLOT, self.tuning_for_k(k))
+            n = 1 << k
+            parts = [("t1_keys", n * 8), ("t1_nonces", n * 4), ("bucket_offsets", (N.VX_NUM_BUCKETS + 1) * 4),
+                     ("t2", cap * 16), ("t2_count", 8), ("workspace", ws)]
+            offs, at = {}, 0
+            for name, nb in parts:
+                offs[name] = (at, nb)
+                at += -(-nb // 256) * 256
+            self._layout[k] = (offs, at, cap)
+            self._fp[k] = at
+        return self._layout[k]
 
     def footprint(self, k: int) -> int:
-        if k not in self._fp:
-            self._fp[k] = self.P.footprint_bytes(k, tuning=self.tuning_for_k(k))
-        return self._fp[k]
+        return self._plan(k)[1]
 
-    def _idle_bytes(self) -> int:
-        return sum(self.footprint(k) * len(v) for k, v in self.pool.items())
+    def can_admit(self, k: int, resident: int, budget: int) -> bool:
+        return self.arena.can_alloc(self.footprint(k))
 
-    def _buffers(self, k: int, in_use: int):
-        if self.pool.get(k):
-            return self.pool[k].pop()
-        # make room among idle pooled buffers if needed
-        while in_use + self._idle_bytes() + self.footprint(k) > self.budget:
-            ks = [kk for kk, v in self.pool.items() if v]
-            if not ks:
-                break
-            self.pool[max(ks)].pop()
-        return self.P.alloc_plot(k, tuning=self.tuning_for_k(k), device=self.device)
+    def _view(self, base: int, off_nb, dtype, shape=None):
+        off, nb = off_nb
+        t = self.mem.narrow(0, base + off, nb).view(dtype)
+        return t.view(shape) if shape else t
 
     def submit(self, job: Job, slot: int):
-        from . import _native as N
-        torch = self.torch
-        in_use = getattr(self, "_in_use", 0)
-        buf = self._buffers(job.k, in_use)
-        self._in_use = in_use + self.footprint(job.k)
+        torch, N = self.torch, self.N
+        offs, total, cap = self._plan(job.k)
+        base = self.arena.alloc(total)
+        if base is None:
+            raise RuntimeError("arena full: admission and allocation disagree")
+        buf = self.P.PlotBuffers(
+            k=job.k,
+            t1_keys=self._view(base, offs["t1_keys"], torch.int64),
+            t1_nonces=self._view(base, offs["t1_nonces"], torch.int32),
+            bucket_offsets=self._view(base, offs["bucket_offsets"], torch.int32),
+            t2=self._view(base, offs["t2"], torch.int64, (cap, 2)),
+            t2_count=self._view(base, offs["t2_count"], torch.int64),
+            workspace=self._view(base, offs["workspace"], torch.uint8),
+        )
         s = self.streams[slot]
         params = N.make_params(job.key, job.k, job.threshold)
         N.vx_plot(params, buf.native(), self.tuning_for_k(job.k), s.cuda_stream)
         ev = torch.cuda.Event()
         ev.record(s)
         job.result = buf
+        job._arena = (base, total)
         return ev
 
     def poll(self, handle) -> bool:
         return handle.query()
 
     def release(self, job: Job) -> None:
-        self._in_use -= self.footprint(job.k)
-        self.pool.setdefault(job.k, []).append(job.result)
+        base, total = job._arena
+        self.arena.release(base, total)
         job.result = None
 
 

@@ -125,3 +125,21 @@ def test_percentiles():
     assert math.isclose(st.percentile(50), 0.50)
     assert math.isclose(st.percentile(99), 0.99)
     assert math.isclose(st.plots_per_hour(), 360000.0)
+
+
+def test_arena_first_fit_and_coalescing():
+    from paper_2606_14007_amd.serve import Arena
+    A = Arena.ALIGN
+    a = Arena(10 * A)
+    x = a.alloc(3 * A)
+    y = a.alloc(1)            # rounds up to one unit
+    z = a.alloc(4 * A)
+    assert (x, y, z) == (0, 3 * A, 4 * A)
+    assert not a.can_alloc(3 * A) and a.can_alloc(2 * A)
+    a.release(y, 1)
+    a.release(x, 3 * A)       # coalesces with y's unit into 4 units at 0
+    assert a.free[0] == (0, 4 * A)
+    assert a.alloc(4 * A) == 0
+    a.release(0, 4 * A)
+    a.release(z, 4 * A)
+    assert a.free == [(0, 10 * A)]
