@@ -104,7 +104,7 @@ typedef struct {
 typedef struct {
     uint32_t group_bits;   /* sort groups = 2^group_bits key prefixes, 1..24 */
     uint32_t pass1_bits;   /* digit bits of the first partition pass, 1..11 */
-    uint32_t group_cap;    /* records a group may hold in LDS, 64..4096 */
+    uint32_t group_cap;    /* records a group may hold in LDS, 64..3072 */
     uint32_t h1_tiles;     /* work-groups of the hash + first partition pass */
     uint32_t match_chunk_bits; /* match works on chunks of 2^bits Table-1 records, 6..11 */
     uint32_t pass2_bits;   /* digit bits of the second pass (a third takes the rest) */

@@ -123,7 +123,7 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl) {
         P.Q[i] = clampu((int64_t)((P.n >> P.pre[i]) >> 17), 1, 64);
     P.cap = t->group_cap ? t->group_cap : (uint32_t)vxk::kGroupCapMax;
     if (P.cap < 64 || P.cap > (uint32_t)vxk::kGroupCapMax)
-        return fail(VX_ERR_UNSUPPORTED, "group_cap must be in [64, 4096]");
+        return fail(VX_ERR_UNSUPPORTED, "group_cap must be in [64, 3072]");
     P.cb = t->match_chunk_bits ? t->match_chunk_bits : (uint32_t)vxk::kMatchChunkBitsMax;
     if (P.cb < 6 || P.cb > (uint32_t)vxk::kMatchChunkBitsMax)
         return fail(VX_ERR_UNSUPPORTED, "match_chunk_bits must be in [6, 11]");

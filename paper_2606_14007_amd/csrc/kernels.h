@@ -13,7 +13,7 @@
 namespace vxk {
 
 constexpr int kMaxDigitBits = 11;     // widest partition digit (LDS histograms)
-constexpr int kGroupCapMax = 4096;    // records a sort group may hold in LDS
+constexpr int kGroupCapMax = 3072;    // records a sort group may hold in LDS
 constexpr uint32_t kFallbackMax = 1u << 20;  // largest group the fallback sorts
 constexpr int kMatchChunkBitsMax = 11;  // match chunk = 2^bits records (LDS capacity 2048)
 

@@ -255,22 +255,22 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ 
         if (tid == 0) s_start[nd] = total;
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const uint64_t idx = base + (uint64_t)j * BLOCK + tid;
-            if (idx < hi) {
-                const uint32_t p = s_start[(uint32_t)(k[j] >> shift) & mask] + slot[j];
-                s_keys[p] = k[j];
-                s_nonces[p] = n[j];
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint64_t idx = base + (uint64_t)j * BLOCK + tid;
+                if (idx < hi) {
+                    const uint32_t p = s_start[(uint32_t)(k[j] >> shift) & mask] + slot[j];
+                    s_keys[p] = k[j];
+                    s_nonces[p] = n[j];
+                }
             }
-        }
-        __syncthreads();
-        for (uint32_t e = tid; e < total; e += BLOCK) {
-            const uint64_t kk = s_keys[e];
-            const uint32_t d = (uint32_t)(kk >> shift) & mask;
-            const uint64_t g = (uint64_t)s_cursor[d] + (e - s_start[d]);
-            out_keys[g] = kk;
-            out_nonces[g] = s_nonces[e];
-        }
+            __syncthreads();
+            for (uint32_t e = tid; e < total; e += BLOCK) {
+                const uint64_t kk = s_keys[e];
+                const uint32_t d = (uint32_t)(kk >> shift) & mask;
+                const uint64_t g = (uint64_t)s_cursor[d] + (e - s_start[d]);
+                out_keys[g] = kk;
+                out_nonces[g] = s_nonces[e];
+            }
         __syncthreads();
         for (uint32_t d = tid; d < nd; d += BLOCK) s_cursor[d] += s_start[d + 1] - s_start[d];
         __syncthreads();
@@ -342,6 +342,9 @@ __device__ __forceinline__ void add_chunk_pairs(const uint64_t *keys, uint32_t l
     }
 }
 
+// Persistent: work-group w sorts groups w, w + gridDim.x, ...; the records
+// of the next group are loaded into registers while the current one is
+// sorted, so the group's global loads overlap LDS work.
 template <int BLOCK, int CAPMAX>
 __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys,
                                                      uint32_t *__restrict__ nonces,
@@ -359,83 +362,123 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys
     __shared__ uint32_t s_start[kSubBins + 1];
     __shared__ uint64_t s_wave[BLOCK / 64 + 1];
     uint32_t *s_wave32 = reinterpret_cast<uint32_t *>(s_wave);
-    const uint32_t g = blockIdx.x, tid = threadIdx.x;
-    const uint32_t lo = gstart[g], hi = gstart[g + 1], n = hi - lo;
-    if (g == gridDim.x - 1 && tid == 0) offsets[VXK_NUM_BUCKETS] = n_total;
-    if (n > cap) {
-        if (tid == 0) {
-            const uint32_t i = atomicAdd(ovf_count, 1u);
-            ovf_list[i] = g;
-        }
-        return;
-    }
-    for (uint32_t i = tid; i < kSubBins; i += BLOCK) s_start[i] = 0;
-    __syncthreads();
+    const uint32_t tid = threadIdx.x;
+    const uint32_t ngroups = 1u << G;
     const uint32_t sb_shift = 64u - G - kSubBinBits;
-    uint64_t k[ITEMS];
-    uint32_t nn[ITEMS], slot[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t e = j * BLOCK + tid;
-        if (e < n) {
-            k[j] = keys[lo + e];
-            nn[j] = nonces[lo + e];
-            slot[j] = atomicAdd(&s_start[(uint32_t)(k[j] >> sb_shift) & (kSubBins - 1)], 1u);
-        }
-    }
-    __syncthreads();
-    vxd::lds_exclusive_scan<BLOCK>(s_start, kSubBins, s_wave32);
-    if (tid == 0) s_start[kSubBins] = n;
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t e = j * BLOCK + tid;
-        if (e < n) {
-            const uint32_t p = s_start[(uint32_t)(k[j] >> sb_shift) & (kSubBins - 1)] + slot[j];
-            s_keys[p] = k[j];
-            s_nonces[p] = nn[j];
-        }
-    }
-    __syncthreads();
-    // Exact rank inside the sub-bin; slot[] is reused for the final position.
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t e = j * BLOCK + tid;
-        if (e < n) {
-            const uint32_t sb = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
-            const uint32_t b0 = s_start[sb], b1 = s_start[sb + 1];
-            uint32_t r = 0;
-            for (uint32_t x = b0; x < b1; ++x) r += rec_less(s_keys[x], s_nonces[x], k[j], nn[j]);
-            slot[j] = b0 + r;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t e = j * BLOCK + tid;
-        if (e < n) {
-            s_keys[slot[j]] = k[j];
-            s_nonces[slot[j]] = nn[j];
-        }
-    }
-    __syncthreads();
-    for (uint32_t e = tid; e < n; e += BLOCK) {
-        keys[lo + e] = s_keys[e];
-        nonces[lo + e] = s_nonces[e];
-    }
-    // offsets[b] for the group's buckets: first record with bucket >= b.
     const uint32_t nbg = 1u << (VXK_BUCKET_BITS - G);
-    const uint32_t bfirst = g << (VXK_BUCKET_BITS - G);
-    for (uint32_t bl = tid; bl < nbg; bl += BLOCK) {
-        const uint32_t b = bfirst + bl;
-        uint32_t a = 0, c = n;
-        while (a < c) {
-            const uint32_t mid = (a + c) >> 1;
-            if ((uint32_t)(s_keys[mid] >> 40) < b) a = mid + 1; else c = mid;
+    if (blockIdx.x == 0 && tid == 0) offsets[VXK_NUM_BUCKETS] = n_total;
+    uint32_t g = blockIdx.x;
+    if (g >= ngroups) return;
+    uint32_t lo = gstart[g], n = gstart[g + 1] - lo;
+    uint64_t pk[ITEMS];
+    uint32_t pn[ITEMS];
+    if (n <= cap) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t e = j * BLOCK + tid;
+            if (e < n) {
+                pk[j] = keys[lo + e];
+                pn[j] = nonces[lo + e];
+            }
         }
-        offsets[b] = lo + a;
     }
-    if (chunk_count && n) add_chunk_pairs<BLOCK>(s_keys, lo, n, T, chunk_count, chunk_bits, s_wave);
+    while (true) {
+        uint64_t k[ITEMS];
+        uint32_t nn[ITEMS], slot[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            k[j] = pk[j];
+            nn[j] = pn[j];
+        }
+        // Prefetch the next group of this work-group.
+        const uint32_t g2 = g + gridDim.x;
+        uint32_t lo2 = 0, n2 = 0;
+        if (g2 < ngroups) {
+            lo2 = gstart[g2];
+            n2 = gstart[g2 + 1] - lo2;
+            if (n2 <= cap) {
+#pragma unroll
+                for (int j = 0; j < ITEMS; ++j) {
+                    const uint32_t e = j * BLOCK + tid;
+                    if (e < n2) {
+                        pk[j] = keys[lo2 + e];
+                        pn[j] = nonces[lo2 + e];
+                    }
+                }
+            }
+        }
+        if (n > cap) {
+            if (tid == 0) {
+                const uint32_t i = atomicAdd(ovf_count, 1u);
+                ovf_list[i] = g;
+            }
+        } else {
+            for (uint32_t i = tid; i < kSubBins; i += BLOCK) s_start[i] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t e = j * BLOCK + tid;
+                if (e < n) slot[j] = atomicAdd(&s_start[(uint32_t)(k[j] >> sb_shift) & (kSubBins - 1)], 1u);
+            }
+            __syncthreads();
+            vxd::lds_exclusive_scan<BLOCK>(s_start, kSubBins, s_wave32);
+            if (tid == 0) s_start[kSubBins] = n;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t e = j * BLOCK + tid;
+                if (e < n) {
+                    const uint32_t q = s_start[(uint32_t)(k[j] >> sb_shift) & (kSubBins - 1)] + slot[j];
+                    s_keys[q] = k[j];
+                    s_nonces[q] = nn[j];
+                }
+            }
+            __syncthreads();
+            // Exact rank inside the sub-bin; slot[] is reused for the final position.
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t e = j * BLOCK + tid;
+                if (e < n) {
+                    const uint32_t sb = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
+                    const uint32_t b0 = s_start[sb], b1 = s_start[sb + 1];
+                    uint32_t r = 0;
+                    for (uint32_t x = b0; x < b1; ++x) r += rec_less(s_keys[x], s_nonces[x], k[j], nn[j]);
+                    slot[j] = b0 + r;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t e = j * BLOCK + tid;
+                if (e < n) {
+                    s_keys[slot[j]] = k[j];
+                    s_nonces[slot[j]] = nn[j];
+                }
+            }
+            __syncthreads();
+            for (uint32_t e = tid; e < n; e += BLOCK) {
+                keys[lo + e] = s_keys[e];
+                nonces[lo + e] = s_nonces[e];
+            }
+            // offsets[b] for the group's buckets: first record with bucket >= b.
+            const uint32_t bfirst = g << (VXK_BUCKET_BITS - G);
+            for (uint32_t bl = tid; bl < nbg; bl += BLOCK) {
+                const uint32_t b = bfirst + bl;
+                uint32_t a = 0, c = n;
+                while (a < c) {
+                    const uint32_t mid = (a + c) >> 1;
+                    if ((uint32_t)(s_keys[mid] >> 40) < b) a = mid + 1; else c = mid;
+                }
+                offsets[b] = lo + a;
+            }
+            if (chunk_count && n) add_chunk_pairs<BLOCK>(s_keys, lo, n, T, chunk_count, chunk_bits, s_wave);
+            __syncthreads();
+        }
+        if (g2 >= ngroups) break;
+        g = g2;
+        lo = lo2;
+        n = n2;
+    }
 }
 
 // Groups larger than the LDS capacity: rank sort against LDS-staged tiles of
@@ -1042,6 +1085,19 @@ __global__ void k_reset_words(uint32_t *__restrict__ p, uint32_t n) {
 // Host-side launchers.
 // ---------------------------------------------------------------------------
 
+// Work-groups of `kernel` that are resident on the whole device at once:
+// persistent kernels are launched with exactly this many, so none waits for
+// a second round (a late round would leave most CUs idle at the tail).
+template <typename K>
+static uint32_t resident_grid(K kernel, int block) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return (uint32_t)(cus * per_cu);
+}
+
 static TileGeom geom_chunks(uint64_t n, uint64_t chunk) {
     TileGeom g;
     g.mode = 0;
@@ -1071,8 +1127,6 @@ constexpr int kFallbackGrid = 256;
 constexpr int kMatchBlock = 512;
 constexpr int kMatchCap = 2048;
 constexpr int kMatchWindow = 2048;
-constexpr int kMatchGrid = 256 * 2 * 2;  // persistent: two rounds of two work-groups per CU
-constexpr int kSortMatchGrid = 256 * 2;  // persistent: two work-groups per CU
 
 hipError_t launch_reset(uint32_t *words, uint32_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_words, dim3(1), dim3(256), 0, s, words, n);
@@ -1145,7 +1199,9 @@ hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint32_t *gs
                             uint32_t cap, uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count,
                             uint32_t *ovf_list, uint64_t T, uint64_t *chunk_count, uint32_t chunk_bits,
                             hipStream_t s) {
-    hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapMax>), dim3(1u << G), dim3(kSortBlock), 0, s,
+    static const uint32_t resident = resident_grid(k_groupsort<kSortBlock, kGroupCapMax>, kSortBlock);
+    const uint32_t grid = min(1u << G, resident);
+    hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapMax>), dim3(grid), dim3(kSortBlock), 0, s,
                        keys, nonces, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T,
                        chunk_count, chunk_bits);
     return hipGetLastError();
@@ -1165,7 +1221,8 @@ hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, uint64_t *scr
 hipError_t launch_match_count(const uint64_t *keys, uint32_t n_total, uint32_t chunk_bits, uint64_t T,
                               uint64_t *counts, hipStream_t s) {
     const uint32_t nchunks = (n_total + (1u << chunk_bits) - 1) >> chunk_bits;
-    const uint32_t grid = min(nchunks, (uint32_t)kMatchGrid * 4);
+    static const uint32_t resident = resident_grid(k_match_count<kMatchBlock, kMatchCap>, kMatchBlock);
+    const uint32_t grid = min(nchunks, resident);
     hipLaunchKernelGGL((k_match_count<kMatchBlock, kMatchCap>), dim3(grid), dim3(kMatchBlock), 0, s,
                        keys, n_total, chunk_bits, T, counts);
     return hipGetLastError();
@@ -1188,7 +1245,8 @@ hipError_t launch_match_emit(const uint32_t key_words[8], const uint64_t *keys, 
     Key key;
     for (int i = 0; i < 8; ++i) key.w[i] = key_words[i];
     const uint32_t nchunks = (n_total + (1u << chunk_bits) - 1) >> chunk_bits;
-    const uint32_t grid = min(nchunks, (uint32_t)kMatchGrid);
+    static const uint32_t resident = resident_grid(k_match_emit<kMatchBlock, kMatchCap>, kMatchBlock);
+    const uint32_t grid = min(nchunks, resident);
     hipLaunchKernelGGL((k_match_emit<kMatchBlock, kMatchCap>), dim3(grid), dim3(kMatchBlock),
                        0, s, key, keys, nonces, n_total, chunk_bits, T, chunk_base, (uint4 *)t2, cap);
     return hipGetLastError();
@@ -1201,7 +1259,9 @@ hipError_t launch_sort_match(const uint32_t key_words[8], uint64_t *keys, uint32
                              uint64_t *t2_count, uint32_t spin_limit, hipStream_t s) {
     Key key;
     for (int i = 0; i < 8; ++i) key.w[i] = key_words[i];
-    const uint32_t grid = min(1u << G, (uint32_t)kSortMatchGrid);
+    static const uint32_t resident =
+        resident_grid(k_sort_match<kSortBlock, kGroupCapMax, kMatchWindow>, kSortBlock);
+    const uint32_t grid = min(1u << G, resident);
     hipLaunchKernelGGL((k_sort_match<kSortBlock, kGroupCapMax, kMatchWindow>), dim3(grid), dim3(kSortBlock),
                        0, s, key, keys, nonces, scr_keys, scr_nonces, gstart, G, cap, offsets, n_total, T,
                        ticket, words, dev_status, (uint4 *)t2, t2cap, t2_count, spin_limit,
