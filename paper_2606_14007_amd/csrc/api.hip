@@ -143,6 +143,7 @@ struct Layout {
     size_t ovf_list = 0;          // u32[2^G]
     size_t lbwords = 0;           // u64[2^G] look-back words of the fused sort + match
     size_t mcount = 0, mbase = 0; // u64[match chunks]: pair counts, Table-2 bases
+    size_t pcnt = 0;              // u8[n]: pair count of each Table-1 record (255 = look again)
     size_t mpart = 0;             // u64[scan parts]
     size_t total = 0;
 };
@@ -185,6 +186,7 @@ Layout layout(const Plan &P, int which) {
         L.mcount = take((size_t)nch * 8);
         L.mbase = take((size_t)nch * 8);
         L.mpart = take((size_t)vxk::scan_parts(nch) * 8);
+        L.pcnt = take(align_up(P.n, 4));
     }
     L.total = at;
     return L;
@@ -252,37 +254,41 @@ vx_status run_partition(const Plan &P, const Layout &L, void *ws, const uint64_t
 
 // In-place group sort of the partitioned Table 1 (+ oversized groups), with
 // bucket offsets.  chunk_count (may be NULL) receives the Table-2 pair count
-// of each match chunk of the sorted table.
+// of each match chunk of the sorted table, and then the workspace's count
+// bytes receive the pair count of each record.
 vx_status run_group_sort(const Plan &P, const Layout &L, void *ws, uint64_t *t1_keys,
                          uint32_t *t1_nonces, uint32_t *offsets, uint64_t *chunk_count, hipStream_t s,
                          hipEvent_t *ev) {
+    uint8_t *pcnt = chunk_count ? at<uint8_t>(ws, L.pcnt) : nullptr;
     uint32_t *hdr = at<uint32_t>(ws, L.header);
     const uint32_t *gstart = at<uint32_t>(ws, L.gstart[P.npass - 1]);
     if (chunk_count) VX_HIP(vxk::launch_zero_u64(chunk_count, match_chunks(P), s), "zero counts");
     VX_HIP(vxk::launch_groupsort(t1_keys, t1_nonces, gstart, P.G, P.cap, offsets, (uint32_t)P.n,
-                                 hdr + 1, at<uint32_t>(ws, L.ovf_list), P.T, chunk_count, P.cb, s),
+                                 hdr + 1, at<uint32_t>(ws, L.ovf_list), P.T, chunk_count, P.cb, pcnt, s),
            "group sort");
     VX_HIP(vxk::launch_group_fallback(t1_keys, t1_nonces, at<uint64_t>(ws, L.scr_keys),
                                       at<uint32_t>(ws, L.scr_nonces), gstart, P.G, offsets, hdr + 1,
-                                      at<uint32_t>(ws, L.ovf_list), hdr, P.T, chunk_count, P.cb, s),
+                                      at<uint32_t>(ws, L.ovf_list), hdr, P.T, chunk_count, P.cb, pcnt, s),
            "group sort fallback");
     VX_HIP(mark(ev, 4, s), "event");
     return VX_OK;
 }
 
 // Match and Table-2 hashing over fixed chunks of Table 1.  counted: the
-// per-chunk pair counts are already in the workspace (the sort produced
-// them); otherwise they are counted here.
+// per-chunk and per-record pair counts are already in the workspace (the
+// sort produced them); otherwise they are counted here.
 vx_status run_match(const Plan &P, const Layout &L, void *ws, const uint64_t *t1_keys,
                     const uint32_t *t1_nonces, vx_t2_record *t2, uint64_t cap, uint64_t *t2_count,
                     bool counted, hipStream_t s, hipEvent_t *ev = nullptr) {
     uint64_t *cnt = at<uint64_t>(ws, L.mcount), *base = at<uint64_t>(ws, L.mbase);
     uint64_t *part = at<uint64_t>(ws, L.mpart);
+    uint8_t *pcnt = at<uint8_t>(ws, L.pcnt);
     if (!counted)
-        VX_HIP(vxk::launch_match_count(t1_keys, (uint32_t)P.n, P.cb, P.T, cnt, s), "match count");
+        VX_HIP(vxk::launch_match_count(t1_keys, (uint32_t)P.n, P.cb, P.T, cnt, pcnt, s), "match count");
     VX_HIP(vxk::launch_scan_u64(cnt, match_chunks(P), base, part, t2_count, s), "match scan");
     VX_HIP(mark(ev, 5, s), "event");
-    VX_HIP(vxk::launch_match_emit(P.key_words, t1_keys, t1_nonces, (uint32_t)P.n, P.cb, P.T, base, t2, cap, s),
+    VX_HIP(vxk::launch_match_emit(P.key_words, t1_keys, t1_nonces, pcnt, (uint32_t)P.n, P.cb, P.T, base, t2,
+                                  cap, s),
            "match emit");
     VX_HIP(mark(ev, 6, s), "event");
     return VX_OK;

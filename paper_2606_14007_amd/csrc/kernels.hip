@@ -285,6 +285,10 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ 
 constexpr int kSubBinBits = 12;
 constexpr int kSubBins = 1 << kSubBinBits;
 
+// Per-record pair counts are kept as bytes; this value means "this many or
+// more" and sends the match back to the keys for that record.
+constexpr uint32_t kPairCountEscape = 255;
+
 // Pairs owned by record e of a sorted run keys[0..n): later records of the
 // same bucket whose key is less than T above keys[e].  The run must end at a
 // bucket boundary (a group always does).
@@ -308,8 +312,11 @@ __device__ __forceinline__ uint32_t pairs_after(const uint64_t *keys, uint32_t e
 // Pairs owned by records [e_lo, e_hi) of a sorted run keys[0..n) (the run
 // ends at a bucket boundary), counted with a two-pointer walk: the last
 // partner of a record never precedes the previous record's last partner.
+// Pairs of records [e_lo, e_hi) of a sorted run keys[0, n), by a two-pointer
+// walk.  pc (may be NULL) receives each record's count as one byte, with
+// kPairCountEscape standing for "that many or more".
 __device__ __forceinline__ uint64_t pairs_in_range(const uint64_t *keys, uint32_t e_lo, uint32_t e_hi,
-                                                   uint32_t n, uint64_t T) {
+                                                   uint32_t n, uint64_t T, uint8_t *pc) {
     uint64_t total = 0;
     uint32_t reach = e_lo;
     for (uint32_t e = e_lo; e < e_hi; ++e) {
@@ -322,6 +329,7 @@ __device__ __forceinline__ uint64_t pairs_in_range(const uint64_t *keys, uint32_
             ++reach;
         }
         total += reach - e;
+        if (pc) pc[e] = (uint8_t)min(reach - e, kPairCountEscape);
     }
     return total;
 }
@@ -329,14 +337,15 @@ __device__ __forceinline__ uint64_t pairs_in_range(const uint64_t *keys, uint32_
 template <int BLOCK>
 __device__ __forceinline__ void add_chunk_pairs(const uint64_t *keys, uint32_t lo, uint32_t n,
                                                 uint64_t T, uint64_t *chunk_count,
-                                                uint32_t chunk_bits, uint64_t *s_wave) {
+                                                uint32_t chunk_bits, uint64_t *s_wave,
+                                                uint8_t *pcnt) {
     const uint32_t c0 = lo >> chunk_bits, c1 = (lo + n - 1) >> chunk_bits;
     for (uint32_t c = c0; c <= c1; ++c) {
         const uint32_t a = max(c << chunk_bits, lo) - lo;
         const uint32_t b = min((c + 1) << chunk_bits, lo + n) - lo;
         const uint32_t per = (b - a + BLOCK - 1) / BLOCK;
         const uint32_t r0 = min(a + per * threadIdx.x, b), r1 = min(r0 + per, b);
-        uint64_t mine = pairs_in_range(keys, r0, r1, n, T);
+        uint64_t mine = pairs_in_range(keys, r0, r1, n, T, pcnt ? pcnt + lo : nullptr);
         mine = vxd::block_sum<BLOCK>(mine, s_wave);
         if (threadIdx.x == 0 && mine) atomicAdd((unsigned long long *)&chunk_count[c], (unsigned long long)mine);
     }
@@ -355,7 +364,7 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys
                                                      uint32_t *__restrict__ ovf_count,
                                                      uint32_t *__restrict__ ovf_list, uint64_t T,
                                                      uint64_t *__restrict__ chunk_count,
-                                                     uint32_t chunk_bits) {
+                                                     uint32_t chunk_bits, uint8_t *__restrict__ pcnt) {
     constexpr int ITEMS = CAPMAX / BLOCK;
     __shared__ uint64_t s_keys[CAPMAX];
     __shared__ uint32_t s_nonces[CAPMAX];
@@ -471,7 +480,7 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys
                 }
                 offsets[b] = lo + a;
             }
-            if (chunk_count && n) add_chunk_pairs<BLOCK>(s_keys, lo, n, T, chunk_count, chunk_bits, s_wave);
+            if (chunk_count && n) add_chunk_pairs<BLOCK>(s_keys, lo, n, T, chunk_count, chunk_bits, s_wave, pcnt);
             __syncthreads();
         }
         if (g2 >= ngroups) break;
@@ -491,7 +500,7 @@ __global__ __launch_bounds__(BLOCK) void k_group_fallback(
     uint32_t *__restrict__ scr_nonces, const uint32_t *__restrict__ gstart, uint32_t G,
     uint32_t *__restrict__ offsets, const uint32_t *__restrict__ ovf_count,
     const uint32_t *__restrict__ ovf_list, uint32_t fb_max, uint32_t *__restrict__ status,
-    uint64_t T, uint64_t *__restrict__ chunk_count, uint32_t chunk_bits) {
+    uint64_t T, uint64_t *__restrict__ chunk_count, uint32_t chunk_bits, uint8_t *__restrict__ pcnt) {
     __shared__ uint64_t s_k[BLOCK];
     __shared__ uint32_t s_n[BLOCK];
     __shared__ uint64_t s_wave[BLOCK / 64 + 1];
@@ -546,7 +555,7 @@ __global__ __launch_bounds__(BLOCK) void k_group_fallback(
             }
             offsets[b] = lo + a;
         }
-        if (chunk_count && n) add_chunk_pairs<BLOCK>(keys + lo, lo, n, T, chunk_count, chunk_bits, s_wave);
+        if (chunk_count && n) add_chunk_pairs<BLOCK>(keys + lo, lo, n, T, chunk_count, chunk_bits, s_wave, pcnt);
         __syncthreads();
     }
 }
@@ -558,11 +567,13 @@ __global__ __launch_bounds__(BLOCK) void k_group_fallback(
 // bucket's end.
 // ---------------------------------------------------------------------------
 
-// Pair count per chunk (used when the sort did not provide it).
+// Pair count per chunk and per record (used when the sort did not provide
+// them).
 template <int BLOCK, int MCAP>
 __global__ __launch_bounds__(BLOCK) void k_match_count(const uint64_t *__restrict__ keys,
                                                        uint32_t n_total, uint32_t cb, uint64_t T,
-                                                       uint64_t *__restrict__ counts) {
+                                                       uint64_t *__restrict__ counts,
+                                                       uint8_t *__restrict__ pcnt) {
     __shared__ uint64_t s_keys[MCAP];
     __shared__ uint64_t s_wave[BLOCK / 64 + 1];
     const uint32_t tid = threadIdx.x;
@@ -576,68 +587,95 @@ __global__ __launch_bounds__(BLOCK) void k_match_count(const uint64_t *__restric
         for (uint32_t e = tid; e < m; e += BLOCK) {
             const uint64_t ki = s_keys[e];
             const uint32_t bi = (uint32_t)(ki >> 40);
+            uint32_t mine = 0;
             for (uint32_t j = c + e + 1; j < n_total; ++j) {
                 const uint64_t kj = (j - c < m) ? s_keys[j - c] : keys[j];
                 if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
-                ++total;
+                ++mine;
             }
+            pcnt[c + e] = (uint8_t)min(mine, kPairCountEscape);
+            total += mine;
         }
         total = vxd::block_sum<BLOCK>(total, s_wave);
         if (tid == 0) counts[ci] = total;
     }
 }
 
+// A value the program knows to be equal in every lane (e.g. loaded from one
+// LDS address), moved to scalar registers.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Pairs owned by record i of the sorted Table 1 (global walk; used for
+// records whose count byte is the escape value).
+__device__ __forceinline__ uint32_t pairs_after_global(const uint64_t *keys, uint32_t i, uint32_t n_total,
+                                                       uint64_t T) {
+    const uint64_t ki = keys[i];
+    const uint32_t bi = (uint32_t)(ki >> 40);
+    uint32_t c = 0;
+    for (uint32_t j = i + 1; j < n_total; ++j) {
+        const uint64_t kj = keys[j];
+        if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
+        ++c;
+    }
+    return c;
+}
+
 // Match + Table-2 hash.  A persistent work-group walks chunks ci =
-// blockIdx.x, blockIdx.x + gridDim.x, ...  Per chunk:
-//  * each thread counts the pairs of its ITEMS consecutive records with a
-//    two-pointer walk (a record's last partner never precedes the previous
-//    record's), so no lane waits on another's long partner list;
-//  * a work-group scan turns the counts into canonical Table-2 slots, and the
-//    first slot of every record is kept in LDS;
-//  * each thread then takes an equal run of consecutive slots, finds the
-//    record of its first slot by binary search and walks on, hashing one pair
-//    per slot -- equal BLAKE3 work per lane whatever the pair distribution.
-// Table-2 index = chunk base + slot.  The next chunk's records are loaded
-// into registers while the current one is worked on.
-template <int BLOCK, int MCAP>
+// blockIdx.x, blockIdx.x + gridDim.x, ...  The pair count of every record
+// was stored as one byte by the kernel that counted the chunks (the group
+// sort, or the match count), so keys are read only for escaped counts.
+// Per chunk:
+//  * thread t owns records 4t .. 4t+3 (one 32-bit load of their count
+//    bytes); a work-group scan turns the counts into canonical Table-2 slots
+//    and each record's first slot is kept in LDS;
+//  * the chunk's slots are taken in windows of SLOTS (one window unless the
+//    keys are crowded): every record writes its index into the LDS word of
+//    each of its slots in the window, then slot q is hashed by lane
+//    q mod BLOCK -- every lane hashes the same number of pairs (+-1) and a
+//    wave's stores fill one contiguous 1 KiB run of Table 2.
+// Table-2 index = chunk base + slot.  The next chunk's nonces and counts are
+// loaded into registers while the current one is worked on.
+template <int BLOCK, int MCAP, int SLOTS>
 __global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *__restrict__ keys,
                                                       const uint32_t *__restrict__ nonces,
+                                                      const uint8_t *__restrict__ pcnt,
                                                       uint32_t n_total, uint32_t cb, uint64_t T,
                                                       const uint64_t *__restrict__ chunk_base,
                                                       uint4 *__restrict__ t2, uint64_t cap) {
     constexpr int ITEMS = MCAP / BLOCK;
-    __shared__ uint64_t s_keys[MCAP];
+    static_assert(ITEMS == 4, "one 32-bit word of count bytes per thread");
     __shared__ uint32_t s_nonces[MCAP];
-    __shared__ uint64_t s_off[MCAP + 1];
+    __shared__ uint64_t s_first[MCAP];  // first Table-2 slot of each record (chunk-relative)
+    __shared__ uint32_t s_slot[SLOTS];  // record owning each slot of the window
     __shared__ uint64_t s_wave[BLOCK / 64 + 1];
     const uint32_t tid = threadIdx.x;
     const uint32_t csize = 1u << cb;  // <= MCAP
     const uint32_t nchunks = (n_total + csize - 1) >> cb;
+    const uint32_t e0 = tid * ITEMS;
     uint32_t ci = blockIdx.x;
     if (ci >= nchunks) return;
-    uint64_t pk[ITEMS];
-    uint32_t pn[ITEMS];
+    uint32_t pn[ITEMS], pc = 0;
     {
         const uint32_t c = ci << cb, m = min(csize, n_total - c);
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t e = tid + i * BLOCK;
-            if (e < m) {
-                pk[i] = keys[c + e];
-                pn[i] = nonces[c + e];
-            }
+            if (e < m) pn[i] = nonces[c + e];
         }
+        if (e0 < m) pc = *reinterpret_cast<const uint32_t *>(pcnt + c + e0);
     }
     while (true) {
         const uint32_t c = ci << cb, m = min(csize, n_total - c);
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t e = tid + i * BLOCK;
-            if (e < m) {
-                s_keys[e] = pk[i];
-                s_nonces[e] = pn[i];
-            }
+            if (e < m) s_nonces[e] = pn[i];
         }
+        const uint32_t cw = pc;
         const uint32_t nci = ci + gridDim.x;
         const bool more = nci < nchunks;
         if (more) {
@@ -645,76 +683,70 @@ __global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *_
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
                 const uint32_t e = tid + i * BLOCK;
-                if (e < nm) {
-                    pk[i] = keys[nc + e];
-                    pn[i] = nonces[nc + e];
-                }
+                if (e < nm) pn[i] = nonces[nc + e];
             }
+            if (e0 < nm) pc = *reinterpret_cast<const uint32_t *>(pcnt + nc + e0);
         }
         const uint64_t base = chunk_base[ci];
-        __syncthreads();
-        // Two-pointer count over records [e0, e0 + ITEMS); reach = index of
-        // the last partner found so far (relative to c; may pass m).
-        const uint32_t e0 = tid * ITEMS;
         uint32_t cnt[ITEMS];
         uint64_t mine = 0;
-        uint32_t reach = e0;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t e = e0 + i;
             uint32_t cc = 0;
-            if (e < m) {
-                const uint64_t ki = s_keys[e];
-                const uint32_t bi = (uint32_t)(ki >> 40);
-                if (reach < e) reach = e;
-                while (c + reach + 1 < n_total) {
-                    const uint32_t j = reach + 1;
-                    const uint64_t kj = j < m ? s_keys[j] : keys[c + j];
-                    if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
-                    reach = j;
-                }
-                cc = reach - e;
+            if (e0 + i < m) {
+                cc = (cw >> (8 * i)) & 0xffu;
+                if (cc == kPairCountEscape) cc = pairs_after_global(keys, c + e0 + i, n_total, T);
             }
             cnt[i] = cc;
             mine += cc;
         }
         uint64_t ctot;
-        uint64_t run = vxd::block_exclusive_scan<BLOCK>(mine, s_wave, &ctot);
+        const uint64_t run = vxd::block_exclusive_scan<BLOCK>(mine, s_wave, &ctot);
+        ctot = uniform_u64(ctot);  // same in every lane: keep it in scalar registers
+        // A pair-free chunk skips the LDS writes below (it has no barrier
+        // after them before the next chunk).
+        const uint64_t run_end = run + mine;
+        if (ctot) {
+            const uint64_t w1 = SLOTS < ctot ? SLOTS : ctot;
+            uint64_t r = run;
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            if (e0 + i < MCAP) s_off[e0 + i] = run;
-            run += cnt[i];
-        }
-        if (tid == 0) s_off[MCAP] = ctot;
-        __syncthreads();
-        // Slots [q0, q1) of this thread.
-        const uint64_t per = (ctot + BLOCK - 1) / BLOCK;
-        const uint64_t q0 = per * tid < ctot ? per * tid : ctot;
-        const uint64_t q1 = q0 + per < ctot ? q0 + per : ctot;
-        if (q0 < q1) {
-            uint32_t lo_e = 0, hi_e = MCAP;  // largest e with s_off[e] <= q0
-            while (hi_e - lo_e > 1) {
-                const uint32_t mid = (lo_e + hi_e) >> 1;
-                if (s_off[mid] <= q0) lo_e = mid; else hi_e = mid;
+            for (int i = 0; i < ITEMS; ++i) {
+                s_first[e0 + i] = r;
+                const uint64_t hi = r + cnt[i] < w1 ? r + cnt[i] : w1;
+                for (uint64_t q = r; q < hi; ++q) s_slot[q] = e0 + i;
+                r += cnt[i];
             }
-            uint32_t e = lo_e;
-            uint64_t e_end = s_off[e + 1];
-            uint32_t na = s_nonces[e];
-            uint4 *out = t2 + base;
+        }
+        uint4 *out = t2 + base;
 #pragma unroll 1
-            for (uint64_t q = q0; q < q1; ++q) {
-                while (q >= e_end) {  // next record with pairs
-                    ++e;
-                    e_end = s_off[e + 1];
-                    na = s_nonces[e];
-                }
-                const uint32_t j = e + 1 + (uint32_t)(q - s_off[e]);
+        for (uint64_t w0 = 0; w0 < ctot;) {
+            const uint64_t w1 = w0 + SLOTS < ctot ? w0 + SLOTS : ctot;
+            __syncthreads();
+            const uint32_t nq = (uint32_t)(w1 - w0);
+#pragma unroll 1
+            for (uint32_t qr = tid; qr < nq; qr += BLOCK) {
+                const uint32_t e = s_slot[qr];
+                const uint64_t q = w0 + qr;
+                const uint32_t j = e + 1 + (uint32_t)(q - s_first[e]);
+                const uint32_t na = s_nonces[e];
                 const uint32_t nb = j < m ? s_nonces[j] : nonces[c + j];
                 const uint64_t h = vxd::h2(key, na, nb);
                 if (base + q < cap) out[q] = make_uint4(na, nb, (uint32_t)h, (uint32_t)(h >> 32));
             }
+            __syncthreads();
+            w0 = w1;
+            if (w0 < ctot) {  // next window (crowded keys only): runs from LDS
+                const uint64_t w2 = w0 + SLOTS < ctot ? w0 + SLOTS : ctot;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint64_t f = s_first[e0 + i];
+                    const uint64_t g = i + 1 < ITEMS ? s_first[e0 + i + 1] : run_end;
+                    const uint64_t lo = f > w0 ? f : w0;
+                    const uint64_t hi = g < w2 ? g : w2;
+                    for (uint64_t q = lo; q < hi; ++q) s_slot[q - w0] = e0 + i;
+                }
+            }
         }
-        __syncthreads();
         if (!more) break;
         ci = nci;
     }
@@ -1126,6 +1158,7 @@ constexpr int kFallbackBlock = 1024;
 constexpr int kFallbackGrid = 256;
 constexpr int kMatchBlock = 512;
 constexpr int kMatchCap = 2048;
+constexpr int kMatchSlots = 4096;
 constexpr int kMatchWindow = 2048;
 
 hipError_t launch_reset(uint32_t *words, uint32_t n, hipStream_t s) {
@@ -1198,12 +1231,12 @@ hipError_t launch_scatter_segments(const uint64_t *in_keys, const uint32_t *in_n
 hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint32_t *gstart, uint32_t G,
                             uint32_t cap, uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count,
                             uint32_t *ovf_list, uint64_t T, uint64_t *chunk_count, uint32_t chunk_bits,
-                            hipStream_t s) {
+                            uint8_t *pcnt, hipStream_t s) {
     static const uint32_t resident = resident_grid(k_groupsort<kSortBlock, kGroupCapMax>, kSortBlock);
     const uint32_t grid = min(1u << G, resident);
     hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapMax>), dim3(grid), dim3(kSortBlock), 0, s,
                        keys, nonces, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T,
-                       chunk_count, chunk_bits);
+                       chunk_count, chunk_bits, pcnt);
     return hipGetLastError();
 }
 
@@ -1211,20 +1244,20 @@ hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, uint64_t *scr
                                  uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G,
                                  uint32_t *offsets, const uint32_t *ovf_count, const uint32_t *ovf_list,
                                  uint32_t *status, uint64_t T, uint64_t *chunk_count,
-                                 uint32_t chunk_bits, hipStream_t s) {
+                                 uint32_t chunk_bits, uint8_t *pcnt, hipStream_t s) {
     hipLaunchKernelGGL(k_group_fallback<kFallbackBlock>, dim3(kFallbackGrid), dim3(kFallbackBlock), 0,
                        s, keys, nonces, scr_keys, scr_nonces, gstart, G, offsets, ovf_count, ovf_list,
-                       (uint32_t)kFallbackMax, status, T, chunk_count, chunk_bits);
+                       (uint32_t)kFallbackMax, status, T, chunk_count, chunk_bits, pcnt);
     return hipGetLastError();
 }
 
 hipError_t launch_match_count(const uint64_t *keys, uint32_t n_total, uint32_t chunk_bits, uint64_t T,
-                              uint64_t *counts, hipStream_t s) {
+                              uint64_t *counts, uint8_t *pcnt, hipStream_t s) {
     const uint32_t nchunks = (n_total + (1u << chunk_bits) - 1) >> chunk_bits;
     static const uint32_t resident = resident_grid(k_match_count<kMatchBlock, kMatchCap>, kMatchBlock);
     const uint32_t grid = min(nchunks, resident);
     hipLaunchKernelGGL((k_match_count<kMatchBlock, kMatchCap>), dim3(grid), dim3(kMatchBlock), 0, s,
-                       keys, n_total, chunk_bits, T, counts);
+                       keys, n_total, chunk_bits, T, counts, pcnt);
     return hipGetLastError();
 }
 
@@ -1240,15 +1273,15 @@ hipError_t launch_scan_u64(const uint64_t *in, uint32_t n, uint64_t *out, uint64
 uint32_t scan_parts(uint32_t n) { return (n + kScanTile - 1) / kScanTile; }
 
 hipError_t launch_match_emit(const uint32_t key_words[8], const uint64_t *keys, const uint32_t *nonces,
-                             uint32_t n_total, uint32_t chunk_bits, uint64_t T, const uint64_t *chunk_base,
-                             void *t2, uint64_t cap, hipStream_t s) {
+                             const uint8_t *pcnt, uint32_t n_total, uint32_t chunk_bits, uint64_t T,
+                             const uint64_t *chunk_base, void *t2, uint64_t cap, hipStream_t s) {
     Key key;
     for (int i = 0; i < 8; ++i) key.w[i] = key_words[i];
     const uint32_t nchunks = (n_total + (1u << chunk_bits) - 1) >> chunk_bits;
-    static const uint32_t resident = resident_grid(k_match_emit<kMatchBlock, kMatchCap>, kMatchBlock);
+    static const uint32_t resident = resident_grid(k_match_emit<kMatchBlock, kMatchCap, kMatchSlots>, kMatchBlock);
     const uint32_t grid = min(nchunks, resident);
-    hipLaunchKernelGGL((k_match_emit<kMatchBlock, kMatchCap>), dim3(grid), dim3(kMatchBlock),
-                       0, s, key, keys, nonces, n_total, chunk_bits, T, chunk_base, (uint4 *)t2, cap);
+    hipLaunchKernelGGL((k_match_emit<kMatchBlock, kMatchCap, kMatchSlots>), dim3(grid), dim3(kMatchBlock),
+                       0, s, key, keys, nonces, pcnt, n_total, chunk_bits, T, chunk_base, (uint4 *)t2, cap);
     return hipGetLastError();
 }
 
