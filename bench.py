@@ -25,7 +25,8 @@ if ROOT not in sys.path:
 STAGES = ["hash", "partition1", "partition2", "group_sort", "match_count", "match_emit"]
 KERNEL_OF_STAGE = {"hash": "k_hash_table1", "match_emit": "k_match_emit",
                    "group_sort": "k_groupsort", "partition1": "k_scatter (pass 1)",
-                   "partition2": "k_scatter (pass 2)", "match_count": "k_match_count"}
+                   "partition2": "k_digit_hist + k_scatter (later passes)",
+                   "match_count": "k_match_count"}
 
 
 def log(*a):
@@ -308,9 +309,10 @@ def main() -> int:
     h2_ops = opcount.valu_per_h2() * t2n
     valu_peak = opcount.MI355X_VALU_LANE_OPS_PER_S
     hbm_peak = opcount.MI355X_HBM_BYTES_PER_S
+    npass = vx.vx_partition_passes(vx.make_params(derive_key(0), k))
     algo_bytes = {
-        "partition1": n * (8 + 12) + 2 * 0,      # read key, write key+nonce
-        "partition2": n * (12 + 12),             # read and write key+nonce
+        "partition1": n * (8 + 12),              # read key, write key+nonce
+        "partition2": (npass - 1) * n * (12 + 12),  # each later pass reads and writes key+nonce
         "group_sort": n * (12 + 12) + (vx.VX_NUM_BUCKETS + 1) * 4,
         "match_count": n * 8,                    # read keys
     }

@@ -121,6 +121,12 @@ uint64_t vx_default_threshold(uint32_t k);
  * NULL).  Returns 0 for invalid params. */
 size_t vx_workspace_bytes(const vx_plot_params *params, int which_call, const vx_tuning *tuning);
 
+/* Number of MSD partition passes (1..3) that the plan for these params and
+ * tuning (may be NULL) makes over Table 1 before sorting inside groups --
+ * what a caller needs to account the bytes a sort moves.  No device work.
+ * Returns 0 for invalid params or tuning. */
+uint32_t vx_partition_passes(const vx_plot_params *params, const vx_tuning *tuning);
+
 /* A Table-2 capacity that holds |Table 2| of a k-plot with threshold T with
  * overwhelming probability (expectation plus a generous margin). */
 uint64_t vx_t2_capacity_hint(uint32_t k, uint64_t threshold);

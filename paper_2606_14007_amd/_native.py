@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+from typing import Optional
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libvx.so")
@@ -62,6 +63,7 @@ SYMBOLS = [
     ("vx_default_threshold", C.c_uint64, [C.c_uint32]),
     ("vx_workspace_bytes", C.c_size_t, [C.POINTER(VxPlotParams), C.c_int, C.POINTER(VxTuning)]),
     ("vx_t2_capacity_hint", C.c_uint64, [C.c_uint32, C.c_uint64]),
+    ("vx_partition_passes", C.c_uint32, [C.POINTER(VxPlotParams), C.POINTER(VxTuning)]),
     ("vx_hash_table1", C.c_int, [C.POINTER(VxPlotParams), C.c_void_p, C.c_void_p]),
     ("vx_bucket_sort", C.c_int, [C.POINTER(VxPlotParams), C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(VxTuning),
@@ -141,6 +143,10 @@ def vx_workspace_bytes(params: VxPlotParams, which: int, tuning: VxTuning | None
 
 def vx_t2_capacity_hint(k: int, threshold: int) -> int:
     return int(lib().vx_t2_capacity_hint(k, threshold))
+
+
+def vx_partition_passes(params: VxPlotParams, tuning: Optional[VxTuning] = None) -> int:
+    return int(lib().vx_partition_passes(C.byref(params), C.byref(tuning) if tuning else None))
 
 
 def vx_hash_table1(params: VxPlotParams, d_keys: int, stream: int = 0) -> None:

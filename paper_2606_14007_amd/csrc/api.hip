@@ -317,6 +317,12 @@ size_t vx_workspace_bytes(const vx_plot_params *params, int which_call, const vx
     return layout(P, which_call).total;
 }
 
+uint32_t vx_partition_passes(const vx_plot_params *params, const vx_tuning *tuning) {
+    Plan P;
+    if (make_plan(params, tuning, &P) != VX_OK) return 0;
+    return P.npass;
+}
+
 uint64_t vx_t2_capacity_hint(uint32_t k, uint64_t threshold) {
     if (k < 1 || k > 31) return 0;
     // Expected pairs per record for uniform keys: neighbours within T inside

@@ -78,3 +78,16 @@ def test_workspace_too_small_is_rejected_on_host():
         # fake, aligned device addresses: rejected before anything is enqueued
         vx.vx_bucket_sort(p, 256, 512, 1024, 2048, 4096, need - 1)
     assert e.value.status == N.VX_ERR_WORKSPACE
+
+
+def test_partition_passes_follow_the_digit_split():
+    # Default groups: G = k - 11 leading bits, cut into passes of at most 9 bits.
+    for k, passes in ((12, 1), (20, 1), (21, 2), (28, 2), (29, 3), (31, 3)):
+        assert vx.vx_partition_passes(vx.make_params(bytes(32), k)) == passes, k
+    p = vx.make_params(bytes(32), 31)
+    assert vx.vx_partition_passes(p, vx.make_tuning(group_bits=20, pass1_bits=10)) == 2
+    assert vx.vx_partition_passes(p, vx.make_tuning(group_bits=15, pass1_bits=5, pass2_bits=5)) == 3
+    assert vx.vx_partition_passes(p, vx.make_tuning(group_bits=25)) == 0
+    bad = vx.make_params(bytes(32), 20)
+    bad.k = 0
+    assert vx.vx_partition_passes(bad) == 0
