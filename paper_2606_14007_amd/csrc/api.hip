@@ -83,15 +83,17 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl) {
     // Sort groups of about 2048 records (half the LDS capacity).
     P.G = t->group_bits ? t->group_bits : clampu((int64_t)p->k - 11, 1, 20);
     if (P.G < 1 || P.G > 24) return fail(VX_ERR_UNSUPPORTED, "group_bits must be in [1, 24]");
-    // Split G into passes of at most 9 bits (8-6-6 at k=31) so that every
-    // digit's run per sub-tile spans whole cache lines.
+    // Split G into passes of at most 9 bits (7-7-6 at k=31) so that every
+    // digit's run per sub-tile spans whole cache lines.  The first pass
+    // scatters over the whole table, where short runs cost the most, so it
+    // takes no more than 7 bits once three passes are needed.
     uint32_t d0, d1, d2;
     if (P.G <= 9) {
         d0 = P.G; d1 = 0; d2 = 0;
     } else if (P.G <= 17) {
         d0 = (P.G + 1) / 2; d1 = P.G - d0; d2 = 0;
     } else {
-        d0 = 8; d1 = (P.G - 8 + 1) / 2; d2 = P.G - 8 - d1;
+        d0 = 7; d1 = (P.G - 7 + 1) / 2; d2 = P.G - 7 - d1;
     }
     if (t->pass1_bits || t->pass2_bits) {
         d0 = t->pass1_bits ? t->pass1_bits : d0;
@@ -253,23 +255,25 @@ vx_status run_partition(const Plan &P, const Layout &L, void *ws, const uint64_t
 }
 
 // In-place group sort of the partitioned Table 1 (+ oversized groups), with
-// bucket offsets.  chunk_count (may be NULL) receives the Table-2 pair count
-// of each match chunk of the sorted table, and then the workspace's count
-// bytes receive the pair count of each record.
+// bucket offsets.  count_pairs: the sort also stores every record's pair
+// count (one byte) in the workspace while the group is in LDS, and the
+// match chunks' counts are summed from those bytes.
 vx_status run_group_sort(const Plan &P, const Layout &L, void *ws, uint64_t *t1_keys,
-                         uint32_t *t1_nonces, uint32_t *offsets, uint64_t *chunk_count, hipStream_t s,
+                         uint32_t *t1_nonces, uint32_t *offsets, bool count_pairs, hipStream_t s,
                          hipEvent_t *ev) {
-    uint8_t *pcnt = chunk_count ? at<uint8_t>(ws, L.pcnt) : nullptr;
     uint32_t *hdr = at<uint32_t>(ws, L.header);
     const uint32_t *gstart = at<uint32_t>(ws, L.gstart[P.npass - 1]);
-    if (chunk_count) VX_HIP(vxk::launch_zero_u64(chunk_count, match_chunks(P), s), "zero counts");
+    uint8_t *pcnt = count_pairs ? at<uint8_t>(ws, L.pcnt) : nullptr;
     VX_HIP(vxk::launch_groupsort(t1_keys, t1_nonces, gstart, P.G, P.cap, offsets, (uint32_t)P.n,
-                                 hdr + 1, at<uint32_t>(ws, L.ovf_list), P.T, chunk_count, P.cb, pcnt, s),
+                                 hdr + 1, at<uint32_t>(ws, L.ovf_list), P.T, pcnt, s),
            "group sort");
     VX_HIP(vxk::launch_group_fallback(t1_keys, t1_nonces, at<uint64_t>(ws, L.scr_keys),
                                       at<uint32_t>(ws, L.scr_nonces), gstart, P.G, offsets, hdr + 1,
-                                      at<uint32_t>(ws, L.ovf_list), hdr, P.T, chunk_count, P.cb, pcnt, s),
+                                      at<uint32_t>(ws, L.ovf_list), hdr, P.T, pcnt, s),
            "group sort fallback");
+    if (count_pairs)
+        VX_HIP(vxk::launch_chunk_sums(pcnt, t1_keys, (uint32_t)P.n, P.cb, P.T, at<uint64_t>(ws, L.mcount), s),
+               "chunk pair sums");
     VX_HIP(mark(ev, 4, s), "event");
     return VX_OK;
 }
@@ -368,7 +372,7 @@ vx_status vx_bucket_sort(const vx_plot_params *params, const uint64_t *d_keys, u
     VX_HIP(vxk::launch_reset(at<uint32_t>(d_workspace, L.header), kHeaderWords, s), "reset");
     st = run_partition(P, L, d_workspace, d_keys, false, d_t1_keys, d_t1_nonces, s, nullptr);
     if (st == VX_OK)
-        st = run_group_sort(P, L, d_workspace, d_t1_keys, d_t1_nonces, d_offsets, nullptr, s, nullptr);
+        st = run_group_sort(P, L, d_workspace, d_t1_keys, d_t1_nonces, d_offsets, false, s, nullptr);
     if (st == VX_OK) g_err[0] = 0;
     return st;
 }
@@ -459,8 +463,7 @@ vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, cons
     if (!P.fused) {
         // Separate kernels: the sort counts each match chunk's pairs while the
         // groups are in LDS, then the match kernel re-reads Table 1.
-        st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets,
-                            at<uint64_t>(ws, L.mcount), s, ev);
+        st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, true, s, ev);
         if (st != VX_OK) return st;
         st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, true, s, ev);
     } else {

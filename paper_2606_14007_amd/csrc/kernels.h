@@ -37,15 +37,15 @@ hipError_t launch_scatter_segments(const uint64_t *in_keys, const uint32_t *in_n
                                    uint32_t bits, hipStream_t s);
 hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint32_t *gstart, uint32_t G,
                             uint32_t cap, uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count,
-                            uint32_t *ovf_list, uint64_t T, uint64_t *chunk_count, uint32_t chunk_bits,
-                            uint8_t *pcnt, hipStream_t s);
+                            uint32_t *ovf_list, uint64_t T, uint8_t *pcnt, hipStream_t s);
 hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, uint64_t *scr_keys,
                                  uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G,
                                  uint32_t *offsets, const uint32_t *ovf_count, const uint32_t *ovf_list,
-                                 uint32_t *status, uint64_t T, uint64_t *chunk_count,
-                                 uint32_t chunk_bits, uint8_t *pcnt, hipStream_t s);
+                                 uint32_t *status, uint64_t T, uint8_t *pcnt, hipStream_t s);
 hipError_t launch_match_count(const uint64_t *keys, uint32_t n_total, uint32_t chunk_bits, uint64_t T,
                               uint64_t *counts, uint8_t *pcnt, hipStream_t s);
+hipError_t launch_chunk_sums(const uint8_t *pcnt, const uint64_t *keys, uint32_t n_total, uint32_t chunk_bits,
+                             uint64_t T, uint64_t *counts, hipStream_t s);
 hipError_t launch_zero_u64(uint64_t *p, uint32_t n, hipStream_t s);
 hipError_t launch_sort_match(const uint32_t key_words[8], uint64_t *keys, uint32_t *nonces, uint64_t *scr_keys,
                              uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G, uint32_t cap,

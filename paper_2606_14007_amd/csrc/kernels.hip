@@ -334,23 +334,6 @@ __device__ __forceinline__ uint64_t pairs_in_range(const uint64_t *keys, uint32_
     return total;
 }
 
-template <int BLOCK>
-__device__ __forceinline__ void add_chunk_pairs(const uint64_t *keys, uint32_t lo, uint32_t n,
-                                                uint64_t T, uint64_t *chunk_count,
-                                                uint32_t chunk_bits, uint64_t *s_wave,
-                                                uint8_t *pcnt) {
-    const uint32_t c0 = lo >> chunk_bits, c1 = (lo + n - 1) >> chunk_bits;
-    for (uint32_t c = c0; c <= c1; ++c) {
-        const uint32_t a = max(c << chunk_bits, lo) - lo;
-        const uint32_t b = min((c + 1) << chunk_bits, lo + n) - lo;
-        const uint32_t per = (b - a + BLOCK - 1) / BLOCK;
-        const uint32_t r0 = min(a + per * threadIdx.x, b), r1 = min(r0 + per, b);
-        uint64_t mine = pairs_in_range(keys, r0, r1, n, T, pcnt ? pcnt + lo : nullptr);
-        mine = vxd::block_sum<BLOCK>(mine, s_wave);
-        if (threadIdx.x == 0 && mine) atomicAdd((unsigned long long *)&chunk_count[c], (unsigned long long)mine);
-    }
-}
-
 // Persistent: work-group w sorts groups w, w + gridDim.x, ...  The kernel
 // is kept under 80 VGPRs so that three work-groups share each CU; their
 // phases interleave, which hides each one's global loads behind the others'
@@ -364,8 +347,7 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys
                                                      uint32_t n_total,
                                                      uint32_t *__restrict__ ovf_count,
                                                      uint32_t *__restrict__ ovf_list, uint64_t T,
-                                                     uint64_t *__restrict__ chunk_count,
-                                                     uint32_t chunk_bits, uint8_t *__restrict__ pcnt) {
+                                                     uint8_t *__restrict__ pcnt) {
     constexpr int ITEMS = CAPMAX / BLOCK;
     __shared__ uint64_t s_keys[CAPMAX];
     __shared__ uint32_t s_nonces[CAPMAX];
@@ -448,9 +430,34 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys
                 }
             }
             __syncthreads();
+            // Write the group out, with each record's pair count (one byte):
+            // lane-strided records keep LDS reads and stores contiguous; a
+            // record tests its next four records with independent reads (no
+            // chain of dependent loads) and walks on only past four partners.
             for (uint32_t e = tid; e < n; e += BLOCK) {
-                keys[lo + e] = s_keys[e];
+                const uint64_t ki = s_keys[e];
+                keys[lo + e] = ki;
                 nonces[lo + e] = s_nonces[e];
+                if (pcnt) {
+                    const uint32_t bi = (uint32_t)(ki >> 40);
+                    uint64_t kn[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) kn[r] = e + 1 + r < n ? s_keys[e + 1 + r] : ~0ull;
+                    uint32_t c = 0;
+                    bool go = true;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        go = go && e + 1 + r < n && (uint32_t)(kn[r] >> 40) == bi && kn[r] - ki < T;
+                        c += go ? 1u : 0u;
+                    }
+                    if (c == 4)
+                        for (uint32_t j = e + 5; j < n; ++j) {
+                            const uint64_t kj = s_keys[j];
+                            if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
+                            ++c;
+                        }
+                    pcnt[lo + e] = (uint8_t)min(c, kPairCountEscape);
+                }
             }
             // offsets[b] for the group's buckets: first record with bucket >= b.
             const uint32_t bfirst = g << (VXK_BUCKET_BITS - G);
@@ -463,7 +470,6 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys
                 }
                 offsets[b] = lo + a;
             }
-            if (chunk_count && n) add_chunk_pairs<BLOCK>(s_keys, lo, n, T, chunk_count, chunk_bits, s_wave, pcnt);
             __syncthreads();
         }
         if (g2 >= ngroups) break;
@@ -483,10 +489,9 @@ __global__ __launch_bounds__(BLOCK) void k_group_fallback(
     uint32_t *__restrict__ scr_nonces, const uint32_t *__restrict__ gstart, uint32_t G,
     uint32_t *__restrict__ offsets, const uint32_t *__restrict__ ovf_count,
     const uint32_t *__restrict__ ovf_list, uint32_t fb_max, uint32_t *__restrict__ status,
-    uint64_t T, uint64_t *__restrict__ chunk_count, uint32_t chunk_bits, uint8_t *__restrict__ pcnt) {
+    uint64_t T, uint8_t *__restrict__ pcnt) {
     __shared__ uint64_t s_k[BLOCK];
     __shared__ uint32_t s_n[BLOCK];
-    __shared__ uint64_t s_wave[BLOCK / 64 + 1];
     const uint32_t tid = threadIdx.x;
     const uint32_t cnt = *ovf_count;
     for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
@@ -538,7 +543,11 @@ __global__ __launch_bounds__(BLOCK) void k_group_fallback(
             }
             offsets[b] = lo + a;
         }
-        if (chunk_count && n) add_chunk_pairs<BLOCK>(keys + lo, lo, n, T, chunk_count, chunk_bits, s_wave, pcnt);
+        if (pcnt && n) {
+            const uint32_t per = (n + BLOCK - 1) / BLOCK;
+            const uint32_t r0 = min(tid * per, n), r1 = min(r0 + per, n);
+            pairs_in_range(keys + lo, r0, r1, n, T, pcnt + lo);
+        }
         __syncthreads();
     }
 }
@@ -605,6 +614,37 @@ __device__ __forceinline__ uint32_t pairs_after_global(const uint64_t *keys, uin
         ++c;
     }
     return c;
+}
+
+// Table-2 pair count of every match chunk from the per-record count bytes:
+// one wave per chunk, 32-bit loads, no barriers.  Escaped bytes are
+// recounted from the keys.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_chunk_sums(const uint8_t *__restrict__ pcnt,
+                                                      const uint64_t *__restrict__ keys, uint32_t n_total,
+                                                      uint32_t cb, uint64_t T, uint64_t *__restrict__ counts) {
+    constexpr int WPB = BLOCK / 64;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t nchunks = (n_total + (1u << cb) - 1) >> cb;
+    const uint32_t ci = blockIdx.x * WPB + threadIdx.x / 64;
+    if (ci >= nchunks) return;
+    const uint32_t c = ci << cb, m = min(1u << cb, n_total - c);
+    const uint32_t nw = (m + 3) / 4;
+    const uint32_t *w32 = reinterpret_cast<const uint32_t *>(pcnt + c);
+    uint64_t sum = 0;
+    for (uint32_t w = lane; w < nw; w += 64) {
+        const uint32_t v = w32[w];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t e = 4 * w + i;
+            if (e < m) {
+                const uint32_t b = (v >> (8 * i)) & 0xffu;
+                sum += b == kPairCountEscape ? pairs_after_global(keys, c + e, n_total, T) : b;
+            }
+        }
+    }
+    sum = vxd::wave_sum(sum);
+    if (lane == 0) counts[ci] = sum;
 }
 
 // Match + Table-2 hash.  A persistent work-group walks chunks ci =
@@ -1213,24 +1253,21 @@ hipError_t launch_scatter_segments(const uint64_t *in_keys, const uint32_t *in_n
 
 hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint32_t *gstart, uint32_t G,
                             uint32_t cap, uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count,
-                            uint32_t *ovf_list, uint64_t T, uint64_t *chunk_count, uint32_t chunk_bits,
-                            uint8_t *pcnt, hipStream_t s) {
+                            uint32_t *ovf_list, uint64_t T, uint8_t *pcnt, hipStream_t s) {
     static const uint32_t resident = resident_grid(k_groupsort<kSortBlock, kGroupCapMax>, kSortBlock);
     const uint32_t grid = min(1u << G, resident);
     hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapMax>), dim3(grid), dim3(kSortBlock), 0, s,
-                       keys, nonces, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T,
-                       chunk_count, chunk_bits, pcnt);
+                       keys, nonces, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T, pcnt);
     return hipGetLastError();
 }
 
 hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, uint64_t *scr_keys,
                                  uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G,
                                  uint32_t *offsets, const uint32_t *ovf_count, const uint32_t *ovf_list,
-                                 uint32_t *status, uint64_t T, uint64_t *chunk_count,
-                                 uint32_t chunk_bits, uint8_t *pcnt, hipStream_t s) {
+                                 uint32_t *status, uint64_t T, uint8_t *pcnt, hipStream_t s) {
     hipLaunchKernelGGL(k_group_fallback<kFallbackBlock>, dim3(kFallbackGrid), dim3(kFallbackBlock), 0,
                        s, keys, nonces, scr_keys, scr_nonces, gstart, G, offsets, ovf_count, ovf_list,
-                       (uint32_t)kFallbackMax, status, T, chunk_count, chunk_bits, pcnt);
+                       (uint32_t)kFallbackMax, status, T, pcnt);
     return hipGetLastError();
 }
 
@@ -1254,6 +1291,16 @@ hipError_t launch_scan_u64(const uint64_t *in, uint32_t n, uint64_t *out, uint64
 }
 
 uint32_t scan_parts(uint32_t n) { return (n + kScanTile - 1) / kScanTile; }
+
+hipError_t launch_chunk_sums(const uint8_t *pcnt, const uint64_t *keys, uint32_t n_total, uint32_t chunk_bits,
+                             uint64_t T, uint64_t *counts, hipStream_t s) {
+    constexpr int kBlock = 256;
+    const uint32_t nchunks = (n_total + (1u << chunk_bits) - 1) >> chunk_bits;
+    const uint32_t grid = (nchunks + kBlock / 64 - 1) / (kBlock / 64);
+    hipLaunchKernelGGL(k_chunk_sums<kBlock>, dim3(grid), dim3(kBlock), 0, s, pcnt, keys, n_total, chunk_bits, T,
+                       counts);
+    return hipGetLastError();
+}
 
 hipError_t launch_match_emit(const uint32_t key_words[8], const uint64_t *keys, const uint32_t *nonces,
                              const uint8_t *pcnt, uint32_t n_total, uint32_t chunk_bits, uint64_t T,
