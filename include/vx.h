@@ -109,7 +109,10 @@ typedef struct {
     uint32_t match_chunk_bits; /* match works on chunks of 2^bits Table-1 records, 6..11 */
     uint32_t pass2_bits;   /* digit bits of the second pass (a third takes the rest) */
     uint32_t fused_sort_match; /* plot: nonzero runs sort, match and Table-2 hash as one kernel */
-    uint32_t reserved;
+    uint32_t pipeline_slices;  /* vx_plot: 0 or 1 = no pipelining (default); 2..16 = slices of the
+                                  work after the first partition pass, whose matches run on a
+                                  second (internal) stream while later slices are partitioned and
+                                  sorted */
 } vx_tuning;
 
 enum { VX_CALL_BUCKET_SORT = 1, VX_CALL_MATCH = 2, VX_CALL_PLOT = 3 };

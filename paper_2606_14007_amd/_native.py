@@ -49,7 +49,7 @@ class VxPlotBuffers(C.Structure):
 class VxTuning(C.Structure):
     _fields_ = [("group_bits", C.c_uint32), ("pass1_bits", C.c_uint32), ("group_cap", C.c_uint32),
                 ("h1_tiles", C.c_uint32), ("match_chunk_bits", C.c_uint32), ("pass2_bits", C.c_uint32),
-                ("fused_sort_match", C.c_uint32), ("reserved", C.c_uint32)]
+                ("fused_sort_match", C.c_uint32), ("pipeline_slices", C.c_uint32)]
 
 
 class VxError(RuntimeError):
@@ -119,11 +119,11 @@ def make_params(key: bytes, k: int, threshold: int | None = None) -> VxPlotParam
 
 
 def make_tuning(group_bits=0, pass1_bits=0, group_cap=0, h1_tiles=0, match_chunk_bits=0,
-                pass2_bits=0, fused_sort_match=0) -> VxTuning:
+                pass2_bits=0, fused_sort_match=0, pipeline_slices=0) -> VxTuning:
     t = VxTuning()
     t.group_bits, t.pass1_bits, t.group_cap = group_bits, pass1_bits, group_cap
     t.h1_tiles, t.match_chunk_bits, t.pass2_bits = h1_tiles, match_chunk_bits, pass2_bits
-    t.fused_sort_match = fused_sort_match
+    t.fused_sort_match, t.pipeline_slices = fused_sort_match, pipeline_slices
     return t
 
 

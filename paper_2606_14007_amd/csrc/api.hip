@@ -38,6 +38,11 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // How one plot is cut into kernels.  Every field only moves work around;
 // outputs never depend on it.
 constexpr int kMaxPasses = 3;
+constexpr uint32_t kMaxSlices = 16;
+// Measured at k=31: the two streams barely overlap (the match's and the
+// partition's work-groups do not share CUs in practice), and the pipelined
+// plot was slower than the sequential one, so pipelining is opt-in.
+constexpr uint32_t kDefaultSlices = 1;
 
 struct Plan {
     uint32_t k = 0;
@@ -54,6 +59,7 @@ struct Plan {
     uint32_t cap = 0;        // LDS capacity of a sort group
     uint32_t cb = 0;         // match chunk = 2^cb consecutive Table-1 records
     bool fused = false;      // plot: one fused sort + match kernel instead of two
+    uint32_t slices = 1;     // plot: pipeline slices of the passes after the first (1 = none)
 };
 
 uint32_t clampu(int64_t v, int64_t lo, int64_t hi) {
@@ -87,9 +93,19 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl) {
     // digit's run per sub-tile spans whole cache lines.  The first pass
     // scatters over the whole table, where short runs cost the most, so it
     // takes no more than 7 bits once three passes are needed.
+    //
+    // A pipelined plot (see run_pipelined; opt-in) instead keeps the later
+    // passes at 6 bits, whose scatter fits on a CU next to two match
+    // work-groups: 8-6-6 at k=31.
+    if (t->pipeline_slices > kMaxSlices) return fail(VX_ERR_UNSUPPORTED, "pipeline_slices must be at most 16");
+    P.fused = t->fused_sort_match != 0;
+    P.slices = t->pipeline_slices ? t->pipeline_slices : kDefaultSlices;
+    if (P.fused) P.slices = 1;
     uint32_t d0, d1, d2;
     if (P.G <= 9) {
         d0 = P.G; d1 = 0; d2 = 0;
+    } else if (P.slices > 1 && P.G >= 13) {
+        d0 = P.G - 12; d1 = 6; d2 = 6;
     } else if (P.G <= 17) {
         d0 = (P.G + 1) / 2; d1 = P.G - d0; d2 = 0;
     } else {
@@ -129,14 +145,17 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl) {
     P.cb = t->match_chunk_bits ? t->match_chunk_bits : (uint32_t)vxk::kMatchChunkBitsMax;
     if (P.cb < 6 || P.cb > (uint32_t)vxk::kMatchChunkBitsMax)
         return fail(VX_ERR_UNSUPPORTED, "match_chunk_bits must be in [6, 11]");
-    P.fused = t->fused_sort_match != 0;
+    // Slices cut the first pass's segments; a plot with one pass has none.
+    if (P.npass < 2) P.slices = 1;
+    P.slices = std::min(P.slices, 1u << P.D[0]);
+    if (P.slices < 1) P.slices = 1;
     *pl = P;
     return VX_OK;
 }
 
 // Workspace regions (byte offsets from the workspace start, 256-aligned).
 struct Layout {
-    size_t header = 0;        // u32 words: [0] status, [1] overflow count
+    size_t header = 0;        // u32 words (kHdr*)
     size_t keys_no = 0;       // u64[n] nonce-order hashes (plot only)
     size_t scr_keys = 0;      // u64[n] partition scratch
     size_t scr_nonces = 0;    // u32[n]
@@ -150,7 +169,15 @@ struct Layout {
     size_t total = 0;
 };
 
-constexpr uint32_t kHeaderWords = 64;  // [0] status, [1] overflow count, [2] sort+match ticket
+// Workspace header: u32 words zeroed at the start of every call.
+constexpr uint32_t kHeaderWords = 64;
+constexpr uint32_t kHdrStatus = 0;       // device status bits
+constexpr uint32_t kHdrFusedTicket = 2;  // group ticket of the fused sort + match
+constexpr uint32_t kHdrAcc = 4;          // u64 (words 4, 5): Table-2 records of the slices scanned so far
+constexpr uint32_t kHdrOvf = 8;          // per slice: oversized groups found
+constexpr uint32_t kHdrSortTicket = 8 + kMaxSlices;       // per slice: group ticket of the sort
+constexpr uint32_t kHdrEmitTicket = 8 + 2 * kMaxSlices;   // per slice: chunk ticket of the match
+static_assert(kHdrEmitTicket + kMaxSlices <= kHeaderWords, "header holds every slice's words");
 constexpr uint32_t kLookbackSpinLimit = 1u << 20;
 
 uint32_t match_chunks(const Plan &P) { return (uint32_t)((P.n + (1ull << P.cb) - 1) >> P.cb); }
@@ -206,94 +233,214 @@ T *at(void *ws, size_t off) {
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-// Partition passes.  Pass 0 reads the nonce-order keys (its histogram comes
-// from the hash kernel in a plot, or from a histogram pass over caller
-// keys); passes alternate between Table 1 and the scratch arrays so that the
-// last one lands in Table 1, where groups are then sorted in place.
-vx_status run_partition(const Plan &P, const Layout &L, void *ws, const uint64_t *keys_no,
-                        bool hist_done, uint64_t *t1_keys, uint32_t *t1_nonces, hipStream_t s,
-                        hipEvent_t *ev) {
+// Where partition pass i writes: the passes alternate between Table 1 and
+// the scratch arrays so that the last one lands in Table 1, where groups are
+// then sorted in place.
+struct PassBufs {
+    const uint64_t *in_k;
+    const uint32_t *in_n;  // NULL: nonce = index (the nonce-order keys)
+    uint64_t *out_k;
+    uint32_t *out_n;
+};
+
+PassBufs pass_bufs(const Plan &P, const Layout &L, void *ws, const uint64_t *keys_no, uint64_t *t1_keys,
+                   uint32_t *t1_nonces, uint32_t i) {
     uint64_t *scr_k = at<uint64_t>(ws, L.scr_keys);
     uint32_t *scr_n = at<uint32_t>(ws, L.scr_nonces);
-    const uint64_t *in_k = keys_no;
-    const uint32_t *in_n = nullptr;
-    for (uint32_t i = 0; i < P.npass; ++i) {
-        const bool to_t1 = ((P.npass - 1 - i) % 2) == 0;
-        uint64_t *out_k = to_t1 ? t1_keys : scr_k;
-        uint32_t *out_n = to_t1 ? t1_nonces : scr_n;
-        uint32_t *hist = at<uint32_t>(ws, L.hist[i]), *off = at<uint32_t>(ws, L.off[i]);
-        uint32_t *gst = at<uint32_t>(ws, L.gstart[i]);
-        const uint32_t nd = 1u << P.D[i];
-        const uint32_t shift = 64 - P.pre[i] - P.D[i];
-        const uint32_t ngroups = 1u << (P.pre[i] + P.D[i]);
+    auto to_t1 = [&](uint32_t j) { return ((P.npass - 1 - j) % 2) == 0; };
+    PassBufs B;
+    if (i == 0) {
+        B.in_k = keys_no;
+        B.in_n = nullptr;
+    } else {
+        B.in_k = to_t1(i - 1) ? t1_keys : scr_k;
+        B.in_n = to_t1(i - 1) ? t1_nonces : scr_n;
+    }
+    B.out_k = to_t1(i) ? t1_keys : scr_k;
+    B.out_n = to_t1(i) ? t1_nonces : scr_n;
+    return B;
+}
+
+// Pass i >= 1 over its input segments [sa, sb) (the groups of pass i - 1):
+// per-tile histograms, their scan inside each segment, and the scatter.
+vx_status run_pass(const Plan &P, const Layout &L, void *ws, const PassBufs &B, uint32_t i, uint32_t sa,
+                   uint32_t sb, hipStream_t s) {
+    const uint32_t nd = 1u << P.D[i];
+    const uint32_t shift = 64 - P.pre[i] - P.D[i];
+    const uint32_t q = P.Q[i];
+    const uint32_t nseg = sb - sa;
+    const uint32_t *seg = at<uint32_t>(ws, L.gstart[i - 1]) + sa;
+    uint32_t *hist = at<uint32_t>(ws, L.hist[i]) + (size_t)sa * q * nd;
+    uint32_t *off = at<uint32_t>(ws, L.off[i]) + (size_t)sa * q * nd;
+    uint32_t *gst = at<uint32_t>(ws, L.gstart[i]) + (size_t)sa * nd;
+    VX_HIP(vxk::launch_hist_segments(B.in_k, seg, nseg, q, shift, P.D[i], hist, s), "pass histogram");
+    VX_HIP(vxk::launch_colscan(hist, off, nseg, q, nd, seg, gst, nseg * nd, (uint32_t)P.n, s), "pass scan");
+    VX_HIP(vxk::launch_scatter_segments(B.in_k, B.in_n, B.out_k, B.out_n, off, seg, nseg, q, shift, P.D[i], s),
+           "pass scatter");
+    return VX_OK;
+}
+
+// Partition passes [0, npass_run).  Pass 0 reads the nonce-order keys (its
+// histogram comes from the hash kernel in a plot, or from a histogram pass
+// over caller keys).
+vx_status run_partition(const Plan &P, const Layout &L, void *ws, const uint64_t *keys_no,
+                        bool hist_done, uint64_t *t1_keys, uint32_t *t1_nonces, uint32_t npass_run,
+                        hipStream_t s, hipEvent_t *ev) {
+    for (uint32_t i = 0; i < npass_run; ++i) {
+        const PassBufs B = pass_bufs(P, L, ws, keys_no, t1_keys, t1_nonces, i);
         if (i == 0) {
+            uint32_t *hist = at<uint32_t>(ws, L.hist[0]), *off = at<uint32_t>(ws, L.off[0]);
+            uint32_t *gst = at<uint32_t>(ws, L.gstart[0]);
+            const uint32_t nd = 1u << P.D[0];
+            const uint32_t shift = 64 - P.D[0];
             if (!hist_done)
-                VX_HIP(vxk::launch_hist_chunks(in_k, P.n, P.W, P.chunk1, shift, P.D[0], hist, s),
+                VX_HIP(vxk::launch_hist_chunks(B.in_k, P.n, P.W, P.chunk1, shift, P.D[0], hist, s),
                        "pass-0 histogram");
-            VX_HIP(vxk::launch_colscan(hist, off, 1, P.W, nd, nullptr, gst, ngroups, (uint32_t)P.n, s),
-                   "pass-0 scan");
-            VX_HIP(vxk::launch_scatter_chunks(in_k, nullptr, out_k, out_n, off, P.n, P.W, P.chunk1,
-                                              shift, P.D[0], s),
+            VX_HIP(vxk::launch_colscan(hist, off, 1, P.W, nd, nullptr, gst, nd, (uint32_t)P.n, s), "pass-0 scan");
+            VX_HIP(vxk::launch_scatter_chunks(B.in_k, nullptr, B.out_k, B.out_n, off, P.n, P.W, P.chunk1, shift,
+                                              P.D[0], s),
                    "pass-0 scatter");
         } else {
-            const uint32_t nseg = 1u << P.pre[i];
-            const uint32_t *seg = at<uint32_t>(ws, L.gstart[i - 1]);
-            VX_HIP(vxk::launch_hist_segments(in_k, seg, nseg, P.Q[i], shift, P.D[i], hist, s),
-                   "pass histogram");
-            VX_HIP(vxk::launch_colscan(hist, off, nseg, P.Q[i], nd, seg, gst, ngroups, (uint32_t)P.n, s),
-                   "pass scan");
-            VX_HIP(vxk::launch_scatter_segments(in_k, in_n, out_k, out_n, off, seg, nseg, P.Q[i], shift,
-                                                P.D[i], s),
-                   "pass scatter");
+            vx_status st = run_pass(P, L, ws, B, i, 0, 1u << P.pre[i], s);
+            if (st != VX_OK) return st;
         }
         VX_HIP(mark(ev, i == 0 ? 2 : 3, s), "event");
-        in_k = out_k;
-        in_n = out_n;
     }
-    if (P.npass == 1) VX_HIP(mark(ev, 3, s), "event");
+    if (npass_run == 1) VX_HIP(mark(ev, 3, s), "event");
     return VX_OK;
 }
 
-// In-place group sort of the partitioned Table 1 (+ oversized groups), with
-// bucket offsets.  count_pairs: the sort also stores every record's pair
-// count (one byte) in the workspace while the group is in LDS, and the
-// match chunks' counts are summed from those bytes.
-vx_status run_group_sort(const Plan &P, const Layout &L, void *ws, uint64_t *t1_keys,
-                         uint32_t *t1_nonces, uint32_t *offsets, bool count_pairs, hipStream_t s,
-                         hipEvent_t *ev) {
+// In-place sort of the partitioned groups [g0, g0 + gcount) (+ oversized
+// groups), with their bucket offsets; `slot` picks the slice's header words.
+// pcnt (may be NULL): the sort also stores every record's pair count (one
+// byte) while the group is in LDS.
+vx_status run_group_sort(const Plan &P, const Layout &L, void *ws, uint64_t *t1_keys, uint32_t *t1_nonces,
+                         uint32_t *offsets, uint8_t *pcnt, uint32_t g0, uint32_t gcount, uint32_t slot,
+                         hipStream_t s) {
     uint32_t *hdr = at<uint32_t>(ws, L.header);
     const uint32_t *gstart = at<uint32_t>(ws, L.gstart[P.npass - 1]);
-    uint8_t *pcnt = count_pairs ? at<uint8_t>(ws, L.pcnt) : nullptr;
+    uint32_t *ovf_list = at<uint32_t>(ws, L.ovf_list) + g0;
     VX_HIP(vxk::launch_groupsort(t1_keys, t1_nonces, gstart, P.G, P.cap, offsets, (uint32_t)P.n,
-                                 hdr + 1, at<uint32_t>(ws, L.ovf_list), P.T, pcnt, s),
+                                 hdr + kHdrOvf + slot, ovf_list, P.T, pcnt, g0, gcount,
+                                 hdr + kHdrSortTicket + slot, s),
            "group sort");
     VX_HIP(vxk::launch_group_fallback(t1_keys, t1_nonces, at<uint64_t>(ws, L.scr_keys),
-                                      at<uint32_t>(ws, L.scr_nonces), gstart, P.G, offsets, hdr + 1,
-                                      at<uint32_t>(ws, L.ovf_list), hdr, P.T, pcnt, s),
+                                      at<uint32_t>(ws, L.scr_nonces), gstart, P.G, offsets, hdr + kHdrOvf + slot,
+                                      ovf_list, hdr + kHdrStatus, P.T, pcnt, s),
            "group sort fallback");
-    if (count_pairs)
-        VX_HIP(vxk::launch_chunk_sums(pcnt, t1_keys, (uint32_t)P.n, P.cb, P.T, at<uint64_t>(ws, L.mcount), s),
-               "chunk pair sums");
-    VX_HIP(mark(ev, 4, s), "event");
     return VX_OK;
 }
 
-// Match and Table-2 hashing over fixed chunks of Table 1.  counted: the
-// per-chunk and per-record pair counts are already in the workspace (the
-// sort produced them); otherwise they are counted here.
+// Match and Table-2 hashing of the chunks owned by records [*r_lo, *r_hi)
+// (NULL: all), whose count bytes are in the workspace: chunk sums, Table-2
+// bases (a device scan over all chunks when unsliced, else a ranged scan that
+// carries the running total), then the match kernel.
 vx_status run_match(const Plan &P, const Layout &L, void *ws, const uint64_t *t1_keys,
                     const uint32_t *t1_nonces, vx_t2_record *t2, uint64_t cap, uint64_t *t2_count,
-                    bool counted, hipStream_t s, hipEvent_t *ev = nullptr) {
+                    const uint32_t *r_lo, const uint32_t *r_hi, uint32_t last, uint32_t slot, uint32_t wg_per_cu,
+                    hipStream_t s, hipEvent_t *ev = nullptr) {
+    uint32_t *hdr = at<uint32_t>(ws, L.header);
     uint64_t *cnt = at<uint64_t>(ws, L.mcount), *base = at<uint64_t>(ws, L.mbase);
-    uint64_t *part = at<uint64_t>(ws, L.mpart);
     uint8_t *pcnt = at<uint8_t>(ws, L.pcnt);
-    if (!counted)
-        VX_HIP(vxk::launch_match_count(t1_keys, (uint32_t)P.n, P.cb, P.T, cnt, pcnt, s), "match count");
-    VX_HIP(vxk::launch_scan_u64(cnt, match_chunks(P), base, part, t2_count, s), "match scan");
+    const uint32_t nch = match_chunks(P);
+    VX_HIP(vxk::launch_chunk_sums(pcnt, t1_keys, (uint32_t)P.n, P.cb, P.T, cnt, r_lo, r_hi, last, nch, s),
+           "chunk pair sums");
+    if (!r_lo) {
+        VX_HIP(vxk::launch_scan_u64(cnt, nch, base, at<uint64_t>(ws, L.mpart), t2_count, s), "match scan");
+    } else {
+        VX_HIP(vxk::launch_scan_range(cnt, base, (uint32_t)P.n, P.cb, r_lo, r_hi, last,
+                                      reinterpret_cast<uint64_t *>(hdr + kHdrAcc), t2_count, s),
+               "match scan");
+    }
     VX_HIP(mark(ev, 5, s), "event");
-    VX_HIP(vxk::launch_match_emit(P.key_words, t1_keys, t1_nonces, pcnt, (uint32_t)P.n, P.cb, P.T, base, t2,
-                                  cap, s),
+    VX_HIP(vxk::launch_match_emit(P.key_words, t1_keys, t1_nonces, pcnt, (uint32_t)P.n, P.cb, P.T, base, t2, cap,
+                                  r_lo, r_hi, last, nch, wg_per_cu, hdr + kHdrEmitTicket + slot, s),
            "match emit");
+    VX_HIP(mark(ev, 6, s), "event");
+    return VX_OK;
+}
+
+// Streams and events for pipelined plots, per device, created at default
+// priority on first use.  A plot takes the next of a few stream slots, so
+// plots enqueued on different caller streams rarely share one.
+constexpr int kPipeSlots = 4;
+
+struct Pipe {
+    std::mutex mu;
+    bool ready = false;
+    uint32_t next = 0;
+    hipStream_t y[kPipeSlots] = {};
+    hipEvent_t ev[kPipeSlots][kMaxSlices + 1] = {};
+};
+
+constexpr int kMaxDevices = 64;
+Pipe g_pipe[kMaxDevices];
+std::mutex g_pipe_mu;
+
+vx_status pipe_for_current_device(Pipe **out) {
+    int dev = 0;
+    VX_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(VX_ERR_UNSUPPORTED, "device index out of range");
+    Pipe &Q = g_pipe[dev];
+    std::lock_guard<std::mutex> guard(g_pipe_mu);
+    if (!Q.ready) {
+        for (int l = 0; l < kPipeSlots; ++l) {
+            VX_HIP(hipStreamCreateWithFlags(&Q.y[l], hipStreamNonBlocking), "pipeline stream");
+            for (uint32_t i = 0; i <= kMaxSlices; ++i)
+                VX_HIP(hipEventCreateWithFlags(&Q.ev[l][i], hipEventDisableTiming), "pipeline event");
+        }
+        Q.ready = true;
+    }
+    *out = &Q;
+    return VX_OK;
+}
+
+// The plot after its first partition pass, software-pipelined over slices
+// of the first pass's segments.  Slice i's later passes and group sort run
+// on the caller's stream; its chunk sums, Table-2 scan and match run on a
+// second stream as soon as that sort is done, while the caller's stream
+// already partitions and sorts slice i + 1.  The match is bound by the
+// vector ALUs and the partition and sort by memory and LDS, so the two
+// streams share each CU (the match takes at most two work-groups per CU;
+// the persistent kernels take work from tickets, so work-groups that start
+// late take less).  A slice owns the match chunks whose last record it
+// holds; those chunks and their partners are final once its sort is done,
+// because every earlier slice was sorted before it on the same stream.
+vx_status run_pipelined(const Plan &P, const Layout &L, void *ws, const vx_plot_buffers *b,
+                        const uint64_t *keys_no, hipStream_t s, hipEvent_t *ev) {
+    Pipe *Q = nullptr;
+    vx_status st = pipe_for_current_device(&Q);
+    if (st != VX_OK) return st;
+    std::lock_guard<std::mutex> guard(Q->mu);
+    const int l = (int)(Q->next++ % kPipeSlots);
+    hipStream_t y = Q->y[l];
+    const uint32_t NS = 1u << P.D[0];
+    const uint32_t S = P.slices;
+    const uint32_t *gst0 = at<uint32_t>(ws, L.gstart[0]);
+    uint8_t *pcnt = at<uint8_t>(ws, L.pcnt);
+    VX_HIP(mark(ev, 3, s), "event");
+    for (uint32_t i = 0; i < S; ++i) {
+        const uint32_t a = (uint32_t)((uint64_t)NS * i / S), e = (uint32_t)((uint64_t)NS * (i + 1) / S);
+        for (uint32_t p = 1; p < P.npass; ++p) {
+            const uint32_t sh = P.pre[p] - P.D[0];
+            st = run_pass(P, L, ws, pass_bufs(P, L, ws, keys_no, b->t1_keys, b->t1_nonces, p), p, a << sh,
+                          e << sh, s);
+            if (st != VX_OK) return st;
+        }
+        const uint32_t gsh = P.G - P.D[0];
+        st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, pcnt, a << gsh,
+                            (e - a) << gsh, i, s);
+        if (st != VX_OK) return st;
+        VX_HIP(hipEventRecord(Q->ev[l][i], s), "slice event");
+        VX_HIP(hipStreamWaitEvent(y, Q->ev[l][i], 0), "slice wait");
+        st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, gst0 + a,
+                       gst0 + e, i + 1 == S, i, 2, y);
+        if (st != VX_OK) return st;
+    }
+    VX_HIP(mark(ev, 4, s), "event");
+    VX_HIP(mark(ev, 5, s), "event");
+    VX_HIP(hipEventRecord(Q->ev[l][kMaxSlices], y), "pipeline join");
+    VX_HIP(hipStreamWaitEvent(s, Q->ev[l][kMaxSlices], 0), "pipeline join wait");
     VX_HIP(mark(ev, 6, s), "event");
     return VX_OK;
 }
@@ -370,9 +517,9 @@ vx_status vx_bucket_sort(const vx_plot_params *params, const uint64_t *d_keys, u
     if ((st = check_ws(L, d_workspace, workspace_bytes)) != VX_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     VX_HIP(vxk::launch_reset(at<uint32_t>(d_workspace, L.header), kHeaderWords, s), "reset");
-    st = run_partition(P, L, d_workspace, d_keys, false, d_t1_keys, d_t1_nonces, s, nullptr);
+    st = run_partition(P, L, d_workspace, d_keys, false, d_t1_keys, d_t1_nonces, P.npass, s, nullptr);
     if (st == VX_OK)
-        st = run_group_sort(P, L, d_workspace, d_t1_keys, d_t1_nonces, d_offsets, false, s, nullptr);
+        st = run_group_sort(P, L, d_workspace, d_t1_keys, d_t1_nonces, d_offsets, nullptr, 0, 1u << P.G, 0, s);
     if (st == VX_OK) g_err[0] = 0;
     return st;
 }
@@ -392,7 +539,12 @@ vx_status vx_match_table2(const vx_plot_params *params, const uint64_t *d_t1_key
     if ((st = check_ws(L, d_workspace, workspace_bytes)) != VX_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     (void)d_offsets;  // validated above; the match walks Table 1 itself
-    st = run_match(P, L, d_workspace, d_t1_keys, d_t1_nonces, d_t2, t2_capacity, d_t2_count, false, s);
+    VX_HIP(vxk::launch_reset(at<uint32_t>(d_workspace, L.header), kHeaderWords, s), "reset");
+    VX_HIP(vxk::launch_match_count(d_t1_keys, (uint32_t)P.n, P.cb, P.T, at<uint64_t>(d_workspace, L.mcount),
+                                   at<uint8_t>(d_workspace, L.pcnt), s),
+           "match count");
+    st = run_match(P, L, d_workspace, d_t1_keys, d_t1_nonces, d_t2, t2_capacity, d_t2_count, nullptr, nullptr, 1,
+                   0, 0, s);
     if (st == VX_OK) g_err[0] = 0;
     return st;
 }
@@ -414,7 +566,6 @@ struct Lanes {
     hipEvent_t join[kBatchLanes] = {};
 };
 
-constexpr int kMaxDevices = 64;
 Lanes g_lanes[kMaxDevices];
 std::mutex g_lanes_mu;
 
@@ -436,8 +587,10 @@ vx_status lanes_for_current_device(Lanes **out) {
     return VX_OK;
 }
 
+// pipelined: the plan's slices may run on a second stream (vx_plot); batch
+// lanes run every plot on its lane alone.
 vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, const vx_tuning *tuning,
-                    hipEvent_t *ev, void *stream) {
+                    hipEvent_t *ev, void *stream, bool pipelined) {
     Plan P;
     vx_status st = make_plan(params, tuning, &P);
     if (st != VX_OK) return st;
@@ -458,15 +611,23 @@ vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, cons
                                    P.D[0], s),
            "hash");
     VX_HIP(mark(ev, 1, s), "event");
-    st = run_partition(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, s, ev);
-    if (st != VX_OK) return st;
-    if (!P.fused) {
-        // Separate kernels: the sort counts each match chunk's pairs while the
-        // groups are in LDS, then the match kernel re-reads Table 1.
-        st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, true, s, ev);
+    if (!P.fused && pipelined && P.slices > 1) {
+        st = run_partition(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, 1, s, ev);
+        if (st == VX_OK) st = run_pipelined(P, L, ws, b, keys_no, s, ev);
+    } else if (!P.fused) {
+        // Separate kernels: the sort stores each record's pair count while
+        // the groups are in LDS, then the match kernel reads nonces and counts.
+        st = run_partition(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, P.npass, s, ev);
         if (st != VX_OK) return st;
-        st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, true, s, ev);
+        st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, at<uint8_t>(ws, L.pcnt), 0,
+                            1u << P.G, 0, s);
+        if (st != VX_OK) return st;
+        VX_HIP(mark(ev, 4, s), "event");
+        st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, nullptr, nullptr,
+                       1, 0, 0, s, ev);
     } else {
+        st = run_partition(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, P.npass, s, ev);
+        if (st != VX_OK) return st;
         uint32_t *hdr = at<uint32_t>(ws, L.header);
         uint64_t *words = at<uint64_t>(ws, L.lbwords);
         VX_HIP(vxk::launch_zero_u64(words, 1u << P.G, s), "zero look-back words");
@@ -474,8 +635,9 @@ vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, cons
         VX_HIP(mark(ev, 5, s), "event");
         VX_HIP(vxk::launch_sort_match(P.key_words, b->t1_keys, b->t1_nonces, at<uint64_t>(ws, L.scr_keys),
                                       at<uint32_t>(ws, L.scr_nonces), at<uint32_t>(ws, L.gstart[P.npass - 1]),
-                                      P.G, P.cap, b->bucket_offsets, (uint32_t)P.n, P.T, hdr + 2, words, hdr,
-                                      b->t2, b->t2_capacity, b->t2_count, kLookbackSpinLimit, s),
+                                      P.G, P.cap, b->bucket_offsets, (uint32_t)P.n, P.T, hdr + kHdrFusedTicket,
+                                      words, hdr + kHdrStatus, b->t2, b->t2_capacity, b->t2_count,
+                                      kLookbackSpinLimit, s),
                "sort + match");
         VX_HIP(mark(ev, 6, s), "event");
     }
@@ -489,7 +651,7 @@ extern "C" {
 
 vx_status vx_plot(const vx_plot_params *params, const vx_plot_buffers *b, const vx_tuning *tuning,
                   void *stream) {
-    return plot_impl(params, b, tuning, nullptr, stream);
+    return plot_impl(params, b, tuning, nullptr, stream, true);
 }
 
 vx_status vx_plot_with_events(const vx_plot_params *params, const vx_plot_buffers *b,
@@ -500,7 +662,7 @@ vx_status vx_plot_with_events(const vx_plot_params *params, const vx_plot_buffer
         if (!events[i]) return fail(VX_ERR_INVALID_ARG, "NULL event");
         ev[i] = (hipEvent_t)events[i];
     }
-    return plot_impl(params, b, tuning, ev, stream);
+    return plot_impl(params, b, tuning, ev, stream, true);
 }
 
 vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buffers, uint32_t n,
@@ -558,7 +720,7 @@ vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buf
         if (used[l]) VX_HIP(hipStreamWaitEvent(ln->s[l], ln->fork, 0), "batch fork wait");
     for (uint32_t i = 0; i < n; ++i) {
         const int l = lane_of_chain[chain_of[i]];
-        st = plot_impl(&params[i], &buffers[i], tuning ? &tuning[i] : nullptr, nullptr, ln->s[l]);
+        st = plot_impl(&params[i], &buffers[i], tuning ? &tuning[i] : nullptr, nullptr, ln->s[l], false);
         if (st != VX_OK) break;
     }
     // Join every used lane back into the caller's stream, also on failure, so

@@ -37,15 +37,23 @@ hipError_t launch_scatter_segments(const uint64_t *in_keys, const uint32_t *in_n
                                    uint32_t bits, hipStream_t s);
 hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint32_t *gstart, uint32_t G,
                             uint32_t cap, uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count,
-                            uint32_t *ovf_list, uint64_t T, uint8_t *pcnt, hipStream_t s);
+                            uint32_t *ovf_list, uint64_t T, uint8_t *pcnt, uint32_t g0, uint32_t gcount,
+                            uint32_t *ticket, hipStream_t s);
 hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, uint64_t *scr_keys,
                                  uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G,
                                  uint32_t *offsets, const uint32_t *ovf_count, const uint32_t *ovf_list,
                                  uint32_t *status, uint64_t T, uint8_t *pcnt, hipStream_t s);
 hipError_t launch_match_count(const uint64_t *keys, uint32_t n_total, uint32_t chunk_bits, uint64_t T,
                               uint64_t *counts, uint8_t *pcnt, hipStream_t s);
+// Ranged launches: the records [*r_lo, *r_hi) (device words; NULL = all
+// records) own the match chunks [*r_lo >> bits, *r_hi >> bits), or up to
+// the last chunk when `last`; max_chunks bounds their number (grid size).
 hipError_t launch_chunk_sums(const uint8_t *pcnt, const uint64_t *keys, uint32_t n_total, uint32_t chunk_bits,
-                             uint64_t T, uint64_t *counts, hipStream_t s);
+                             uint64_t T, uint64_t *counts, const uint32_t *r_lo, const uint32_t *r_hi,
+                             uint32_t last, uint32_t max_chunks, hipStream_t s);
+hipError_t launch_scan_range(const uint64_t *counts, uint64_t *bases, uint32_t n_total, uint32_t chunk_bits,
+                             const uint32_t *r_lo, const uint32_t *r_hi, uint32_t last, uint64_t *acc,
+                             uint64_t *t2_count, hipStream_t s);
 hipError_t launch_zero_u64(uint64_t *p, uint32_t n, hipStream_t s);
 hipError_t launch_sort_match(const uint32_t key_words[8], uint64_t *keys, uint32_t *nonces, uint64_t *scr_keys,
                              uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G, uint32_t cap,
@@ -55,8 +63,12 @@ hipError_t launch_sort_match(const uint32_t key_words[8], uint64_t *keys, uint32
 hipError_t launch_scan_u64(const uint64_t *in, uint32_t n, uint64_t *out, uint64_t *part,
                            uint64_t *total, hipStream_t s);
 uint32_t scan_parts(uint32_t n);
+// wg_per_cu: 0 = as many work-groups as fit on the device, else at most
+// that many per CU (to leave room for kernels of another stream).
 hipError_t launch_match_emit(const uint32_t key_words[8], const uint64_t *keys, const uint32_t *nonces,
                              const uint8_t *pcnt, uint32_t n_total, uint32_t chunk_bits, uint64_t T,
-                             const uint64_t *chunk_base, void *t2, uint64_t cap, hipStream_t s);
+                             const uint64_t *chunk_base, void *t2, uint64_t cap, const uint32_t *r_lo,
+                             const uint32_t *r_hi, uint32_t last, uint32_t max_chunks, uint32_t wg_per_cu,
+                             uint32_t *ticket, hipStream_t s);
 
 }  // namespace vxk

@@ -119,7 +119,9 @@ __global__ __launch_bounds__(BLOCK) void k_digit_hist(const uint64_t *__restrict
 // [s * rps, (s + 1) * rps) and starts at record seg_base[s] (0 if NULL).
 // off[r][c] = seg_base + sum_{c' < c} total(s, c') + sum_{rows r' < r of s} hist[r'][c]
 // gstart[s * ncol + c] = seg_base + sum_{c' < c} total(s, c'); the last
-// work-group also writes gstart[n_groups] = n_total.
+// work-group also writes gstart[n_groups], the end of the last segment
+// (seg_base[nseg], or n_total without segments), so a launch over a range of
+// segments leaves a complete group-start array for that range.
 // ---------------------------------------------------------------------------
 
 template <int BLOCK>
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(BLOCK) void k_colscan(const uint32_t *__restrict__ 
             }
         }
     }
-    if (s == gridDim.x - 1 && tid == 0) gstart[n_groups] = n_total;
+    if (s == gridDim.x - 1 && tid == 0) gstart[n_groups] = seg_base ? seg_base[gridDim.x] : n_total;
 }
 
 // ---------------------------------------------------------------------------
@@ -334,10 +336,13 @@ __device__ __forceinline__ uint64_t pairs_in_range(const uint64_t *keys, uint32_
     return total;
 }
 
-// Persistent: work-group w sorts groups w, w + gridDim.x, ...  The kernel
-// is kept under 80 VGPRs so that three work-groups share each CU; their
-// phases interleave, which hides each one's global loads behind the others'
-// LDS work (better, measured, than prefetching into registers at two per CU).
+// Persistent: each work-group takes groups of [g0, g0 + gcount) from a
+// ticket counter (*ticket, zero at launch) until none is left, so work-groups
+// that start late -- while another stream's kernel holds part of the device
+// -- simply take fewer groups.  The kernel is kept under 80 VGPRs so that
+// three work-groups share each CU; their phases interleave, which hides each
+// one's global loads behind the others' LDS work (better, measured, than
+// prefetching into registers at two per CU).
 template <int BLOCK, int CAPMAX>
 __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys,
                                                      uint32_t *__restrict__ nonces,
@@ -347,22 +352,26 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys
                                                      uint32_t n_total,
                                                      uint32_t *__restrict__ ovf_count,
                                                      uint32_t *__restrict__ ovf_list, uint64_t T,
-                                                     uint8_t *__restrict__ pcnt) {
+                                                     uint8_t *__restrict__ pcnt, uint32_t g0,
+                                                     uint32_t gcount, uint32_t *__restrict__ ticket) {
     constexpr int ITEMS = CAPMAX / BLOCK;
     __shared__ uint64_t s_keys[CAPMAX];
     __shared__ uint32_t s_nonces[CAPMAX];
     __shared__ uint32_t s_start[kSubBins + 1];
     __shared__ uint64_t s_wave[BLOCK / 64 + 1];
+    __shared__ uint32_t s_tk[2];  // alternate, so a slow reader never sees the next ticket
     uint32_t *s_wave32 = reinterpret_cast<uint32_t *>(s_wave);
     const uint32_t tid = threadIdx.x;
-    const uint32_t ngroups = 1u << G;
     const uint32_t sb_shift = 64u - G - kSubBinBits;
     const uint32_t nbg = 1u << (VXK_BUCKET_BITS - G);
     if (blockIdx.x == 0 && tid == 0) offsets[VXK_NUM_BUCKETS] = n_total;
-    uint32_t g = blockIdx.x;
-    if (g >= ngroups) return;
-    uint32_t lo = gstart[g], n = gstart[g + 1] - lo;
-    while (true) {
+    for (uint32_t it = 0;; ++it) {
+        if (tid == 0) s_tk[it & 1] = atomicAdd(ticket, 1u);
+        __syncthreads();
+        const uint32_t t = s_tk[it & 1];
+        if (t >= gcount) break;
+        const uint32_t g = g0 + t;
+        const uint32_t lo = gstart[g], n = gstart[g + 1] - lo;
         uint64_t k[ITEMS];
         uint32_t nn[ITEMS], slot[ITEMS];
         if (n <= cap) {
@@ -374,12 +383,6 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys
                     nn[j] = nonces[lo + e];
                 }
             }
-        }
-        const uint32_t g2 = g + gridDim.x;
-        uint32_t lo2 = 0, n2 = 0;
-        if (g2 < ngroups) {
-            lo2 = gstart[g2];
-            n2 = gstart[g2 + 1] - lo2;
         }
         if (n > cap) {
             if (tid == 0) {
@@ -472,10 +475,6 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys
             }
             __syncthreads();
         }
-        if (g2 >= ngroups) break;
-        g = g2;
-        lo = lo2;
-        n = n2;
     }
 }
 
@@ -616,39 +615,92 @@ __device__ __forceinline__ uint32_t pairs_after_global(const uint64_t *keys, uin
     return c;
 }
 
-// Table-2 pair count of every match chunk from the per-record count bytes:
-// one wave per chunk, 32-bit loads, no barriers.  Escaped bytes are
-// recounted from the keys.
+// Match chunks owned by a range of Table-1 records: a chunk belongs to the
+// range holding its last record, so chunks [*r_lo >> cb, *r_hi >> cb) (to
+// the end for the last range) -- once every record before *r_hi is sorted,
+// these chunks and all their partners are final.  No range (r_lo NULL): all.
+__device__ __forceinline__ void chunk_range(const uint32_t *r_lo, const uint32_t *r_hi, uint32_t last,
+                                            uint32_t cb, uint32_t nchunks, uint32_t &c0, uint32_t &c1) {
+    if (!r_lo) {
+        c0 = 0;
+        c1 = nchunks;
+        return;
+    }
+    c0 = min(*r_lo >> cb, nchunks);
+    c1 = last ? nchunks : min(*r_hi >> cb, nchunks);
+    if (c1 < c0) c1 = c0;
+}
+
+// Table-2 pair count of every match chunk (of a record range) from the
+// per-record count bytes: one wave per chunk, 32-bit loads, no barriers.
+// Escaped bytes are recounted from the keys.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_chunk_sums(const uint8_t *__restrict__ pcnt,
                                                       const uint64_t *__restrict__ keys, uint32_t n_total,
-                                                      uint32_t cb, uint64_t T, uint64_t *__restrict__ counts) {
+                                                      uint32_t cb, uint64_t T, uint64_t *__restrict__ counts,
+                                                      const uint32_t *r_lo, const uint32_t *r_hi,
+                                                      uint32_t last) {
     constexpr int WPB = BLOCK / 64;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t nchunks = (n_total + (1u << cb) - 1) >> cb;
-    const uint32_t ci = blockIdx.x * WPB + threadIdx.x / 64;
-    if (ci >= nchunks) return;
-    const uint32_t c = ci << cb, m = min(1u << cb, n_total - c);
-    const uint32_t nw = (m + 3) / 4;
-    const uint32_t *w32 = reinterpret_cast<const uint32_t *>(pcnt + c);
-    uint64_t sum = 0;
-    for (uint32_t w = lane; w < nw; w += 64) {
-        const uint32_t v = w32[w];
+    uint32_t c0, c1;
+    chunk_range(r_lo, r_hi, last, cb, nchunks, c0, c1);
+    for (uint32_t ci = c0 + blockIdx.x * WPB + threadIdx.x / 64; ci < c1; ci += gridDim.x * WPB) {
+        const uint32_t c = ci << cb, m = min(1u << cb, n_total - c);
+        const uint32_t nw = (m + 3) / 4;
+        const uint32_t *w32 = reinterpret_cast<const uint32_t *>(pcnt + c);
+        uint64_t sum = 0;
+        for (uint32_t w = lane; w < nw; w += 64) {
+            const uint32_t v = w32[w];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint32_t e = 4 * w + i;
-            if (e < m) {
-                const uint32_t b = (v >> (8 * i)) & 0xffu;
-                sum += b == kPairCountEscape ? pairs_after_global(keys, c + e, n_total, T) : b;
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t e = 4 * w + i;
+                if (e < m) {
+                    const uint32_t b = (v >> (8 * i)) & 0xffu;
+                    sum += b == kPairCountEscape ? pairs_after_global(keys, c + e, n_total, T) : b;
+                }
             }
         }
+        sum = vxd::wave_sum(sum);
+        if (lane == 0) counts[ci] = sum;
     }
-    sum = vxd::wave_sum(sum);
-    if (lane == 0) counts[ci] = sum;
 }
 
-// Match + Table-2 hash.  A persistent work-group walks chunks ci =
-// blockIdx.x, blockIdx.x + gridDim.x, ...  The pair count of every record
+// Table-2 bases of the chunks of a record range: bases = *acc + exclusive
+// prefix of the counts; *acc then grows by the range's total, and the last
+// range stores the grand total in *t2_count.  One work-group; ranges are
+// scanned in order on one stream.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_scan_range(const uint64_t *__restrict__ counts,
+                                                      uint64_t *__restrict__ bases, uint32_t n_total,
+                                                      uint32_t cb, const uint32_t *r_lo, const uint32_t *r_hi,
+                                                      uint32_t last, uint64_t *acc, uint64_t *t2_count) {
+    __shared__ uint64_t s_wave[BLOCK / 64 + 1];
+    const uint32_t nchunks = (n_total + (1u << cb) - 1) >> cb;
+    uint32_t c0, c1;
+    chunk_range(r_lo, r_hi, last, cb, nchunks, c0, c1);
+    const uint32_t n = c1 - c0;
+    const uint32_t per = (n + BLOCK - 1) / BLOCK;
+    const uint32_t a = c0 + min(threadIdx.x * per, n), b = c0 + min((threadIdx.x + 1) * per, n);
+    uint64_t mine = 0;
+    for (uint32_t c = a; c < b; ++c) mine += counts[c];
+    uint64_t total;
+    uint64_t run = vxd::block_exclusive_scan<BLOCK>(mine, s_wave, &total) + *acc;
+    for (uint32_t c = a; c < b; ++c) {
+        const uint64_t v = counts[c];
+        bases[c] = run;
+        run += v;
+    }
+    __syncthreads();  // every thread has read *acc
+    if (threadIdx.x == 0) {
+        const uint64_t t = *acc + total;
+        *acc = t;
+        if (last) *t2_count = t;
+    }
+}
+
+// Match + Table-2 hash.  A persistent work-group takes match chunks from a
+// ticket counter (*ticket, zero at launch).  The pair count of every record
 // was stored as one byte by the kernel that counted the chunks (the group
 // sort, or the match count), so keys are read only for escaped counts.
 // Per chunk:
@@ -668,18 +720,24 @@ __global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *_
                                                       const uint8_t *__restrict__ pcnt,
                                                       uint32_t n_total, uint32_t cb, uint64_t T,
                                                       const uint64_t *__restrict__ chunk_base,
-                                                      uint4 *__restrict__ t2, uint64_t cap) {
+                                                      uint4 *__restrict__ t2, uint64_t cap,
+                                                      const uint32_t *r_lo, const uint32_t *r_hi,
+                                                      uint32_t last, uint32_t *__restrict__ ticket) {
     constexpr int ITEMS = MCAP / BLOCK;
     static_assert(ITEMS == 4, "one 32-bit word of count bytes per thread");
     __shared__ uint32_t s_nonces[MCAP];
     __shared__ uint64_t s_first[MCAP];  // first Table-2 slot of each record (chunk-relative)
     __shared__ uint32_t s_slot[SLOTS];  // record owning each slot of the window
     __shared__ uint64_t s_wave[BLOCK / 64 + 1];
+    __shared__ uint32_t s_tk[2];  // alternate, so a slow reader never sees the next ticket
     const uint32_t tid = threadIdx.x;
     const uint32_t csize = 1u << cb;  // <= MCAP
-    const uint32_t nchunks = (n_total + csize - 1) >> cb;
     const uint32_t e0 = tid * ITEMS;
-    uint32_t ci = blockIdx.x;
+    uint32_t c0, nchunks;  // this launch's chunks: [c0, nchunks)
+    chunk_range(r_lo, r_hi, last, cb, (n_total + csize - 1) >> cb, c0, nchunks);
+    if (tid == 0) s_tk[1] = atomicAdd(ticket, 1u);
+    __syncthreads();
+    uint32_t ci = c0 + s_tk[1];
     if (ci >= nchunks) return;
     uint32_t pn[ITEMS], pc = 0;
     {
@@ -691,7 +749,7 @@ __global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *_
         }
         if (e0 < m) pc = *reinterpret_cast<const uint32_t *>(pcnt + c + e0);
     }
-    while (true) {
+    for (uint32_t it = 0;; ++it) {
         const uint32_t c = ci << cb, m = min(csize, n_total - c);
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
@@ -699,17 +757,7 @@ __global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *_
             if (e < m) s_nonces[e] = pn[i];
         }
         const uint32_t cw = pc;
-        const uint32_t nci = ci + gridDim.x;
-        const bool more = nci < nchunks;
-        if (more) {
-            const uint32_t nc = nci << cb, nm = min(csize, n_total - nc);
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const uint32_t e = tid + i * BLOCK;
-                if (e < nm) pn[i] = nonces[nc + e];
-            }
-            if (e0 < nm) pc = *reinterpret_cast<const uint32_t *>(pcnt + nc + e0);
-        }
+        if (tid == 0) s_tk[it & 1] = atomicAdd(ticket, 1u);  // the next chunk, read after the scan
         const uint64_t base = chunk_base[ci];
         uint32_t cnt[ITEMS];
         uint64_t mine = 0;
@@ -726,6 +774,18 @@ __global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *_
         uint64_t ctot;
         const uint64_t run = vxd::block_exclusive_scan<BLOCK>(mine, s_wave, &ctot);
         ctot = uniform_u64(ctot);  // same in every lane: keep it in scalar registers
+        // Prefetch the next chunk into registers while this one is hashed.
+        const uint32_t nci = c0 + s_tk[it & 1];
+        const bool more = nci < nchunks;
+        if (more) {
+            const uint32_t nc = nci << cb, nm = min(csize, n_total - nc);
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t e = tid + i * BLOCK;
+                if (e < nm) pn[i] = nonces[nc + e];
+            }
+            if (e0 < nm) pc = *reinterpret_cast<const uint32_t *>(pcnt + nc + e0);
+        }
         // A pair-free chunk skips the LDS writes below (it has no barrier
         // after them before the next chunk).
         const uint64_t run_end = run + mine;
@@ -1143,6 +1203,14 @@ __global__ void k_reset_words(uint32_t *__restrict__ p, uint32_t n) {
 // Work-groups of `kernel` that are resident on the whole device at once:
 // persistent kernels are launched with exactly this many, so none waits for
 // a second round (a late round would leave most CUs idle at the tail).
+static int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return 256;
+    return cus;
+}
+
 template <typename K>
 static uint32_t resident_grid(K kernel, int block) {
     int dev = 0, cus = 0, per_cu = 0;
@@ -1253,11 +1321,14 @@ hipError_t launch_scatter_segments(const uint64_t *in_keys, const uint32_t *in_n
 
 hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint32_t *gstart, uint32_t G,
                             uint32_t cap, uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count,
-                            uint32_t *ovf_list, uint64_t T, uint8_t *pcnt, hipStream_t s) {
+                            uint32_t *ovf_list, uint64_t T, uint8_t *pcnt, uint32_t g0, uint32_t gcount,
+                            uint32_t *ticket, hipStream_t s) {
     static const uint32_t resident = resident_grid(k_groupsort<kSortBlock, kGroupCapMax>, kSortBlock);
-    const uint32_t grid = min(1u << G, resident);
+    const uint32_t grid = min(gcount, resident);
+    if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapMax>), dim3(grid), dim3(kSortBlock), 0, s,
-                       keys, nonces, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T, pcnt);
+                       keys, nonces, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T, pcnt, g0,
+                       gcount, ticket);
     return hipGetLastError();
 }
 
@@ -1293,25 +1364,37 @@ hipError_t launch_scan_u64(const uint64_t *in, uint32_t n, uint64_t *out, uint64
 uint32_t scan_parts(uint32_t n) { return (n + kScanTile - 1) / kScanTile; }
 
 hipError_t launch_chunk_sums(const uint8_t *pcnt, const uint64_t *keys, uint32_t n_total, uint32_t chunk_bits,
-                             uint64_t T, uint64_t *counts, hipStream_t s) {
+                             uint64_t T, uint64_t *counts, const uint32_t *r_lo, const uint32_t *r_hi,
+                             uint32_t last, uint32_t max_chunks, hipStream_t s) {
     constexpr int kBlock = 256;
-    const uint32_t nchunks = (n_total + (1u << chunk_bits) - 1) >> chunk_bits;
-    const uint32_t grid = (nchunks + kBlock / 64 - 1) / (kBlock / 64);
+    const uint32_t grid = max(1u, min((max_chunks + kBlock / 64 - 1) / (kBlock / 64), 8192u));
     hipLaunchKernelGGL(k_chunk_sums<kBlock>, dim3(grid), dim3(kBlock), 0, s, pcnt, keys, n_total, chunk_bits, T,
-                       counts);
+                       counts, r_lo, r_hi, last);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_range(const uint64_t *counts, uint64_t *bases, uint32_t n_total, uint32_t chunk_bits,
+                             const uint32_t *r_lo, const uint32_t *r_hi, uint32_t last, uint64_t *acc,
+                             uint64_t *t2_count, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_range<1024>, dim3(1), dim3(1024), 0, s, counts, bases, n_total, chunk_bits, r_lo,
+                       r_hi, last, acc, t2_count);
     return hipGetLastError();
 }
 
 hipError_t launch_match_emit(const uint32_t key_words[8], const uint64_t *keys, const uint32_t *nonces,
                              const uint8_t *pcnt, uint32_t n_total, uint32_t chunk_bits, uint64_t T,
-                             const uint64_t *chunk_base, void *t2, uint64_t cap, hipStream_t s) {
+                             const uint64_t *chunk_base, void *t2, uint64_t cap, const uint32_t *r_lo,
+                             const uint32_t *r_hi, uint32_t last, uint32_t max_chunks, uint32_t wg_per_cu,
+                             uint32_t *ticket, hipStream_t s) {
     Key key;
     for (int i = 0; i < 8; ++i) key.w[i] = key_words[i];
-    const uint32_t nchunks = (n_total + (1u << chunk_bits) - 1) >> chunk_bits;
     static const uint32_t resident = resident_grid(k_match_emit<kMatchBlock, kMatchCap, kMatchSlots>, kMatchBlock);
-    const uint32_t grid = min(nchunks, resident);
+    static const uint32_t per_cu = max(1u, resident / max(1u, (uint32_t)device_cus()));
+    const uint32_t want = wg_per_cu ? min(wg_per_cu, per_cu) * (uint32_t)device_cus() : resident;
+    const uint32_t grid = max(1u, min(max_chunks, want));
     hipLaunchKernelGGL((k_match_emit<kMatchBlock, kMatchCap, kMatchSlots>), dim3(grid), dim3(kMatchBlock),
-                       0, s, key, keys, nonces, pcnt, n_total, chunk_bits, T, chunk_base, (uint4 *)t2, cap);
+                       0, s, key, keys, nonces, pcnt, n_total, chunk_bits, T, chunk_base, (uint4 *)t2, cap,
+                       r_lo, r_hi, last, ticket);
     return hipGetLastError();
 }
 

@@ -91,3 +91,15 @@ def test_partition_passes_follow_the_digit_split():
     bad = vx.make_params(bytes(32), 20)
     bad.k = 0
     assert vx.vx_partition_passes(bad) == 0
+
+
+def test_pipeline_slices_validation_and_split():
+    p = vx.make_params(bytes(32), 31)
+    assert vx.vx_workspace_bytes(p, vx.VX_CALL_PLOT, vx.make_tuning(pipeline_slices=17)) == 0
+    assert vx.vx_workspace_bytes(p, vx.VX_CALL_PLOT, vx.make_tuning(pipeline_slices=16)) > 0
+    # pipelined plans keep three passes at k=31 (8-6-6), unpipelined ones too (7-7-6)
+    assert vx.vx_partition_passes(p) == 3
+    assert vx.vx_partition_passes(p, vx.make_tuning(pipeline_slices=8)) == 3
+    # a pipelined 13-bit group plan takes three passes (1-6-6), an unpipelined one two
+    assert vx.vx_partition_passes(p, vx.make_tuning(group_bits=13, pipeline_slices=2)) == 3
+    assert vx.vx_partition_passes(p, vx.make_tuning(group_bits=13, pipeline_slices=1)) == 2

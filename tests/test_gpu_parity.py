@@ -94,6 +94,12 @@ TUNINGS = [
     dict(fused_sort_match=1, group_cap=64),   # fused kernel, most groups on its slow path
     dict(fused_sort_match=1, group_bits=3),   # fused kernel, few large groups
     dict(group_bits=20, pass1_bits=10),       # a 10-bit pass (wide-digit scatter)
+    dict(group_bits=13, pipeline_slices=2),   # pipelined tail: 1-6-6 passes, two slices
+    dict(group_bits=14, pipeline_slices=4),   # four slices, one per first-pass segment
+    dict(group_bits=12, pipeline_slices=3),   # pipelined with two passes, uneven slices
+    dict(group_bits=16, pipeline_slices=16, group_cap=64),   # 16 slices, oversized groups
+    dict(group_bits=15, pipeline_slices=5, match_chunk_bits=6),  # many small chunks per slice
+    dict(group_bits=9, pipeline_slices=4),    # one pass: nothing to pipeline
 ]
 
 
@@ -104,6 +110,19 @@ def test_plot_tunings_do_not_change_outputs(vx, tun):
     t = vx.make_tuning(**tun)
     b = vx.plot(KEY0, k, threshold=T, tuning=t)
     _assert_plot_equal(vx, b, ref)
+
+
+@pytest.mark.parametrize("T", [1 << 40, 1 << 44])
+def test_pipelined_plot_at_large_group_count(vx, T):
+    """k=22 with 2^18 groups (the group count of a k=29 plot): the pipelined
+    plan (6-6-6 passes, eight slices) and the sequential one against the
+    oracle."""
+    k = 22
+    ref = oracle.plot(KEY0, k, threshold=T, threads=8)
+    b = vx.plot(KEY0, k, threshold=T, tuning=vx.make_tuning(group_bits=18, pipeline_slices=8))
+    _assert_plot_equal(vx, b, ref)
+    b2 = vx.plot(KEY0, k, threshold=T, tuning=vx.make_tuning(group_bits=18))
+    _assert_plot_equal(vx, b2, ref)
 
 
 @pytest.mark.parametrize("T", [0, 1 << 34, 1 << 37, 1 << 40, (1 << 64) - 1])
