@@ -22,11 +22,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-STAGES = ["hash", "partition1", "partition2", "group_sort", "match_count", "match_emit"]
+STAGES = ["hash", "partition1", "partition2", "group_sort", "chunk_sums", "match_emit"]
 KERNEL_OF_STAGE = {"hash": "k_hash_table1", "match_emit": "k_match_emit",
                    "group_sort": "k_groupsort", "partition1": "k_scatter (pass 1)",
                    "partition2": "k_digit_hist + k_scatter (later passes)",
-                   "match_count": "k_match_count"}
+                   "chunk_sums": "k_chunk_sums + k_scan_*"}
 
 
 def log(*a):
@@ -313,8 +313,9 @@ def main() -> int:
     algo_bytes = {
         "partition1": n * (8 + 12),              # read key, write key+nonce
         "partition2": (npass - 1) * n * (12 + 12),  # each later pass reads and writes key+nonce
-        "group_sort": n * (12 + 12) + (vx.VX_NUM_BUCKETS + 1) * 4,
-        "match_count": n * 8,                    # read keys
+        # read and write key+nonce, offsets, one pair-count byte per record
+        "group_sort": n * (12 + 12 + 1) + (vx.VX_NUM_BUCKETS + 1) * 4,
+        "chunk_sums": n * 1,                     # read the count bytes
     }
     stages = {}
     for s in STAGES:
