@@ -150,6 +150,102 @@ def bench_batched(args) -> dict:
     }
 
 
+def bench_egress(args) -> dict:
+    """Plots of one k (default 28) whose Tables 2 leave the device through
+    vx_egress as flat plot files: compute alone, compute then egress one
+    plot at a time, and egress of plot i overlapped with the computation of
+    plot i + 1 (two buffer sets).  The sink is discarded by default (the
+    copy path alone: device -> pinned host memory -> writer thread); with
+    --egress-dir the files are written there."""
+    import torch
+    import paper_2606_14007_amd as vx
+    from paper_2606_14007_amd import egress as E
+    from vx_inputs import derive_key
+
+    k = args.egress_k
+    nplots = max(2, args.steps)
+    keys = [derive_key(100 + i) for i in range(nplots)]
+    sets = [vx.alloc_plot(k) for _ in range(2)]
+    fd = -1
+    path = None
+    if args.egress_dir:
+        path = os.path.join(args.egress_dir, f"plots_k{k}.bin")
+        fd = E.open_for_append(path)
+    eg = E.Egress(fd, slot_bytes=args.egress_slot_mb << 20, slots=args.egress_slots)
+    log(f"egress: {nplots} plots at k={k}, sink {'discard' if fd < 0 else path}, "
+        f"{args.egress_slots} x {args.egress_slot_mb} MiB pinned staging")
+    stream = torch.cuda.current_stream()
+
+    def compute_only():
+        for i in range(nplots):
+            vx.plot(keys[i], k, buffers=sets[i % 2])
+
+    def sequential():
+        for i in range(nplots):
+            b = sets[i % 2]
+            vx.plot(keys[i], k, buffers=b)
+            eg.wait(eg.submit(keys[i], k, b))
+
+    def overlapped():
+        jobs = []
+        for i in range(nplots):
+            b = sets[i % 2]
+            if i >= 2:
+                eg.wait(jobs[i - 2])     # this buffer set's previous Table 2 is out
+            vx.plot(keys[i], k, buffers=b)
+            jobs.append(eg.submit(keys[i], k, b))
+        eg.wait()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        b0 = eg.bytes
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        eg.wait()
+        return time.perf_counter() - t0, eg.bytes - b0
+
+    compute_only()
+    torch.cuda.synchronize()
+    t_comp, _ = timed(compute_only)
+    t_seq, by_seq = timed(sequential)
+    t_ovl, by_ovl = timed(overlapped)
+    # copy path alone: one finished plot egressed with nothing else running
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eg.wait(eg.submit(keys[0], k, sets[0]))
+    t_one = time.perf_counter() - t0
+    one_bytes = 128 + 16 * vx.t2_count(sets[0])
+    eg.close()
+    if fd >= 0:
+        os.close(fd)
+    for b in sets:
+        if vx.t2_count(b) > b.t2_capacity:
+            raise RuntimeError("Table 2 overflow")
+    log(f"compute only {t_comp * 1e3 / nplots:.1f} ms/plot; sequential egress "
+        f"{t_seq * 1e3 / nplots:.1f} ms/plot; overlapped {t_ovl * 1e3 / nplots:.1f} ms/plot; "
+        f"one Table 2 ({one_bytes / 1e9:.2f} GB) alone {t_one * 1e3:.1f} ms")
+    return {
+        "metric": f"K={k} plots/hour with Table-2 egress",
+        "value": round(nplots * 3600.0 / t_ovl, 1),
+        "unit": "plots/h",
+        "n_gpus": 1, "steps": nplots, "warmup": 1,
+        "ms_per_step": round(t_ovl * 1e3 / nplots, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"k={k} plots, keys from SplitMix64 seeds 100.., Table 2 "
+                               f"streamed to {'a discarding sink' if fd < 0 else 'plot files'}",
+                   "k": k, "slots": args.egress_slots, "slot_mib": args.egress_slot_mb,
+                   "parallelism": "single GPU"},
+        "compute_only_plots_per_hour": round(nplots * 3600.0 / t_comp, 1),
+        "sequential_egress_plots_per_hour": round(nplots * 3600.0 / t_seq, 1),
+        "overlapped_egress_plots_per_hour": round(nplots * 3600.0 / t_ovl, 1),
+        "egress_GBps_alone": round(one_bytes / t_one / 1e9, 2),
+        "egress_GBps_overlapped": round(by_ovl / t_ovl / 1e9, 2),
+        "table2_bytes_per_plot": one_bytes,
+    }
+
+
 def bench_serving(args) -> dict:
     """Poisson plot requests (SplitMix64 seed 5), k uniform in 22..30, at
     about 80% of the plain one-at-a-time service rate; continuous batching
@@ -216,10 +312,14 @@ def main() -> int:
     ap.add_argument("--k", type=int, default=31)
     ap.add_argument("--cpu-sample-k", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["k31", "batched", "serving"], default="k31",
+    ap.add_argument("--workload", choices=["k31", "batched", "serving", "egress"], default="k31",
                     help="k31: one whole plot (the default line); batched: the 32-plot mix; "
                          "serving: Poisson requests through the continuous-batching server")
     ap.add_argument("--requests", type=int, default=400, help="serving: number of requests")
+    ap.add_argument("--egress-k", type=int, default=28, help="egress: k of every plot")
+    ap.add_argument("--egress-dir", default=None, help="egress: write plot files here (default: discard)")
+    ap.add_argument("--egress-slots", type=int, default=4, help="egress: pinned staging buffers")
+    ap.add_argument("--egress-slot-mb", type=int, default=64, help="egress: MiB per staging buffer")
     ap.add_argument("--budget-gb", type=float, default=250.0, help="serving: HBM budget (GiB)")
     ap.add_argument("--autotune", action="store_true",
                     help="batched: use the cached autotuned tuning per k")
@@ -235,10 +335,10 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
-    if args.workload in ("batched", "serving"):
+    if args.workload in ("batched", "serving", "egress"):
         import torch
         torch.cuda.set_device(0)
-        fn = bench_batched if args.workload == "batched" else bench_serving
+        fn = {"batched": bench_batched, "serving": bench_serving, "egress": bench_egress}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return 0
 

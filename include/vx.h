@@ -51,6 +51,7 @@ typedef enum {
     VX_ERR_DEVICE = 3,        /* a HIP call failed; see vx_last_error() */
     VX_ERR_OUT_OF_MEMORY = 4, /* reserved for callers that allocate through the library */
     VX_ERR_UNSUPPORTED = 5,   /* a tuning value outside its supported range */
+    VX_ERR_IO = 6,            /* writing a plot file failed (vx_egress_*) */
 } vx_status;
 
 /* Device status word bits (vx_read_status). */
@@ -198,6 +199,56 @@ vx_status vx_read_status(const void *d_workspace, uint32_t *h_status, void *stre
 
 /* Message for the calling thread's last failed call ("" if none). */
 const char *vx_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Table-2 egress.  The paper's plotter copies Table 2 to the host and writes
+ * it to storage after the kernels (sec. III-A); at K=27..31 that copy and
+ * write take most of a plot's time (sec. IV), and overlapping them with the
+ * computation is the first item of its future work (sec. V).  A vx_egress
+ * streams finished Tables 2 off the device while the caller's stream goes on
+ * computing: it owns pinned host staging buffers (`slots` of `slot_bytes`),
+ * an internal copy stream and one writer thread, all on the device current
+ * at creation.  Each submitted plot becomes one flat plot file appended to
+ * the file descriptor, little-endian:
+ *   bytes   0..7    magic "VXPLOT01"
+ *   bytes   8..11   header bytes (128)      12..15  record bytes (16)
+ *   bytes  16..19   k                       20..23  bucket bits (24)
+ *   bytes  24..31   match threshold T
+ *   bytes  32..39   |Table 2| as counted on the device
+ *   bytes  40..47   records that follow: min(|Table 2|, t2_capacity)
+ *   bytes  48..79   the 32-byte plot key
+ *   bytes  80..127  zero
+ *   then the records in canonical order, 16 bytes each (vx_t2_record).
+ * The egress is not for HIP graph capture. */
+typedef struct vx_egress vx_egress;
+
+/* Creates an egress writing to `fd` (an open file descriptor that the caller
+ * keeps and closes; -1 discards the bytes, to measure the copy path alone).
+ * slot_bytes: a multiple of 16 in [1 MiB, 1 GiB]; slots: 2..64.  Argument
+ * errors return before any allocation. */
+vx_status vx_egress_create(int fd, size_t slot_bytes, uint32_t slots, vx_egress **out);
+
+/* Queues one plot file.  Once the work enqueued so far on `stream` is done,
+ * the writer thread reads *d_t2_count, copies min(*d_t2_count, t2_capacity)
+ * records of d_t2 piece by piece on the egress's stream -- overlapping
+ * whatever the caller enqueues next -- and appends the header and records to
+ * the file.  d_t2 and d_t2_count must not change until vx_egress_wait() has
+ * returned for this job.  *job receives its number (1, 2, ... in submission
+ * order).  Returns at once. */
+vx_status vx_egress_submit(vx_egress *e, const vx_plot_params *params, const vx_t2_record *d_t2,
+                           uint64_t t2_capacity, const uint64_t *d_t2_count, void *stream,
+                           uint64_t *job);
+
+/* Blocks until jobs 1..job are written (job = 0: all submitted so far).
+ * Returns the first error that any job hit (VX_ERR_IO, VX_ERR_DEVICE). */
+vx_status vx_egress_wait(vx_egress *e, uint64_t job);
+
+/* Bytes of plot files written (or discarded) so far. */
+uint64_t vx_egress_bytes(const vx_egress *e);
+
+/* Waits for every job, stops the writer thread and frees the egress (NULL is
+ * a no-op).  Returns the first error any job hit. */
+vx_status vx_egress_destroy(vx_egress *e);
 
 #ifdef __cplusplus
 }

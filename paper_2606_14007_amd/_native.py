@@ -19,7 +19,7 @@ VX_ERR_DEVICE = 3
 VX_ERR_OUT_OF_MEMORY = 4
 VX_ERR_UNSUPPORTED = 5
 STATUS_NAMES = {0: "VX_OK", 1: "VX_ERR_INVALID_ARG", 2: "VX_ERR_WORKSPACE", 3: "VX_ERR_DEVICE",
-                4: "VX_ERR_OUT_OF_MEMORY", 5: "VX_ERR_UNSUPPORTED"}
+                4: "VX_ERR_OUT_OF_MEMORY", 5: "VX_ERR_UNSUPPORTED", 6: "VX_ERR_IO"}
 
 VX_DEV_STATUS_GROUP_TOO_LARGE = 0x1
 VX_DEV_STATUS_LOOKBACK_TIMEOUT = 0x2
@@ -79,6 +79,12 @@ SYMBOLS = [
                                 C.POINTER(VxTuning), C.c_void_p]),
     ("vx_read_status", C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.c_void_p]),
     ("vx_last_error", C.c_char_p, []),
+    ("vx_egress_create", C.c_int, [C.c_int, C.c_size_t, C.c_uint32, C.POINTER(C.c_void_p)]),
+    ("vx_egress_submit", C.c_int, [C.c_void_p, C.POINTER(VxPlotParams), C.c_void_p, C.c_uint64, C.c_void_p,
+                                   C.c_void_p, C.POINTER(C.c_uint64)]),
+    ("vx_egress_wait", C.c_int, [C.c_void_p, C.c_uint64]),
+    ("vx_egress_bytes", C.c_uint64, [C.c_void_p]),
+    ("vx_egress_destroy", C.c_int, [C.c_void_p]),
 ]
 
 _lib = None
@@ -201,3 +207,30 @@ def vx_read_status(d_ws: int, stream: int = 0) -> int:
 
 def vx_last_error() -> str:
     return lib().vx_last_error().decode(errors="replace")
+
+
+def vx_egress_create(fd: int, slot_bytes: int, slots: int) -> int:
+    """Returns the opaque vx_egress handle (an int)."""
+    h = C.c_void_p(None)
+    _check(lib().vx_egress_create(fd, slot_bytes, slots, C.byref(h)), "vx_egress_create")
+    return int(h.value)
+
+
+def vx_egress_submit(handle: int, params: VxPlotParams, d_t2: int, t2_capacity: int, d_t2_count: int,
+                     stream: int = 0) -> int:
+    job = C.c_uint64(0)
+    _check(lib().vx_egress_submit(handle, C.byref(params), d_t2, t2_capacity, d_t2_count, stream,
+                                  C.byref(job)), "vx_egress_submit")
+    return int(job.value)
+
+
+def vx_egress_wait(handle: int, job: int = 0) -> None:
+    _check(lib().vx_egress_wait(handle, job), "vx_egress_wait")
+
+
+def vx_egress_bytes(handle: int) -> int:
+    return int(lib().vx_egress_bytes(handle))
+
+
+def vx_egress_destroy(handle: int) -> None:
+    _check(lib().vx_egress_destroy(handle), "vx_egress_destroy")

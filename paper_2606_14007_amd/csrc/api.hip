@@ -10,6 +10,7 @@
 #include <mutex>
 #include <vector>
 
+#include "errors.h"
 #include "kernels.h"
 #include "vx.h"
 
@@ -550,6 +551,10 @@ vx_status vx_match_table2(const vx_plot_params *params, const uint64_t *d_t1_key
 }
 
 }  // extern "C"
+
+namespace vxs {
+void set_error(const char *msg) { snprintf(g_err, sizeof(g_err), "%s", msg); }
+}  // namespace vxs
 
 namespace {
 
