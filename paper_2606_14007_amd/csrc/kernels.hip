@@ -217,16 +217,30 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ 
     for (uint32_t d = tid; d < nd; d += BLOCK) s_cursor[d] = off[(uint64_t)blockIdx.x * nd + d];
     uint64_t lo, hi;
     tile_range(geom, blockIdx.x, lo, hi);
+    // Loads of a sub-tile: indices past the tile are clamped to its last
+    // record (and ignored later), so every load is unconditional and a wave
+    // issues all of them before it waits for any.
+    auto load = [&](uint64_t b, uint64_t(&kk)[ITEMS], uint32_t(&nv)[ITEMS]) {
+        if (in_nonces) {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint64_t idx = b + (uint64_t)j * BLOCK + tid;
+                const uint64_t ic = idx < hi ? idx : hi - 1;
+                kk[j] = in_keys[ic];
+                nv[j] = in_nonces[ic];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint64_t idx = b + (uint64_t)j * BLOCK + tid;
+                kk[j] = in_keys[idx < hi ? idx : hi - 1];
+                nv[j] = (uint32_t)idx;
+            }
+        }
+    };
     uint64_t nk[ITEMS];
     uint32_t nn[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const uint64_t idx = lo + (uint64_t)j * BLOCK + tid;
-        if (idx < hi) {
-            nk[j] = in_keys[idx];
-            nn[j] = in_nonces ? in_nonces[idx] : (uint32_t)idx;
-        }
-    }
+    if (lo < hi) load(lo, nk, nn);
     for (uint64_t base = lo; base < hi; base += SUB) {
         uint64_t k[ITEMS];
         uint32_t n[ITEMS], slot[ITEMS];
@@ -244,14 +258,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ 
         }
         // Prefetch the next sub-tile.
         const uint64_t nbase = base + SUB;
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const uint64_t idx = nbase + (uint64_t)j * BLOCK + tid;
-            if (idx < hi) {
-                nk[j] = in_keys[idx];
-                nn[j] = in_nonces ? in_nonces[idx] : (uint32_t)idx;
-            }
-        }
+        if (nbase < hi) load(nbase, nk, nn);
         __syncthreads();
         const uint32_t total = vxd::lds_exclusive_scan<BLOCK>(s_start, (int)nd, s_wave);
         if (tid == 0) s_start[nd] = total;
@@ -374,14 +381,14 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys
         const uint32_t lo = gstart[g], n = gstart[g + 1] - lo;
         uint64_t k[ITEMS];
         uint32_t nn[ITEMS], slot[ITEMS];
-        if (n <= cap) {
+        if (n <= cap && n > 0) {
+            // Clamped, unconditional loads: a wave issues all before waiting.
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) {
                 const uint32_t e = j * BLOCK + tid;
-                if (e < n) {
-                    k[j] = keys[lo + e];
-                    nn[j] = nonces[lo + e];
-                }
+                const uint32_t ec = e < n ? e : n - 1;
+                k[j] = keys[lo + ec];
+                nn[j] = nonces[lo + ec];
             }
         }
         if (n > cap) {
