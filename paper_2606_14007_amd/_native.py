@@ -97,8 +97,7 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(
                 f"libvx.so not found at {LIB_PATH}: build it with "
-                "`python -c 'import __graft_entry__ as g; g.build()'` "
-                "(there is no fallback path)")
+                "`python paper_2606_14007_amd/build.py` (there is no fallback path)")
         L = C.CDLL(LIB_PATH)
         for name, res, args in SYMBOLS:
             f = getattr(L, name)
