@@ -304,6 +304,88 @@ def bench_serving(args) -> dict:
     }
 
 
+def bench_chunked(args) -> dict:
+    """One whole plot made as 2^c chunks through vx_plot_chunk (default
+    k=32, c=1: 2^32 nonces, two chunks of 2^23 buckets; one set of chunk
+    buffers serves both).  Seconds per whole plot, and per chunk.  At k <= 31
+    the same plot through vx_plot is timed too, for the cost of chunking."""
+    import torch
+    import paper_2606_14007_amd as vx
+    from vx_inputs import derive_key
+
+    k, c = args.chunk_k, args.chunk_bits
+    key = derive_key(0)
+    b = vx.alloc_chunk(k, c)
+    log(f"chunked: k={k} in {1 << c} chunks, {b.nbytes() / 2**30:.1f} GiB of chunk buffers")
+    nchunks = 1 << c
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nchunks + 1)]
+
+    def whole_plot(timed_chunks=None):
+        t1 = t2 = 0
+        for r in range(nchunks):
+            if timed_chunks is not None:
+                evs[r].record()
+            vx.plot_chunk(key, k, c, r, b)
+            t2n = vx.t2_count(b)  # synchronises; the buffers are reused by the next chunk
+            if t2n > b.t2_capacity:
+                raise RuntimeError("Table 2 overflow")
+            t1 += int(b.t1_count.item())
+            t2 += t2n
+        if timed_chunks is not None:
+            evs[nchunks].record()
+        return t1, t2
+
+    for _ in range(max(1, args.warmup)):
+        whole_plot()
+    if vx.device_status(b.workspace):
+        raise RuntimeError("device status")
+    steps = max(1, args.steps)
+    chunk_ms = [0.0] * nchunks
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t1, t2 = whole_plot(timed_chunks=True)
+        torch.cuda.synchronize()
+        for r in range(nchunks):
+            chunk_ms[r] += evs[r].elapsed_time(evs[r + 1]) / steps
+    sec = (time.perf_counter() - t0) / steps
+    if t1 != 1 << k:
+        raise RuntimeError(f"chunks hold {t1} records, not 2^{k}")
+    log(f"k={k}: {sec * 1e3:.1f} ms per plot in {nchunks} chunks "
+        f"({', '.join(f'{x:.1f}' for x in chunk_ms)} ms)")
+    out = {
+        "metric": f"K={k} plot seconds (chunked)",
+        "value": round(sec, 5),
+        "unit": "s",
+        "n_gpus": 1, "steps": steps, "warmup": max(1, args.warmup),
+        "ms_per_step": round(sec * 1e3, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"k={k} single plot in {nchunks} chunks of {1 << (24 - c)} buckets",
+                   "k": k, "chunk_bits": c, "key_seed": 0, "threshold": f"2^{64 - k}",
+                   "parallelism": "single GPU"},
+        "chunk_ms": [round(x, 3) for x in chunk_ms],
+        "table1_records": t1, "table2_records": t2,
+        "chunk_buffer_bytes": b.nbytes(),
+        "blake3_hashes_per_s_useful": round(((1 << k) + t2) / sec, 1),
+    }
+    if k <= 31:
+        del b
+        torch.cuda.empty_cache()
+        wb = vx.alloc_plot(k)
+        vx.plot(key, k, buffers=wb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            vx.plot(key, k, buffers=wb)
+        torch.cuda.synchronize()
+        ws = (time.perf_counter() - t0) / steps
+        log(f"k={k}: {ws * 1e3:.1f} ms as one vx_plot")
+        out["whole_plot_ms"] = round(ws * 1e3, 3)
+        out["chunking_cost"] = round(sec / ws, 3)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,9 +394,12 @@ def main() -> int:
     ap.add_argument("--k", type=int, default=31)
     ap.add_argument("--cpu-sample-k", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["k31", "batched", "serving", "egress"], default="k31",
+    ap.add_argument("--workload", choices=["k31", "batched", "serving", "egress", "chunked"], default="k31",
                     help="k31: one whole plot (the default line); batched: the 32-plot mix; "
-                         "serving: Poisson requests through the continuous-batching server")
+                         "serving: Poisson requests through the continuous-batching server; "
+                         "egress: Table 2 streamed to plot files; chunked: one plot in chunks")
+    ap.add_argument("--chunk-k", type=int, default=32, help="chunked: k of the plot")
+    ap.add_argument("--chunk-bits", type=int, default=1, help="chunked: 2^c chunks")
     ap.add_argument("--requests", type=int, default=400, help="serving: number of requests")
     ap.add_argument("--egress-k", type=int, default=28, help="egress: k of every plot")
     ap.add_argument("--egress-dir", default=None, help="egress: write plot files here (default: discard)")
@@ -335,10 +420,11 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
-    if args.workload in ("batched", "serving", "egress"):
+    if args.workload in ("batched", "serving", "egress", "chunked"):
         import torch
         torch.cuda.set_device(0)
-        fn = {"batched": bench_batched, "serving": bench_serving, "egress": bench_egress}[args.workload]
+        fn = {"batched": bench_batched, "serving": bench_serving, "egress": bench_egress,
+              "chunked": bench_chunked}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return 0
 

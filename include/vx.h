@@ -193,6 +193,44 @@ vx_status vx_plot_with_events(const vx_plot_params *params, const vx_plot_buffer
 vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buffers,
                         uint32_t n, const vx_tuning *tuning, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Chunked plots.  A plot can be made in 2^chunk_bits chunks of its bucket
+ * space: chunk r holds the buckets whose top chunk_bits bits equal r
+ * (buckets [r * 2^(24 - chunk_bits), (r + 1) * 2^(24 - chunk_bits))).  Each
+ * chunk hashes every nonce of the plot, keeps its own records, and sorts and
+ * matches them like a whole plot; pairs never cross buckets (sec. III-A),
+ * so Table 2 of a chunk is exactly that of its buckets.  The whole plot's
+ * Table 1 and Table 2 are the chunks' in chunk order, and its bucket offsets
+ * those of each chunk plus the records of the chunks before it.  Device
+ * memory is then bounded by one chunk, and k = 32 -- 2^32 records, more
+ * than the 32-bit offsets of a whole plot hold -- is made in two or more
+ * chunks (the paper plots up to K=31 and names larger plots as future work,
+ * sec. V).  k may be 32 in these calls; nonces stay 4-byte little-endian. */
+
+/* Table-1 records a chunk holds with overwhelming probability (expectation
+ * plus 8 standard deviations plus 4096), or 0 if that reaches 2^32 or the
+ * arguments are out of range (k in [1, 32], chunk_bits in [0, 8] and at most
+ * k).  *t2_capacity (may be NULL) receives the matching Table-2 capacity for
+ * threshold T. */
+uint64_t vx_chunk_capacity_hint(uint32_t k, uint32_t chunk_bits, uint64_t threshold, uint64_t *t2_capacity);
+
+/* Workspace bytes of vx_plot_chunk for up to t1_capacity records (0 for
+ * invalid arguments or a fused tuning). */
+size_t vx_chunk_workspace_bytes(const vx_plot_params *params, uint32_t chunk_bits, uint64_t t1_capacity,
+                                const vx_tuning *tuning);
+
+/* Chunk `chunk` of a plot cut by chunk_bits: writes the chunk's Table 1
+ * (m records; t1_keys / t1_nonces must hold t1_capacity), its bucket offsets
+ * (2^24 + 1 entries; buckets before the chunk's range get 0, those after it
+ * m), its Table 2 and count as vx_plot does, and m to *d_t1_count.  Unlike
+ * the other calls it synchronises `stream` once, after the hash, to plan
+ * the sort for m records.  Returns VX_ERR_WORKSPACE if m exceeds t1_capacity
+ * (nothing further is written).  The fused sort + match tuning is not
+ * supported here. */
+vx_status vx_plot_chunk(const vx_plot_params *params, uint32_t chunk_bits, uint32_t chunk,
+                        const vx_plot_buffers *buffers, uint64_t t1_capacity, uint64_t *d_t1_count,
+                        const vx_tuning *tuning, void *stream);
+
 /* Copies the device status word at the start of a workspace used by
  * vx_bucket_sort or vx_plot to *h_status (synchronising `stream`). */
 vx_status vx_read_status(const void *d_workspace, uint32_t *h_status, void *stream);

@@ -14,9 +14,10 @@ from ._native import (VX_BUCKET_BITS, VX_CALL_BUCKET_SORT, VX_CALL_MATCH, VX_CAL
                       VX_PLOT_EVENTS, vx_read_status,
                       vx_partition_passes, vx_t2_capacity_hint, vx_workspace_bytes,
                       vx_egress_create, vx_egress_submit, vx_egress_wait, vx_egress_bytes,
-                      vx_egress_destroy)
-from .plotter import (T2_DTYPE, PlotBuffers, alloc_plot, bucket_sort, device_status,
-                      footprint_bytes, hash_table1, match_table2, plot, t2_count, t2_records,
+                      vx_egress_destroy, vx_chunk_capacity_hint, vx_chunk_workspace_bytes,
+                      vx_plot_chunk)
+from .plotter import (T2_DTYPE, ChunkBuffers, PlotBuffers, alloc_chunk, alloc_plot, bucket_sort, device_status,
+                      footprint_bytes, hash_table1, match_table2, plot, plot_chunk, t2_count, t2_records,
                       u32, u64)
 
 __all__ = [n for n in dir() if not n.startswith("_")]

@@ -79,6 +79,11 @@ SYMBOLS = [
                                 C.POINTER(VxTuning), C.c_void_p]),
     ("vx_read_status", C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.c_void_p]),
     ("vx_last_error", C.c_char_p, []),
+    ("vx_chunk_capacity_hint", C.c_uint64, [C.c_uint32, C.c_uint32, C.c_uint64, C.POINTER(C.c_uint64)]),
+    ("vx_chunk_workspace_bytes", C.c_size_t, [C.POINTER(VxPlotParams), C.c_uint32, C.c_uint64,
+                                              C.POINTER(VxTuning)]),
+    ("vx_plot_chunk", C.c_int, [C.POINTER(VxPlotParams), C.c_uint32, C.c_uint32, C.POINTER(VxPlotBuffers),
+                                C.c_uint64, C.c_void_p, C.POINTER(VxTuning), C.c_void_p]),
     ("vx_egress_create", C.c_int, [C.c_int, C.c_size_t, C.c_uint32, C.POINTER(C.c_void_p)]),
     ("vx_egress_submit", C.c_int, [C.c_void_p, C.POINTER(VxPlotParams), C.c_void_p, C.c_uint64, C.c_void_p,
                                    C.c_void_p, C.POINTER(C.c_uint64)]),
@@ -206,6 +211,24 @@ def vx_read_status(d_ws: int, stream: int = 0) -> int:
 
 def vx_last_error() -> str:
     return lib().vx_last_error().decode(errors="replace")
+
+
+def vx_chunk_capacity_hint(k: int, chunk_bits: int, threshold: int):
+    """(Table-1 capacity, Table-2 capacity) of one chunk; (0, 0) if invalid."""
+    t2 = C.c_uint64(0)
+    t1 = int(lib().vx_chunk_capacity_hint(k, chunk_bits, threshold, C.byref(t2)))
+    return t1, int(t2.value)
+
+
+def vx_chunk_workspace_bytes(params: VxPlotParams, chunk_bits: int, t1_capacity: int,
+                             tuning: Optional[VxTuning] = None) -> int:
+    return int(lib().vx_chunk_workspace_bytes(C.byref(params), chunk_bits, t1_capacity, _tref(tuning)))
+
+
+def vx_plot_chunk(params: VxPlotParams, chunk_bits: int, chunk: int, buffers: VxPlotBuffers, t1_capacity: int,
+                  d_t1_count: int, tuning: Optional[VxTuning] = None, stream: int = 0) -> None:
+    _check(lib().vx_plot_chunk(C.byref(params), chunk_bits, chunk, C.byref(buffers), t1_capacity, d_t1_count,
+                               _tref(tuning), stream), "vx_plot_chunk")
 
 
 def vx_egress_create(fd: int, slot_bytes: int, slots: int) -> int:

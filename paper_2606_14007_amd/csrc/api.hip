@@ -67,19 +67,23 @@ uint32_t clampu(int64_t v, int64_t lo, int64_t hi) {
     return (uint32_t)(v < lo ? lo : (v > hi ? hi : v));
 }
 
-vx_status check_params(const vx_plot_params *p) {
+vx_status check_params(const vx_plot_params *p, uint32_t max_k = 31) {
     if (!p) return fail(VX_ERR_INVALID_ARG, "params is NULL");
-    if (p->k < 1 || p->k > 31) return fail(VX_ERR_INVALID_ARG, "k must be in [1, 31]");
+    if (p->k < 1 || p->k > max_k)
+        return fail(VX_ERR_INVALID_ARG, max_k == 31 ? "k must be in [1, 31]" : "k must be in [1, 32]");
     if (p->bucket_bits != VX_BUCKET_BITS) return fail(VX_ERR_INVALID_ARG, "bucket_bits must be 24");
     return VX_OK;
 }
 
-vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl) {
-    vx_status st = check_params(p);
+// records: the table's size when it is not 2^k (a chunk of a chunked plot,
+// at most 2^32 - 1); 0 = 2^k.  Groups, digits and the threshold follow k.
+vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint64_t records = 0,
+                    uint32_t max_k = 31) {
+    vx_status st = check_params(p, max_k);
     if (st != VX_OK) return st;
     Plan P;
     P.k = p->k;
-    P.n = 1ull << p->k;
+    P.n = records ? records : 1ull << p->k;
     for (int i = 0; i < 8; ++i)
         P.key_words[i] = (uint32_t)p->key[4 * i] | ((uint32_t)p->key[4 * i + 1] << 8) |
                          ((uint32_t)p->key[4 * i + 2] << 16) | ((uint32_t)p->key[4 * i + 3] << 24);
@@ -88,7 +92,7 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl) {
     memset(&z, 0, sizeof(z));
     if (!t) t = &z;
     // Sort groups of about 2048 records (half the LDS capacity).
-    P.G = t->group_bits ? t->group_bits : clampu((int64_t)p->k - 11, 1, 20);
+    P.G = t->group_bits ? t->group_bits : clampu((int64_t)p->k - 11, 1, 21);
     if (P.G < 1 || P.G > 24) return fail(VX_ERR_UNSUPPORTED, "group_bits must be in [1, 24]");
     // Split G into passes of at most 9 bits (7-7-6 at k=31) so that every
     // digit's run per sub-tile spans whole cache lines.  The first pass
@@ -166,6 +170,7 @@ struct Layout {
     size_t lbwords = 0;           // u64[2^G] look-back words of the fused sort + match
     size_t mcount = 0, mbase = 0; // u64[match chunks]: pair counts, Table-2 bases
     size_t pcnt = 0;              // u8[n]: pair count of each Table-1 record (255 = look again)
+    size_t nonces_in = 0;         // u32[n]: nonces of a chunk's records (chunked plots)
     size_t mpart = 0;             // u64[scan parts]
     size_t total = 0;
 };
@@ -175,11 +180,15 @@ constexpr uint32_t kHeaderWords = 64;
 constexpr uint32_t kHdrStatus = 0;       // device status bits
 constexpr uint32_t kHdrFusedTicket = 2;  // group ticket of the fused sort + match
 constexpr uint32_t kHdrAcc = 4;          // u64 (words 4, 5): Table-2 records of the slices scanned so far
+constexpr uint32_t kHdrChunkCount = 6;   // u64 (words 6, 7): records a chunk's hash kept
 constexpr uint32_t kHdrOvf = 8;          // per slice: oversized groups found
 constexpr uint32_t kHdrSortTicket = 8 + kMaxSlices;       // per slice: group ticket of the sort
 constexpr uint32_t kHdrEmitTicket = 8 + 2 * kMaxSlices;   // per slice: chunk ticket of the match
 static_assert(kHdrEmitTicket + kMaxSlices <= kHeaderWords, "header holds every slice's words");
 constexpr uint32_t kLookbackSpinLimit = 1u << 20;
+
+constexpr int kCallChunk = 4;  // internal: the workspace of vx_plot_chunk
+constexpr uint32_t kMaxChunkBits = 8;
 
 uint32_t match_chunks(const Plan &P) { return (uint32_t)((P.n + (1ull << P.cb) - 1) >> P.cb); }
 
@@ -196,9 +205,12 @@ Layout layout(const Plan &P, int which) {
         return o;
     };
     L.header = take(kHeaderWords * 4);
+    const bool chunk = which == kCallChunk;
+    if (chunk) which = VX_CALL_PLOT;
     const bool sort = which == VX_CALL_BUCKET_SORT || which == VX_CALL_PLOT;
     const bool match = which == VX_CALL_MATCH || which == VX_CALL_PLOT;
     if (which == VX_CALL_PLOT) L.keys_no = take(P.n * 8);
+    if (chunk) L.nonces_in = take(P.n * 4);
     if (sort) {
         L.scr_keys = take(P.n * 8);
         L.scr_nonces = take(P.n * 4);
@@ -245,14 +257,14 @@ struct PassBufs {
 };
 
 PassBufs pass_bufs(const Plan &P, const Layout &L, void *ws, const uint64_t *keys_no, uint64_t *t1_keys,
-                   uint32_t *t1_nonces, uint32_t i) {
+                   uint32_t *t1_nonces, uint32_t i, const uint32_t *nonces_in = nullptr) {
     uint64_t *scr_k = at<uint64_t>(ws, L.scr_keys);
     uint32_t *scr_n = at<uint32_t>(ws, L.scr_nonces);
     auto to_t1 = [&](uint32_t j) { return ((P.npass - 1 - j) % 2) == 0; };
     PassBufs B;
     if (i == 0) {
         B.in_k = keys_no;
-        B.in_n = nullptr;
+        B.in_n = nonces_in;
     } else {
         B.in_k = to_t1(i - 1) ? t1_keys : scr_k;
         B.in_n = to_t1(i - 1) ? t1_nonces : scr_n;
@@ -286,9 +298,9 @@ vx_status run_pass(const Plan &P, const Layout &L, void *ws, const PassBufs &B, 
 // over caller keys).
 vx_status run_partition(const Plan &P, const Layout &L, void *ws, const uint64_t *keys_no,
                         bool hist_done, uint64_t *t1_keys, uint32_t *t1_nonces, uint32_t npass_run,
-                        hipStream_t s, hipEvent_t *ev) {
+                        hipStream_t s, hipEvent_t *ev, const uint32_t *nonces_in = nullptr) {
     for (uint32_t i = 0; i < npass_run; ++i) {
-        const PassBufs B = pass_bufs(P, L, ws, keys_no, t1_keys, t1_nonces, i);
+        const PassBufs B = pass_bufs(P, L, ws, keys_no, t1_keys, t1_nonces, i, nonces_in);
         if (i == 0) {
             uint32_t *hist = at<uint32_t>(ws, L.hist[0]), *off = at<uint32_t>(ws, L.off[0]);
             uint32_t *gst = at<uint32_t>(ws, L.gstart[0]);
@@ -298,7 +310,7 @@ vx_status run_partition(const Plan &P, const Layout &L, void *ws, const uint64_t
                 VX_HIP(vxk::launch_hist_chunks(B.in_k, P.n, P.W, P.chunk1, shift, P.D[0], hist, s),
                        "pass-0 histogram");
             VX_HIP(vxk::launch_colscan(hist, off, 1, P.W, nd, nullptr, gst, nd, (uint32_t)P.n, s), "pass-0 scan");
-            VX_HIP(vxk::launch_scatter_chunks(B.in_k, nullptr, B.out_k, B.out_n, off, P.n, P.W, P.chunk1, shift,
+            VX_HIP(vxk::launch_scatter_chunks(B.in_k, B.in_n, B.out_k, B.out_n, off, P.n, P.W, P.chunk1, shift,
                                               P.D[0], s),
                    "pass-0 scatter");
         } else {
@@ -546,6 +558,92 @@ vx_status vx_match_table2(const vx_plot_params *params, const uint64_t *d_t1_key
            "match count");
     st = run_match(P, L, d_workspace, d_t1_keys, d_t1_nonces, d_t2, t2_capacity, d_t2_count, nullptr, nullptr, 1,
                    0, 0, s);
+    if (st == VX_OK) g_err[0] = 0;
+    return st;
+}
+
+uint64_t vx_chunk_capacity_hint(uint32_t k, uint32_t chunk_bits, uint64_t threshold, uint64_t *t2_capacity) {
+    if (t2_capacity) *t2_capacity = 0;
+    if (k < 1 || k > 32 || chunk_bits > kMaxChunkBits || chunk_bits > k) return 0;
+    const double recs = __builtin_ldexp(1.0, (int)k - (int)chunk_bits);
+    const double cap1 = recs + 8.0 * __builtin_sqrt(recs) + 4096.0;
+    if (cap1 >= 4294967296.0) return 0;  // a chunk holds fewer than 2^32 records
+    if (t2_capacity) {
+        // As vx_t2_capacity_hint, for the chunk's share of the records.
+        const double lam = __builtin_ldexp(1.0, (int)k - 24);
+        const double w = (double)(1ull << 40);
+        const double t = threshold >= (1ull << 40) ? w : (double)threshold;
+        const double expect = recs * lam * (t / w) * (1.0 - 0.5 * t / w);
+        *t2_capacity = (uint64_t)(expect * 1.05 + 8.0 * __builtin_sqrt(expect + 1.0) + 4096.0);
+    }
+    return (uint64_t)cap1;
+}
+
+size_t vx_chunk_workspace_bytes(const vx_plot_params *params, uint32_t chunk_bits, uint64_t t1_capacity,
+                                const vx_tuning *tuning) {
+    Plan P;
+    if (chunk_bits > kMaxChunkBits || t1_capacity == 0 || t1_capacity >= (1ull << 32)) return 0;
+    if (make_plan(params, tuning, &P, t1_capacity, 32) != VX_OK) return 0;
+    if (P.fused) return 0;
+    return layout(P, kCallChunk).total;
+}
+
+vx_status vx_plot_chunk(const vx_plot_params *params, uint32_t chunk_bits, uint32_t chunk,
+                        const vx_plot_buffers *b, uint64_t t1_capacity, uint64_t *d_t1_count,
+                        const vx_tuning *tuning, void *stream) {
+    Plan Pc;
+    vx_status st = make_plan(params, tuning, &Pc, t1_capacity ? t1_capacity : 1, 32);
+    if (st != VX_OK) return st;
+    if (chunk_bits > kMaxChunkBits || chunk >= (1u << chunk_bits))
+        return fail(VX_ERR_INVALID_ARG, "chunk_bits must be at most 8 and chunk below 2^chunk_bits");
+    if (t1_capacity == 0 || t1_capacity >= (1ull << 32))
+        return fail(VX_ERR_INVALID_ARG, "t1_capacity must be in [1, 2^32)");
+    if (Pc.fused) return fail(VX_ERR_UNSUPPORTED, "chunked plots use the split sort and match");
+    if (!b || !d_t1_count) return fail(VX_ERR_INVALID_ARG, "buffers or d_t1_count is NULL");
+    if (!b->t1_keys || !b->t1_nonces || !b->bucket_offsets || !b->t2_count || (b->t2_capacity && !b->t2))
+        return fail(VX_ERR_INVALID_ARG, "NULL buffer");
+    if (!aligned(b->t1_keys, 8) || !aligned(b->t1_nonces, 4) || !aligned(b->bucket_offsets, 4) ||
+        !aligned(b->t2_count, 8) || !aligned(d_t1_count, 8) || (b->t2 && !aligned(b->t2, 16)))
+        return fail(VX_ERR_INVALID_ARG, "misaligned buffer");
+    Layout L = layout(Pc, kCallChunk);
+    if ((st = check_ws(L, b->workspace, b->workspace_bytes)) != VX_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    void *ws = b->workspace;
+    uint32_t *hdr = at<uint32_t>(ws, L.header);
+    uint64_t *keys_in = at<uint64_t>(ws, L.keys_no);
+    uint32_t *nonces_in = at<uint32_t>(ws, L.nonces_in);
+    unsigned long long *count = reinterpret_cast<unsigned long long *>(hdr + kHdrChunkCount);
+    VX_HIP(vxk::launch_reset(hdr, kHeaderWords, s), "reset");
+    // Hash every nonce of the plot and keep this chunk's bucket range.
+    const uint64_t n_all = 1ull << params->k;
+    const uint32_t tiles = clampu((int64_t)(n_all >> 16), 1, 16384);
+    VX_HIP(vxk::launch_hash_filter(Pc.key_words, n_all, tiles, (n_all + tiles - 1) / tiles, chunk_bits, chunk,
+                                   keys_in, nonces_in, t1_capacity, count, s),
+           "chunk hash");
+    // The sort is planned for the records kept: wait for their number.
+    uint64_t m = 0;
+    VX_HIP(hipMemcpyAsync(&m, count, sizeof(m), hipMemcpyDeviceToHost, s), "chunk count");
+    VX_HIP(hipStreamSynchronize(s), "chunk count");
+    VX_HIP(hipMemcpyAsync(d_t1_count, &m, sizeof(m), hipMemcpyHostToDevice, s), "chunk count");
+    VX_HIP(hipStreamSynchronize(s), "chunk count");
+    if (m > t1_capacity) return fail(VX_ERR_WORKSPACE, "the chunk holds more records than t1_capacity");
+    if (m == 0) {
+        VX_HIP(vxk::launch_fill_u32(b->bucket_offsets, (uint64_t)VX_NUM_BUCKETS + 1, 0u, s), "empty chunk");
+        VX_HIP(vxk::launch_zero_u64(b->t2_count, 1, s), "empty chunk");
+        g_err[0] = 0;
+        return VX_OK;
+    }
+    Plan P;
+    if ((st = make_plan(params, tuning, &P, m, 32)) != VX_OK) return st;
+    // Same groups and digits as the capacity plan, so L fits (it was sized
+    // for t1_capacity >= m records).
+    st = run_partition(P, L, ws, keys_in, false, b->t1_keys, b->t1_nonces, P.npass, s, nullptr, nonces_in);
+    if (st == VX_OK)
+        st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, at<uint8_t>(ws, L.pcnt), 0,
+                            1u << P.G, 0, s);
+    if (st == VX_OK)
+        st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, nullptr, nullptr, 1,
+                       0, 0, s);
     if (st == VX_OK) g_err[0] = 0;
     return st;
 }

@@ -232,14 +232,14 @@ vx_status vx_egress_submit(vx_egress *e, const vx_plot_params *params, const vx_
                            uint64_t *job) {
     if (!e || !params || !d_t2_count || (t2_capacity && !d_t2))
         return fail(VX_ERR_INVALID_ARG, "NULL egress, params or buffer");
-    if (params->k < 1 || params->k > 31) return fail(VX_ERR_INVALID_ARG, "k must be in [1, 31]");
+    if (params->k < 1 || params->k > 32) return fail(VX_ERR_INVALID_ARG, "k must be in [1, 32]");
     if (((uintptr_t)d_t2 % 16) || ((uintptr_t)d_t2_count % 8)) return fail(VX_ERR_INVALID_ARG, "misaligned buffer");
     Job j;
     j.t2 = d_t2;
     j.cap = t2_capacity;
     j.count = d_t2_count;
     j.k = params->k;
-    j.T = params->match_threshold ? params->match_threshold : (1ull << (64 - params->k));
+    j.T = params->match_threshold;
     memcpy(j.key, params->key, 32);
     hipError_t h = hipEventCreateWithFlags(&j.ready, hipEventDisableTiming);
     if (h == hipSuccess) h = hipEventRecord(j.ready, (hipStream_t)stream);

@@ -18,6 +18,13 @@ constexpr uint32_t kFallbackMax = 1u << 20;  // largest group the fallback sorts
 constexpr int kMatchChunkBitsMax = 11;  // match chunk = 2^bits records (LDS capacity 2048)
 
 hipError_t launch_reset(uint32_t *words, uint32_t n, hipStream_t s);
+// Chunked plots: hash all n nonces, keep keys whose top pbits bits are
+// `prefix`; *count (zero at launch) receives how many (records past cap are
+// not written).
+hipError_t launch_hash_filter(const uint32_t key_words[8], uint64_t n, uint32_t tiles, uint64_t chunk,
+                              uint32_t pbits, uint32_t prefix, uint64_t *keys, uint32_t *nonces, uint64_t cap,
+                              unsigned long long *count, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_hash_table1(const uint32_t key_words[8], uint64_t n, uint32_t tiles, uint64_t chunk,
                               uint64_t *keys, uint32_t *hist, uint32_t hist_bits, hipStream_t s);
 hipError_t launch_hist_chunks(const uint64_t *keys, uint64_t n, uint32_t tiles, uint64_t chunk,

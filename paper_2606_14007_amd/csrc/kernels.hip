@@ -94,6 +94,69 @@ __global__ __launch_bounds__(BLOCK) void k_hash_table1(Key key, uint64_t n, uint
 }
 
 // ---------------------------------------------------------------------------
+// Table-1 hash of one bucket range (chunked plots): every nonce of the tile
+// is hashed and the records whose key has `prefix` in its top `pbits` bits
+// are kept.  Per sub-tile of BLOCK * ITEMS nonces, wave w hashes a contiguous
+// run of 64 * ITEMS nonces and packs its matches into its own LDS region
+// (ballot + mbcnt), the work-group claims room for the sub-tile's matches
+// with one global atomic on *count, and each wave copies its run out.  The
+// output is in no particular order (the sort orders records fully); records
+// past `cap` are counted but not written.
+// ---------------------------------------------------------------------------
+
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_hash_filter(Key key, uint64_t n, uint64_t chunk, uint32_t pbits,
+                                                       uint32_t prefix, uint64_t *__restrict__ out_keys,
+                                                       uint32_t *__restrict__ out_nonces, uint64_t cap,
+                                                       unsigned long long *__restrict__ count) {
+    constexpr int NW = BLOCK / 64;
+    constexpr int PER_WAVE = 64 * ITEMS;
+    __shared__ uint64_t s_k[BLOCK * ITEMS];
+    __shared__ uint32_t s_n[BLOCK * ITEMS];
+    __shared__ uint32_t s_wc[NW];
+    __shared__ unsigned long long s_base;
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    const uint64_t lo = (uint64_t)blockIdx.x * chunk;
+    const uint64_t hi = lo + chunk < n ? lo + chunk : n;
+    for (uint64_t base = lo; base < hi; base += (uint64_t)BLOCK * ITEMS) {
+        uint32_t cnt = 0;  // matches of this wave so far (same in every lane)
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint64_t i = base + (uint64_t)w * PER_WAVE + (uint64_t)j * 64 + lane;
+            uint32_t nonce = (uint32_t)i;
+            asm volatile("" : "+v"(nonce));  // as in k_hash_table1
+            const uint64_t a = vxd::h1(key, nonce);
+            const bool m = i < hi && (pbits == 0 || (uint32_t)(a >> (64 - pbits)) == prefix);
+            const uint64_t bal = __ballot(m);
+            if (m) {
+                const uint32_t pos = cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                s_k[w * PER_WAVE + pos] = a;
+                s_n[w * PER_WAVE + pos] = (uint32_t)i;
+            }
+            cnt += (uint32_t)__popcll(bal);
+        }
+        if (lane == 0) s_wc[w] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long tot = 0;
+            for (int x = 0; x < NW; ++x) tot += s_wc[x];
+            s_base = tot ? atomicAdd(count, tot) : 0ull;
+        }
+        __syncthreads();
+        unsigned long long wb = s_base;
+        for (uint32_t x = 0; x < w; ++x) wb += s_wc[x];
+        for (uint32_t p = lane; p < cnt; p += 64) {
+            const unsigned long long o = wb + p;
+            if (o < cap) {
+                out_keys[o] = s_k[w * PER_WAVE + p];
+                out_nonces[o] = s_n[w * PER_WAVE + p];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Digit histogram per tile
 // ---------------------------------------------------------------------------
 
@@ -1258,6 +1321,26 @@ constexpr int kMatchBlock = 512;
 constexpr int kMatchCap = 2048;
 constexpr int kMatchSlots = 4096;
 constexpr int kMatchWindow = 2048;
+
+hipError_t launch_hash_filter(const uint32_t key_words[8], uint64_t n, uint32_t tiles, uint64_t chunk,
+                              uint32_t pbits, uint32_t prefix, uint64_t *keys, uint32_t *nonces, uint64_t cap,
+                              unsigned long long *count, hipStream_t s) {
+    Key key;
+    for (int i = 0; i < 8; ++i) key.w[i] = key_words[i];
+    hipLaunchKernelGGL((k_hash_filter<kHashBlock, 8>), dim3(tiles), dim3(kHashBlock), 0, s, key, n, chunk, pbits,
+                       prefix, keys, nonces, cap, count);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint64_t n, uint32_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
 
 hipError_t launch_reset(uint32_t *words, uint32_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_words, dim3(1), dim3(256), 0, s, words, n);

@@ -110,6 +110,58 @@ def plot(key: bytes, k: int, threshold: int | None = None, buffers: PlotBuffers 
     return buffers
 
 
+@dataclass
+class ChunkBuffers(PlotBuffers):
+    """Device memory of one chunk of a chunked plot (vx_plot_chunk): Table 1
+    holds up to t1_capacity records, t1_count receives how many it got."""
+    chunk_bits: int = 0
+    t1_count: torch.Tensor | None = None  # int64[1], read as u64
+
+    @property
+    def t1_capacity(self) -> int:
+        return self.t1_keys.shape[0]
+
+
+def alloc_chunk(k: int, chunk_bits: int, threshold: int | None = None, t1_capacity: int | None = None,
+                t2_capacity: int | None = None, tuning: N.VxTuning | None = None, device=None) -> ChunkBuffers:
+    """Buffers for the chunks of a plot cut into 2^chunk_bits bucket ranges
+    (one set serves every chunk in turn)."""
+    dev = _dev(device)
+    p = N.make_params(bytes(32), k, threshold)
+    cap1, cap2 = N.vx_chunk_capacity_hint(k, chunk_bits, p.match_threshold)
+    if cap1 == 0:
+        raise ValueError("invalid k / chunk_bits (a chunk must hold fewer than 2^32 records)")
+    cap1 = cap1 if t1_capacity is None else int(t1_capacity)
+    cap2 = cap2 if t2_capacity is None else int(t2_capacity)
+    ws = N.vx_chunk_workspace_bytes(p, chunk_bits, cap1, tuning)
+    if ws == 0:
+        raise ValueError("invalid chunk parameters or tuning")
+    return ChunkBuffers(
+        k=k,
+        t1_keys=torch.empty(cap1, dtype=torch.int64, device=dev),
+        t1_nonces=torch.empty(cap1, dtype=torch.int32, device=dev),
+        bucket_offsets=torch.empty(N.VX_NUM_BUCKETS + 1, dtype=torch.int32, device=dev),
+        t2=torch.empty((cap2, 2), dtype=torch.int64, device=dev),
+        t2_count=torch.zeros(1, dtype=torch.int64, device=dev),
+        workspace=torch.empty(ws, dtype=torch.uint8, device=dev),
+        chunk_bits=chunk_bits,
+        t1_count=torch.zeros(1, dtype=torch.int64, device=dev),
+    )
+
+
+def plot_chunk(key: bytes, k: int, chunk_bits: int, chunk: int, buffers: ChunkBuffers,
+               threshold: int | None = None, tuning: N.VxTuning | None = None, stream=None) -> ChunkBuffers:
+    """Chunk `chunk` of a plot (vx_plot_chunk): Table 1 and Table 2 of the
+    buckets whose top chunk_bits bits equal `chunk`.  Synchronises `stream`
+    once (the record count plans the sort)."""
+    if buffers.k != k or buffers.chunk_bits != chunk_bits:
+        raise ValueError("buffers were allocated for another k or chunk_bits")
+    p = N.make_params(key, k, threshold)
+    N.vx_plot_chunk(p, chunk_bits, chunk, buffers.native(), buffers.t1_capacity, buffers.t1_count.data_ptr(),
+                    tuning, _stream(stream))
+    return buffers
+
+
 def hash_table1(key: bytes, k: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     p = N.make_params(key, k)
     n = 1 << k

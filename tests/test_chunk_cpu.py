@@ -1,0 +1,94 @@
+"""Chunked plots on the CPU: capacity hints, workspace sizes and the argument
+checks of vx_plot_chunk, which all return before any device work."""
+import math
+
+import pytest
+
+import paper_2606_14007_amd as vx
+from paper_2606_14007_amd import _native as N
+
+
+def test_chunk_capacity_hint_bounds_the_chunk():
+    # A chunk of a 2^k plot cut by c bits holds Binomial(2^k, 2^-c) records.
+    for k, c in ((12, 0), (20, 2), (27, 3), (31, 1), (32, 1), (32, 8)):
+        cap1, cap2 = vx.vx_chunk_capacity_hint(k, c, 1 << (64 - k))
+        mean = 2.0 ** (k - c)
+        assert cap1 >= mean + 8 * math.sqrt(mean), (k, c)
+        assert cap1 <= mean + 8 * math.sqrt(mean) + 4097, (k, c)
+        # Table 2: the whole plot's expectation over 2^c chunks, plus margin
+        lam = 2.0 ** (k - 24)
+        t = min(1 << (64 - k), 1 << 40) / float(1 << 40)
+        expect = mean * lam * t * (1 - t / 2)
+        assert cap2 >= expect * 1.04 + 4096, (k, c)
+
+
+@pytest.mark.parametrize("k,c", [(0, 0), (33, 1), (32, 0), (12, 9), (3, 4)])
+def test_chunk_capacity_hint_rejects(k, c):
+    assert vx.vx_chunk_capacity_hint(k, c, 1) == (0, 0)
+
+
+def test_chunk_workspace_sizes():
+    p = vx.make_params(bytes(32), 20)
+    a = vx.vx_chunk_workspace_bytes(p, 2, 1 << 18)
+    b = vx.vx_chunk_workspace_bytes(p, 2, 1 << 19)
+    # keys, nonces, scratch and pair counts: at least 25 bytes per record
+    assert a >= 25 << 18 and b >= a + (25 << 18)
+    assert vx.vx_chunk_workspace_bytes(p, 2, 0) == 0
+    assert vx.vx_chunk_workspace_bytes(p, 9, 1 << 18) == 0
+    assert vx.vx_chunk_workspace_bytes(p, 2, 1 << 18, vx.make_tuning(fused_sort_match=1)) == 0
+    p32 = vx.make_params(bytes(32), 32)
+    assert p32.match_threshold == 1 << 32
+    assert vx.vx_chunk_workspace_bytes(p32, 1, (1 << 32) - 1) > 0
+    assert vx.vx_chunk_workspace_bytes(p32, 1, 1 << 32) == 0
+    # whole plots stay at k <= 31
+    assert vx.vx_workspace_bytes(p32, vx.VX_CALL_PLOT) == 0
+
+
+def _buffers(k=20, cap2=1024):
+    b = N.VxPlotBuffers()
+    b.t1_keys, b.t1_nonces, b.bucket_offsets = 1 << 20, 2 << 20, 3 << 20
+    b.t2, b.t2_capacity, b.t2_count = 4 << 20, cap2, 5 << 20
+    b.workspace, b.workspace_bytes = 6 << 20, 0
+    return b
+
+
+@pytest.mark.parametrize("case,status", [
+    ("chunk_too_big", N.VX_ERR_INVALID_ARG),
+    ("chunk_bits_9", N.VX_ERR_INVALID_ARG),
+    ("k33", N.VX_ERR_INVALID_ARG),
+    ("cap0", N.VX_ERR_INVALID_ARG),
+    ("cap_2_32", N.VX_ERR_INVALID_ARG),
+    ("fused", N.VX_ERR_UNSUPPORTED),
+    ("null_keys", N.VX_ERR_INVALID_ARG),
+    ("null_count", N.VX_ERR_INVALID_ARG),
+    ("misaligned", N.VX_ERR_INVALID_ARG),
+    ("workspace", N.VX_ERR_WORKSPACE),
+])
+def test_plot_chunk_argument_checks(case, status):
+    # Fake aligned device addresses: every case is rejected before any
+    # device call.
+    p = vx.make_params(bytes(32), 20)
+    b = _buffers()
+    c, r, cap, cnt, tun = 2, 1, 1 << 18, 7 << 20, None
+    if case == "chunk_too_big":
+        r = 4
+    elif case == "chunk_bits_9":
+        c, r = 9, 0
+    elif case == "k33":
+        p.k = 33
+    elif case == "cap0":
+        cap = 0
+    elif case == "cap_2_32":
+        cap = 1 << 32
+    elif case == "fused":
+        tun = vx.make_tuning(fused_sort_match=1)
+    elif case == "null_keys":
+        b.t1_keys = None
+    elif case == "null_count":
+        cnt = 0
+    elif case == "misaligned":
+        b.t1_keys += 4
+    with pytest.raises(vx.VxError) as e:
+        vx.vx_plot_chunk(p, c, r, b, cap, cnt, tun)
+    assert e.value.status == status
+    assert vx.vx_last_error()

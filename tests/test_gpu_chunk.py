@@ -1,0 +1,154 @@
+"""GPU parity of chunked plots (vx_plot_chunk) against the oracle, bit-exact.
+
+Chunk r of a plot cut by c bits is the plot restricted to the buckets whose
+top c bits equal r: Table 1 is the oracle's slice between those buckets'
+offsets, the bucket offsets are the oracle's shifted to start at 0 (clamped
+to [0, m] outside the range), and Table 2 is the contiguous slice of the
+oracle's canonical Table 2 whose first member lies in the range (pairs never
+cross buckets).  One set of buffers serves every chunk in turn, so stale
+contents of an earlier chunk would show.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from vx_inputs import derive_key
+from paper_2606_14007_amd import _native as N
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+KEY0 = derive_key(0)
+
+
+@pytest.fixture(scope="module")
+def vx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_14007_amd as m
+    m.lib()
+    return m
+
+
+def _expected_chunk(ref, c, r):
+    n = len(ref.t1_keys)
+    off = ref.offsets.astype(np.int64)
+    b0, b1 = r << (24 - c), (r + 1) << (24 - c)
+    lo, hi = int(off[b0]), int(off[b1])
+    rank = np.empty(n, np.int64)
+    rank[ref.t1_nonces] = np.arange(n)
+    ra = rank[ref.t2["nonce_a"]]
+    p0, p1 = np.searchsorted(ra, lo), np.searchsorted(ra, hi)
+    return (ref.t1_keys[lo:hi], ref.t1_nonces[lo:hi], np.clip(off - lo, 0, hi - lo).astype(np.uint32),
+            ref.t2[p0:p1])
+
+
+def _check_chunk(vx, b, ref, c, r):
+    torch.cuda.synchronize()
+    ek, en, eoff, et2 = _expected_chunk(ref, c, r)
+    m = int(b.t1_count.item())
+    assert m == len(ek)
+    assert vx.device_status(b.workspace) == 0
+    assert np.array_equal(vx.u64(b.t1_keys[:m]), ek)
+    assert np.array_equal(vx.u32(b.t1_nonces[:m]), en)
+    assert np.array_equal(vx.u32(b.bucket_offsets), eoff)
+    cnt = vx.t2_count(b)
+    assert cnt == len(et2)
+    assert np.array_equal(vx.t2_records(b.t2, cnt), et2)
+    return m, cnt
+
+
+@pytest.mark.parametrize("k,c,T", [
+    (20, 2, None),
+    (18, 1, None),
+    (16, 3, 1 << 44),
+    (14, 2, (1 << 64) - 1),
+    (13, 2, 0),
+    (12, 0, None),
+    (9, 4, 1 << 50),
+    (3, 3, None),
+    (1, 1, None),
+])
+def test_chunks_match_the_oracle(vx, k, c, T):
+    ref = oracle.plot(KEY0, k, threshold=T, threads=8)
+    b = vx.alloc_chunk(k, c, threshold=T)
+    total1 = total2 = 0
+    for r in range(1 << c):
+        print(f"k={k} c={c} chunk={r}", flush=True)
+        vx.plot_chunk(KEY0, k, c, r, b, threshold=T)
+        m, cnt = _check_chunk(vx, b, ref, c, r)
+        total1 += m
+        total2 += cnt
+    assert total1 == 1 << k
+    assert total2 == len(ref.t2)
+
+
+def test_chunks_concatenate_to_the_whole_plot(vx):
+    k, c = 17, 2
+    whole = vx.plot(KEY0, k)
+    torch.cuda.synchronize()
+    b = vx.alloc_chunk(k, c)
+    keys, nonces, t2, offs = [], [], [], []
+    base = 0
+    for r in range(1 << c):
+        vx.plot_chunk(KEY0, k, c, r, b)
+        torch.cuda.synchronize()
+        m = int(b.t1_count.item())
+        keys.append(vx.u64(b.t1_keys[:m]))
+        nonces.append(vx.u32(b.t1_nonces[:m]))
+        t2.append(vx.t2_records(b.t2, vx.t2_count(b)))
+        o = vx.u32(b.bucket_offsets).astype(np.int64)
+        b0, b1 = r << (24 - c), (r + 1) << (24 - c)
+        offs.append(o[b0:b1] + base)
+        base += m
+    assert np.array_equal(np.concatenate(keys), vx.u64(whole.t1_keys))
+    assert np.array_equal(np.concatenate(nonces), vx.u32(whole.t1_nonces))
+    assert np.array_equal(np.concatenate(offs + [np.array([base])]),
+                          vx.u32(whole.bucket_offsets).astype(np.int64))
+    assert np.array_equal(np.concatenate(t2), vx.t2_records(whole.t2, vx.t2_count(whole)))
+
+
+def test_many_mostly_empty_chunks(vx):
+    # 256 records over 256 chunks: most chunks hold zero, one or two records.
+    k, c = 8, 8
+    ref = oracle.plot(KEY0, k, threshold=1 << 60)
+    b = vx.alloc_chunk(k, c, threshold=1 << 60)
+    empty = 0
+    for r in range(1 << c):
+        vx.plot_chunk(KEY0, k, c, r, b, threshold=1 << 60)
+        m, _ = _check_chunk(vx, b, ref, c, r)
+        empty += m == 0
+    assert empty > 0
+
+
+@pytest.mark.parametrize("tun", [
+    dict(group_cap=64),                          # oversized groups take the fallback
+    dict(group_bits=4, match_chunk_bits=6),      # one pass, tiny match chunks
+    dict(group_bits=13, pass1_bits=5, pass2_bits=4),
+    dict(h1_tiles=3),
+    dict(group_bits=14, pipeline_slices=4),      # the pipelined plan's 2-6-6 digit split
+])
+def test_chunk_tunings(vx, tun):
+    k, c = 16, 2
+    ref = oracle.plot(KEY0, k, threads=8)
+    t = vx.make_tuning(**tun)
+    b = vx.alloc_chunk(k, c, tuning=t)
+    for r in range(1 << c):
+        vx.plot_chunk(KEY0, k, c, r, b, tuning=t)
+        _check_chunk(vx, b, ref, c, r)
+
+
+def test_chunk_over_capacity_is_reported(vx):
+    k, c = 14, 1
+    small = vx.alloc_chunk(k, c, t1_capacity=1 << 12)
+    with pytest.raises(vx.VxError) as e:
+        vx.plot_chunk(KEY0, k, c, 0, small)
+    assert e.value.status == N.VX_ERR_WORKSPACE
+    torch.cuda.synchronize()
+    assert int(small.t1_count.item()) > 1 << 12  # the records the chunk holds
+    # the same device afterwards plots a chunk correctly
+    ref = oracle.plot(KEY0, k)
+    b = vx.alloc_chunk(k, c)
+    vx.plot_chunk(KEY0, k, c, 0, b)
+    _check_chunk(vx, b, ref, c, 0)

@@ -1,7 +1,7 @@
 """GPU parity at the full plot sizes: k = 27 bit-exact against the oracle in
-full; k = 31 (about 105 GB on the device) bit-exact on oracle-computed
-sampled buckets and sampled records, plus whole-table properties checked on
-the device with torch: Table 1 sorted by (key64, nonce) and a permutation of
+full; k = 31 (about 105 GB on the device) and k = 32 in two chunks (about
+112 GB) bit-exact on oracle-computed sampled buckets and sampled records,
+plus whole-table properties checked on the device with torch: Table 1 sorted by (key64, nonce) and a permutation of
 all nonces, bucket offsets equal to the bucket histogram's prefix sums, every
 Table-2 record valid and in canonical order, and |Table 2| equal to an
 independent pair count from searchsorted."""
@@ -167,3 +167,126 @@ def test_k31_sampled_and_whole_table_properties(vx):
         assert np.array_equal(got, s.t2[t2_pos:t2_pos + pc])
         t2_pos += pc
     assert t2_pos == len(s.t2) and t2_pos > 0
+
+
+@pytest.mark.timeout(1200)
+def test_k32_in_two_chunks_sampled_and_properties(vx):
+    """k = 32 (2^32 nonces) as two chunks of 2^23 buckets each, one set of
+    buffers (about 112 GB).  Per chunk: every key carries the chunk's prefix,
+    Table 1 is sorted by (key64, nonce), the offsets are the bucket
+    histogram's prefix sums (0 before the range, m after it), |Table 2|
+    equals an independent count and every record is valid and canonical;
+    over both chunks every nonce appears exactly once.  Sampled buckets of
+    both chunks are bit-exact against the oracle."""
+    k, c = 32, 1
+    T = vx.vx_default_threshold(k)
+    dev = torch.device("cuda")
+    print("k=32: oracle sampled buckets", flush=True)
+    buckets = sampled_buckets(1024)
+    s = oracle.sample_buckets(KEY0, k, buckets, threads=THREADS)
+    print("k=32: allocating chunk buffers", flush=True)
+    b = vx.alloc_chunk(k, c)
+    seen = torch.zeros(1 << k, dtype=torch.bool, device=dev)
+    rank = torch.empty(1 << k, dtype=torch.int64, device=dev)  # nonce -> position in its chunk
+    step = 1 << 28
+    total_m = 0
+    t1_pos = t2_pos = 0
+    for r in range(1 << c):
+        print(f"k=32: chunk {r}: GPU", flush=True)
+        vx.plot_chunk(KEY0, k, c, r, b)
+        torch.cuda.synchronize()
+        assert vx.device_status(b.workspace) == 0
+        m = int(b.t1_count.item())
+        total_m += m
+        cnt = vx.t2_count(b)
+        assert 0 < cnt <= b.t2_capacity
+        keys, non = b.t1_keys[:m], b.t1_nonces[:m]
+        sk = _signed_order(keys)
+
+        print(f"k=32: chunk {r}: order, prefix, nonces", flush=True)
+        for lo in range(0, m - 1, step):
+            hi = min(lo + step + 1, m)
+            a, cc = sk[lo:hi - 1], sk[lo + 1:hi]
+            na, nc = non[lo:hi - 1], non[lo + 1:hi]
+            na = na.long() & 0xFFFFFFFF
+            nc = nc.long() & 0xFFFFFFFF
+            assert bool(torch.all((a < cc) | ((a == cc) & (na < nc))))
+        for lo in range(0, m, step):
+            kk = keys[lo:lo + step]
+            assert bool(torch.all(((kk >> 63) & 1) == r))
+            ni = non[lo:lo + step].long() & 0xFFFFFFFF
+            assert not bool(seen[ni].any())
+            seen[ni] = True
+            rank[ni] = torch.arange(lo, min(lo + step, m), dtype=torch.int64, device=dev)
+
+        print(f"k=32: chunk {r}: bucket offsets", flush=True)
+        counts = torch.zeros(1 << 24, dtype=torch.int64, device=dev)
+        for lo in range(0, m, step):
+            counts += torch.bincount((keys[lo:lo + step] >> 40) & 0xFFFFFF, minlength=1 << 24)
+        off = b.bucket_offsets.long() & 0xFFFFFFFF
+        b0, b1 = r << 23, (r + 1) << 23
+        assert bool(torch.all(off[:b0 + 1] == 0)) and bool(torch.all(off[b1:] == m))
+        assert torch.equal(off[1:] - off[:-1], counts)
+        bucket_end = off[1:]
+
+        print(f"k=32: chunk {r}: independent |Table 2| count", flush=True)
+        total = 0
+        for lo in range(0, m, step):
+            hi = min(lo + step, m)
+            kk = sk[lo:hi]
+            bk = (keys[lo:hi] >> 40) & 0xFFFFFF
+            over = kk > (((1 << 63) - 1) - T)
+            lim = torch.searchsorted(sk, torch.where(over, kk, kk + T), side="left")
+            lim = torch.where(over, torch.full_like(lim, m), lim)
+            lim = torch.minimum(lim, bucket_end[bk])
+            idx = torch.arange(lo, hi, device=dev)
+            total += int((lim - idx - 1).clamp_min(0).sum())
+        assert total == cnt
+
+        print(f"k=32: chunk {r}: Table-2 validity and canonical order", flush=True)
+        t2 = b.t2[:cnt]
+        prev = None
+        ra_parts = []
+        for lo in range(0, cnt, step):
+            rec = t2[lo:lo + step]
+            na = (rec[:, 0] & 0xFFFFFFFF).long()
+            nb = ((rec[:, 0] >> 32) & 0xFFFFFFFF).long()
+            ra, rb = rank[na], rank[nb]
+            assert bool(seen[na].all()) and bool(seen[nb].all())
+            assert bool(torch.all((ra < m) & (rb < m)))
+            ka, kb = keys[ra], keys[rb]
+            assert bool(torch.all(ra < rb))
+            assert bool(torch.all(((ka >> 40) & 0xFFFFFF) == ((kb >> 40) & 0xFFFFFF)))
+            d = _signed_order(kb) - _signed_order(ka)  # same bucket, ordered: 0 <= d < 2^40
+            assert bool(torch.all((d >= 0) & (d < T)))
+            comp = ra * m + rb  # rb < m; ra * 2^32 would overflow past 2^31 records
+            assert bool(torch.all(comp[1:] > comp[:-1]))
+            if prev is not None:
+                assert int(comp[0]) > prev
+            prev = int(comp[-1])
+            ra_parts.append(ra)
+        ra_all = torch.cat(ra_parts)
+        del ra_parts
+
+        print(f"k=32: chunk {r}: sampled buckets against the oracle", flush=True)
+        mine = [(i, bk) for i, bk in enumerate(s.buckets) if b0 <= bk < b1]
+        assert mine
+        offh = vx.u32(b.bucket_offsets).astype(np.int64)
+        for i, bk in mine:
+            a, e = int(offh[bk]), int(offh[bk + 1])
+            nbk = int(s.bucket_counts[i])
+            assert e - a == nbk
+            assert np.array_equal(vx.u64(keys[a:e]), s.t1_keys[t1_pos:t1_pos + nbk])
+            assert np.array_equal(vx.u32(non[a:e]), s.t1_nonces[t1_pos:t1_pos + nbk])
+            t1_pos += nbk
+            pc = int(s.pair_counts[i])
+            p_lo = int(torch.searchsorted(ra_all, torch.tensor([a], device=dev), side="left"))
+            p_hi = int(torch.searchsorted(ra_all, torch.tensor([e], device=dev), side="left"))
+            assert p_hi - p_lo == pc
+            got = vx.t2_records(t2[p_lo:p_hi], pc)
+            assert np.array_equal(got, s.t2[t2_pos:t2_pos + pc])
+            t2_pos += pc
+        del ra_all
+    assert total_m == 1 << k
+    assert bool(seen.all())
+    assert t1_pos == len(s.t1_keys) and t2_pos == len(s.t2) and t2_pos > 0
