@@ -23,8 +23,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 STAGES = ["hash", "partition1", "partition2", "group_sort", "chunk_sums", "match_emit"]
-KERNEL_OF_STAGE = {"hash": "k_hash_table1", "match_emit": "k_match_emit",
-                   "group_sort": "k_groupsort", "partition1": "k_scatter (pass 1)",
+KERNEL_OF_STAGE = {"hash": "k_hash_scatter", "match_emit": "k_match_emit",
+                   "group_sort": "k_groupsort", "partition1": "k_region_scan (pass 1 is in the hash)",
                    "partition2": "k_digit_hist + k_scatter (later passes)",
                    "chunk_sums": "k_chunk_sums + k_scan_*"}
 
@@ -496,8 +496,14 @@ def main() -> int:
     valu_peak = opcount.MI355X_VALU_LANE_OPS_PER_S
     hbm_peak = opcount.MI355X_HBM_BYTES_PER_S
     npass = vx.vx_partition_passes(vx.make_params(derive_key(0), k))
+    # With two or more passes the hash kernel also does the first pass (its
+    # stage is then only the region scan); a one-pass plot hashes alone.
+    fused_first = npass >= 2
+    kernel_of = dict(KERNEL_OF_STAGE)
+    if not fused_first:
+        kernel_of.update(hash="k_hash_table1", partition1="k_digit_hist + k_scatter (pass 1)")
     algo_bytes = {
-        "partition1": n * (8 + 12),              # read key, write key+nonce
+        "partition1": 0 if fused_first else n * (8 + 12),  # read key, write key+nonce
         "partition2": (npass - 1) * n * (12 + 12),  # each later pass reads and writes key+nonce
         # read and write key+nonce, offsets, one pair-count byte per record
         "group_sort": n * (12 + 12 + 1) + (vx.VX_NUM_BUCKETS + 1) * 4,
@@ -506,7 +512,7 @@ def main() -> int:
     stages = {}
     for s in STAGES:
         sec = stage_ms[s] / 1000.0
-        ent = {"ms": round(stage_ms[s], 3), "kernel": KERNEL_OF_STAGE[s]}
+        ent = {"ms": round(stage_ms[s], 3), "kernel": kernel_of[s]}
         if sec > 0:
             if s == "hash":
                 ent.update(bound="alu", achieved=h1_ops / sec / 1e12, peak=valu_peak / 1e12,
@@ -514,15 +520,16 @@ def main() -> int:
             elif s == "match_emit":
                 ent.update(bound="alu", achieved=h2_ops / sec / 1e12, peak=valu_peak / 1e12,
                            unit="T lane-ops/s")
-            else:
+            elif algo_bytes[s]:
                 ent.update(bound="hbm", achieved=algo_bytes[s] / sec / 1e9, peak=hbm_peak / 1e9,
                            unit="GB/s")
-            ent["frac"] = round(ent["achieved"] / ent["peak"], 4)
-            ent["achieved"] = round(ent["achieved"], 2)
+            if "peak" in ent:
+                ent["frac"] = round(ent["achieved"] / ent["peak"], 4)
+                ent["achieved"] = round(ent["achieved"], 2)
         stages[s] = ent
     dom = max(STAGES, key=lambda s: stage_ms[s])
     d = stages[dom]
-    traffic = load_traffic(KERNEL_OF_STAGE[dom], k)
+    traffic = load_traffic(kernel_of[dom], k)
     roofline = {"bound": d.get("bound"), "achieved": d.get("achieved"), "peak": d.get("peak"),
                 "unit": "TOP/s" if d.get("bound") == "alu" else "GB/s",
                 "frac": d.get("frac"), "traffic": traffic, "kernel": d["kernel"], "stage": dom,

@@ -57,6 +57,9 @@ typedef enum {
 /* Device status word bits (vx_read_status). */
 #define VX_DEV_STATUS_GROUP_TOO_LARGE 0x1u /* a sort group exceeded the fallback limit */
 #define VX_DEV_STATUS_LOOKBACK_TIMEOUT 0x2u /* vx_plot: a Table-2 base wait hit its bound */
+#define VX_DEV_STATUS_REGION_OVERFLOW 0x4u /* vx_plot: a first-pass region of the fused hash
+                                              overflowed (about 8 standard deviations above its
+                                              expected fill; Table 1 is then incomplete) */
 
 #define VX_BUCKET_BITS 24
 #define VX_NUM_BUCKETS (1u << VX_BUCKET_BITS)
@@ -114,6 +117,9 @@ typedef struct {
                                   work after the first partition pass, whose matches run on a
                                   second (internal) stream while later slices are partitioned and
                                   sorted */
+    uint32_t separate_hash;    /* plot: nonzero keeps the hash and the first partition pass as two
+                                  kernels (by default a plot with two or more passes hashes and
+                                  files records by their first digit in one kernel) */
 } vx_tuning;
 
 enum { VX_CALL_BUCKET_SORT = 1, VX_CALL_MATCH = 2, VX_CALL_PLOT = 3 };

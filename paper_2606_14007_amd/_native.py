@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "VX_OK", 1: "VX_ERR_INVALID_ARG", 2: "VX_ERR_WORKSPACE", 3: "
 
 VX_DEV_STATUS_GROUP_TOO_LARGE = 0x1
 VX_DEV_STATUS_LOOKBACK_TIMEOUT = 0x2
+VX_DEV_STATUS_REGION_OVERFLOW = 0x4
 VX_BUCKET_BITS = 24
 VX_NUM_BUCKETS = 1 << 24
 
@@ -49,7 +50,8 @@ class VxPlotBuffers(C.Structure):
 class VxTuning(C.Structure):
     _fields_ = [("group_bits", C.c_uint32), ("pass1_bits", C.c_uint32), ("group_cap", C.c_uint32),
                 ("h1_tiles", C.c_uint32), ("match_chunk_bits", C.c_uint32), ("pass2_bits", C.c_uint32),
-                ("fused_sort_match", C.c_uint32), ("pipeline_slices", C.c_uint32)]
+                ("fused_sort_match", C.c_uint32), ("pipeline_slices", C.c_uint32),
+                ("separate_hash", C.c_uint32)]
 
 
 class VxError(RuntimeError):
@@ -129,11 +131,12 @@ def make_params(key: bytes, k: int, threshold: int | None = None) -> VxPlotParam
 
 
 def make_tuning(group_bits=0, pass1_bits=0, group_cap=0, h1_tiles=0, match_chunk_bits=0,
-                pass2_bits=0, fused_sort_match=0, pipeline_slices=0) -> VxTuning:
+                pass2_bits=0, fused_sort_match=0, pipeline_slices=0, separate_hash=0) -> VxTuning:
     t = VxTuning()
     t.group_bits, t.pass1_bits, t.group_cap = group_bits, pass1_bits, group_cap
     t.h1_tiles, t.match_chunk_bits, t.pass2_bits = h1_tiles, match_chunk_bits, pass2_bits
     t.fused_sort_match, t.pipeline_slices = fused_sort_match, pipeline_slices
+    t.separate_hash = separate_hash
     return t
 
 

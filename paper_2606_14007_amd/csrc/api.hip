@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <vector>
 
@@ -61,6 +62,8 @@ struct Plan {
     uint32_t cb = 0;         // match chunk = 2^cb consecutive Table-1 records
     bool fused = false;      // plot: one fused sort + match kernel instead of two
     uint32_t slices = 1;     // plot: pipeline slices of the passes after the first (1 = none)
+    bool hs = false;         // plot: the hash kernel also does the first partition pass
+    uint32_t R = 0;          // hs: records per first-pass region (digit)
 };
 
 uint32_t clampu(int64_t v, int64_t lo, int64_t hi) {
@@ -94,10 +97,14 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     // Sort groups of about 2048 records (half the LDS capacity).
     P.G = t->group_bits ? t->group_bits : clampu((int64_t)p->k - 11, 1, 21);
     if (P.G < 1 || P.G > 24) return fail(VX_ERR_UNSUPPORTED, "group_bits must be in [1, 24]");
-    // Split G into passes of at most 9 bits (7-7-6 at k=31) so that every
-    // digit's run per sub-tile spans whole cache lines.  The first pass
-    // scatters over the whole table, where short runs cost the most, so it
-    // takes no more than 7 bits once three passes are needed.
+    // Split G into passes of at most 9 bits so that every digit's run per
+    // sub-tile spans whole cache lines.  The first pass scatters over the
+    // whole table, where short runs cost the most, so it takes no more than
+    // 7 bits once three passes are needed (7-7-6 at k=31).  When the hash
+    // kernel does the first pass (see below), that digit stays at 8 bits or
+    // less, and 6 with three passes (6-7-7 at k=31): it files sub-tiles of
+    // only 2048 records, so narrower digits keep its runs longer (measured
+    // at k=28 and k=31).
     //
     // A pipelined plot (see run_pipelined; opt-in) instead keeps the later
     // passes at 6 bits, whose scatter fits on a CU next to two match
@@ -106,15 +113,18 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     P.fused = t->fused_sort_match != 0;
     P.slices = t->pipeline_slices ? t->pipeline_slices : kDefaultSlices;
     if (P.fused) P.slices = 1;
+    const bool hs_ok = !records && !t->separate_hash && !P.fused;
     uint32_t d0, d1, d2;
     if (P.G <= 9) {
         d0 = P.G; d1 = 0; d2 = 0;
     } else if (P.slices > 1 && P.G >= 13) {
         d0 = P.G - 12; d1 = 6; d2 = 6;
     } else if (P.G <= 17) {
-        d0 = (P.G + 1) / 2; d1 = P.G - d0; d2 = 0;
+        d0 = (P.G + 1) / 2;
+        if (hs_ok) d0 = std::min(d0, 8u);
+        d1 = P.G - d0; d2 = 0;
     } else {
-        d0 = 7; d1 = (P.G - 7 + 1) / 2; d2 = P.G - 7 - d1;
+        d0 = hs_ok ? 6 : 7; d1 = (P.G - d0 + 1) / 2; d2 = P.G - d0 - d1;
     }
     if (t->pass1_bits || t->pass2_bits) {
         d0 = t->pass1_bits ? t->pass1_bits : d0;
@@ -154,6 +164,17 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     if (P.npass < 2) P.slices = 1;
     P.slices = std::min(P.slices, 1u << P.D[0]);
     if (P.slices < 1) P.slices = 1;
+    // Plots with two or more passes fuse the first into the hash kernel.
+    // Its regions hold the expected records of a digit plus 8 standard
+    // deviations and a sub-tile (fewer than one plot in 10^13 overflows one,
+    // which the device status reports).
+    P.hs = hs_ok && P.npass >= 2 && P.D[0] <= (uint32_t)vxk::kHashScatterMaxBits;
+    if (P.hs) {
+        const uint32_t nd = 1u << P.D[0];
+        const double mean = (double)((P.n + nd - 1) / nd);
+        P.R = (uint32_t)(mean + 8.0 * std::sqrt(mean)) + vxk::kHashScatterSub;
+        if ((uint64_t)P.R * nd >= (1ull << 32)) P.hs = false;
+    }
     *pl = P;
     return VX_OK;
 }
@@ -171,6 +192,8 @@ struct Layout {
     size_t mcount = 0, mbase = 0; // u64[match chunks]: pair counts, Table-2 bases
     size_t pcnt = 0;              // u8[n]: pair count of each Table-1 record (255 = look again)
     size_t nonces_in = 0;         // u32[n]: nonces of a chunk's records (chunked plots)
+    size_t reg_nonces = 0;        // u32[regions]: nonces of a fused-hash plot's first pass
+    size_t fill = 0, seg_lo = 0, seg_hi = 0;  // u32[2^D0]: fused-hash regions
     size_t mpart = 0;             // u64[scan parts]
     size_t total = 0;
 };
@@ -209,7 +232,18 @@ Layout layout(const Plan &P, int which) {
     if (chunk) which = VX_CALL_PLOT;
     const bool sort = which == VX_CALL_BUCKET_SORT || which == VX_CALL_PLOT;
     const bool match = which == VX_CALL_MATCH || which == VX_CALL_PLOT;
-    if (which == VX_CALL_PLOT) L.keys_no = take(P.n * 8);
+    // A fused-hash plot (P.hs) writes the first pass into keys_no +
+    // reg_nonces, as regions with slack; the later passes alternate between
+    // the scratch arrays and Table 1 as in any plot.
+    const bool hs = which == VX_CALL_PLOT && !chunk && P.hs;
+    const uint64_t regions = hs ? (uint64_t)P.R << P.D[0] : P.n;
+    if (which == VX_CALL_PLOT) L.keys_no = take(regions * 8);
+    if (hs) L.reg_nonces = take(regions * 4);
+    if (hs) {
+        L.fill = take((size_t)4 << P.D[0]);
+        L.seg_lo = take((size_t)4 << P.D[0]);
+        L.seg_hi = take((size_t)4 << P.D[0]);
+    }
     if (chunk) L.nonces_in = take(P.n * 4);
     if (sort) {
         L.scr_keys = take(P.n * 8);
@@ -262,6 +296,17 @@ PassBufs pass_bufs(const Plan &P, const Layout &L, void *ws, const uint64_t *key
     uint32_t *scr_n = at<uint32_t>(ws, L.scr_nonces);
     auto to_t1 = [&](uint32_t j) { return ((P.npass - 1 - j) % 2) == 0; };
     PassBufs B;
+    if (P.hs && i <= 1) {
+        // Pass 0 (in the hash kernel) fills the regions in keys_no +
+        // reg_nonces; pass 1 reads them.
+        uint64_t *reg_k = at<uint64_t>(ws, L.keys_no);
+        uint32_t *reg_n = at<uint32_t>(ws, L.reg_nonces);
+        B.in_k = i == 0 ? nullptr : reg_k;
+        B.in_n = i == 0 ? nullptr : reg_n;
+        B.out_k = i == 0 ? reg_k : (to_t1(1) ? t1_keys : scr_k);
+        B.out_n = i == 0 ? reg_n : (to_t1(1) ? t1_nonces : scr_n);
+        return B;
+    }
     if (i == 0) {
         B.in_k = keys_no;
         B.in_n = nonces_in;
@@ -276,19 +321,26 @@ PassBufs pass_bufs(const Plan &P, const Layout &L, void *ws, const uint64_t *key
 
 // Pass i >= 1 over its input segments [sa, sb) (the groups of pass i - 1):
 // per-tile histograms, their scan inside each segment, and the scatter.
+// Segments lie back to back at the previous pass's group starts, except the
+// regions of a fused-hash first pass (seg_lo / seg_hi), whose records move
+// to the group starts.
 vx_status run_pass(const Plan &P, const Layout &L, void *ws, const PassBufs &B, uint32_t i, uint32_t sa,
                    uint32_t sb, hipStream_t s) {
     const uint32_t nd = 1u << P.D[i];
     const uint32_t shift = 64 - P.pre[i] - P.D[i];
     const uint32_t q = P.Q[i];
     const uint32_t nseg = sb - sa;
-    const uint32_t *seg = at<uint32_t>(ws, L.gstart[i - 1]) + sa;
+    const uint32_t *base = at<uint32_t>(ws, L.gstart[i - 1]) + sa;
+    const bool regions = P.hs && i == 1;
+    const uint32_t *seg = regions ? at<uint32_t>(ws, L.seg_lo) + sa : base;
+    const uint32_t *seg_end = regions ? at<uint32_t>(ws, L.seg_hi) + sa : nullptr;
     uint32_t *hist = at<uint32_t>(ws, L.hist[i]) + (size_t)sa * q * nd;
     uint32_t *off = at<uint32_t>(ws, L.off[i]) + (size_t)sa * q * nd;
     uint32_t *gst = at<uint32_t>(ws, L.gstart[i]) + (size_t)sa * nd;
-    VX_HIP(vxk::launch_hist_segments(B.in_k, seg, nseg, q, shift, P.D[i], hist, s), "pass histogram");
-    VX_HIP(vxk::launch_colscan(hist, off, nseg, q, nd, seg, gst, nseg * nd, (uint32_t)P.n, s), "pass scan");
-    VX_HIP(vxk::launch_scatter_segments(B.in_k, B.in_n, B.out_k, B.out_n, off, seg, nseg, q, shift, P.D[i], s),
+    VX_HIP(vxk::launch_hist_segments(B.in_k, seg, seg_end, nseg, q, shift, P.D[i], hist, s), "pass histogram");
+    VX_HIP(vxk::launch_colscan(hist, off, nseg, q, nd, base, gst, nseg * nd, (uint32_t)P.n, s), "pass scan");
+    VX_HIP(vxk::launch_scatter_segments(B.in_k, B.in_n, B.out_k, B.out_n, off, seg, seg_end, nseg, q, shift,
+                                        P.D[i], s),
            "pass scatter");
     return VX_OK;
 }
@@ -299,7 +351,7 @@ vx_status run_pass(const Plan &P, const Layout &L, void *ws, const PassBufs &B, 
 vx_status run_partition(const Plan &P, const Layout &L, void *ws, const uint64_t *keys_no,
                         bool hist_done, uint64_t *t1_keys, uint32_t *t1_nonces, uint32_t npass_run,
                         hipStream_t s, hipEvent_t *ev, const uint32_t *nonces_in = nullptr) {
-    for (uint32_t i = 0; i < npass_run; ++i) {
+    for (uint32_t i = P.hs ? 1 : 0; i < npass_run; ++i) {
         const PassBufs B = pass_bufs(P, L, ws, keys_no, t1_keys, t1_nonces, i, nonces_in);
         if (i == 0) {
             uint32_t *hist = at<uint32_t>(ws, L.hist[0]), *off = at<uint32_t>(ws, L.off[0]);
@@ -522,6 +574,7 @@ vx_status vx_bucket_sort(const vx_plot_params *params, const uint64_t *d_keys, u
     Plan P;
     vx_status st = make_plan(params, tuning, &P);
     if (st != VX_OK) return st;
+    P.hs = false;  // caller keys: the first pass runs on them
     if (!d_keys || !d_t1_keys || !d_t1_nonces || !d_offsets)
         return fail(VX_ERR_INVALID_ARG, "NULL buffer");
     if (!aligned(d_keys, 8) || !aligned(d_t1_keys, 8) || !aligned(d_t1_nonces, 4) || !aligned(d_offsets, 4))
@@ -708,12 +761,26 @@ vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, cons
     hipStream_t s = (hipStream_t)stream;
     void *ws = b->workspace;
     uint64_t *keys_no = at<uint64_t>(ws, L.keys_no);
-    VX_HIP(vxk::launch_reset(at<uint32_t>(ws, L.header), kHeaderWords, s), "reset");
+    uint32_t *hdr = at<uint32_t>(ws, L.header);
+    VX_HIP(vxk::launch_reset(hdr, kHeaderWords, s), "reset");
+    if (P.hs) VX_HIP(vxk::launch_reset(at<uint32_t>(ws, L.fill), 1u << P.D[0], s), "reset");
     VX_HIP(mark(ev, 0, s), "event");
-    VX_HIP(vxk::launch_hash_table1(P.key_words, P.n, P.W, P.chunk1, keys_no, at<uint32_t>(ws, L.hist[0]),
-                                   P.D[0], s),
-           "hash");
-    VX_HIP(mark(ev, 1, s), "event");
+    if (P.hs) {
+        // Hash + first partition pass in one kernel, then the regions' bounds.
+        VX_HIP(vxk::launch_hash_scatter(P.key_words, P.n, P.D[0], P.R, keys_no, at<uint32_t>(ws, L.reg_nonces),
+                                        at<uint32_t>(ws, L.fill), hdr + kHdrStatus, s),
+               "hash + first pass");
+        VX_HIP(mark(ev, 1, s), "event");
+        VX_HIP(vxk::launch_region_scan(at<uint32_t>(ws, L.fill), 1u << P.D[0], P.R, at<uint32_t>(ws, L.seg_lo),
+                                       at<uint32_t>(ws, L.seg_hi), at<uint32_t>(ws, L.gstart[0]), s),
+               "region scan");
+        VX_HIP(mark(ev, 2, s), "event");
+    } else {
+        VX_HIP(vxk::launch_hash_table1(P.key_words, P.n, P.W, P.chunk1, keys_no, at<uint32_t>(ws, L.hist[0]),
+                                       P.D[0], s),
+               "hash");
+        VX_HIP(mark(ev, 1, s), "event");
+    }
     if (!P.fused && pipelined && P.slices > 1) {
         st = run_partition(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, 1, s, ev);
         if (st == VX_OK) st = run_pipelined(P, L, ws, b, keys_no, s, ev);
@@ -731,7 +798,6 @@ vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, cons
     } else {
         st = run_partition(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, P.npass, s, ev);
         if (st != VX_OK) return st;
-        uint32_t *hdr = at<uint32_t>(ws, L.header);
         uint64_t *words = at<uint64_t>(ws, L.lbwords);
         VX_HIP(vxk::launch_zero_u64(words, 1u << P.G, s), "zero look-back words");
         VX_HIP(mark(ev, 4, s), "event");

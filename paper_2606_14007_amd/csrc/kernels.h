@@ -9,6 +9,7 @@
 #define VXK_NUM_BUCKETS (1u << VXK_BUCKET_BITS)
 #define VXK_DEV_STATUS_GROUP_TOO_LARGE 0x1u
 #define VXK_DEV_STATUS_LOOKBACK_TIMEOUT 0x2u
+#define VXK_DEV_STATUS_REGION_OVERFLOW 0x4u
 
 namespace vxk {
 
@@ -16,6 +17,12 @@ constexpr int kMaxDigitBits = 11;     // widest partition digit (LDS histograms)
 constexpr int kGroupCapMax = 3072;    // records a sort group may hold in LDS
 constexpr uint32_t kFallbackMax = 1u << 20;  // largest group the fallback sorts
 constexpr int kMatchChunkBitsMax = 11;  // match chunk = 2^bits records (LDS capacity 2048)
+// Hash fused with the first partition pass: sub-tiles of 256 * 8 nonces,
+// at most 2^8 digits.
+constexpr int kHashScatterItems = 8;
+constexpr int kHashScatterMaxBits = 8;
+constexpr int kHashScatterMaxDigits = 1 << kHashScatterMaxBits;
+constexpr uint32_t kHashScatterSub = 256u * kHashScatterItems;
 
 hipError_t launch_reset(uint32_t *words, uint32_t n, hipStream_t s);
 // Chunked plots: hash all n nonces, keep keys whose top pbits bits are
@@ -25,12 +32,22 @@ hipError_t launch_hash_filter(const uint32_t key_words[8], uint64_t n, uint32_t 
                               uint32_t pbits, uint32_t prefix, uint64_t *keys, uint32_t *nonces, uint64_t cap,
                               unsigned long long *count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+// Plot hash fused with the first partition pass (2^bits digits, bits <=
+// kHashScatterMaxBits): record of digit d goes to region d = [d * R,
+// (d + 1) * R) of keys / nonces; fill[d] (zero at launch) counts them.
+hipError_t launch_hash_scatter(const uint32_t key_words[8], uint64_t n, uint32_t bits, uint32_t R, uint64_t *keys,
+                               uint32_t *nonces, uint32_t *fill, uint32_t *status, hipStream_t s);
+// Region bounds and output starts of the regions (one work-group).
+hipError_t launch_region_scan(const uint32_t *fill, uint32_t nd, uint32_t R, uint32_t *seg_lo, uint32_t *seg_hi,
+                              uint32_t *gstart, hipStream_t s);
 hipError_t launch_hash_table1(const uint32_t key_words[8], uint64_t n, uint32_t tiles, uint64_t chunk,
                               uint64_t *keys, uint32_t *hist, uint32_t hist_bits, hipStream_t s);
 hipError_t launch_hist_chunks(const uint64_t *keys, uint64_t n, uint32_t tiles, uint64_t chunk,
                               uint32_t shift, uint32_t bits, uint32_t *hist, hipStream_t s);
-hipError_t launch_hist_segments(const uint64_t *keys, const uint32_t *seg, uint32_t nseg, uint32_t q,
-                                uint32_t shift, uint32_t bits, uint32_t *hist, hipStream_t s);
+// Segmented launches: segment s covers [seg[s], seg_end[s]); seg_end = NULL
+// means back-to-back segments ending at seg[s + 1].
+hipError_t launch_hist_segments(const uint64_t *keys, const uint32_t *seg, const uint32_t *seg_end, uint32_t nseg,
+                                uint32_t q, uint32_t shift, uint32_t bits, uint32_t *hist, hipStream_t s);
 hipError_t launch_colscan(const uint32_t *hist, uint32_t *off, uint32_t nseg, uint32_t rps,
                           uint32_t ncol, const uint32_t *seg_base, uint32_t *gstart, uint32_t n_groups,
                           uint32_t n_total, hipStream_t s);
@@ -40,8 +57,8 @@ hipError_t launch_scatter_chunks(const uint64_t *in_keys, const uint32_t *in_non
                                  uint32_t bits, hipStream_t s);
 hipError_t launch_scatter_segments(const uint64_t *in_keys, const uint32_t *in_nonces,
                                    uint64_t *out_keys, uint32_t *out_nonces, const uint32_t *off,
-                                   const uint32_t *seg, uint32_t nseg, uint32_t q, uint32_t shift,
-                                   uint32_t bits, hipStream_t s);
+                                   const uint32_t *seg, const uint32_t *seg_end, uint32_t nseg, uint32_t q,
+                                   uint32_t shift, uint32_t bits, hipStream_t s);
 hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint32_t *gstart, uint32_t G,
                             uint32_t cap, uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count,
                             uint32_t *ovf_list, uint64_t T, uint8_t *pcnt, uint32_t g0, uint32_t gcount,

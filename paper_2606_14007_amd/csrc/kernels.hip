@@ -6,9 +6,11 @@
 //
 // How the work maps onto CDNA4 (the paper's atomic slot claim into fixed-size
 // buckets and its one-thread insertion sort are replaced):
-//  * hash: one nonce per lane, BLAKE3 held in VGPRs, key in SGPRs; the same
-//    kernel counts the first partition digit in an LDS histogram;
-//  * bucketing: one or two MSD partition passes over the leading key bits
+//  * hash: one nonce per lane, BLAKE3 held in VGPRs, key in SGPRs; in a plot
+//    the same kernel also does the first partition pass, filing each
+//    sub-tile's keys into per-digit regions claimed with global atomics
+//    (the ALU-bound hash hides that pass's memory traffic);
+//  * bucketing: up to three MSD partition passes over the leading key bits
 //    (histogram per tile -> column scan -> LDS-ranked scatter that writes
 //    each digit's run contiguously), so that every "group" of keys sharing
 //    the leading G bits is contiguous and small enough for LDS;
@@ -35,12 +37,14 @@ constexpr int kMaxDigits = 1 << kMaxDigitBits;
 struct TileGeom {
     // mode 0: tile t covers [t * chunk, min((t + 1) * chunk, n)).
     // mode 1: tile t is part (t % q) of q equal parts of segment s = t / q,
-    //         which covers [seg[s], seg[s + 1]).
+    //         which covers [seg[s], seg_end[s]) (seg_end = seg + 1 for
+    //         back-to-back segments).
     uint32_t mode;
     uint32_t q;
     uint64_t chunk;
     uint64_t n;
     const uint32_t *seg;
+    const uint32_t *seg_end;
 };
 
 __device__ __forceinline__ void tile_range(const TileGeom &g, uint32_t t, uint64_t &lo,
@@ -52,7 +56,7 @@ __device__ __forceinline__ void tile_range(const TileGeom &g, uint32_t t, uint64
         if (hi > g.n) hi = g.n;
     } else {
         const uint32_t s = t / g.q, part = t % g.q;
-        const uint64_t a = g.seg[s], b = g.seg[s + 1], len = b - a;
+        const uint64_t a = g.seg[s], b = g.seg_end[s], len = b - a;
         lo = a + len * part / g.q;
         hi = a + len * (part + 1) / g.q;
     }
@@ -154,6 +158,113 @@ __global__ __launch_bounds__(BLOCK) void k_hash_filter(Key key, uint64_t n, uint
         }
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// Table-1 hash fused with the first partition pass.  The digit of a key
+// (its top `bits` bits) picks one of 2^bits regions of R records each; a
+// region fills in no particular order, which is harmless because the group
+// sort orders each group fully by (key, nonce).  Per sub-tile of BLOCK *
+// ITEMS nonces the work-group hashes into registers, ranks the keys by digit
+// with LDS atomics, claims room in each region with one global atomic per
+// digit on fill[d], lays the sub-tile out digit by digit in LDS and writes
+// every digit's run contiguously.  Work-group b takes sub-tiles
+// [b * per_wg, (b + 1) * per_wg).  Records past a region's capacity are not
+// written and raise VXK_DEV_STATUS_REGION_OVERFLOW (fill[d] still counts
+// them).
+// ---------------------------------------------------------------------------
+
+template <int BLOCK, int ITEMS, int MAXD>
+__global__ __launch_bounds__(BLOCK) void k_hash_scatter(Key key, uint64_t n, uint64_t per_wg, uint32_t bits,
+                                                        uint32_t R, uint64_t *__restrict__ out_keys,
+                                                        uint32_t *__restrict__ out_nonces,
+                                                        uint32_t *__restrict__ fill,
+                                                        uint32_t *__restrict__ status) {
+    constexpr int SUB = BLOCK * ITEMS;
+    static_assert(MAXD <= BLOCK, "one thread per digit claims its region room");
+    __shared__ uint64_t s_keys[SUB];
+    __shared__ uint32_t s_non[SUB];
+    __shared__ uint32_t s_start[MAXD];
+    __shared__ uint32_t s_claim[MAXD];
+    __shared__ uint32_t s_wave[BLOCK / 64 + 1];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nd = 1u << bits, shift = 64u - bits;
+    const uint64_t nsub = (n + SUB - 1) / SUB;
+    const uint64_t s0 = (uint64_t)blockIdx.x * per_wg;
+    const uint64_t s1 = s0 + per_wg < nsub ? s0 + per_wg : nsub;
+    bool over = false;
+    for (uint64_t sub = s0; sub < s1; ++sub) {
+        const uint64_t base = sub * SUB;
+        for (uint32_t d = tid; d < nd; d += BLOCK) s_start[d] = 0;
+        __syncthreads();
+        uint64_t k[ITEMS];
+        uint32_t slot[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint64_t i = base + (uint64_t)j * BLOCK + tid;
+            // As in k_hash_table1: keep the nonce opaque to the optimiser.
+            uint32_t nonce = (uint32_t)i;
+            asm volatile("" : "+v"(nonce));
+            k[j] = vxd::h1(key, nonce);
+            if (i < n) slot[j] = atomicAdd(&s_start[(uint32_t)(k[j] >> shift)], 1u);
+        }
+        __syncthreads();
+        // Claim room in the regions (thread d <-> digit d, nd <= BLOCK); the
+        // atomics are in flight during the digit scan and the LDS layout.
+        uint32_t claim = 0;
+        if (tid < nd) {
+            const uint32_t c = s_start[tid];
+            if (c) claim = atomicAdd(&fill[tid], c);
+        }
+        const uint32_t total = vxd::lds_exclusive_scan<BLOCK>(s_start, (int)nd, s_wave);
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint64_t i = base + (uint64_t)j * BLOCK + tid;
+            if (i < n) {
+                const uint32_t p = s_start[(uint32_t)(k[j] >> shift)] + slot[j];
+                s_keys[p] = k[j];
+                s_non[p] = (uint32_t)i;
+            }
+        }
+        if (tid < nd) s_claim[tid] = claim;
+        __syncthreads();
+        for (uint32_t e = tid; e < total; e += BLOCK) {
+            const uint64_t kk = s_keys[e];
+            const uint32_t d = (uint32_t)(kk >> shift);
+            const uint32_t r = s_claim[d] + (e - s_start[d]);
+            if (r < R) {
+                const uint64_t g = (uint64_t)d * R + r;
+                out_keys[g] = kk;
+                out_nonces[g] = s_non[e];
+            } else {
+                over = true;
+            }
+        }
+        __syncthreads();
+    }
+    if (over) atomicOr(status, (uint32_t)VXK_DEV_STATUS_REGION_OVERFLOW);
+}
+
+// Regions of k_hash_scatter as partition segments: region d holds records
+// [d * R, d * R + min(fill[d], R)) (seg_lo / seg_hi), and its records go to
+// gstart[d] = the sum of the regions before it; gstart[nd] = all records.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_region_scan(const uint32_t *__restrict__ fill, uint32_t nd, uint32_t R,
+                                                       uint32_t *__restrict__ seg_lo,
+                                                       uint32_t *__restrict__ seg_hi,
+                                                       uint32_t *__restrict__ gstart) {
+    __shared__ uint32_t s[kMaxDigits];
+    __shared__ uint32_t s_wave[BLOCK / 64 + 1];
+    for (uint32_t d = threadIdx.x; d < nd; d += BLOCK) {
+        const uint32_t c = min(fill[d], R);
+        s[d] = c;
+        seg_lo[d] = d * R;
+        seg_hi[d] = d * R + c;
+    }
+    __syncthreads();
+    const uint32_t total = vxd::lds_exclusive_scan<BLOCK>(s, (int)nd, s_wave);
+    for (uint32_t d = threadIdx.x; d < nd; d += BLOCK) gstart[d] = s[d];
+    if (threadIdx.x == 0) gstart[nd] = total;
 }
 
 // ---------------------------------------------------------------------------
@@ -1298,16 +1409,19 @@ static TileGeom geom_chunks(uint64_t n, uint64_t chunk) {
     g.chunk = chunk;
     g.n = n;
     g.seg = nullptr;
+    g.seg_end = nullptr;
     return g;
 }
 
-static TileGeom geom_segments(const uint32_t *seg, uint32_t q) {
+// seg_end == NULL: back-to-back segments (segment s ends at seg[s + 1]).
+static TileGeom geom_segments(const uint32_t *seg, const uint32_t *seg_end, uint32_t q) {
     TileGeom g;
     g.mode = 1;
     g.q = q;
     g.chunk = 0;
     g.n = 0;
     g.seg = seg;
+    g.seg_end = seg_end ? seg_end : seg + 1;
     return g;
 }
 
@@ -1329,6 +1443,34 @@ hipError_t launch_hash_filter(const uint32_t key_words[8], uint64_t n, uint32_t 
     for (int i = 0; i < 8; ++i) key.w[i] = key_words[i];
     hipLaunchKernelGGL((k_hash_filter<kHashBlock, 8>), dim3(tiles), dim3(kHashBlock), 0, s, key, n, chunk, pbits,
                        prefix, keys, nonces, cap, count);
+    return hipGetLastError();
+}
+
+uint32_t hash_scatter_grid() {
+    static const uint32_t g = resident_grid(k_hash_scatter<kHashBlock, kHashScatterItems, kHashScatterMaxDigits>,
+                                            kHashBlock);
+    return g;
+}
+
+hipError_t launch_hash_scatter(const uint32_t key_words[8], uint64_t n, uint32_t bits, uint32_t R, uint64_t *keys,
+                               uint32_t *nonces, uint32_t *fill, uint32_t *status, hipStream_t s) {
+    if (bits < 1 || bits > (uint32_t)kHashScatterMaxBits) return hipErrorInvalidValue;
+    Key key;
+    for (int i = 0; i < 8; ++i) key.w[i] = key_words[i];
+    constexpr uint64_t SUB = (uint64_t)kHashBlock * kHashScatterItems;
+    const uint64_t nsub = (n + SUB - 1) / SUB;
+    const uint32_t grid = hash_scatter_grid();
+    const uint64_t per = (nsub + grid - 1) / grid;
+    const uint32_t used = (uint32_t)((nsub + per - 1) / per);
+    hipLaunchKernelGGL((k_hash_scatter<kHashBlock, kHashScatterItems, kHashScatterMaxDigits>), dim3(used),
+                       dim3(kHashBlock), 0, s, key, n, per, bits, R, keys, nonces, fill, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_region_scan(const uint32_t *fill, uint32_t nd, uint32_t R, uint32_t *seg_lo, uint32_t *seg_hi,
+                              uint32_t *gstart, hipStream_t s) {
+    hipLaunchKernelGGL(k_region_scan<kColBlock>, dim3(1), dim3(kColBlock), 0, s, fill, nd, R, seg_lo, seg_hi,
+                       gstart);
     return hipGetLastError();
 }
 
@@ -1363,10 +1505,10 @@ hipError_t launch_hist_chunks(const uint64_t *keys, uint64_t n, uint32_t tiles, 
     return hipGetLastError();
 }
 
-hipError_t launch_hist_segments(const uint64_t *keys, const uint32_t *seg, uint32_t nseg, uint32_t q,
-                                uint32_t shift, uint32_t bits, uint32_t *hist, hipStream_t s) {
+hipError_t launch_hist_segments(const uint64_t *keys, const uint32_t *seg, const uint32_t *seg_end, uint32_t nseg,
+                                uint32_t q, uint32_t shift, uint32_t bits, uint32_t *hist, hipStream_t s) {
     hipLaunchKernelGGL(k_digit_hist<kHistBlock>, dim3(nseg * q), dim3(kHistBlock), 0, s, keys,
-                       geom_segments(seg, q), shift, bits, hist);
+                       geom_segments(seg, seg_end, q), shift, bits, hist);
     return hipGetLastError();
 }
 
@@ -1403,10 +1545,10 @@ hipError_t launch_scatter_chunks(const uint64_t *in_keys, const uint32_t *in_non
 
 hipError_t launch_scatter_segments(const uint64_t *in_keys, const uint32_t *in_nonces,
                                    uint64_t *out_keys, uint32_t *out_nonces, const uint32_t *off,
-                                   const uint32_t *seg, uint32_t nseg, uint32_t q, uint32_t shift,
-                                   uint32_t bits, hipStream_t s) {
+                                   const uint32_t *seg, const uint32_t *seg_end, uint32_t nseg, uint32_t q,
+                                   uint32_t shift, uint32_t bits, hipStream_t s) {
     return launch_scatter_cfg(bits, nseg * q, s, in_keys, in_nonces, out_keys, out_nonces, off,
-                              geom_segments(seg, q), shift, bits);
+                              geom_segments(seg, seg_end, q), shift, bits);
 }
 
 hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint32_t *gstart, uint32_t G,

@@ -97,6 +97,10 @@ TUNINGS = [
     dict(group_bits=13, pipeline_slices=2),   # pipelined tail: 1-6-6 passes, two slices
     dict(group_bits=14, pipeline_slices=4),   # four slices, one per first-pass segment
     dict(group_bits=12, pipeline_slices=3),   # pipelined with two passes, uneven slices
+    dict(separate_hash=1),                    # hash and first pass as two kernels
+    dict(separate_hash=1, group_bits=15, pass1_bits=5, pass2_bits=5),
+    dict(group_bits=16, pass1_bits=8),        # fused hash with 256 first-pass regions
+    dict(group_bits=9, pass1_bits=1, pass2_bits=4),  # fused hash with two regions, three passes
     dict(group_bits=16, pipeline_slices=16, group_cap=64),   # 16 slices, oversized groups
     dict(group_bits=15, pipeline_slices=5, match_chunk_bits=6),  # many small chunks per slice
     dict(group_bits=9, pipeline_slices=4),    # one pass: nothing to pipeline
