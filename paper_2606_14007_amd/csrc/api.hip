@@ -62,8 +62,8 @@ struct Plan {
     uint32_t cb = 0;         // match chunk = 2^cb consecutive Table-1 records
     bool fused = false;      // plot: one fused sort + match kernel instead of two
     uint32_t slices = 1;     // plot: pipeline slices of the passes after the first (1 = none)
-    bool hs = false;         // plot: the hash kernel also does the first partition pass
-    uint32_t R = 0;          // hs: records per first-pass region (digit)
+    bool hs = false;         // plot: region passes (the hash does the first; see make_plan)
+    uint32_t R[kMaxPasses] = {};  // hs: records per region of each pass
 };
 
 uint32_t clampu(int64_t v, int64_t lo, int64_t hi) {
@@ -164,16 +164,27 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     if (P.npass < 2) P.slices = 1;
     P.slices = std::min(P.slices, 1u << P.D[0]);
     if (P.slices < 1) P.slices = 1;
-    // Plots with two or more passes fuse the first into the hash kernel.
-    // Its regions hold the expected records of a digit plus 8 standard
-    // deviations and a sub-tile (fewer than one plot in 10^13 overflows one,
-    // which the device status reports).
-    P.hs = hs_ok && P.npass >= 2 && P.D[0] <= (uint32_t)vxk::kHashScatterMaxBits;
-    if (P.hs) {
-        const uint32_t nd = 1u << P.D[0];
-        const double mean = (double)((P.n + nd - 1) / nd);
-        P.R = (uint32_t)(mean + 8.0 * std::sqrt(mean)) + vxk::kHashScatterSub;
-        if ((uint64_t)P.R * nd >= (1ull << 32)) P.hs = false;
+    // Plots with two or more passes fuse the first into the hash kernel,
+    // and every pass files records into fixed-size regions, one per (input
+    // segment, digit), claiming room with a global atomic per sub-tile run
+    // (no histogram passes); the group sort then gathers each group from its
+    // region into Table 1.  A region holds the expected records plus 8
+    // standard deviations and some slack (fewer than one plot in 10^9
+    // overflows one, which the device status reports).
+    //
+    // A pipelined plan with three passes keeps the contiguous passes: there a
+    // slice's last pass would file into the buffer that still holds the
+    // first pass's regions of later slices.
+    P.hs = hs_ok && P.npass >= 2 && P.D[0] <= (uint32_t)vxk::kHashScatterMaxBits &&
+           !(P.slices > 1 && P.npass > 2);
+    for (uint32_t i = 1; i < P.npass; ++i)
+        if (P.D[i] > (uint32_t)vxk::kClaimMaxBits) P.hs = false;
+    for (uint32_t i = 0; P.hs && i < P.npass; ++i) {
+        const uint32_t bits = P.pre[i] + P.D[i];
+        const double mean = (double)((P.n + (1ull << bits) - 1) >> bits);
+        const uint32_t slack = i == 0 ? vxk::kHashScatterSub : 64u;
+        P.R[i] = (uint32_t)(mean + 8.0 * std::sqrt(mean)) + slack;
+        if (((uint64_t)P.R[i] << bits) >= (1ull << 32)) P.hs = false;
     }
     *pl = P;
     return VX_OK;
@@ -192,8 +203,9 @@ struct Layout {
     size_t mcount = 0, mbase = 0; // u64[match chunks]: pair counts, Table-2 bases
     size_t pcnt = 0;              // u8[n]: pair count of each Table-1 record (255 = look again)
     size_t nonces_in = 0;         // u32[n]: nonces of a chunk's records (chunked plots)
-    size_t reg_nonces = 0;        // u32[regions]: nonces of a fused-hash plot's first pass
-    size_t fill = 0, seg_lo = 0, seg_hi = 0;  // u32[2^D0]: fused-hash regions
+    size_t reg_nonces = 0;        // u32[regions]: nonces of the even passes' regions (hs)
+    // hs, per pass: u32[2^(pre + D)] region fill counts and bounds
+    size_t fill[kMaxPasses] = {}, seg_lo[kMaxPasses] = {}, seg_hi[kMaxPasses] = {};
     size_t mpart = 0;             // u64[scan parts]
     size_t total = 0;
 };
@@ -232,22 +244,30 @@ Layout layout(const Plan &P, int which) {
     if (chunk) which = VX_CALL_PLOT;
     const bool sort = which == VX_CALL_BUCKET_SORT || which == VX_CALL_PLOT;
     const bool match = which == VX_CALL_MATCH || which == VX_CALL_PLOT;
-    // A fused-hash plot (P.hs) writes the first pass into keys_no +
-    // reg_nonces, as regions with slack; the later passes alternate between
-    // the scratch arrays and Table 1 as in any plot.
+    // A region-pass plot (P.hs) files the even passes (the first in the
+    // hash kernel) into keys_no + reg_nonces and the odd ones into the
+    // scratch arrays, each as fixed-size regions with slack; Table 1 is
+    // written only by the group sort.
     const bool hs = which == VX_CALL_PLOT && !chunk && P.hs;
-    const uint64_t regions = hs ? (uint64_t)P.R << P.D[0] : P.n;
-    if (which == VX_CALL_PLOT) L.keys_no = take(regions * 8);
-    if (hs) L.reg_nonces = take(regions * 4);
-    if (hs) {
-        L.fill = take((size_t)4 << P.D[0]);
-        L.seg_lo = take((size_t)4 << P.D[0]);
-        L.seg_hi = take((size_t)4 << P.D[0]);
+    uint64_t cap_even = P.n, cap_odd = P.n;
+    for (uint32_t i = 0; hs && i < P.npass; ++i) {
+        const uint64_t c = (uint64_t)P.R[i] << (P.pre[i] + P.D[i]);
+        uint64_t &m = (i % 2 == 0) ? cap_even : cap_odd;
+        m = std::max(m, c);
+    }
+    if (which == VX_CALL_PLOT) L.keys_no = take(cap_even * 8);
+    if (hs) L.reg_nonces = take(cap_even * 4);
+    for (uint32_t i = 0; hs && i < P.npass; ++i) {
+        const size_t nr = (size_t)1 << (P.pre[i] + P.D[i]);
+        L.fill[i] = take(nr * 4);
+        L.seg_lo[i] = take(nr * 4);
+        L.seg_hi[i] = take(nr * 4);
     }
     if (chunk) L.nonces_in = take(P.n * 4);
+    const uint64_t scr = cap_odd;
     if (sort) {
-        L.scr_keys = take(P.n * 8);
-        L.scr_nonces = take(P.n * 4);
+        L.scr_keys = take(scr * 8);
+        L.scr_nonces = take(scr * 4);
         for (uint32_t i = 0; i < P.npass; ++i) {
             const size_t cells = (size_t)pass_tiles(P, i) << P.D[i];
             L.hist[i] = take(cells * 4);
@@ -296,15 +316,15 @@ PassBufs pass_bufs(const Plan &P, const Layout &L, void *ws, const uint64_t *key
     uint32_t *scr_n = at<uint32_t>(ws, L.scr_nonces);
     auto to_t1 = [&](uint32_t j) { return ((P.npass - 1 - j) % 2) == 0; };
     PassBufs B;
-    if (P.hs && i <= 1) {
-        // Pass 0 (in the hash kernel) fills the regions in keys_no +
-        // reg_nonces; pass 1 reads them.
+    if (P.hs) {
+        // Even passes (the first in the hash kernel) fill regions in keys_no +
+        // reg_nonces, odd ones in the scratch arrays; each reads the other.
         uint64_t *reg_k = at<uint64_t>(ws, L.keys_no);
         uint32_t *reg_n = at<uint32_t>(ws, L.reg_nonces);
-        B.in_k = i == 0 ? nullptr : reg_k;
-        B.in_n = i == 0 ? nullptr : reg_n;
-        B.out_k = i == 0 ? reg_k : (to_t1(1) ? t1_keys : scr_k);
-        B.out_n = i == 0 ? reg_n : (to_t1(1) ? t1_nonces : scr_n);
+        B.in_k = i == 0 ? nullptr : (i % 2 ? reg_k : scr_k);
+        B.in_n = i == 0 ? nullptr : (i % 2 ? reg_n : scr_n);
+        B.out_k = i % 2 ? scr_k : reg_k;
+        B.out_n = i % 2 ? scr_n : reg_n;
         return B;
     }
     if (i == 0) {
@@ -319,11 +339,12 @@ PassBufs pass_bufs(const Plan &P, const Layout &L, void *ws, const uint64_t *key
     return B;
 }
 
-// Pass i >= 1 over its input segments [sa, sb) (the groups of pass i - 1):
-// per-tile histograms, their scan inside each segment, and the scatter.
-// Segments lie back to back at the previous pass's group starts, except the
-// regions of a fused-hash first pass (seg_lo / seg_hi), whose records move
-// to the group starts.
+// Pass i >= 1 over its input segments [sa, sb) (the groups of pass i - 1).
+// A region-pass plan (P.hs) reads the previous pass's regions and claims
+// room in its own: the scatter, the clamp of the region counts, and their
+// scan (one row per segment, on top of the segments' bases) into the group
+// starts.  Otherwise segments lie back to back at the previous pass's group
+// starts: per-tile histograms, their scan inside each segment, the scatter.
 vx_status run_pass(const Plan &P, const Layout &L, void *ws, const PassBufs &B, uint32_t i, uint32_t sa,
                    uint32_t sb, hipStream_t s) {
     const uint32_t nd = 1u << P.D[i];
@@ -331,15 +352,26 @@ vx_status run_pass(const Plan &P, const Layout &L, void *ws, const PassBufs &B, 
     const uint32_t q = P.Q[i];
     const uint32_t nseg = sb - sa;
     const uint32_t *base = at<uint32_t>(ws, L.gstart[i - 1]) + sa;
-    const bool regions = P.hs && i == 1;
-    const uint32_t *seg = regions ? at<uint32_t>(ws, L.seg_lo) + sa : base;
-    const uint32_t *seg_end = regions ? at<uint32_t>(ws, L.seg_hi) + sa : nullptr;
-    uint32_t *hist = at<uint32_t>(ws, L.hist[i]) + (size_t)sa * q * nd;
     uint32_t *off = at<uint32_t>(ws, L.off[i]) + (size_t)sa * q * nd;
     uint32_t *gst = at<uint32_t>(ws, L.gstart[i]) + (size_t)sa * nd;
-    VX_HIP(vxk::launch_hist_segments(B.in_k, seg, seg_end, nseg, q, shift, P.D[i], hist, s), "pass histogram");
+    if (P.hs) {
+        const uint32_t *seg = at<uint32_t>(ws, L.seg_lo[i - 1]) + sa;
+        const uint32_t *seg_end = at<uint32_t>(ws, L.seg_hi[i - 1]) + sa;
+        uint32_t *fill = at<uint32_t>(ws, L.fill[i]) + (size_t)sa * nd;
+        const uint64_t first = (uint64_t)sa * nd * P.R[i];
+        VX_HIP(vxk::launch_scatter_claim(B.in_k, B.in_n, B.out_k + first, B.out_n + first, seg, seg_end, nseg, q,
+                                         shift, P.D[i], fill, P.R[i], at<uint32_t>(ws, L.header) + kHdrStatus, s),
+               "pass scatter");
+        VX_HIP(vxk::launch_region_bounds(fill, sa * nd, nseg * nd, P.R[i], at<uint32_t>(ws, L.seg_lo[i]) + sa * nd,
+                                         at<uint32_t>(ws, L.seg_hi[i]) + sa * nd, s),
+               "pass regions");
+        VX_HIP(vxk::launch_colscan(fill, off, nseg, 1, nd, base, gst, nseg * nd, (uint32_t)P.n, s), "pass scan");
+        return VX_OK;
+    }
+    uint32_t *hist = at<uint32_t>(ws, L.hist[i]) + (size_t)sa * q * nd;
+    VX_HIP(vxk::launch_hist_segments(B.in_k, base, nullptr, nseg, q, shift, P.D[i], hist, s), "pass histogram");
     VX_HIP(vxk::launch_colscan(hist, off, nseg, q, nd, base, gst, nseg * nd, (uint32_t)P.n, s), "pass scan");
-    VX_HIP(vxk::launch_scatter_segments(B.in_k, B.in_n, B.out_k, B.out_n, off, seg, seg_end, nseg, q, shift,
+    VX_HIP(vxk::launch_scatter_segments(B.in_k, B.in_n, B.out_k, B.out_n, off, base, nullptr, nseg, q, shift,
                                         P.D[i], s),
            "pass scatter");
     return VX_OK;
@@ -375,21 +407,31 @@ vx_status run_partition(const Plan &P, const Layout &L, void *ws, const uint64_t
     return VX_OK;
 }
 
-// In-place sort of the partitioned groups [g0, g0 + gcount) (+ oversized
-// groups), with their bucket offsets; `slot` picks the slice's header words.
-// pcnt (may be NULL): the sort also stores every record's pair count (one
-// byte) while the group is in LDS.
+// Sort of the partitioned groups [g0, g0 + gcount) (+ oversized groups)
+// into Table 1, with their bucket offsets; `slot` picks the slice's header
+// words.  Groups are sorted in place, or (region-pass plans) gathered from
+// the last pass's regions.  pcnt (may be NULL): the sort also stores every
+// record's pair count (one byte) while the group is in LDS.
 vx_status run_group_sort(const Plan &P, const Layout &L, void *ws, uint64_t *t1_keys, uint32_t *t1_nonces,
                          uint32_t *offsets, uint8_t *pcnt, uint32_t g0, uint32_t gcount, uint32_t slot,
                          hipStream_t s) {
     uint32_t *hdr = at<uint32_t>(ws, L.header);
-    const uint32_t *gstart = at<uint32_t>(ws, L.gstart[P.npass - 1]);
+    const uint32_t last = P.npass - 1;
+    const uint32_t *gstart = at<uint32_t>(ws, L.gstart[last]);
     uint32_t *ovf_list = at<uint32_t>(ws, L.ovf_list) + g0;
-    VX_HIP(vxk::launch_groupsort(t1_keys, t1_nonces, gstart, P.G, P.cap, offsets, (uint32_t)P.n,
+    const uint64_t *in_k = nullptr;
+    const uint32_t *in_n = nullptr, *in_lo = nullptr;
+    if (P.hs) {
+        const PassBufs B = pass_bufs(P, L, ws, nullptr, t1_keys, t1_nonces, last);
+        in_k = B.out_k;
+        in_n = B.out_n;
+        in_lo = at<uint32_t>(ws, L.seg_lo[last]);
+    }
+    VX_HIP(vxk::launch_groupsort(t1_keys, t1_nonces, in_k, in_n, in_lo, gstart, P.G, P.cap, offsets, (uint32_t)P.n,
                                  hdr + kHdrOvf + slot, ovf_list, P.T, pcnt, g0, gcount,
                                  hdr + kHdrSortTicket + slot, s),
            "group sort");
-    VX_HIP(vxk::launch_group_fallback(t1_keys, t1_nonces, at<uint64_t>(ws, L.scr_keys),
+    VX_HIP(vxk::launch_group_fallback(t1_keys, t1_nonces, in_k, in_n, in_lo, at<uint64_t>(ws, L.scr_keys),
                                       at<uint32_t>(ws, L.scr_nonces), gstart, P.G, offsets, hdr + kHdrOvf + slot,
                                       ovf_list, hdr + kHdrStatus, P.T, pcnt, s),
            "group sort fallback");
@@ -763,16 +805,18 @@ vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, cons
     uint64_t *keys_no = at<uint64_t>(ws, L.keys_no);
     uint32_t *hdr = at<uint32_t>(ws, L.header);
     VX_HIP(vxk::launch_reset(hdr, kHeaderWords, s), "reset");
-    if (P.hs) VX_HIP(vxk::launch_reset(at<uint32_t>(ws, L.fill), 1u << P.D[0], s), "reset");
+    for (uint32_t i = 0; P.hs && i < P.npass; ++i)
+        VX_HIP(vxk::launch_fill_u32(at<uint32_t>(ws, L.fill[i]), 1ull << (P.pre[i] + P.D[i]), 0u, s), "reset");
     VX_HIP(mark(ev, 0, s), "event");
     if (P.hs) {
         // Hash + first partition pass in one kernel, then the regions' bounds.
-        VX_HIP(vxk::launch_hash_scatter(P.key_words, P.n, P.D[0], P.R, keys_no, at<uint32_t>(ws, L.reg_nonces),
-                                        at<uint32_t>(ws, L.fill), hdr + kHdrStatus, s),
+        VX_HIP(vxk::launch_hash_scatter(P.key_words, P.n, P.D[0], P.R[0], keys_no, at<uint32_t>(ws, L.reg_nonces),
+                                        at<uint32_t>(ws, L.fill[0]), hdr + kHdrStatus, s),
                "hash + first pass");
         VX_HIP(mark(ev, 1, s), "event");
-        VX_HIP(vxk::launch_region_scan(at<uint32_t>(ws, L.fill), 1u << P.D[0], P.R, at<uint32_t>(ws, L.seg_lo),
-                                       at<uint32_t>(ws, L.seg_hi), at<uint32_t>(ws, L.gstart[0]), s),
+        VX_HIP(vxk::launch_region_scan(at<uint32_t>(ws, L.fill[0]), 1u << P.D[0], P.R[0],
+                                       at<uint32_t>(ws, L.seg_lo[0]), at<uint32_t>(ws, L.seg_hi[0]),
+                                       at<uint32_t>(ws, L.gstart[0]), s),
                "region scan");
         VX_HIP(mark(ev, 2, s), "event");
     } else {

@@ -23,6 +23,7 @@ constexpr int kHashScatterItems = 8;
 constexpr int kHashScatterMaxBits = 8;
 constexpr int kHashScatterMaxDigits = 1 << kHashScatterMaxBits;
 constexpr uint32_t kHashScatterSub = 256u * kHashScatterItems;
+constexpr int kClaimMaxBits = 9;  // widest digit of a claiming scatter
 
 hipError_t launch_reset(uint32_t *words, uint32_t n, hipStream_t s);
 // Chunked plots: hash all n nonces, keep keys whose top pbits bits are
@@ -59,11 +60,26 @@ hipError_t launch_scatter_segments(const uint64_t *in_keys, const uint32_t *in_n
                                    uint64_t *out_keys, uint32_t *out_nonces, const uint32_t *off,
                                    const uint32_t *seg, const uint32_t *seg_end, uint32_t nseg, uint32_t q,
                                    uint32_t shift, uint32_t bits, hipStream_t s);
-hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint32_t *gstart, uint32_t G,
-                            uint32_t cap, uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count,
-                            uint32_t *ovf_list, uint64_t T, uint8_t *pcnt, uint32_t g0, uint32_t gcount,
-                            uint32_t *ticket, hipStream_t s);
-hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, uint64_t *scr_keys,
+// Scatter that claims room in fixed regions instead of using a histogram
+// scan (bits <= kClaimMaxBits): record of segment s and digit d goes to
+// region s * 2^bits + d = [region * R, + R) of out; fill[region] (zero at
+// launch) counts them, overflow raises VXK_DEV_STATUS_REGION_OVERFLOW.
+hipError_t launch_scatter_claim(const uint64_t *in_keys, const uint32_t *in_nonces, uint64_t *out_keys,
+                                uint32_t *out_nonces, const uint32_t *seg, const uint32_t *seg_end, uint32_t nseg,
+                                uint32_t q, uint32_t shift, uint32_t bits, uint32_t *fill, uint32_t R,
+                                uint32_t *status, hipStream_t s);
+// Clamps the counts of regions [r0, r0 + nregions) (fill, seg_lo and seg_hi
+// point at region r0) to R in place and writes their bounds.
+hipError_t launch_region_bounds(uint32_t *fill, uint32_t r0, uint32_t nregions, uint32_t R, uint32_t *seg_lo,
+                                uint32_t *seg_hi, hipStream_t s);
+// Group sorts write group g to keys / nonces at gstart[g].  They read it in
+// place, or (in_keys != NULL) from record in_lo[g] of in_keys / in_nonces.
+hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint64_t *in_keys, const uint32_t *in_nonces,
+                            const uint32_t *in_lo, const uint32_t *gstart, uint32_t G, uint32_t cap,
+                            uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count, uint32_t *ovf_list, uint64_t T,
+                            uint8_t *pcnt, uint32_t g0, uint32_t gcount, uint32_t *ticket, hipStream_t s);
+hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, const uint64_t *in_keys,
+                                 const uint32_t *in_nonces, const uint32_t *in_lo, uint64_t *scr_keys,
                                  uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G,
                                  uint32_t *offsets, const uint32_t *ovf_count, const uint32_t *ovf_list,
                                  uint32_t *status, uint64_t T, uint8_t *pcnt, hipStream_t s);

@@ -371,16 +371,38 @@ __global__ __launch_bounds__(BLOCK) void k_colscan(const uint32_t *__restrict__ 
 // contiguously at the tile's running cursor for that digit.  The next
 // sub-tile's loads are issued before the current one's LDS work and stores,
 // so a lone work-group per CU still keeps HBM reads in flight.
+//
+// CLAIM: instead of cursors from a histogram scan, every sub-tile claims
+// room for its digit runs with one global atomic per digit in fixed-size
+// regions: region (s, d) of segment s and digit d holds records
+// [(s * 2^bits + d) * claim.R, + claim.R) of the output, and claim.fill
+// counts its records (the same scheme as k_hash_scatter, records past a
+// region's capacity raise VXK_DEV_STATUS_REGION_OVERFLOW).
 // ---------------------------------------------------------------------------
 
-template <int BLOCK, int ITEMS, int MAXD>
+struct Claim {
+    uint32_t *fill;
+    uint32_t R;
+    uint32_t *status;
+};
+
+// Where a group sort reads group g: keys / nonces from record lo[g] of the
+// input regions, or (keys == NULL) in place at the group's own start.
+struct GroupIn {
+    const uint64_t *keys;
+    const uint32_t *nonces;
+    const uint32_t *lo;
+};
+
+template <int BLOCK, int ITEMS, int MAXD, bool CLAIM>
 __global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ in_keys,
                                                    const uint32_t *__restrict__ in_nonces,
                                                    uint64_t *__restrict__ out_keys,
                                                    uint32_t *__restrict__ out_nonces,
                                                    const uint32_t *__restrict__ off, TileGeom geom,
-                                                   uint32_t shift, uint32_t bits) {
+                                                   uint32_t shift, uint32_t bits, Claim claim) {
     constexpr int SUB = BLOCK * ITEMS;
+    static_assert(!CLAIM || MAXD <= BLOCK, "one thread per digit claims its region room");
     __shared__ uint64_t s_keys[SUB];
     __shared__ uint32_t s_nonces[SUB];
     __shared__ uint32_t s_cursor[MAXD];
@@ -388,7 +410,11 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ 
     __shared__ uint32_t s_wave[BLOCK / 64 + 1];
     const uint32_t nd = 1u << bits, mask = nd - 1u;
     const uint32_t tid = threadIdx.x;
-    for (uint32_t d = tid; d < nd; d += BLOCK) s_cursor[d] = off[(uint64_t)blockIdx.x * nd + d];
+    if (!CLAIM)
+        for (uint32_t d = tid; d < nd; d += BLOCK) s_cursor[d] = off[(uint64_t)blockIdx.x * nd + d];
+    // Claim mode: this tile's segment and the first of its regions.
+    const uint64_t region0 = CLAIM ? (uint64_t)(blockIdx.x / geom.q) * nd : 0;
+    bool over = false;
     uint64_t lo, hi;
     tile_range(geom, blockIdx.x, lo, hi);
     // Loads of a sub-tile: indices past the tile are clamped to its last
@@ -434,29 +460,62 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ 
         const uint64_t nbase = base + SUB;
         if (nbase < hi) load(nbase, nk, nn);
         __syncthreads();
+        // Claim mode: thread d claims digit d's room; the atomic is in
+        // flight during the scan and the LDS layout.
+        uint32_t got = 0;
+        if (CLAIM && tid < nd) {
+            const uint32_t c = s_start[tid];
+            if (c) got = atomicAdd(&claim.fill[region0 + tid], c);
+        }
         const uint32_t total = vxd::lds_exclusive_scan<BLOCK>(s_start, (int)nd, s_wave);
         if (tid == 0) s_start[nd] = total;
         __syncthreads();
 #pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                const uint64_t idx = base + (uint64_t)j * BLOCK + tid;
-                if (idx < hi) {
-                    const uint32_t p = s_start[(uint32_t)(k[j] >> shift) & mask] + slot[j];
-                    s_keys[p] = k[j];
-                    s_nonces[p] = n[j];
-                }
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint64_t idx = base + (uint64_t)j * BLOCK + tid;
+            if (idx < hi) {
+                const uint32_t p = s_start[(uint32_t)(k[j] >> shift) & mask] + slot[j];
+                s_keys[p] = k[j];
+                s_nonces[p] = n[j];
             }
-            __syncthreads();
-            for (uint32_t e = tid; e < total; e += BLOCK) {
-                const uint64_t kk = s_keys[e];
-                const uint32_t d = (uint32_t)(kk >> shift) & mask;
+        }
+        if (CLAIM && tid < nd) s_cursor[tid] = got;
+        __syncthreads();
+        for (uint32_t e = tid; e < total; e += BLOCK) {
+            const uint64_t kk = s_keys[e];
+            const uint32_t d = (uint32_t)(kk >> shift) & mask;
+            if (CLAIM) {
+                const uint32_t r = s_cursor[d] + (e - s_start[d]);
+                if (r < claim.R) {
+                    const uint64_t g = (region0 + d) * claim.R + r;
+                    out_keys[g] = kk;
+                    out_nonces[g] = s_nonces[e];
+                } else {
+                    over = true;
+                }
+            } else {
                 const uint64_t g = (uint64_t)s_cursor[d] + (e - s_start[d]);
                 out_keys[g] = kk;
                 out_nonces[g] = s_nonces[e];
             }
+        }
         __syncthreads();
-        for (uint32_t d = tid; d < nd; d += BLOCK) s_cursor[d] += s_start[d + 1] - s_start[d];
+        if (!CLAIM)
+            for (uint32_t d = tid; d < nd; d += BLOCK) s_cursor[d] += s_start[d + 1] - s_start[d];
         __syncthreads();
+    }
+    if (CLAIM && over) atomicOr(claim.status, (uint32_t)VXK_DEV_STATUS_REGION_OVERFLOW);
+}
+
+// Claimed regions as segments of the next pass: counts clamped to the
+// capacity R (in place), region r covering [r * R, r * R + count).
+__global__ void k_region_bounds(uint32_t *__restrict__ fill, uint32_t r0, uint32_t nregions, uint32_t R,
+                                uint32_t *__restrict__ seg_lo, uint32_t *__restrict__ seg_hi) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nregions; r += gridDim.x * blockDim.x) {
+        const uint32_t c = min(fill[r], R);
+        fill[r] = c;
+        seg_lo[r] = (r0 + r) * R;
+        seg_hi[r] = (r0 + r) * R + c;
     }
 }
 
@@ -525,8 +584,7 @@ __device__ __forceinline__ uint64_t pairs_in_range(const uint64_t *keys, uint32_
 // one's global loads behind the others' LDS work (better, measured, than
 // prefetching into registers at two per CU).
 template <int BLOCK, int CAPMAX>
-__global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys,
-                                                     uint32_t *__restrict__ nonces,
+__global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *keys, uint32_t *nonces, GroupIn in,
                                                      const uint32_t *__restrict__ gstart,
                                                      uint32_t G, uint32_t cap,
                                                      uint32_t *__restrict__ offsets,
@@ -553,6 +611,8 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys
         if (t >= gcount) break;
         const uint32_t g = g0 + t;
         const uint32_t lo = gstart[g], n = gstart[g + 1] - lo;
+        const uint64_t *src_k = in.keys ? in.keys + in.lo[g] : keys + lo;
+        const uint32_t *src_n = in.keys ? in.nonces + in.lo[g] : nonces + lo;
         uint64_t k[ITEMS];
         uint32_t nn[ITEMS], slot[ITEMS];
         if (n <= cap && n > 0) {
@@ -561,8 +621,8 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys
             for (int j = 0; j < ITEMS; ++j) {
                 const uint32_t e = j * BLOCK + tid;
                 const uint32_t ec = e < n ? e : n - 1;
-                k[j] = keys[lo + ec];
-                nn[j] = nonces[lo + ec];
+                k[j] = src_k[ec];
+                nn[j] = src_n[ec];
             }
         }
         if (n > cap) {
@@ -665,8 +725,8 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *__restrict__ keys
 // and stay unsorted.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_group_fallback(
-    uint64_t *__restrict__ keys, uint32_t *__restrict__ nonces, uint64_t *__restrict__ scr_keys,
-    uint32_t *__restrict__ scr_nonces, const uint32_t *__restrict__ gstart, uint32_t G,
+    uint64_t *keys, uint32_t *nonces, GroupIn in, uint64_t *scr_keys,
+    uint32_t *scr_nonces, const uint32_t *__restrict__ gstart, uint32_t G,
     uint32_t *__restrict__ offsets, const uint32_t *__restrict__ ovf_count,
     const uint32_t *__restrict__ ovf_list, uint32_t fb_max, uint32_t *__restrict__ status,
     uint64_t T, uint8_t *__restrict__ pcnt) {
@@ -681,9 +741,20 @@ __global__ __launch_bounds__(BLOCK) void k_group_fallback(
             if (tid == 0) atomicOr(status, (uint32_t)VXK_DEV_STATUS_GROUP_TOO_LARGE);
             continue;
         }
-        for (uint32_t e = tid; e < n; e += BLOCK) {
-            scr_keys[lo + e] = keys[lo + e];
-            scr_nonces[lo + e] = nonces[lo + e];
+        // The records to rank: the input regions, or (in place) a copy in
+        // the scratch arrays.
+        const uint64_t *sk;
+        const uint32_t *sn;
+        if (in.keys) {
+            sk = in.keys + in.lo[g];
+            sn = in.nonces + in.lo[g];
+        } else {
+            for (uint32_t e = tid; e < n; e += BLOCK) {
+                scr_keys[lo + e] = keys[lo + e];
+                scr_nonces[lo + e] = nonces[lo + e];
+            }
+            sk = scr_keys + lo;
+            sn = scr_nonces + lo;
         }
         __syncthreads();
         for (uint32_t e0 = 0; e0 < n; e0 += BLOCK) {
@@ -692,14 +763,14 @@ __global__ __launch_bounds__(BLOCK) void k_group_fallback(
             uint64_t mk = 0;
             uint32_t mn = 0, r = 0;
             if (valid) {
-                mk = scr_keys[lo + e];
-                mn = scr_nonces[lo + e];
+                mk = sk[e];
+                mn = sn[e];
             }
             for (uint32_t t0 = 0; t0 < n; t0 += BLOCK) {
                 __syncthreads();
                 if (t0 + tid < n) {
-                    s_k[tid] = scr_keys[lo + t0 + tid];
-                    s_n[tid] = scr_nonces[lo + t0 + tid];
+                    s_k[tid] = sk[t0 + tid];
+                    s_n[tid] = sn[t0 + tid];
                 }
                 __syncthreads();
                 const uint32_t m = min((uint32_t)BLOCK, n - t0);
@@ -1527,11 +1598,12 @@ hipError_t launch_colscan(const uint32_t *hist, uint32_t *off, uint32_t nseg, ui
 template <typename... A>
 static hipError_t launch_scatter_cfg(uint32_t bits, uint32_t grid, hipStream_t s, A... args) {
     if (bits <= 6)
-        hipLaunchKernelGGL((k_scatter<512, 8, 64>), dim3(grid), dim3(512), 0, s, args...);
+        hipLaunchKernelGGL((k_scatter<512, 8, 64, false>), dim3(grid), dim3(512), 0, s, args..., Claim{});
     else if (bits <= 9)
-        hipLaunchKernelGGL((k_scatter<1024, 8, 512>), dim3(grid), dim3(1024), 0, s, args...);
+        hipLaunchKernelGGL((k_scatter<1024, 8, 512, false>), dim3(grid), dim3(1024), 0, s, args..., Claim{});
     else
-        hipLaunchKernelGGL((k_scatter<1024, 8, kMaxDigits>), dim3(grid), dim3(1024), 0, s, args...);
+        hipLaunchKernelGGL((k_scatter<1024, 8, kMaxDigits, false>), dim3(grid), dim3(1024), 0, s, args...,
+                           Claim{});
     return hipGetLastError();
 }
 
@@ -1551,25 +1623,52 @@ hipError_t launch_scatter_segments(const uint64_t *in_keys, const uint32_t *in_n
                               geom_segments(seg, seg_end, q), shift, bits);
 }
 
-hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint32_t *gstart, uint32_t G,
-                            uint32_t cap, uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count,
-                            uint32_t *ovf_list, uint64_t T, uint8_t *pcnt, uint32_t g0, uint32_t gcount,
-                            uint32_t *ticket, hipStream_t s) {
+hipError_t launch_scatter_claim(const uint64_t *in_keys, const uint32_t *in_nonces, uint64_t *out_keys,
+                                uint32_t *out_nonces, const uint32_t *seg, const uint32_t *seg_end, uint32_t nseg,
+                                uint32_t q, uint32_t shift, uint32_t bits, uint32_t *fill, uint32_t R,
+                                uint32_t *status, hipStream_t s) {
+    if (bits < 1 || bits > (uint32_t)kClaimMaxBits) return hipErrorInvalidValue;
+    const Claim c{fill, R, status};
+    const TileGeom g = geom_segments(seg, seg_end, q);
+    if (bits <= 6)
+        hipLaunchKernelGGL((k_scatter<512, 8, 64, true>), dim3(nseg * q), dim3(512), 0, s, in_keys, in_nonces,
+                           out_keys, out_nonces, nullptr, g, shift, bits, c);
+    else
+        hipLaunchKernelGGL((k_scatter<1024, 8, 512, true>), dim3(nseg * q), dim3(1024), 0, s, in_keys, in_nonces,
+                           out_keys, out_nonces, nullptr, g, shift, bits, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_region_bounds(uint32_t *fill, uint32_t r0, uint32_t nregions, uint32_t R, uint32_t *seg_lo,
+                                uint32_t *seg_hi, hipStream_t s) {
+    const uint32_t blocks = (nregions + 255) / 256;
+    hipLaunchKernelGGL(k_region_bounds, dim3(blocks < 1024 ? blocks : 1024), dim3(256), 0, s, fill, r0, nregions,
+                       R, seg_lo, seg_hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint64_t *in_keys, const uint32_t *in_nonces,
+                            const uint32_t *in_lo, const uint32_t *gstart, uint32_t G, uint32_t cap,
+                            uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count, uint32_t *ovf_list, uint64_t T,
+                            uint8_t *pcnt, uint32_t g0, uint32_t gcount, uint32_t *ticket, hipStream_t s) {
     static const uint32_t resident = resident_grid(k_groupsort<kSortBlock, kGroupCapMax>, kSortBlock);
     const uint32_t grid = min(gcount, resident);
     if (grid == 0) return hipSuccess;
+    const GroupIn in{in_keys, in_nonces, in_lo};
     hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapMax>), dim3(grid), dim3(kSortBlock), 0, s,
-                       keys, nonces, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T, pcnt, g0,
+                       keys, nonces, in, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T, pcnt, g0,
                        gcount, ticket);
     return hipGetLastError();
 }
 
-hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, uint64_t *scr_keys,
+hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, const uint64_t *in_keys,
+                                 const uint32_t *in_nonces, const uint32_t *in_lo, uint64_t *scr_keys,
                                  uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G,
                                  uint32_t *offsets, const uint32_t *ovf_count, const uint32_t *ovf_list,
                                  uint32_t *status, uint64_t T, uint8_t *pcnt, hipStream_t s) {
+    const GroupIn in{in_keys, in_nonces, in_lo};
     hipLaunchKernelGGL(k_group_fallback<kFallbackBlock>, dim3(kFallbackGrid), dim3(kFallbackBlock), 0,
-                       s, keys, nonces, scr_keys, scr_nonces, gstart, G, offsets, ovf_count, ovf_list,
+                       s, keys, nonces, in, scr_keys, scr_nonces, gstart, G, offsets, ovf_count, ovf_list,
                        (uint32_t)kFallbackMax, status, T, pcnt);
     return hipGetLastError();
 }
