@@ -152,8 +152,8 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     P.W = t->h1_tiles ? t->h1_tiles : clampu((int64_t)(P.n >> 14), 1, 2048);
     if (P.W < 1 || P.W > 65536) return fail(VX_ERR_UNSUPPORTED, "h1_tiles must be in [1, 65536]");
     P.chunk1 = (P.n + P.W - 1) / P.W;
-    for (uint32_t i = 1; i < P.npass; ++i)  // about 2^17 records per tile
-        P.Q[i] = clampu((int64_t)((P.n >> P.pre[i]) >> 17), 1, 64);
+    for (uint32_t i = 1; i < P.npass; ++i)  // about 2^16 records per tile
+        P.Q[i] = clampu((int64_t)((P.n >> P.pre[i]) >> 16), 1, 256);
     P.cap = t->group_cap ? t->group_cap : (uint32_t)vxk::kGroupCapMax;
     if (P.cap < 64 || P.cap > (uint32_t)vxk::kGroupCapMax)
         return fail(VX_ERR_UNSUPPORTED, "group_cap must be in [64, 3072]");
