@@ -305,72 +305,96 @@ def bench_serving(args) -> dict:
 
 
 def bench_chunked(args) -> dict:
-    """One whole plot made as 2^c chunks through vx_plot_chunk (default
-    k=32, c=1: 2^32 nonces, two chunks of 2^23 buckets; one set of chunk
-    buffers serves both).  Seconds per whole plot, and per chunk.  At k <= 31
-    the same plot through vx_plot is timed too, for the cost of chunking."""
+    """One whole plot made as 2^c chunks (default k=32, c=1: 2^32 nonces,
+    two chunks of 2^23 buckets; one set of chunk buffers serves both), two
+    ways: every chunk hashing all nonces (vx_plot_chunk), and one stage hash
+    from which every chunk is made (vx_stage_plot + vx_plot_staged_chunk).
+    Seconds per whole plot (the staged way is `value`), and per chunk.  At
+    k <= 31 the same plot through vx_plot is timed too."""
     import torch
     import paper_2606_14007_amd as vx
     from vx_inputs import derive_key
 
     k, c = args.chunk_k, args.chunk_bits
     key = derive_key(0)
-    b = vx.alloc_chunk(k, c)
-    log(f"chunked: k={k} in {1 << c} chunks, {b.nbytes() / 2**30:.1f} GiB of chunk buffers")
     nchunks = 1 << c
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nchunks + 1)]
+    steps = max(1, args.steps)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nchunks + 2)]
 
-    def whole_plot(timed_chunks=None):
+    def run(make_chunk, b, stage_fn=None, timed=False):
         t1 = t2 = 0
+        if timed:
+            evs[0].record()
+        if stage_fn:
+            stage_fn()
+        if timed:
+            evs[1].record()
         for r in range(nchunks):
-            if timed_chunks is not None:
-                evs[r].record()
-            vx.plot_chunk(key, k, c, r, b)
+            make_chunk(r)
             t2n = vx.t2_count(b)  # synchronises; the buffers are reused by the next chunk
             if t2n > b.t2_capacity:
                 raise RuntimeError("Table 2 overflow")
             t1 += int(b.t1_count.item())
             t2 += t2n
-        if timed_chunks is not None:
-            evs[nchunks].record()
+            if timed:
+                evs[r + 2].record()
         return t1, t2
 
-    for _ in range(max(1, args.warmup)):
-        whole_plot()
-    if vx.device_status(b.workspace):
-        raise RuntimeError("device status")
-    steps = max(1, args.steps)
-    chunk_ms = [0.0] * nchunks
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        t1, t2 = whole_plot(timed_chunks=True)
+    def measure(label, make_chunk, b, stage_fn=None):
+        for _ in range(max(1, args.warmup)):
+            run(make_chunk, b, stage_fn)
+        if vx.device_status(b.workspace):
+            raise RuntimeError("device status")
+        part = [0.0] * (nchunks + 1)
         torch.cuda.synchronize()
-        for r in range(nchunks):
-            chunk_ms[r] += evs[r].elapsed_time(evs[r + 1]) / steps
-    sec = (time.perf_counter() - t0) / steps
-    if t1 != 1 << k:
-        raise RuntimeError(f"chunks hold {t1} records, not 2^{k}")
-    log(f"k={k}: {sec * 1e3:.1f} ms per plot in {nchunks} chunks "
-        f"({', '.join(f'{x:.1f}' for x in chunk_ms)} ms)")
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            t1, t2 = run(make_chunk, b, stage_fn, timed=True)
+            torch.cuda.synchronize()
+            for i in range(nchunks + 1):
+                part[i] += evs[i].elapsed_time(evs[i + 1]) / steps
+        sec = (time.perf_counter() - t0) / steps
+        if t1 != 1 << k:
+            raise RuntimeError(f"chunks hold {t1} records, not 2^{k}")
+        log(f"k={k} {label}: {sec * 1e3:.1f} ms per plot in {nchunks} chunks "
+            f"(stage {part[0]:.1f} ms; chunks {', '.join(f'{x:.1f}' for x in part[1:])} ms)")
+        return sec, part, t2
+
+    b = vx.alloc_chunk(k, c)
+    log(f"chunked: k={k} in {nchunks} chunks, {b.nbytes() / 2**30:.1f} GiB of chunk buffers")
+    rehash_s, rehash_part, t2 = measure("rehash", lambda r: vx.plot_chunk(key, k, c, r, b), b)
+    rehash_bytes = b.nbytes()
+    del b
+    torch.cuda.empty_cache()
+    st = vx.alloc_stage(k, c)
+    b = vx.alloc_staged_chunk(k, c)
+    staged_bytes = b.nbytes() + st.data.numel()
+    log(f"staged: {st.data.numel() / 2**30:.1f} GiB stage + {b.nbytes() / 2**30:.1f} GiB of chunk buffers")
+    staged_s, staged_part, t2s = measure("staged", lambda r: vx.plot_staged_chunk(key, st, r, b), b,
+                                         lambda: vx.stage_plot(key, k, c, st))
+    if t2s != t2:
+        raise RuntimeError("staged and rehashed chunks differ in |Table 2|")
     out = {
         "metric": f"K={k} plot seconds (chunked)",
-        "value": round(sec, 5),
+        "value": round(staged_s, 5),
         "unit": "s",
         "n_gpus": 1, "steps": steps, "warmup": max(1, args.warmup),
-        "ms_per_step": round(sec * 1e3, 3),
+        "ms_per_step": round(staged_s * 1e3, 3),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"k={k} single plot in {nchunks} chunks of {1 << (24 - c)} buckets",
                    "k": k, "chunk_bits": c, "key_seed": 0, "threshold": f"2^{64 - k}",
                    "parallelism": "single GPU"},
-        "chunk_ms": [round(x, 3) for x in chunk_ms],
-        "table1_records": t1, "table2_records": t2,
-        "chunk_buffer_bytes": b.nbytes(),
-        "blake3_hashes_per_s_useful": round(((1 << k) + t2) / sec, 1),
+        "staged_stage_ms": round(staged_part[0], 3),
+        "staged_chunk_ms": [round(x, 3) for x in staged_part[1:]],
+        "rehash_plot_s": round(rehash_s, 5),
+        "rehash_chunk_ms": [round(x, 3) for x in rehash_part[1:]],
+        "table1_records": 1 << k, "table2_records": t2,
+        "staged_device_bytes": staged_bytes, "rehash_device_bytes": rehash_bytes,
+        "blake3_hashes_per_s_useful": round(((1 << k) + t2) / staged_s, 1),
     }
     if k <= 31:
-        del b
+        del b, st
         torch.cuda.empty_cache()
         wb = vx.alloc_plot(k)
         vx.plot(key, k, buffers=wb)
@@ -382,7 +406,7 @@ def bench_chunked(args) -> dict:
         ws = (time.perf_counter() - t0) / steps
         log(f"k={k}: {ws * 1e3:.1f} ms as one vx_plot")
         out["whole_plot_ms"] = round(ws * 1e3, 3)
-        out["chunking_cost"] = round(sec / ws, 3)
+        out["staged_cost_vs_whole"] = round(staged_s / ws, 3)
     return out
 
 

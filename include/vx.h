@@ -237,6 +237,43 @@ vx_status vx_plot_chunk(const vx_plot_params *params, uint32_t chunk_bits, uint3
                         const vx_plot_buffers *buffers, uint64_t t1_capacity, uint64_t *d_t1_count,
                         const vx_tuning *tuning, void *stream);
 
+/* Staged chunks.  vx_stage_plot hashes every nonce of a plot once and files
+ * the records by their first partition digit into a caller-owned device
+ * buffer (the stage); vx_plot_staged_chunk then makes chunk r of the plot
+ * from the stage, exactly as vx_plot_chunk does (same outputs, same chunk
+ * definition), without hashing again.  The stage holds 12 bytes per record
+ * plus slack (51.6 GB at k=32), so making 2^chunk_bits chunks costs one hash
+ * of the plot instead of 2^chunk_bits.  The stage stays valid until it is
+ * overwritten; chunks may be made in any order and more than once.  A stage
+ * is made for one key, k, chunk_bits and tuning, and the chunk calls check
+ * this.  Overflow of a stage region (fewer than one plot in 10^13) sets
+ * VX_DEV_STATUS_REGION_OVERFLOW in the stage's status word (vx_read_status
+ * on the stage).  k may be 32; chunk_bits must not exceed the first digit's
+ * width (6 bits with three passes, the default from k=29 up). */
+
+/* Bytes of the stage for these parameters, or 0 if they do not allow a
+ * staged plot (fused sort + match, separate_hash, or digits out of range). */
+size_t vx_stage_bytes(const vx_plot_params *params, uint32_t chunk_bits, const vx_tuning *tuning);
+
+/* Enqueues the stage hash on `stream` (no synchronisation).  d_stage: at
+ * least vx_stage_bytes bytes, 256-byte aligned. */
+vx_status vx_stage_plot(const vx_plot_params *params, uint32_t chunk_bits, const vx_tuning *tuning, void *d_stage,
+                        size_t stage_bytes, void *stream);
+
+/* Workspace bytes of vx_plot_staged_chunk for up to t1_capacity records (use
+ * vx_chunk_capacity_hint), or 0. */
+size_t vx_staged_chunk_workspace_bytes(const vx_plot_params *params, uint32_t chunk_bits, uint64_t t1_capacity,
+                                       const vx_tuning *tuning);
+
+/* Chunk `chunk` of the staged plot: outputs as vx_plot_chunk (Table 1, the
+ * offsets relative to the chunk, Table 2 and its count, m in *d_t1_count).
+ * Synchronises `stream` once (the record count plans the sort, and the
+ * stage's identity is checked: VX_ERR_INVALID_ARG if it was made for other
+ * parameters).  VX_ERR_WORKSPACE if m exceeds t1_capacity. */
+vx_status vx_plot_staged_chunk(const vx_plot_params *params, uint32_t chunk_bits, uint32_t chunk,
+                               const void *d_stage, size_t stage_bytes, const vx_plot_buffers *buffers,
+                               uint64_t t1_capacity, uint64_t *d_t1_count, const vx_tuning *tuning, void *stream);
+
 /* Copies the device status word at the start of a workspace used by
  * vx_bucket_sort or vx_plot to *h_status (synchronising `stream`). */
 vx_status vx_read_status(const void *d_workspace, uint32_t *h_status, void *stream);

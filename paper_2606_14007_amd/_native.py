@@ -86,6 +86,14 @@ SYMBOLS = [
                                               C.POINTER(VxTuning)]),
     ("vx_plot_chunk", C.c_int, [C.POINTER(VxPlotParams), C.c_uint32, C.c_uint32, C.POINTER(VxPlotBuffers),
                                 C.c_uint64, C.c_void_p, C.POINTER(VxTuning), C.c_void_p]),
+    ("vx_stage_bytes", C.c_size_t, [C.POINTER(VxPlotParams), C.c_uint32, C.POINTER(VxTuning)]),
+    ("vx_stage_plot", C.c_int, [C.POINTER(VxPlotParams), C.c_uint32, C.POINTER(VxTuning), C.c_void_p, C.c_size_t,
+                                C.c_void_p]),
+    ("vx_staged_chunk_workspace_bytes", C.c_size_t, [C.POINTER(VxPlotParams), C.c_uint32, C.c_uint64,
+                                                     C.POINTER(VxTuning)]),
+    ("vx_plot_staged_chunk", C.c_int, [C.POINTER(VxPlotParams), C.c_uint32, C.c_uint32, C.c_void_p, C.c_size_t,
+                                       C.POINTER(VxPlotBuffers), C.c_uint64, C.c_void_p, C.POINTER(VxTuning),
+                                       C.c_void_p]),
     ("vx_egress_create", C.c_int, [C.c_int, C.c_size_t, C.c_uint32, C.POINTER(C.c_void_p)]),
     ("vx_egress_submit", C.c_int, [C.c_void_p, C.POINTER(VxPlotParams), C.c_void_p, C.c_uint64, C.c_void_p,
                                    C.c_void_p, C.POINTER(C.c_uint64)]),
@@ -232,6 +240,28 @@ def vx_plot_chunk(params: VxPlotParams, chunk_bits: int, chunk: int, buffers: Vx
                   d_t1_count: int, tuning: Optional[VxTuning] = None, stream: int = 0) -> None:
     _check(lib().vx_plot_chunk(C.byref(params), chunk_bits, chunk, C.byref(buffers), t1_capacity, d_t1_count,
                                _tref(tuning), stream), "vx_plot_chunk")
+
+
+def vx_stage_bytes(params: VxPlotParams, chunk_bits: int, tuning: Optional[VxTuning] = None) -> int:
+    return int(lib().vx_stage_bytes(C.byref(params), chunk_bits, _tref(tuning)))
+
+
+def vx_stage_plot(params: VxPlotParams, chunk_bits: int, d_stage: int, stage_bytes: int,
+                  tuning: Optional[VxTuning] = None, stream: int = 0) -> None:
+    _check(lib().vx_stage_plot(C.byref(params), chunk_bits, _tref(tuning), d_stage, stage_bytes, stream),
+           "vx_stage_plot")
+
+
+def vx_staged_chunk_workspace_bytes(params: VxPlotParams, chunk_bits: int, t1_capacity: int,
+                                    tuning: Optional[VxTuning] = None) -> int:
+    return int(lib().vx_staged_chunk_workspace_bytes(C.byref(params), chunk_bits, t1_capacity, _tref(tuning)))
+
+
+def vx_plot_staged_chunk(params: VxPlotParams, chunk_bits: int, chunk: int, d_stage: int, stage_bytes: int,
+                         buffers: VxPlotBuffers, t1_capacity: int, d_t1_count: int,
+                         tuning: Optional[VxTuning] = None, stream: int = 0) -> None:
+    _check(lib().vx_plot_staged_chunk(C.byref(params), chunk_bits, chunk, d_stage, stage_bytes, C.byref(buffers),
+                                      t1_capacity, d_t1_count, _tref(tuning), stream), "vx_plot_staged_chunk")
 
 
 def vx_egress_create(fd: int, slot_bytes: int, slots: int) -> int:

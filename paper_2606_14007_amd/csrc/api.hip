@@ -64,6 +64,7 @@ struct Plan {
     uint32_t slices = 1;     // plot: pipeline slices of the passes after the first (1 = none)
     bool hs = false;         // plot: region passes (the hash does the first; see make_plan)
     uint32_t R[kMaxPasses] = {};  // hs: records per region of each pass
+    int staged = -1;         // >= 0: one chunk (of 2^staged) of a staged plot; see vx_stage_plot
 };
 
 uint32_t clampu(int64_t v, int64_t lo, int64_t hi) {
@@ -80,8 +81,10 @@ vx_status check_params(const vx_plot_params *p, uint32_t max_k = 31) {
 
 // records: the table's size when it is not 2^k (a chunk of a chunked plot,
 // at most 2^32 - 1); 0 = 2^k.  Groups, digits and the threshold follow k.
+// staged >= 0: the plan of a staged plot (records = 0) or of one of its
+// 2^staged chunks (records = the chunk's), with region passes throughout.
 vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint64_t records = 0,
-                    uint32_t max_k = 31) {
+                    uint32_t max_k = 31, int staged = -1) {
     vx_status st = check_params(p, max_k);
     if (st != VX_OK) return st;
     Plan P;
@@ -97,6 +100,9 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     // Sort groups of about 2048 records (half the LDS capacity).
     P.G = t->group_bits ? t->group_bits : clampu((int64_t)p->k - 11, 1, 21);
     if (P.G < 1 || P.G > 24) return fail(VX_ERR_UNSUPPORTED, "group_bits must be in [1, 24]");
+    // A staged plot needs two passes (the stage holds the first), so small
+    // staged plots take smaller groups.
+    if (staged >= 0 && !t->group_bits && P.G < 10) P.G = 10;
     // Split G into passes of at most 9 bits so that every digit's run per
     // sub-tile spans whole cache lines.  The first pass scatters over the
     // whole table, where short runs cost the most, so it takes no more than
@@ -113,7 +119,13 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     P.fused = t->fused_sort_match != 0;
     P.slices = t->pipeline_slices ? t->pipeline_slices : kDefaultSlices;
     if (P.fused) P.slices = 1;
-    const bool hs_ok = !records && !t->separate_hash && !P.fused;
+    P.staged = staged;
+    if (staged >= 0) {
+        if (P.fused || t->separate_hash)
+            return fail(VX_ERR_UNSUPPORTED, "staged plots use the fused hash and the split sort and match");
+        P.slices = 1;
+    }
+    const bool hs_ok = (!records || staged >= 0) && !t->separate_hash && !P.fused;
     uint32_t d0, d1, d2;
     if (P.G <= 9) {
         d0 = P.G; d1 = 0; d2 = 0;
@@ -152,8 +164,11 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     P.W = t->h1_tiles ? t->h1_tiles : clampu((int64_t)(P.n >> 14), 1, 2048);
     if (P.W < 1 || P.W > 65536) return fail(VX_ERR_UNSUPPORTED, "h1_tiles must be in [1, 65536]");
     P.chunk1 = (P.n + P.W - 1) / P.W;
+    // Segments of pass i hold 2^(k - pre) records on average (also in a
+    // chunk, whose other segments are empty).
+    const uint64_t dens = 1ull << P.k;
     for (uint32_t i = 1; i < P.npass; ++i)  // about 2^16 records per tile
-        P.Q[i] = clampu((int64_t)((P.n >> P.pre[i]) >> 16), 1, 256);
+        P.Q[i] = clampu((int64_t)((dens >> P.pre[i]) >> 16), 1, 256);
     P.cap = t->group_cap ? t->group_cap : (uint32_t)vxk::kGroupCapMax;
     if (P.cap < 64 || P.cap > (uint32_t)vxk::kGroupCapMax)
         return fail(VX_ERR_UNSUPPORTED, "group_cap must be in [64, 3072]");
@@ -179,13 +194,20 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
            !(P.slices > 1 && P.npass > 2);
     for (uint32_t i = 1; i < P.npass; ++i)
         if (P.D[i] > (uint32_t)vxk::kClaimMaxBits) P.hs = false;
+    // A chunk of a staged plot addresses only its own 2^-staged share of
+    // each pass's regions.
+    const uint32_t cbits = staged > 0 ? (uint32_t)staged : 0;
     for (uint32_t i = 0; P.hs && i < P.npass; ++i) {
         const uint32_t bits = P.pre[i] + P.D[i];
-        const double mean = (double)((P.n + (1ull << bits) - 1) >> bits);
+        const double mean = (double)((dens + (1ull << bits) - 1) >> bits);
         const uint32_t slack = i == 0 ? vxk::kHashScatterSub : 64u;
         P.R[i] = (uint32_t)(mean + 8.0 * std::sqrt(mean)) + slack;
-        if (((uint64_t)P.R[i] << bits) >= (1ull << 32)) P.hs = false;
+        if (bits < cbits || ((uint64_t)P.R[i] << (bits - cbits)) >= (1ull << 32)) P.hs = false;
     }
+    if (staged >= 0 && !P.hs)
+        return fail(VX_ERR_UNSUPPORTED,
+                    "staged plots need two or more partition passes, a first digit of at most 8 bits and at "
+                    "least chunk_bits, later digits of at most 9 bits, and chunks of fewer than 2^32 records");
     *pl = P;
     return VX_OK;
 }
@@ -222,7 +244,8 @@ constexpr uint32_t kHdrEmitTicket = 8 + 2 * kMaxSlices;   // per slice: chunk ti
 static_assert(kHdrEmitTicket + kMaxSlices <= kHeaderWords, "header holds every slice's words");
 constexpr uint32_t kLookbackSpinLimit = 1u << 20;
 
-constexpr int kCallChunk = 4;  // internal: the workspace of vx_plot_chunk
+constexpr int kCallChunk = 4;        // internal: the workspace of vx_plot_chunk
+constexpr int kCallStagedChunk = 5;  // internal: the workspace of vx_plot_staged_chunk
 constexpr uint32_t kMaxChunkBits = 8;
 
 uint32_t match_chunks(const Plan &P) { return (uint32_t)((P.n + (1ull << P.cb) - 1) >> P.cb); }
@@ -241,17 +264,20 @@ Layout layout(const Plan &P, int which) {
     };
     L.header = take(kHeaderWords * 4);
     const bool chunk = which == kCallChunk;
-    if (chunk) which = VX_CALL_PLOT;
+    const bool staged = which == kCallStagedChunk;
+    if (chunk || staged) which = VX_CALL_PLOT;
     const bool sort = which == VX_CALL_BUCKET_SORT || which == VX_CALL_PLOT;
     const bool match = which == VX_CALL_MATCH || which == VX_CALL_PLOT;
     // A region-pass plot (P.hs) files the even passes (the first in the
     // hash kernel) into keys_no + reg_nonces and the odd ones into the
     // scratch arrays, each as fixed-size regions with slack; Table 1 is
-    // written only by the group sort.
+    // written only by the group sort.  A staged chunk's first pass is in the
+    // stage, and its later passes hold only the chunk's share of regions.
     const bool hs = which == VX_CALL_PLOT && !chunk && P.hs;
-    uint64_t cap_even = P.n, cap_odd = P.n;
-    for (uint32_t i = 0; hs && i < P.npass; ++i) {
-        const uint64_t c = (uint64_t)P.R[i] << (P.pre[i] + P.D[i]);
+    const uint32_t cbits = staged ? (uint32_t)P.staged : 0;
+    uint64_t cap_even = staged ? 0 : P.n, cap_odd = staged ? 0 : P.n;
+    for (uint32_t i = staged ? 1 : 0; hs && i < P.npass; ++i) {
+        const uint64_t c = (uint64_t)P.R[i] << (P.pre[i] + P.D[i] - cbits);
         uint64_t &m = (i % 2 == 0) ? cap_even : cap_odd;
         m = std::max(m, c);
     }
@@ -286,6 +312,47 @@ Layout layout(const Plan &P, int which) {
     }
     L.total = at;
     return L;
+}
+
+// A stage (vx_stage_plot): header words, the first pass's region fills and
+// its regions (SoA).
+constexpr uint32_t kStageMagic = 0x56585354u;  // "VXST"
+constexpr uint32_t kStageIdWords = 16;  // header words [1, 16): what the stage was made for
+struct StageLayout {
+    // u32[64]: [0] status; [1] magic, [2] k, [3] D0, [4] R0, [5] chunk_bits,
+    // [6, 14) key words, [14, 16) zero
+    size_t header = 0;
+    size_t fill = 0;    // u32[2^D0]
+    size_t keys = 0;    // u64[2^D0 * R0]
+    size_t nonces = 0;  // u32[2^D0 * R0]
+    size_t total = 0;
+};
+
+void stage_id(const Plan &P, uint32_t chunk_bits, uint32_t id[kStageIdWords]) {
+    memset(id, 0, kStageIdWords * 4);
+    id[1] = kStageMagic;
+    id[2] = P.k;
+    id[3] = P.D[0];
+    id[4] = P.R[0];
+    id[5] = chunk_bits;
+    for (int i = 0; i < 8; ++i) id[6 + i] = P.key_words[i];
+}
+
+StageLayout stage_layout(const Plan &P) {
+    StageLayout S;
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = at;
+        at = align_up(at + bytes, 256);
+        return o;
+    };
+    const uint64_t recs = (uint64_t)P.R[0] << P.D[0];
+    S.header = take(kHeaderWords * 4);
+    S.fill = take((size_t)4 << P.D[0]);
+    S.keys = take(recs * 8);
+    S.nonces = take(recs * 4);
+    S.total = at;
+    return S;
 }
 
 // Records ev[i] on s when an event array is given (stage timing).
@@ -345,8 +412,11 @@ PassBufs pass_bufs(const Plan &P, const Layout &L, void *ws, const uint64_t *key
 // scan (one row per segment, on top of the segments' bases) into the group
 // starts.  Otherwise segments lie back to back at the previous pass's group
 // starts: per-tile histograms, their scan inside each segment, the scatter.
+//
+// origin: the segment whose regions start the output buffer (a staged chunk
+// holds only its own share of regions; 0 otherwise).
 vx_status run_pass(const Plan &P, const Layout &L, void *ws, const PassBufs &B, uint32_t i, uint32_t sa,
-                   uint32_t sb, hipStream_t s) {
+                   uint32_t sb, hipStream_t s, uint32_t origin = 0) {
     const uint32_t nd = 1u << P.D[i];
     const uint32_t shift = 64 - P.pre[i] - P.D[i];
     const uint32_t q = P.Q[i];
@@ -358,11 +428,12 @@ vx_status run_pass(const Plan &P, const Layout &L, void *ws, const PassBufs &B, 
         const uint32_t *seg = at<uint32_t>(ws, L.seg_lo[i - 1]) + sa;
         const uint32_t *seg_end = at<uint32_t>(ws, L.seg_hi[i - 1]) + sa;
         uint32_t *fill = at<uint32_t>(ws, L.fill[i]) + (size_t)sa * nd;
-        const uint64_t first = (uint64_t)sa * nd * P.R[i];
+        const uint64_t first = (uint64_t)(sa - origin) * nd * P.R[i];
         VX_HIP(vxk::launch_scatter_claim(B.in_k, B.in_n, B.out_k + first, B.out_n + first, seg, seg_end, nseg, q,
                                          shift, P.D[i], fill, P.R[i], at<uint32_t>(ws, L.header) + kHdrStatus, s),
                "pass scatter");
-        VX_HIP(vxk::launch_region_bounds(fill, sa * nd, nseg * nd, P.R[i], at<uint32_t>(ws, L.seg_lo[i]) + sa * nd,
+        VX_HIP(vxk::launch_region_bounds(fill, (sa - origin) * nd, nseg * nd, P.R[i],
+                                         at<uint32_t>(ws, L.seg_lo[i]) + sa * nd,
                                          at<uint32_t>(ws, L.seg_hi[i]) + sa * nd, s),
                "pass regions");
         VX_HIP(vxk::launch_colscan(fill, off, nseg, 1, nd, base, gst, nseg * nd, (uint32_t)P.n, s), "pass scan");
@@ -739,6 +810,134 @@ vx_status vx_plot_chunk(const vx_plot_params *params, uint32_t chunk_bits, uint3
     if (st == VX_OK)
         st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, nullptr, nullptr, 1,
                        0, 0, s);
+    if (st == VX_OK) g_err[0] = 0;
+    return st;
+}
+
+size_t vx_stage_bytes(const vx_plot_params *params, uint32_t chunk_bits, const vx_tuning *tuning) {
+    Plan P;
+    if (chunk_bits > kMaxChunkBits) return 0;
+    if (make_plan(params, tuning, &P, 0, 32, (int)chunk_bits) != VX_OK) return 0;
+    return stage_layout(P).total;
+}
+
+vx_status vx_stage_plot(const vx_plot_params *params, uint32_t chunk_bits, const vx_tuning *tuning, void *d_stage,
+                        size_t stage_bytes, void *stream) {
+    if (chunk_bits > kMaxChunkBits) return fail(VX_ERR_INVALID_ARG, "chunk_bits must be at most 8");
+    Plan P;
+    vx_status st = make_plan(params, tuning, &P, 0, 32, (int)chunk_bits);
+    if (st != VX_OK) return st;
+    if (!d_stage) return fail(VX_ERR_INVALID_ARG, "stage is NULL");
+    if (!aligned(d_stage, 256)) return fail(VX_ERR_INVALID_ARG, "misaligned stage");
+    const StageLayout S = stage_layout(P);
+    if (stage_bytes < S.total) return fail(VX_ERR_WORKSPACE, "stage smaller than vx_stage_bytes");
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *hdr = at<uint32_t>(d_stage, S.header);
+    uint32_t id[kStageIdWords];
+    stage_id(P, chunk_bits, id);
+    VX_HIP(vxk::launch_reset(hdr, kHeaderWords, s), "reset");
+    VX_HIP(vxk::launch_put_words(hdr + 1, id + 1, kStageIdWords - 1, s), "stage header");
+    VX_HIP(vxk::launch_fill_u32(at<uint32_t>(d_stage, S.fill), 1ull << P.D[0], 0u, s), "reset");
+    VX_HIP(vxk::launch_hash_scatter(P.key_words, P.n, P.D[0], P.R[0], at<uint64_t>(d_stage, S.keys),
+                                    at<uint32_t>(d_stage, S.nonces), at<uint32_t>(d_stage, S.fill), hdr + kHdrStatus,
+                                    s),
+           "stage hash");
+    g_err[0] = 0;
+    return VX_OK;
+}
+
+size_t vx_staged_chunk_workspace_bytes(const vx_plot_params *params, uint32_t chunk_bits, uint64_t t1_capacity,
+                                       const vx_tuning *tuning) {
+    Plan P;
+    if (chunk_bits > kMaxChunkBits || t1_capacity == 0 || t1_capacity >= (1ull << 32)) return 0;
+    if (make_plan(params, tuning, &P, t1_capacity, 32, (int)chunk_bits) != VX_OK) return 0;
+    return layout(P, kCallStagedChunk).total;
+}
+
+vx_status vx_plot_staged_chunk(const vx_plot_params *params, uint32_t chunk_bits, uint32_t chunk,
+                               const void *d_stage, size_t stage_bytes, const vx_plot_buffers *b,
+                               uint64_t t1_capacity, uint64_t *d_t1_count, const vx_tuning *tuning, void *stream) {
+    if (chunk_bits > kMaxChunkBits || chunk >= (1u << chunk_bits))
+        return fail(VX_ERR_INVALID_ARG, "chunk_bits must be at most 8 and chunk below 2^chunk_bits");
+    if (t1_capacity == 0 || t1_capacity >= (1ull << 32))
+        return fail(VX_ERR_INVALID_ARG, "t1_capacity must be in [1, 2^32)");
+    Plan Pc;
+    vx_status st = make_plan(params, tuning, &Pc, t1_capacity, 32, (int)chunk_bits);
+    if (st != VX_OK) return st;
+    if (!d_stage || !b || !d_t1_count) return fail(VX_ERR_INVALID_ARG, "stage, buffers or d_t1_count is NULL");
+    if (!b->t1_keys || !b->t1_nonces || !b->bucket_offsets || !b->t2_count || (b->t2_capacity && !b->t2))
+        return fail(VX_ERR_INVALID_ARG, "NULL buffer");
+    if (!aligned(d_stage, 256) || !aligned(b->t1_keys, 8) || !aligned(b->t1_nonces, 4) ||
+        !aligned(b->bucket_offsets, 4) || !aligned(b->t2_count, 8) || !aligned(d_t1_count, 8) ||
+        (b->t2 && !aligned(b->t2, 16)))
+        return fail(VX_ERR_INVALID_ARG, "misaligned buffer");
+    const Layout L = layout(Pc, kCallStagedChunk);
+    if ((st = check_ws(L, b->workspace, b->workspace_bytes)) != VX_OK) return st;
+    const StageLayout S = stage_layout(Pc);
+    if (stage_bytes < S.total) return fail(VX_ERR_INVALID_ARG, "stage smaller than these parameters need");
+    hipStream_t s = (hipStream_t)stream;
+    void *ws = b->workspace;
+    uint32_t *hdr = at<uint32_t>(ws, L.header);
+    // The chunk's first-pass regions in the stage, and where it starts.
+    const uint32_t ndc = 1u << (Pc.D[0] - chunk_bits);
+    const uint32_t d_first = chunk * ndc;
+    const uint64_t *stage_k = at<const uint64_t>(const_cast<void *>(d_stage), S.keys) + (uint64_t)d_first * Pc.R[0];
+    const uint32_t *stage_n = at<const uint32_t>(const_cast<void *>(d_stage), S.nonces) + (uint64_t)d_first * Pc.R[0];
+    const uint32_t *stage_fill = at<const uint32_t>(const_cast<void *>(d_stage), S.fill) + d_first;
+    VX_HIP(vxk::launch_reset(hdr, kHeaderWords, s), "reset");
+    for (uint32_t i = 1; i < Pc.npass; ++i)
+        VX_HIP(vxk::launch_fill_u32(at<uint32_t>(ws, L.fill[i]), 1ull << (Pc.pre[i] + Pc.D[i]), 0u, s), "reset");
+    uint32_t *gst0 = at<uint32_t>(ws, L.gstart[0]);
+    VX_HIP(vxk::launch_region_scan(stage_fill, ndc, Pc.R[0], at<uint32_t>(ws, L.seg_lo[0]) + d_first,
+                                   at<uint32_t>(ws, L.seg_hi[0]) + d_first, gst0 + d_first, s),
+           "chunk regions");
+    // The sort is planned for the chunk's records: wait for their number,
+    // and check that the stage was made for these parameters.
+    uint32_t m32 = 0, id[kStageIdWords], want[kStageIdWords];
+    VX_HIP(hipMemcpyAsync(&m32, gst0 + d_first + ndc, sizeof(m32), hipMemcpyDeviceToHost, s), "chunk count");
+    VX_HIP(hipMemcpyAsync(id, at<const uint32_t>(const_cast<void *>(d_stage), S.header), sizeof(id),
+                          hipMemcpyDeviceToHost, s),
+           "stage header");
+    VX_HIP(hipStreamSynchronize(s), "chunk count");
+    stage_id(Pc, chunk_bits, want);
+    if (memcmp(id + 1, want + 1, (kStageIdWords - 1) * 4) != 0)
+        return fail(VX_ERR_INVALID_ARG, "the stage was made for another key, k, chunk_bits or tuning");
+    const uint64_t m = m32;
+    VX_HIP(hipMemcpyAsync(d_t1_count, &m, sizeof(m), hipMemcpyHostToDevice, s), "chunk count");
+    VX_HIP(hipStreamSynchronize(s), "chunk count");
+    if (m > t1_capacity) return fail(VX_ERR_WORKSPACE, "the chunk holds more records than t1_capacity");
+    if (m == 0) {
+        VX_HIP(vxk::launch_fill_u32(b->bucket_offsets, (uint64_t)VX_NUM_BUCKETS + 1, 0u, s), "empty chunk");
+        VX_HIP(vxk::launch_zero_u64(b->t2_count, 1, s), "empty chunk");
+        g_err[0] = 0;
+        return VX_OK;
+    }
+    Plan P;
+    if ((st = make_plan(params, tuning, &P, m, 32, (int)chunk_bits)) != VX_OK) return st;
+    // Same digits and regions as the capacity plan, so L fits.  Pass 1 reads
+    // the stage; later passes alternate between the workspace's buffers.
+    for (uint32_t i = 1; i < P.npass; ++i) {
+        PassBufs B = pass_bufs(P, L, ws, nullptr, b->t1_keys, b->t1_nonces, i);
+        if (i == 1) {
+            B.in_k = stage_k;
+            B.in_n = stage_n;
+        }
+        const uint32_t sh = P.pre[i] - P.D[0];
+        if ((st = run_pass(P, L, ws, B, i, d_first << sh, (d_first + ndc) << sh, s, d_first << sh)) != VX_OK)
+            return st;
+    }
+    const uint32_t gsh = P.G - P.D[0];
+    st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, at<uint8_t>(ws, L.pcnt),
+                        d_first << gsh, ndc << gsh, 0, s);
+    if (st != VX_OK) return st;
+    // Buckets before the chunk start at 0, those after it (and the end) at m.
+    const uint64_t b0 = (uint64_t)chunk << (VX_BUCKET_BITS - chunk_bits);
+    const uint64_t b1 = (uint64_t)(chunk + 1) << (VX_BUCKET_BITS - chunk_bits);
+    if (b0) VX_HIP(vxk::launch_fill_u32(b->bucket_offsets, b0, 0u, s), "chunk offsets");
+    VX_HIP(vxk::launch_fill_u32(b->bucket_offsets + b1, (uint64_t)VX_NUM_BUCKETS + 1 - b1, (uint32_t)m, s),
+           "chunk offsets");
+    st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, nullptr, nullptr, 1, 0,
+                   0, s);
     if (st == VX_OK) g_err[0] = 0;
     return st;
 }

@@ -33,6 +33,8 @@ hipError_t launch_hash_filter(const uint32_t key_words[8], uint64_t n, uint32_t 
                               uint32_t pbits, uint32_t prefix, uint64_t *keys, uint32_t *nonces, uint64_t cap,
                               unsigned long long *count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+// Stores n <= 16 words (passed by value) at p.
+hipError_t launch_put_words(uint32_t *p, const uint32_t *values, uint32_t n, hipStream_t s);
 // Plot hash fused with the first partition pass (2^bits digits, bits <=
 // kHashScatterMaxBits): record of digit d goes to region d = [d * R,
 // (d + 1) * R) of keys / nonces; fill[d] (zero at launch) counts them.

@@ -1545,6 +1545,22 @@ hipError_t launch_region_scan(const uint32_t *fill, uint32_t nd, uint32_t R, uin
     return hipGetLastError();
 }
 
+struct Words16 {
+    uint32_t w[16];
+};
+
+__global__ void k_put_words(uint32_t *__restrict__ p, Words16 v, uint32_t n) {
+    if (threadIdx.x < n) p[threadIdx.x] = v.w[threadIdx.x];
+}
+
+hipError_t launch_put_words(uint32_t *p, const uint32_t *values, uint32_t n, hipStream_t s) {
+    if (n > 16) return hipErrorInvalidValue;
+    Words16 v = {};
+    for (uint32_t i = 0; i < n; ++i) v.w[i] = values[i];
+    hipLaunchKernelGGL(k_put_words, dim3(1), dim3(64), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
 __global__ void k_fill_u32(uint32_t *__restrict__ p, uint64_t n, uint32_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = v;

@@ -123,7 +123,8 @@ class ChunkBuffers(PlotBuffers):
 
 
 def alloc_chunk(k: int, chunk_bits: int, threshold: int | None = None, t1_capacity: int | None = None,
-                t2_capacity: int | None = None, tuning: N.VxTuning | None = None, device=None) -> ChunkBuffers:
+                t2_capacity: int | None = None, tuning: N.VxTuning | None = None, device=None,
+                workspace: bool = True) -> ChunkBuffers:
     """Buffers for the chunks of a plot cut into 2^chunk_bits bucket ranges
     (one set serves every chunk in turn)."""
     dev = _dev(device)
@@ -133,8 +134,8 @@ def alloc_chunk(k: int, chunk_bits: int, threshold: int | None = None, t1_capaci
         raise ValueError("invalid k / chunk_bits (a chunk must hold fewer than 2^32 records)")
     cap1 = cap1 if t1_capacity is None else int(t1_capacity)
     cap2 = cap2 if t2_capacity is None else int(t2_capacity)
-    ws = N.vx_chunk_workspace_bytes(p, chunk_bits, cap1, tuning)
-    if ws == 0:
+    ws = N.vx_chunk_workspace_bytes(p, chunk_bits, cap1, tuning) if workspace else 0
+    if workspace and ws == 0:
         raise ValueError("invalid chunk parameters or tuning")
     return ChunkBuffers(
         k=k,
@@ -159,6 +160,58 @@ def plot_chunk(key: bytes, k: int, chunk_bits: int, chunk: int, buffers: ChunkBu
     p = N.make_params(key, k, threshold)
     N.vx_plot_chunk(p, chunk_bits, chunk, buffers.native(), buffers.t1_capacity, buffers.t1_count.data_ptr(),
                     tuning, _stream(stream))
+    return buffers
+
+
+@dataclass
+class Stage:
+    """A staged plot (vx_stage_plot): every record hashed once and filed by
+    its first digit, from which the chunks are made."""
+    k: int
+    chunk_bits: int
+    data: torch.Tensor  # uint8[vx_stage_bytes]
+
+
+def alloc_stage(k: int, chunk_bits: int, tuning: N.VxTuning | None = None, device=None) -> Stage:
+    n = N.vx_stage_bytes(N.make_params(bytes(32), k), chunk_bits, tuning)
+    if n == 0:
+        raise ValueError("these parameters do not allow a staged plot")
+    return Stage(k, chunk_bits, torch.empty(n, dtype=torch.uint8, device=_dev(device)))
+
+
+def stage_plot(key: bytes, k: int, chunk_bits: int, stage: Stage | None = None, tuning: N.VxTuning | None = None,
+               stream=None) -> Stage:
+    """Enqueue the one hash of a staged plot into `stage`."""
+    if stage is None:
+        stage = alloc_stage(k, chunk_bits, tuning)
+    if stage.k != k or stage.chunk_bits != chunk_bits:
+        raise ValueError("stage was allocated for another k or chunk_bits")
+    N.vx_stage_plot(N.make_params(key, k), chunk_bits, stage.data.data_ptr(), stage.data.numel(), tuning,
+                    _stream(stream))
+    return stage
+
+
+def alloc_staged_chunk(k: int, chunk_bits: int, threshold: int | None = None, t1_capacity: int | None = None,
+                       t2_capacity: int | None = None, tuning: N.VxTuning | None = None,
+                       device=None) -> ChunkBuffers:
+    """Buffers for the chunks of a staged plot (one set serves every chunk)."""
+    b = alloc_chunk(k, chunk_bits, threshold, t1_capacity, t2_capacity, device=device, workspace=False)
+    p = N.make_params(bytes(32), k, threshold)
+    ws = N.vx_staged_chunk_workspace_bytes(p, chunk_bits, b.t1_capacity, tuning)
+    if ws == 0:
+        raise ValueError("invalid staged chunk parameters or tuning")
+    b.workspace = torch.empty(ws, dtype=torch.uint8, device=b.t1_keys.device)
+    return b
+
+
+def plot_staged_chunk(key: bytes, stage: Stage, chunk: int, buffers: ChunkBuffers, threshold: int | None = None,
+                      tuning: N.VxTuning | None = None, stream=None) -> ChunkBuffers:
+    """Chunk `chunk` of the staged plot (vx_plot_staged_chunk)."""
+    if buffers.k != stage.k or buffers.chunk_bits != stage.chunk_bits:
+        raise ValueError("buffers were allocated for another k or chunk_bits")
+    p = N.make_params(key, stage.k, threshold)
+    N.vx_plot_staged_chunk(p, stage.chunk_bits, chunk, stage.data.data_ptr(), stage.data.numel(), buffers.native(),
+                           buffers.t1_capacity, buffers.t1_count.data_ptr(), tuning, _stream(stream))
     return buffers
 
 

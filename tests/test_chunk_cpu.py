@@ -92,3 +92,59 @@ def test_plot_chunk_argument_checks(case, status):
         vx.vx_plot_chunk(p, c, r, b, cap, cnt, tun)
     assert e.value.status == status
     assert vx.vx_last_error()
+
+
+def test_stage_sizes_and_limits():
+    p32 = vx.make_params(bytes(32), 32)
+    st = vx.vx_stage_bytes(p32, 1)
+    # 12 bytes per record of the plot, plus slack and the header
+    assert 12 << 32 < st < (12 << 32) * 1.01
+    assert vx.vx_stage_bytes(p32, 2) == st          # the stage does not depend on the chunk count
+    assert vx.vx_stage_bytes(p32, 7) == 0           # wider than the first digit (6 bits)
+    assert vx.vx_stage_bytes(p32, 0) == 0           # one chunk of 2^32 records
+    assert vx.vx_stage_bytes(p32, 1, vx.make_tuning(fused_sort_match=1)) == 0
+    assert vx.vx_stage_bytes(p32, 1, vx.make_tuning(separate_hash=1)) == 0
+    p12 = vx.make_params(bytes(32), 12)
+    assert vx.vx_stage_bytes(p12, 1) > 0            # small plots take smaller groups
+    cap = vx.vx_chunk_capacity_hint(32, 1, 1 << 32)[0]
+    assert vx.vx_staged_chunk_workspace_bytes(p32, 1, cap) > 0
+    assert vx.vx_staged_chunk_workspace_bytes(p32, 1, 0) == 0
+
+
+@pytest.mark.parametrize("case,status", [
+    ("chunk_too_big", N.VX_ERR_INVALID_ARG),
+    ("null_stage", N.VX_ERR_INVALID_ARG),
+    ("small_stage", N.VX_ERR_INVALID_ARG),
+    ("fused", N.VX_ERR_UNSUPPORTED),
+    ("workspace", N.VX_ERR_WORKSPACE),
+])
+def test_plot_staged_chunk_argument_checks(case, status):
+    p = vx.make_params(bytes(32), 20)
+    c, r, cap = 2, 1, 1 << 18
+    need = vx.vx_staged_chunk_workspace_bytes(p, c, cap)
+    b = _buffers()
+    b.workspace_bytes = need
+    stage, stage_bytes, tun = 8 << 20, vx.vx_stage_bytes(p, c), None
+    if case == "chunk_too_big":
+        r = 4
+    elif case == "null_stage":
+        stage = 0
+    elif case == "small_stage":
+        stage_bytes -= 1
+    elif case == "fused":
+        tun = vx.make_tuning(fused_sort_match=1)
+    elif case == "workspace":
+        b.workspace_bytes = need - 1
+    with pytest.raises(vx.VxError) as e:
+        vx.vx_plot_staged_chunk(p, c, r, stage, stage_bytes, b, cap, 7 << 20, tun)
+    assert e.value.status == status
+
+
+def test_stage_plot_argument_checks():
+    p = vx.make_params(bytes(32), 20)
+    with pytest.raises(vx.VxError) as e:
+        vx.vx_stage_plot(p, 2, 8 << 20, vx.vx_stage_bytes(p, 2) - 1)
+    assert e.value.status == N.VX_ERR_WORKSPACE
+    with pytest.raises(vx.VxError) as e:
+        vx.vx_stage_plot(p, 9, 8 << 20, 1 << 30)
+    assert e.value.status == N.VX_ERR_INVALID_ARG

@@ -1,4 +1,5 @@
-"""GPU parity of chunked plots (vx_plot_chunk) against the oracle, bit-exact.
+"""GPU parity of chunked plots (vx_plot_chunk, and vx_stage_plot +
+vx_plot_staged_chunk) against the oracle, bit-exact.
 
 Chunk r of a plot cut by c bits is the plot restricted to the buckets whose
 top c bits equal r: Table 1 is the oracle's slice between those buckets'
@@ -59,7 +60,7 @@ def _check_chunk(vx, b, ref, c, r):
     return m, cnt
 
 
-@pytest.mark.parametrize("k,c,T", [
+CASES = [
     (20, 2, None),
     (18, 1, None),
     (16, 3, 1 << 44),
@@ -69,7 +70,10 @@ def _check_chunk(vx, b, ref, c, r):
     (9, 4, 1 << 50),
     (3, 3, None),
     (1, 1, None),
-])
+]
+
+
+@pytest.mark.parametrize("k,c,T", CASES)
 def test_chunks_match_the_oracle(vx, k, c, T):
     ref = oracle.plot(KEY0, k, threshold=T, threads=8)
     b = vx.alloc_chunk(k, c, threshold=T)
@@ -82,6 +86,60 @@ def test_chunks_match_the_oracle(vx, k, c, T):
         total2 += cnt
     assert total1 == 1 << k
     assert total2 == len(ref.t2)
+
+
+@pytest.mark.parametrize("k,c,T", CASES)
+def test_staged_chunks_match_the_oracle(vx, k, c, T):
+    # Chunks in reverse order: the stage is read, never consumed.
+    ref = oracle.plot(KEY0, k, threshold=T, threads=8)
+    st = vx.stage_plot(KEY0, k, c)
+    b = vx.alloc_staged_chunk(k, c, threshold=T)
+    total1 = total2 = 0
+    for r in reversed(range(1 << c)):
+        print(f"staged k={k} c={c} chunk={r}", flush=True)
+        vx.plot_staged_chunk(KEY0, st, r, b, threshold=T)
+        m, cnt = _check_chunk(vx, b, ref, c, r)
+        total1 += m
+        total2 += cnt
+    assert vx.device_status(st.data) == 0
+    assert total1 == 1 << k
+    assert total2 == len(ref.t2)
+
+
+@pytest.mark.parametrize("tun", [
+    dict(group_cap=64),
+    dict(group_bits=14, pass1_bits=4, pass2_bits=5),  # three passes
+    dict(group_bits=16, match_chunk_bits=6),
+    dict(pipeline_slices=4),                          # ignored by staged plots
+])
+def test_staged_chunk_tunings(vx, tun):
+    k, c = 17, 2
+    ref = oracle.plot(KEY0, k, threads=8)
+    t = vx.make_tuning(**tun)
+    st = vx.stage_plot(KEY0, k, c, tuning=t)
+    b = vx.alloc_staged_chunk(k, c, tuning=t)
+    for r in range(1 << c):
+        vx.plot_staged_chunk(KEY0, st, r, b, tuning=t)
+        _check_chunk(vx, b, ref, c, r)
+    # the same chunk again, after the others
+    vx.plot_staged_chunk(KEY0, st, 1, b, tuning=t)
+    _check_chunk(vx, b, ref, c, 1)
+
+
+def test_staged_chunk_checks_the_stage(vx):
+    k, c = 14, 1
+    st = vx.stage_plot(derive_key(5), k, c)
+    b = vx.alloc_staged_chunk(k, c)
+    with pytest.raises(vx.VxError) as e:
+        vx.plot_staged_chunk(KEY0, st, 0, b)   # stage made for another key
+    assert e.value.status == N.VX_ERR_INVALID_ARG
+    with pytest.raises(vx.VxError) as e:
+        vx.plot_staged_chunk(derive_key(5), st, 0, b, tuning=vx.make_tuning(group_bits=11))
+    assert e.value.status in (N.VX_ERR_INVALID_ARG, N.VX_ERR_WORKSPACE)
+    # and works for the right key afterwards
+    ref = oracle.plot(derive_key(5), k)
+    vx.plot_staged_chunk(derive_key(5), st, 1, b)
+    _check_chunk(vx, b, ref, c, 1)
 
 
 def test_chunks_concatenate_to_the_whole_plot(vx):

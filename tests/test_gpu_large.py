@@ -170,9 +170,12 @@ def test_k31_sampled_and_whole_table_properties(vx):
 
 
 @pytest.mark.timeout(1200)
-def test_k32_in_two_chunks_sampled_and_properties(vx):
+@pytest.mark.parametrize("mode", ["rehash", "staged"])
+def test_k32_in_two_chunks_sampled_and_properties(vx, mode):
     """k = 32 (2^32 nonces) as two chunks of 2^23 buckets each, one set of
-    buffers (about 112 GB).  Per chunk: every key carries the chunk's prefix,
+    buffers (about 112 GB), each chunk hashing every nonce (vx_plot_chunk)
+    or both made from one stage (vx_stage_plot + vx_plot_staged_chunk, about
+    170 GB).  Per chunk: every key carries the chunk's prefix,
     Table 1 is sorted by (key64, nonce), the offsets are the bucket
     histogram's prefix sums (0 before the range, m after it), |Table 2|
     equals an independent count and every record is valid and canonical;
@@ -184,8 +187,12 @@ def test_k32_in_two_chunks_sampled_and_properties(vx):
     print("k=32: oracle sampled buckets", flush=True)
     buckets = sampled_buckets(1024)
     s = oracle.sample_buckets(KEY0, k, buckets, threads=THREADS)
-    print("k=32: allocating chunk buffers", flush=True)
-    b = vx.alloc_chunk(k, c)
+    print(f"k=32 ({mode}): allocating chunk buffers", flush=True)
+    if mode == "staged":
+        stage = vx.stage_plot(KEY0, k, c)
+        b = vx.alloc_staged_chunk(k, c)
+    else:
+        b = vx.alloc_chunk(k, c)
     seen = torch.zeros(1 << k, dtype=torch.bool, device=dev)
     rank = torch.empty(1 << k, dtype=torch.int64, device=dev)  # nonce -> position in its chunk
     step = 1 << 28
@@ -193,7 +200,10 @@ def test_k32_in_two_chunks_sampled_and_properties(vx):
     t1_pos = t2_pos = 0
     for r in range(1 << c):
         print(f"k=32: chunk {r}: GPU", flush=True)
-        vx.plot_chunk(KEY0, k, c, r, b)
+        if mode == "staged":
+            vx.plot_staged_chunk(KEY0, stage, r, b)
+        else:
+            vx.plot_chunk(KEY0, k, c, r, b)
         torch.cuda.synchronize()
         assert vx.device_status(b.workspace) == 0
         m = int(b.t1_count.item())
@@ -289,4 +299,6 @@ def test_k32_in_two_chunks_sampled_and_properties(vx):
         del ra_all
     assert total_m == 1 << k
     assert bool(seen.all())
+    if mode == "staged":
+        assert vx.device_status(stage.data) == 0
     assert t1_pos == len(s.t1_keys) and t2_pos == len(s.t2) and t2_pos > 0
