@@ -143,8 +143,11 @@ def test_k31_sampled_and_whole_table_properties(vx):
         assert int(r["hash2"]) == oracle.h2(KEY0, int(r["nonce_a"]), int(r["nonce_b"]))
 
     print(f"k=31: oracle sampled buckets with {THREADS} threads", flush=True)
-    buckets = sampled_buckets(1024)
-    s = oracle.sample_buckets(KEY0, k, buckets, threads=THREADS)
+    # 4096 SplitMix64-drawn buckets, the first and last, and the fullest one.
+    largest = int(torch.argmax(counts))
+    s = oracle.sample_buckets(KEY0, k, sampled_buckets(4096) + [largest], threads=THREADS)
+    buckets = [int(x) for x in s.buckets]
+    assert largest in buckets and len(buckets) >= 4096
     offh = vx.u32(b.bucket_offsets).astype(np.int64)
     bidx = torch.tensor(buckets, device=keys.device)
     lo_t = off[bidx]
@@ -185,8 +188,7 @@ def test_k32_in_two_chunks_sampled_and_properties(vx, mode):
     T = vx.vx_default_threshold(k)
     dev = torch.device("cuda")
     print("k=32: oracle sampled buckets", flush=True)
-    buckets = sampled_buckets(1024)
-    s = oracle.sample_buckets(KEY0, k, buckets, threads=THREADS)
+    s = oracle.sample_buckets(KEY0, k, sampled_buckets(4096), threads=THREADS)
     print(f"k=32 ({mode}): allocating chunk buffers", flush=True)
     if mode == "staged":
         stage = vx.stage_plot(KEY0, k, c)
