@@ -367,9 +367,11 @@ T *at(void *ws, size_t off) {
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-// Where partition pass i writes: the passes alternate between Table 1 and
-// the scratch arrays so that the last one lands in Table 1, where groups are
-// then sorted in place.
+// Where partition pass i reads and writes.  Contiguous passes alternate
+// between Table 1 and the scratch arrays so that the last one lands in
+// Table 1, where groups are then sorted in place; region passes (P.hs)
+// alternate between keys_no + reg_nonces and the scratch arrays, and the
+// group sort gathers into Table 1.
 struct PassBufs {
     const uint64_t *in_k;
     const uint32_t *in_n;  // NULL: nonce = index (the nonce-order keys)

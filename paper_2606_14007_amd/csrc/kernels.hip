@@ -4,23 +4,25 @@
 // 2^24 buckets by hash prefix, sort inside buckets, then match neighbours
 // below the threshold and hash each pair into Table 2.
 //
-// How the work maps onto CDNA4 (the paper's atomic slot claim into fixed-size
-// buckets and its one-thread insertion sort are replaced):
+// How the work maps onto CDNA4 (the paper's per-record atomic slot claim
+// into fixed-size buckets and its one-thread insertion sort are replaced):
 //  * hash: one nonce per lane, BLAKE3 held in VGPRs, key in SGPRs; in a plot
-//    the same kernel also does the first partition pass, filing each
-//    sub-tile's keys into per-digit regions claimed with global atomics
-//    (the ALU-bound hash hides that pass's memory traffic);
-//  * bucketing: up to three MSD partition passes over the leading key bits
-//    (histogram per tile -> column scan -> LDS-ranked scatter that writes
-//    each digit's run contiguously), so that every "group" of keys sharing
-//    the leading G bits is contiguous and small enough for LDS;
+//    the same kernel also does the first partition pass (the ALU-bound hash
+//    hides that pass's memory traffic);
+//  * bucketing: up to three MSD partition passes over the leading key bits,
+//    each ranking a sub-tile's records by digit in LDS and writing every
+//    digit's run contiguously, so that every "group" of keys sharing the
+//    leading G bits ends up together and small enough for LDS.  A plot's
+//    passes claim room for each run in fixed-size regions with one global
+//    atomic per (sub-tile, digit); caller keys and chunks use a histogram
+//    per tile and a column scan instead;
 //  * sort: one work-group per group: LDS counting sort on the next 12 bits,
-//    then an exact rank inside each (tiny) sub-bin; bucket offsets come from
-//    a binary search of the sorted group;
-//  * match + Table-2 hash: one work-group per group of buckets, per-record
-//    pair counts, a work-group scan and a device scan give every pair its
-//    canonical slot; pairs are expanded into an LDS list and hashed one pair
-//    per lane.
+//    then an exact rank inside each (tiny) sub-bin, written to the group's
+//    place in Table 1; bucket offsets come from a binary search of the
+//    sorted group, and each record's pair count is stored as one byte;
+//  * match + Table-2 hash: fixed chunks of Table 1, a work-group scan of the
+//    count bytes and a device scan give every pair its canonical slot;
+//    pairs are expanded into an LDS list and hashed one pair per lane.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -520,8 +522,9 @@ __global__ void k_region_bounds(uint32_t *__restrict__ fill, uint32_t r0, uint32
 }
 
 // ---------------------------------------------------------------------------
-// Group sort in LDS (in place on Table 1), bucket offsets of the group, and
-// (optionally) the group's Table-2 pair count.
+// Group sort in LDS (into Table 1: in place, or gathered from the last
+// pass's regions), bucket offsets of the group, and (optionally) each
+// record's Table-2 pair count.
 // ---------------------------------------------------------------------------
 
 constexpr int kSubBinBits = 12;
