@@ -34,10 +34,18 @@ def log(*a):
 
 
 def source_digest() -> str:
+    """SHA-256 prefix of the kernel sources' code: comments, blank lines and
+    trailing spaces are left out, so that editing a comment keeps the
+    counters that were taken on the same code."""
+    import re
     h = hashlib.sha256()
     for f in ("kernels.hip", "blake3_device.h", "block_scan.h", "kernels.h"):
-        with open(os.path.join(ROOT, "paper_2606_14007_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2606_14007_amd", "csrc", f), encoding="utf-8") as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.splitlines():
+            line = re.sub(r"//.*", "", line).rstrip()
+            if line:
+                h.update(line.encode() + b"\n")
     return h.hexdigest()[:16]
 
 
