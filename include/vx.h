@@ -298,7 +298,12 @@ const char *vx_last_error(void);
  *   bytes  32..39   |Table 2| as counted on the device
  *   bytes  40..47   records that follow: min(|Table 2|, t2_capacity)
  *   bytes  48..79   the 32-byte plot key
- *   bytes  80..127  zero
+ *   bytes  80..83   chunk_bits              84..87  chunk
+ *                   (0, 0 for a whole plot; for chunk r of a chunked plot
+ *                   the records are the plot's Table 2 restricted to the
+ *                   chunk's buckets, and the chunks' files in chunk order
+ *                   concatenate to the plot's Table 2)
+ *   bytes  88..127  zero
  *   then the records in canonical order, 16 bytes each (vx_t2_record).
  * The egress is not for HIP graph capture. */
 typedef struct vx_egress vx_egress;
@@ -319,6 +324,13 @@ vx_status vx_egress_create(int fd, size_t slot_bytes, uint32_t slots, vx_egress 
 vx_status vx_egress_submit(vx_egress *e, const vx_plot_params *params, const vx_t2_record *d_t2,
                            uint64_t t2_capacity, const uint64_t *d_t2_count, void *stream,
                            uint64_t *job);
+
+/* As vx_egress_submit, for the Table 2 of chunk `chunk` of a plot cut by
+ * chunk_bits (vx_plot_chunk, vx_plot_staged_chunk): the file header records
+ * chunk_bits and chunk.  chunk_bits <= 8 and chunk < 2^chunk_bits. */
+vx_status vx_egress_submit_chunk(vx_egress *e, const vx_plot_params *params, uint32_t chunk_bits, uint32_t chunk,
+                                 const vx_t2_record *d_t2, uint64_t t2_capacity, const uint64_t *d_t2_count,
+                                 void *stream, uint64_t *job);
 
 /* Blocks until jobs 1..job are written (job = 0: all submitted so far).
  * Returns the first error that any job hit (VX_ERR_IO, VX_ERR_DEVICE). */

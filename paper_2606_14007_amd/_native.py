@@ -97,6 +97,8 @@ SYMBOLS = [
     ("vx_egress_create", C.c_int, [C.c_int, C.c_size_t, C.c_uint32, C.POINTER(C.c_void_p)]),
     ("vx_egress_submit", C.c_int, [C.c_void_p, C.POINTER(VxPlotParams), C.c_void_p, C.c_uint64, C.c_void_p,
                                    C.c_void_p, C.POINTER(C.c_uint64)]),
+    ("vx_egress_submit_chunk", C.c_int, [C.c_void_p, C.POINTER(VxPlotParams), C.c_uint32, C.c_uint32, C.c_void_p,
+                                         C.c_uint64, C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64)]),
     ("vx_egress_wait", C.c_int, [C.c_void_p, C.c_uint64]),
     ("vx_egress_bytes", C.c_uint64, [C.c_void_p]),
     ("vx_egress_destroy", C.c_int, [C.c_void_p]),
@@ -276,6 +278,14 @@ def vx_egress_submit(handle: int, params: VxPlotParams, d_t2: int, t2_capacity: 
     job = C.c_uint64(0)
     _check(lib().vx_egress_submit(handle, C.byref(params), d_t2, t2_capacity, d_t2_count, stream,
                                   C.byref(job)), "vx_egress_submit")
+    return int(job.value)
+
+
+def vx_egress_submit_chunk(handle: int, params: VxPlotParams, chunk_bits: int, chunk: int, d_t2: int,
+                           t2_capacity: int, d_t2_count: int, stream: int = 0) -> int:
+    job = C.c_uint64(0)
+    _check(lib().vx_egress_submit_chunk(handle, C.byref(params), chunk_bits, chunk, d_t2, t2_capacity, d_t2_count,
+                                        stream, C.byref(job)), "vx_egress_submit_chunk")
     return int(job.value)
 
 

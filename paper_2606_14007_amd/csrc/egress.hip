@@ -37,6 +37,7 @@ struct Job {
     uint32_t k = 0;
     uint64_t T = 0;
     uint8_t key[32] = {};
+    uint32_t chunk_bits = 0, chunk = 0;
 };
 
 void put32(uint8_t *p, uint32_t v) {
@@ -114,6 +115,8 @@ struct vx_egress {
         put64(hdr + 32, cnt);
         put64(hdr + 40, nrec);
         memcpy(hdr + 48, j.key, 32);
+        put32(hdr + 80, j.chunk_bits);
+        put32(hdr + 84, j.chunk);
         vx_status st = write_all(hdr, sizeof(hdr), msg, msglen);
         if (st != VX_OK) return st;
         const uint64_t total = nrec * kRecordBytes;
@@ -230,8 +233,16 @@ vx_status vx_egress_create(int fd, size_t slot_bytes, uint32_t slots, vx_egress 
 vx_status vx_egress_submit(vx_egress *e, const vx_plot_params *params, const vx_t2_record *d_t2,
                            uint64_t t2_capacity, const uint64_t *d_t2_count, void *stream,
                            uint64_t *job) {
+    return vx_egress_submit_chunk(e, params, 0, 0, d_t2, t2_capacity, d_t2_count, stream, job);
+}
+
+vx_status vx_egress_submit_chunk(vx_egress *e, const vx_plot_params *params, uint32_t chunk_bits, uint32_t chunk,
+                                 const vx_t2_record *d_t2, uint64_t t2_capacity, const uint64_t *d_t2_count,
+                                 void *stream, uint64_t *job) {
     if (!e || !params || !d_t2_count || (t2_capacity && !d_t2))
         return fail(VX_ERR_INVALID_ARG, "NULL egress, params or buffer");
+    if (chunk_bits > 8 || chunk >= (1u << chunk_bits))
+        return fail(VX_ERR_INVALID_ARG, "chunk_bits must be at most 8 and chunk below 2^chunk_bits");
     if (params->k < 1 || params->k > 32) return fail(VX_ERR_INVALID_ARG, "k must be in [1, 32]");
     if (((uintptr_t)d_t2 % 16) || ((uintptr_t)d_t2_count % 8)) return fail(VX_ERR_INVALID_ARG, "misaligned buffer");
     Job j;
@@ -241,6 +252,8 @@ vx_status vx_egress_submit(vx_egress *e, const vx_plot_params *params, const vx_
     j.k = params->k;
     j.T = params->match_threshold;
     memcpy(j.key, params->key, 32);
+    j.chunk_bits = chunk_bits;
+    j.chunk = chunk;
     hipError_t h = hipEventCreateWithFlags(&j.ready, hipEventDisableTiming);
     if (h == hipSuccess) h = hipEventRecord(j.ready, (hipStream_t)stream);
     if (h != hipSuccess) {

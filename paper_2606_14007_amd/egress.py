@@ -5,7 +5,9 @@ A plot file is a 128-byte little-endian header followed by the Table-2
 records in canonical order (16 bytes each: nonce_a u32, nonce_b u32,
 hash2 u64).  Header fields: magic "VXPLOT01", header bytes (128), record
 bytes (16), k, bucket bits (24), threshold T, |Table 2| as counted on the
-device, records that follow (min(|Table 2|, capacity)), the 32-byte key.
+device, records that follow (min(|Table 2|, capacity)), the 32-byte key,
+chunk_bits and chunk (0 and 0 for a whole plot; a chunk's file holds the
+plot's Table 2 restricted to the chunk's buckets).
 """
 from __future__ import annotations
 
@@ -21,7 +23,7 @@ from . import _native as N
 HEADER_BYTES = 128
 RECORD_BYTES = 16
 MAGIC = b"VXPLOT01"
-_HEADER = struct.Struct("<8sIIIIQQQ32s48x")
+_HEADER = struct.Struct("<8sIIIIQQQ32sII40x")
 assert _HEADER.size == HEADER_BYTES
 T2_RECORD = np.dtype([("nonce_a", "<u4"), ("nonce_b", "<u4"), ("hash2", "<u8")])  # vx_t2_record
 
@@ -34,20 +36,22 @@ class PlotFileHeader:
     t2_count: int
     records: int
     key: bytes
+    chunk_bits: int = 0
+    chunk: int = 0
 
 
 def pack_header(h: PlotFileHeader) -> bytes:
     return _HEADER.pack(MAGIC, HEADER_BYTES, RECORD_BYTES, h.k, h.bucket_bits, h.threshold,
-                        h.t2_count, h.records, h.key)
+                        h.t2_count, h.records, h.key, h.chunk_bits, h.chunk)
 
 
 def parse_header(raw: bytes) -> PlotFileHeader:
     if len(raw) < HEADER_BYTES:
         raise ValueError("truncated plot file header")
-    magic, hb, rb, k, bb, T, cnt, nrec, key = _HEADER.unpack(raw[:HEADER_BYTES])
+    magic, hb, rb, k, bb, T, cnt, nrec, key, cbits, chunk = _HEADER.unpack(raw[:HEADER_BYTES])
     if magic != MAGIC or hb != HEADER_BYTES or rb != RECORD_BYTES:
         raise ValueError("not a plot file (magic or sizes differ)")
-    return PlotFileHeader(k, bb, T, cnt, nrec, key)
+    return PlotFileHeader(k, bb, T, cnt, nrec, key, cbits, chunk)
 
 
 def read_plot_files(path: str):
@@ -74,13 +78,15 @@ class Egress:
     def __init__(self, fd: int = -1, slot_bytes: int = 64 << 20, slots: int = 4):
         self.handle = N.vx_egress_create(fd, slot_bytes, slots)
 
-    def submit(self, key: bytes, k: int, buffers, threshold: Optional[int] = None, stream=None) -> int:
-        """Queue the plot file of `buffers` (a PlotBuffers whose plot is
-        enqueued on `stream`); returns the job number."""
+    def submit(self, key: bytes, k: int, buffers, threshold: Optional[int] = None, stream=None,
+               chunk_bits: int = 0, chunk: int = 0) -> int:
+        """Queue the plot file of `buffers` (a PlotBuffers whose plot, or a
+        ChunkBuffers whose chunk `chunk` of 2^chunk_bits, is enqueued on
+        `stream`); returns the job number."""
         from .plotter import _stream
         p = N.make_params(key, k, threshold)
-        return N.vx_egress_submit(self.handle, p, buffers.t2.data_ptr(), buffers.t2.shape[0],
-                                  buffers.t2_count.data_ptr(), _stream(stream))
+        return N.vx_egress_submit_chunk(self.handle, p, chunk_bits, chunk, buffers.t2.data_ptr(),
+                                        buffers.t2.shape[0], buffers.t2_count.data_ptr(), _stream(stream))
 
     def wait(self, job: int = 0) -> None:
         N.vx_egress_wait(self.handle, job)

@@ -9,7 +9,7 @@ import paper_2606_14007_amd as vx
 from paper_2606_14007_amd import egress as E
 
 
-def _hand_header(k, T, cnt, nrec, key):
+def _hand_header(k, T, cnt, nrec, key, chunk_bits=0, chunk=0):
     # The layout include/vx.h documents, written out field by field.
     h = bytearray(128)
     h[0:8] = b"VXPLOT01"
@@ -21,6 +21,8 @@ def _hand_header(k, T, cnt, nrec, key):
     h[32:40] = cnt.to_bytes(8, "little")
     h[40:48] = nrec.to_bytes(8, "little")
     h[48:80] = key
+    h[80:84] = chunk_bits.to_bytes(4, "little")
+    h[84:88] = chunk.to_bytes(4, "little")
     return bytes(h)
 
 
@@ -29,6 +31,10 @@ def test_header_layout_matches_the_documented_offsets():
     h = E.PlotFileHeader(k=27, bucket_bits=24, threshold=1 << 37, t2_count=125_000_123, records=99, key=key)
     assert E.pack_header(h) == _hand_header(27, 1 << 37, 125_000_123, 99, key)
     assert E.parse_header(_hand_header(27, 1 << 37, 125_000_123, 99, key)) == h
+    hc = E.PlotFileHeader(k=32, bucket_bits=24, threshold=1 << 32, t2_count=7, records=7, key=key,
+                          chunk_bits=2, chunk=3)
+    assert E.pack_header(hc) == _hand_header(32, 1 << 32, 7, 7, key, 2, 3)
+    assert E.parse_header(E.pack_header(hc)) == hc
 
 
 def test_read_back_concatenated_plot_files(tmp_path):

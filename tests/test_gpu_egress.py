@@ -100,3 +100,32 @@ def test_discarding_egress_counts_the_bytes(vx):
         eg.wait(j1)
         eg.wait(j2)
         assert eg.bytes == 2 * (128 + 16 * n)
+
+
+def test_chunk_files_concatenate_to_the_plot(vx, tmp_path):
+    """The chunks of a staged plot egressed one by one (two buffer sets, each
+    reused once its file is out): every file is marked with its chunk, and
+    the records concatenate to the oracle's Table 2."""
+    from paper_2606_14007_amd import egress as E
+    key, k, c = derive_key(9), 18, 2
+    ref = oracle.plot(key, k, threads=8)
+    st = vx.stage_plot(key, k, c)
+    sets = [vx.alloc_staged_chunk(k, c) for _ in range(2)]
+    path = str(tmp_path / "chunks.bin")
+    fd = E.open_for_append(path)
+    try:
+        with E.Egress(fd, slot_bytes=1 << 20, slots=2) as eg:
+            jobs = []
+            for r in range(1 << c):
+                if r >= 2:
+                    eg.wait(jobs[r - 2])
+                b = sets[r % 2]
+                vx.plot_staged_chunk(key, st, r, b)
+                jobs.append(eg.submit(key, k, b, chunk_bits=c, chunk=r))
+            eg.wait()
+    finally:
+        os.close(fd)
+    got = E.read_plot_files(path)
+    assert [(h.chunk_bits, h.chunk, h.k) for h, _ in got] == [(c, r, k) for r in range(1 << c)]
+    assert sum(h.t2_count for h, _ in got) == len(ref.t2)
+    assert np.array_equal(np.concatenate([rec for _, rec in got]), ref.t2)
