@@ -806,9 +806,24 @@ vx_status vx_plot_chunk(const vx_plot_params *params, uint32_t chunk_bits, uint3
     // Same groups and digits as the capacity plan, so L fits (it was sized
     // for t1_capacity >= m records).
     st = run_partition(P, L, ws, keys_in, false, b->t1_keys, b->t1_nonces, P.npass, s, nullptr, nonces_in);
-    if (st == VX_OK)
-        st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, at<uint8_t>(ws, L.pcnt), 0,
-                            1u << P.G, 0, s);
+    {
+        // Only the chunk's groups hold records (when the groups are at least
+        // as fine as the chunks): sort those, and give the buckets before
+        // the chunk offset 0 and those after it m.
+        const bool own = chunk_bits <= P.G;
+        const uint32_t g0 = own ? chunk << (P.G - chunk_bits) : 0;
+        const uint32_t gn = own ? 1u << (P.G - chunk_bits) : 1u << P.G;
+        if (st == VX_OK)
+            st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, at<uint8_t>(ws, L.pcnt), g0,
+                                gn, 0, s);
+        if (st == VX_OK && own) {
+            const uint64_t b0 = (uint64_t)chunk << (VX_BUCKET_BITS - chunk_bits);
+            const uint64_t b1 = (uint64_t)(chunk + 1) << (VX_BUCKET_BITS - chunk_bits);
+            if (b0) VX_HIP(vxk::launch_fill_u32(b->bucket_offsets, b0, 0u, s), "chunk offsets");
+            VX_HIP(vxk::launch_fill_u32(b->bucket_offsets + b1, (uint64_t)VX_NUM_BUCKETS + 1 - b1, (uint32_t)m, s),
+                   "chunk offsets");
+        }
+    }
     if (st == VX_OK)
         st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, nullptr, nullptr, 1,
                        0, 0, s);
