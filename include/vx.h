@@ -57,7 +57,7 @@ typedef enum {
 /* Device status word bits (vx_read_status). */
 #define VX_DEV_STATUS_GROUP_TOO_LARGE 0x1u /* a sort group exceeded the fallback limit */
 #define VX_DEV_STATUS_LOOKBACK_TIMEOUT 0x2u /* vx_plot: a Table-2 base wait hit its bound */
-#define VX_DEV_STATUS_REGION_OVERFLOW 0x4u /* vx_plot: a first-pass region of the fused hash
+#define VX_DEV_STATUS_REGION_OVERFLOW 0x4u /* vx_plot, staged plots: a partition region
                                               overflowed (about 8 standard deviations above its
                                               expected fill; Table 1 is then incomplete) */
 
@@ -109,7 +109,8 @@ typedef struct {
     uint32_t group_bits;   /* sort groups = 2^group_bits key prefixes, 1..24 */
     uint32_t pass1_bits;   /* digit bits of the first partition pass, 1..11 */
     uint32_t group_cap;    /* records a group may hold in LDS, 64..3072 */
-    uint32_t h1_tiles;     /* work-groups of the hash + first partition pass */
+    uint32_t h1_tiles;     /* work-groups of a separate hash and first partition pass (a plot whose
+                              hash does the first pass sizes that kernel's grid itself) */
     uint32_t match_chunk_bits; /* match works on chunks of 2^bits Table-1 records, 6..11 */
     uint32_t pass2_bits;   /* digit bits of the second pass (a third takes the rest) */
     uint32_t fused_sort_match; /* plot: nonzero runs sort, match and Table-2 hash as one kernel */
