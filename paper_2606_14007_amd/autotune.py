@@ -1,7 +1,8 @@
 """Autotuner for the plot's implementation parameters (vx_tuning).
 
 For a given k it times a small set of candidate tunings -- sort-group size,
-match-chunk size, hash tiles -- on the current GPU and keeps the fastest.
+match-chunk size, hash fused with the first pass or not -- on the current
+GPU and keeps the fastest.
 No candidate changes any output (they only move work between kernels), so
 picking by time is safe.  Results are cached in JSON keyed by GPU
 architecture and k (tuning_cache.json next to this file, or the path in
@@ -39,8 +40,10 @@ def candidates(k: int) -> List[Dict[str, int]]:
         if not 1 <= gb <= 20:
             continue
         for cb in (10, 11):
-            for tiles in (0, max(1, min(65536, (1 << k) >> 13))):
-                out.append({"group_bits": gb, "match_chunk_bits": cb, "h1_tiles": tiles})
+            # the hash with the first partition pass fused in (default), or
+            # the two as separate kernels
+            for sep in (0, 1):
+                out.append({"group_bits": gb, "match_chunk_bits": cb, "separate_hash": sep})
     return out
 
 
