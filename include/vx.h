@@ -101,8 +101,8 @@ typedef struct {
     size_t workspace_bytes;
 } vx_plot_buffers;
 
-/* Implementation parameters.  None of them changes any output; they only
- * move work between kernels.  Zero in any field selects the built-in
+/* Implementation parameters.  None of them changes any output (except
+ * region_pct below 100, a test hook); they only move work between kernels.  Zero in any field selects the built-in
  * default for the plot's k.  The group_bits leading key bits are split over
  * at most three partition passes of at most 11 bits each. */
 typedef struct {
@@ -121,6 +121,10 @@ typedef struct {
     uint32_t separate_hash;    /* plot: nonzero keeps the hash and the first partition pass as two
                                   kernels (by default a plot with two or more passes hashes and
                                   files records by their first digit in one kernel) */
+    uint32_t region_pct;       /* plot, staged plots: capacity of the partition regions in percent of
+                                  the default (0 = 100).  The one exception to "no output
+                                  changes": below 100 regions can overflow, which sets
+                                  VX_DEV_STATUS_REGION_OVERFLOW (for tests of that report) */
 } vx_tuning;
 
 enum { VX_CALL_BUCKET_SORT = 1, VX_CALL_MATCH = 2, VX_CALL_PLOT = 3 };

@@ -51,7 +51,7 @@ class VxTuning(C.Structure):
     _fields_ = [("group_bits", C.c_uint32), ("pass1_bits", C.c_uint32), ("group_cap", C.c_uint32),
                 ("h1_tiles", C.c_uint32), ("match_chunk_bits", C.c_uint32), ("pass2_bits", C.c_uint32),
                 ("fused_sort_match", C.c_uint32), ("pipeline_slices", C.c_uint32),
-                ("separate_hash", C.c_uint32)]
+                ("separate_hash", C.c_uint32), ("region_pct", C.c_uint32)]
 
 
 class VxError(RuntimeError):
@@ -141,12 +141,14 @@ def make_params(key: bytes, k: int, threshold: int | None = None) -> VxPlotParam
 
 
 def make_tuning(group_bits=0, pass1_bits=0, group_cap=0, h1_tiles=0, match_chunk_bits=0,
-                pass2_bits=0, fused_sort_match=0, pipeline_slices=0, separate_hash=0) -> VxTuning:
+                pass2_bits=0, fused_sort_match=0, pipeline_slices=0, separate_hash=0,
+                region_pct=0) -> VxTuning:
     t = VxTuning()
     t.group_bits, t.pass1_bits, t.group_cap = group_bits, pass1_bits, group_cap
     t.h1_tiles, t.match_chunk_bits, t.pass2_bits = h1_tiles, match_chunk_bits, pass2_bits
     t.fused_sort_match, t.pipeline_slices = fused_sort_match, pipeline_slices
     t.separate_hash = separate_hash
+    t.region_pct = region_pct
     return t
 
 

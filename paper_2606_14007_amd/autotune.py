@@ -24,7 +24,7 @@ CACHE_PATH = os.environ.get("VX_TUNING_CACHE",
                             os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                          "tuning_cache.json"))
 FIELDS = ("group_bits", "pass1_bits", "group_cap", "h1_tiles", "match_chunk_bits", "pass2_bits",
-          "fused_sort_match", "pipeline_slices", "separate_hash")
+          "fused_sort_match", "pipeline_slices", "separate_hash", "region_pct")
 
 
 def arch() -> str:

@@ -116,6 +116,7 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     // passes at 6 bits, whose scatter fits on a CU next to two match
     // work-groups: 8-6-6 at k=31.
     if (t->pipeline_slices > kMaxSlices) return fail(VX_ERR_UNSUPPORTED, "pipeline_slices must be at most 16");
+    if (t->region_pct > 1000) return fail(VX_ERR_UNSUPPORTED, "region_pct must be at most 1000");
     P.fused = t->fused_sort_match != 0;
     P.slices = t->pipeline_slices ? t->pipeline_slices : kDefaultSlices;
     if (P.fused) P.slices = 1;
@@ -202,6 +203,7 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
         const double mean = (double)((dens + (1ull << bits) - 1) >> bits);
         const uint32_t slack = i == 0 ? vxk::kHashScatterSub : 64u;
         P.R[i] = (uint32_t)(mean + 8.0 * std::sqrt(mean)) + slack;
+        if (t->region_pct) P.R[i] = std::max<uint32_t>(1, (uint32_t)((uint64_t)P.R[i] * t->region_pct / 100));
         if (bits < cbits || ((uint64_t)P.R[i] << (bits - cbits)) >= (1ull << 32)) P.hs = false;
     }
     if (staged >= 0 && !P.hs)

@@ -103,3 +103,11 @@ def test_pipeline_slices_validation_and_split():
     # a pipelined 13-bit group plan takes three passes (1-6-6), an unpipelined one two
     assert vx.vx_partition_passes(p, vx.make_tuning(group_bits=13, pipeline_slices=2)) == 3
     assert vx.vx_partition_passes(p, vx.make_tuning(group_bits=13, pipeline_slices=1)) == 2
+
+
+def test_region_pct_limits():
+    p = vx.make_params(bytes(32), 20)
+    base = vx.vx_workspace_bytes(p, vx.VX_CALL_PLOT, vx.make_tuning(group_bits=12))
+    small = vx.vx_workspace_bytes(p, vx.VX_CALL_PLOT, vx.make_tuning(group_bits=12, region_pct=25))
+    assert 0 < small < base
+    assert vx.vx_workspace_bytes(p, vx.VX_CALL_PLOT, vx.make_tuning(region_pct=1001)) == 0

@@ -204,3 +204,21 @@ def test_invalid_arguments_raise(vx):
     b = vx.alloc_plot(10)
     with pytest.raises(vx.VxError):
         vx.plot(KEY0, 10, buffers=b, tuning=vx.make_tuning(group_cap=8))
+
+
+def test_region_overflow_is_reported(vx):
+    """Regions shrunk to a quarter of their capacity (a test hook) must
+    overflow, report it in the device status and still finish; the same plan
+    at full capacity is exact.  T = 0, so that the records the overflow left
+    out of Table 1 cannot make the match walk far."""
+    from paper_2606_14007_amd import _native as N
+    k = 16
+    small = vx.make_tuning(group_bits=12, region_pct=25)
+    b = vx.plot(KEY0, k, threshold=0, tuning=small)
+    torch.cuda.synchronize()
+    assert vx.device_status(b.workspace) & N.VX_DEV_STATUS_REGION_OVERFLOW
+    st = vx.stage_plot(KEY0, k, 1, tuning=small)
+    torch.cuda.synchronize()
+    assert vx.device_status(st.data) & N.VX_DEV_STATUS_REGION_OVERFLOW
+    b = vx.plot(KEY0, k, threshold=0, tuning=vx.make_tuning(group_bits=12))
+    _assert_plot_equal(vx, b, oracle.plot(KEY0, k, threshold=0))
