@@ -634,6 +634,50 @@ vx_status check_ws(const Layout &L, const void *ws, size_t bytes) {
     return VX_OK;
 }
 
+// Argument checks shared by the chunk calls (vx_plot_chunk,
+// vx_plot_staged_chunk).
+vx_status check_chunk_args(uint32_t chunk_bits, uint32_t chunk, uint64_t t1_capacity, const vx_plot_buffers *b,
+                           const uint64_t *d_t1_count) {
+    if (chunk_bits > kMaxChunkBits || chunk >= (1u << chunk_bits))
+        return fail(VX_ERR_INVALID_ARG, "chunk_bits must be at most 8 and chunk below 2^chunk_bits");
+    if (t1_capacity == 0 || t1_capacity >= (1ull << 32))
+        return fail(VX_ERR_INVALID_ARG, "t1_capacity must be in [1, 2^32)");
+    if (!b || !d_t1_count) return fail(VX_ERR_INVALID_ARG, "buffers or d_t1_count is NULL");
+    if (!b->t1_keys || !b->t1_nonces || !b->bucket_offsets || !b->t2_count || (b->t2_capacity && !b->t2))
+        return fail(VX_ERR_INVALID_ARG, "NULL buffer");
+    if (!aligned(b->t1_keys, 8) || !aligned(b->t1_nonces, 4) || !aligned(b->bucket_offsets, 4) ||
+        !aligned(b->t2_count, 8) || !aligned(d_t1_count, 8) || (b->t2 && !aligned(b->t2, 16)))
+        return fail(VX_ERR_INVALID_ARG, "misaligned buffer");
+    return VX_OK;
+}
+
+// Stores a chunk's record count m (known on the host) in *d_t1_count and
+// checks it against the capacity; an empty chunk's outputs are written here
+// (*empty = true: nothing is left to do).
+vx_status publish_chunk_count(uint64_t m, uint64_t *d_t1_count, uint64_t t1_capacity, const vx_plot_buffers *b,
+                              hipStream_t s, bool *empty) {
+    *empty = false;
+    VX_HIP(hipMemcpyAsync(d_t1_count, &m, sizeof(m), hipMemcpyHostToDevice, s), "chunk count");
+    VX_HIP(hipStreamSynchronize(s), "chunk count");  // m lives on this stack frame
+    if (m > t1_capacity) return fail(VX_ERR_WORKSPACE, "the chunk holds more records than t1_capacity");
+    if (m == 0) {
+        VX_HIP(vxk::launch_fill_u32(b->bucket_offsets, (uint64_t)VX_NUM_BUCKETS + 1, 0u, s), "empty chunk");
+        VX_HIP(vxk::launch_zero_u64(b->t2_count, 1, s), "empty chunk");
+        *empty = true;
+    }
+    return VX_OK;
+}
+
+// Offsets of the buckets outside chunk `chunk`: 0 before it, m after it
+// (and at the end).
+vx_status fill_outside_offsets(uint32_t *offsets, uint32_t chunk_bits, uint32_t chunk, uint64_t m, hipStream_t s) {
+    const uint64_t b0 = (uint64_t)chunk << (VX_BUCKET_BITS - chunk_bits);
+    const uint64_t b1 = (uint64_t)(chunk + 1) << (VX_BUCKET_BITS - chunk_bits);
+    if (b0) VX_HIP(vxk::launch_fill_u32(offsets, b0, 0u, s), "chunk offsets");
+    VX_HIP(vxk::launch_fill_u32(offsets + b1, (uint64_t)VX_NUM_BUCKETS + 1 - b1, (uint32_t)m, s), "chunk offsets");
+    return VX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -764,17 +808,8 @@ vx_status vx_plot_chunk(const vx_plot_params *params, uint32_t chunk_bits, uint3
     Plan Pc;
     vx_status st = make_plan(params, tuning, &Pc, t1_capacity ? t1_capacity : 1, 32);
     if (st != VX_OK) return st;
-    if (chunk_bits > kMaxChunkBits || chunk >= (1u << chunk_bits))
-        return fail(VX_ERR_INVALID_ARG, "chunk_bits must be at most 8 and chunk below 2^chunk_bits");
-    if (t1_capacity == 0 || t1_capacity >= (1ull << 32))
-        return fail(VX_ERR_INVALID_ARG, "t1_capacity must be in [1, 2^32)");
+    if ((st = check_chunk_args(chunk_bits, chunk, t1_capacity, b, d_t1_count)) != VX_OK) return st;
     if (Pc.fused) return fail(VX_ERR_UNSUPPORTED, "chunked plots use the split sort and match");
-    if (!b || !d_t1_count) return fail(VX_ERR_INVALID_ARG, "buffers or d_t1_count is NULL");
-    if (!b->t1_keys || !b->t1_nonces || !b->bucket_offsets || !b->t2_count || (b->t2_capacity && !b->t2))
-        return fail(VX_ERR_INVALID_ARG, "NULL buffer");
-    if (!aligned(b->t1_keys, 8) || !aligned(b->t1_nonces, 4) || !aligned(b->bucket_offsets, 4) ||
-        !aligned(b->t2_count, 8) || !aligned(d_t1_count, 8) || (b->t2 && !aligned(b->t2, 16)))
-        return fail(VX_ERR_INVALID_ARG, "misaligned buffer");
     Layout L = layout(Pc, kCallChunk);
     if ((st = check_ws(L, b->workspace, b->workspace_bytes)) != VX_OK) return st;
     hipStream_t s = (hipStream_t)stream;
@@ -794,12 +829,9 @@ vx_status vx_plot_chunk(const vx_plot_params *params, uint32_t chunk_bits, uint3
     uint64_t m = 0;
     VX_HIP(hipMemcpyAsync(&m, count, sizeof(m), hipMemcpyDeviceToHost, s), "chunk count");
     VX_HIP(hipStreamSynchronize(s), "chunk count");
-    VX_HIP(hipMemcpyAsync(d_t1_count, &m, sizeof(m), hipMemcpyHostToDevice, s), "chunk count");
-    VX_HIP(hipStreamSynchronize(s), "chunk count");
-    if (m > t1_capacity) return fail(VX_ERR_WORKSPACE, "the chunk holds more records than t1_capacity");
-    if (m == 0) {
-        VX_HIP(vxk::launch_fill_u32(b->bucket_offsets, (uint64_t)VX_NUM_BUCKETS + 1, 0u, s), "empty chunk");
-        VX_HIP(vxk::launch_zero_u64(b->t2_count, 1, s), "empty chunk");
+    bool empty = false;
+    if ((st = publish_chunk_count(m, d_t1_count, t1_capacity, b, s, &empty)) != VX_OK) return st;
+    if (empty) {
         g_err[0] = 0;
         return VX_OK;
     }
@@ -808,24 +840,15 @@ vx_status vx_plot_chunk(const vx_plot_params *params, uint32_t chunk_bits, uint3
     // Same groups and digits as the capacity plan, so L fits (it was sized
     // for t1_capacity >= m records).
     st = run_partition(P, L, ws, keys_in, false, b->t1_keys, b->t1_nonces, P.npass, s, nullptr, nonces_in);
-    {
-        // Only the chunk's groups hold records (when the groups are at least
-        // as fine as the chunks): sort those, and give the buckets before
-        // the chunk offset 0 and those after it m.
-        const bool own = chunk_bits <= P.G;
-        const uint32_t g0 = own ? chunk << (P.G - chunk_bits) : 0;
-        const uint32_t gn = own ? 1u << (P.G - chunk_bits) : 1u << P.G;
-        if (st == VX_OK)
-            st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, at<uint8_t>(ws, L.pcnt), g0,
-                                gn, 0, s);
-        if (st == VX_OK && own) {
-            const uint64_t b0 = (uint64_t)chunk << (VX_BUCKET_BITS - chunk_bits);
-            const uint64_t b1 = (uint64_t)(chunk + 1) << (VX_BUCKET_BITS - chunk_bits);
-            if (b0) VX_HIP(vxk::launch_fill_u32(b->bucket_offsets, b0, 0u, s), "chunk offsets");
-            VX_HIP(vxk::launch_fill_u32(b->bucket_offsets + b1, (uint64_t)VX_NUM_BUCKETS + 1 - b1, (uint32_t)m, s),
-                   "chunk offsets");
-        }
-    }
+    if (st != VX_OK) return st;
+    // Only the chunk's groups hold records (when the groups are at least as
+    // fine as the chunks): sort those, and fill the other buckets' offsets.
+    const bool own = chunk_bits <= P.G;
+    const uint32_t g0 = own ? chunk << (P.G - chunk_bits) : 0;
+    const uint32_t gn = own ? 1u << (P.G - chunk_bits) : 1u << P.G;
+    st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, at<uint8_t>(ws, L.pcnt), g0, gn, 0,
+                        s);
+    if (st == VX_OK && own) st = fill_outside_offsets(b->bucket_offsets, chunk_bits, chunk, m, s);
     if (st == VX_OK)
         st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, nullptr, nullptr, 1,
                        0, 0, s);
@@ -876,20 +899,12 @@ size_t vx_staged_chunk_workspace_bytes(const vx_plot_params *params, uint32_t ch
 vx_status vx_plot_staged_chunk(const vx_plot_params *params, uint32_t chunk_bits, uint32_t chunk,
                                const void *d_stage, size_t stage_bytes, const vx_plot_buffers *b,
                                uint64_t t1_capacity, uint64_t *d_t1_count, const vx_tuning *tuning, void *stream) {
-    if (chunk_bits > kMaxChunkBits || chunk >= (1u << chunk_bits))
-        return fail(VX_ERR_INVALID_ARG, "chunk_bits must be at most 8 and chunk below 2^chunk_bits");
-    if (t1_capacity == 0 || t1_capacity >= (1ull << 32))
-        return fail(VX_ERR_INVALID_ARG, "t1_capacity must be in [1, 2^32)");
-    Plan Pc;
-    vx_status st = make_plan(params, tuning, &Pc, t1_capacity, 32, (int)chunk_bits);
+    vx_status st = check_chunk_args(chunk_bits, chunk, t1_capacity, b, d_t1_count);
     if (st != VX_OK) return st;
-    if (!d_stage || !b || !d_t1_count) return fail(VX_ERR_INVALID_ARG, "stage, buffers or d_t1_count is NULL");
-    if (!b->t1_keys || !b->t1_nonces || !b->bucket_offsets || !b->t2_count || (b->t2_capacity && !b->t2))
-        return fail(VX_ERR_INVALID_ARG, "NULL buffer");
-    if (!aligned(d_stage, 256) || !aligned(b->t1_keys, 8) || !aligned(b->t1_nonces, 4) ||
-        !aligned(b->bucket_offsets, 4) || !aligned(b->t2_count, 8) || !aligned(d_t1_count, 8) ||
-        (b->t2 && !aligned(b->t2, 16)))
-        return fail(VX_ERR_INVALID_ARG, "misaligned buffer");
+    Plan Pc;
+    if ((st = make_plan(params, tuning, &Pc, t1_capacity, 32, (int)chunk_bits)) != VX_OK) return st;
+    if (!d_stage) return fail(VX_ERR_INVALID_ARG, "stage is NULL");
+    if (!aligned(d_stage, 256)) return fail(VX_ERR_INVALID_ARG, "misaligned stage");
     const Layout L = layout(Pc, kCallStagedChunk);
     if ((st = check_ws(L, b->workspace, b->workspace_bytes)) != VX_OK) return st;
     const StageLayout S = stage_layout(Pc);
@@ -922,12 +937,9 @@ vx_status vx_plot_staged_chunk(const vx_plot_params *params, uint32_t chunk_bits
     if (memcmp(id + 1, want + 1, (kStageIdWords - 1) * 4) != 0)
         return fail(VX_ERR_INVALID_ARG, "the stage was made for another key, k, chunk_bits or tuning");
     const uint64_t m = m32;
-    VX_HIP(hipMemcpyAsync(d_t1_count, &m, sizeof(m), hipMemcpyHostToDevice, s), "chunk count");
-    VX_HIP(hipStreamSynchronize(s), "chunk count");
-    if (m > t1_capacity) return fail(VX_ERR_WORKSPACE, "the chunk holds more records than t1_capacity");
-    if (m == 0) {
-        VX_HIP(vxk::launch_fill_u32(b->bucket_offsets, (uint64_t)VX_NUM_BUCKETS + 1, 0u, s), "empty chunk");
-        VX_HIP(vxk::launch_zero_u64(b->t2_count, 1, s), "empty chunk");
+    bool empty = false;
+    if ((st = publish_chunk_count(m, d_t1_count, t1_capacity, b, s, &empty)) != VX_OK) return st;
+    if (empty) {
         g_err[0] = 0;
         return VX_OK;
     }
@@ -950,11 +962,7 @@ vx_status vx_plot_staged_chunk(const vx_plot_params *params, uint32_t chunk_bits
                         d_first << gsh, ndc << gsh, 0, s);
     if (st != VX_OK) return st;
     // Buckets before the chunk start at 0, those after it (and the end) at m.
-    const uint64_t b0 = (uint64_t)chunk << (VX_BUCKET_BITS - chunk_bits);
-    const uint64_t b1 = (uint64_t)(chunk + 1) << (VX_BUCKET_BITS - chunk_bits);
-    if (b0) VX_HIP(vxk::launch_fill_u32(b->bucket_offsets, b0, 0u, s), "chunk offsets");
-    VX_HIP(vxk::launch_fill_u32(b->bucket_offsets + b1, (uint64_t)VX_NUM_BUCKETS + 1 - b1, (uint32_t)m, s),
-           "chunk offsets");
+    if ((st = fill_outside_offsets(b->bucket_offsets, chunk_bits, chunk, m, s)) != VX_OK) return st;
     st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, nullptr, nullptr, 1, 0,
                    0, s);
     if (st == VX_OK) g_err[0] = 0;
