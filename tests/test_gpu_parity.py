@@ -67,7 +67,7 @@ def test_hash_table1_k20_several_keys(vx):
         assert np.array_equal(vx.u64(out), oracle.hash_table1(key, 20, threads=8))
 
 
-@pytest.mark.parametrize("k", [1, 3, 9, 12, 13, 15, 17, 20])
+@pytest.mark.parametrize("k", [1, 3, 9, 12, 13, 15, 17, 20, 21, 22, 24])
 def test_plot_default_threshold(vx, k):
     b = vx.plot(KEY0, k)
     _assert_plot_equal(vx, b, oracle.plot(KEY0, k, threads=8))
