@@ -969,6 +969,10 @@ __global__ __launch_bounds__(BLOCK) void k_scan_range(const uint64_t *__restrict
 //    wave's stores fill one contiguous 1 KiB run of Table 2.
 // Table-2 index = chunk base + slot.  The next chunk's nonces and counts are
 // loaded into registers while the current one is worked on.
+// A Table-1 nonce read from global memory, kept out of line (see its use in
+// k_match_emit).
+__device__ __noinline__ uint32_t load_nonce_slow(const uint32_t *nonces, uint32_t i) { return nonces[i]; }
+
 template <int BLOCK, int MCAP, int SLOTS>
 __global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *__restrict__ keys,
                                                       const uint32_t *__restrict__ nonces,
@@ -1067,7 +1071,14 @@ __global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *_
                 const uint64_t q = w0 + qr;
                 const uint32_t j = e + 1 + (uint32_t)(q - s_first[e]);
                 const uint32_t na = s_nonces[e];
-                const uint32_t nb = j < m ? s_nonces[j] : nonces[c + j];
+                // The partner is almost always in this chunk's LDS copy; an
+                // out-of-line load for the rest keeps the compiler from
+                // merging the two into a generic (flat) load per pair.
+                uint32_t nb;
+                if (__builtin_expect(j < m, 1))
+                    nb = s_nonces[j];
+                else
+                    nb = load_nonce_slow(nonces, c + j);
                 const uint64_t h = vxd::h2(key, na, nb);
                 if (base + q < cap) out[q] = make_uint4(na, nb, (uint32_t)h, (uint32_t)(h >> 32));
             }
