@@ -215,6 +215,18 @@ def plot_staged_chunk(key: bytes, stage: Stage, chunk: int, buffers: ChunkBuffer
     return buffers
 
 
+def staged_chunks(key: bytes, k: int, chunk_bits: int, threshold: int | None = None,
+                  tuning: N.VxTuning | None = None, stream=None):
+    """Make a whole plot chunk by chunk from one stage (k up to 32): yields
+    (chunk, buffers) after each chunk is enqueued; the buffers are reused by
+    the next chunk, so copy out what is needed before continuing."""
+    stage = stage_plot(key, k, chunk_bits, tuning=tuning, stream=stream)
+    buffers = alloc_staged_chunk(k, chunk_bits, threshold=threshold, tuning=tuning)
+    for r in range(1 << chunk_bits):
+        plot_staged_chunk(key, stage, r, buffers, threshold=threshold, tuning=tuning, stream=stream)
+        yield r, buffers
+
+
 def hash_table1(key: bytes, k: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     p = N.make_params(key, k)
     n = 1 << k

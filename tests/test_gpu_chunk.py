@@ -210,3 +210,16 @@ def test_chunk_over_capacity_is_reported(vx):
     b = vx.alloc_chunk(k, c)
     vx.plot_chunk(KEY0, k, c, 0, b)
     _check_chunk(vx, b, ref, c, 0)
+
+
+def test_staged_chunks_generator_makes_the_whole_plot(vx):
+    k, c = 18, 2
+    ref = oracle.plot(KEY0, k, threads=8)
+    keys, t2 = [], []
+    for r, b in vx.staged_chunks(KEY0, k, c):
+        torch.cuda.synchronize()
+        m = int(b.t1_count.item())
+        keys.append(vx.u64(b.t1_keys[:m]))
+        t2.append(vx.t2_records(b.t2, vx.t2_count(b)))
+    assert np.array_equal(np.concatenate(keys), ref.t1_keys)
+    assert np.array_equal(np.concatenate(t2), ref.t2)
