@@ -74,7 +74,8 @@ uint32_t clampu(int64_t v, int64_t lo, int64_t hi) {
 vx_status check_params(const vx_plot_params *p, uint32_t max_k = 31) {
     if (!p) return fail(VX_ERR_INVALID_ARG, "params is NULL");
     if (p->k < 1 || p->k > max_k)
-        return fail(VX_ERR_INVALID_ARG, max_k == 31 ? "k must be in [1, 31]" : "k must be in [1, 32]");
+        return fail(VX_ERR_INVALID_ARG, max_k == 31 ? "k must be in [1, 31] (k = 32: the chunk calls)"
+                                                    : "k must be in [1, 32]");
     if (p->bucket_bits != VX_BUCKET_BITS) return fail(VX_ERR_INVALID_ARG, "bucket_bits must be 24");
     return VX_OK;
 }
