@@ -25,7 +25,7 @@ if ROOT not in sys.path:
 STAGES = ["hash", "partition1", "partition2", "group_sort", "chunk_sums", "match_emit"]
 KERNEL_OF_STAGE = {"hash": "k_hash_scatter", "match_emit": "k_match_emit",
                    "group_sort": "k_groupsort", "partition1": "k_region_scan (pass 1 is in the hash)",
-                   "partition2": "k_digit_hist + k_scatter (later passes)",
+                   "partition2": "k_scatter claiming regions + k_region_bounds + k_colscan (later passes)",
                    "chunk_sums": "k_chunk_sums + k_scan_*"}
 
 

@@ -183,22 +183,23 @@ __global__ __launch_bounds__(BLOCK) void k_hash_scatter(Key key, uint64_t n, uin
                                                         uint32_t *__restrict__ fill,
                                                         uint32_t *__restrict__ status) {
     constexpr int SUB = BLOCK * ITEMS;
+    constexpr int PER = (MAXD + 63) / 64;  // digits per lane of the one-wave scan
     static_assert(MAXD <= BLOCK, "one thread per digit claims its region room");
     __shared__ uint64_t s_keys[SUB];
     __shared__ uint32_t s_non[SUB];
-    __shared__ uint32_t s_start[MAXD];
+    __shared__ uint32_t s_cnt[MAXD];      // digit counts of the sub-tile
+    __shared__ uint32_t s_pos[MAXD + 1];  // their exclusive prefix, and the total
     __shared__ uint32_t s_claim[MAXD];
-    __shared__ uint32_t s_wave[BLOCK / 64 + 1];
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
     const uint32_t nd = 1u << bits, shift = 64u - bits;
     const uint64_t nsub = (n + SUB - 1) / SUB;
     const uint64_t s0 = (uint64_t)blockIdx.x * per_wg;
     const uint64_t s1 = s0 + per_wg < nsub ? s0 + per_wg : nsub;
     bool over = false;
+    if (tid < nd) s_cnt[tid] = 0;
+    __syncthreads();
     for (uint64_t sub = s0; sub < s1; ++sub) {
         const uint64_t base = sub * SUB;
-        for (uint32_t d = tid; d < nd; d += BLOCK) s_start[d] = 0;
-        __syncthreads();
         uint64_t k[ITEMS];
         uint32_t slot[ITEMS];
 #pragma unroll
@@ -208,32 +209,58 @@ __global__ __launch_bounds__(BLOCK) void k_hash_scatter(Key key, uint64_t n, uin
             uint32_t nonce = (uint32_t)i;
             asm volatile("" : "+v"(nonce));
             k[j] = vxd::h1(key, nonce);
-            if (i < n) slot[j] = atomicAdd(&s_start[(uint32_t)(k[j] >> shift)], 1u);
+            if (i < n) slot[j] = atomicAdd(&s_cnt[(uint32_t)(k[j] >> shift)], 1u);
         }
         __syncthreads();
-        // Claim room in the regions (thread d <-> digit d, nd <= BLOCK); the
-        // atomics are in flight during the digit scan and the LDS layout.
+        // Claim room in the regions (thread d <-> digit d); the atomics are in
+        // flight during the scan and the LDS layout.  Wave 0 scans the counts
+        // on its own (no block-wide barriers).
         uint32_t claim = 0;
         if (tid < nd) {
-            const uint32_t c = s_start[tid];
+            const uint32_t c = s_cnt[tid];
             if (c) claim = atomicAdd(&fill[tid], c);
         }
-        const uint32_t total = vxd::lds_exclusive_scan<BLOCK>(s_start, (int)nd, s_wave);
+        if (tid < 64) {
+            uint32_t v[PER], sum = 0;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const uint32_t d = lane * PER + q;
+                v[q] = d < nd ? s_cnt[d] : 0u;
+                sum += v[q];
+            }
+            const uint32_t inc = vxd::wave_inclusive_scan(sum);
+            uint32_t run = inc - sum;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const uint32_t d = lane * PER + q;
+                if (d < nd) s_pos[d] = run;
+                run += v[q];
+            }
+            if (lane == 63) s_pos[MAXD] = inc;
+        }
+        __syncthreads();
+        // The counts are consumed: clear them for the next sub-tile (its
+        // atomics come after the next barrier).
+        if (tid < nd) s_cnt[tid] = 0;
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const uint64_t i = base + (uint64_t)j * BLOCK + tid;
             if (i < n) {
-                const uint32_t p = s_start[(uint32_t)(k[j] >> shift)] + slot[j];
+                const uint32_t p = s_pos[(uint32_t)(k[j] >> shift)] + slot[j];
                 s_keys[p] = k[j];
                 s_non[p] = (uint32_t)i;
             }
         }
         if (tid < nd) s_claim[tid] = claim;
         __syncthreads();
+        // No barrier after the write-out: the next sub-tile's LDS layout waits
+        // for the barrier after its hash, which every thread reaches only once
+        // its reads here are done.
+        const uint32_t total = s_pos[MAXD];
         for (uint32_t e = tid; e < total; e += BLOCK) {
             const uint64_t kk = s_keys[e];
             const uint32_t d = (uint32_t)(kk >> shift);
-            const uint32_t r = s_claim[d] + (e - s_start[d]);
+            const uint32_t r = s_claim[d] + (e - s_pos[d]);
             if (r < R) {
                 const uint64_t g = (uint64_t)d * R + r;
                 out_keys[g] = kk;
@@ -242,7 +269,6 @@ __global__ __launch_bounds__(BLOCK) void k_hash_scatter(Key key, uint64_t n, uin
                 over = true;
             }
         }
-        __syncthreads();
     }
     if (over) atomicOr(status, (uint32_t)VXK_DEV_STATUS_REGION_OVERFLOW);
 }
