@@ -108,7 +108,7 @@ typedef struct {
 typedef struct {
     uint32_t group_bits;   /* sort groups = 2^group_bits key prefixes, 1..24 */
     uint32_t pass1_bits;   /* digit bits of the first partition pass, 1..11 */
-    uint32_t group_cap;    /* records a group may hold in LDS, 64..3072 */
+    uint32_t group_cap;    /* records a group may hold in LDS, 64..3072 (0: 2560, or 3072 with fused_sort_match) */
     uint32_t h1_tiles;     /* work-groups of a separate hash and first partition pass (a plot whose
                               hash does the first pass sizes that kernel's grid itself) */
     uint32_t match_chunk_bits; /* match works on chunks of 2^bits Table-1 records, 6..11 */

@@ -171,7 +171,11 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     const uint64_t dens = 1ull << P.k;
     for (uint32_t i = 1; i < P.npass; ++i)  // about 2^16 records per tile
         P.Q[i] = clampu((int64_t)((dens >> P.pre[i]) >> 16), 1, 256);
-    P.cap = t->group_cap ? t->group_cap : (uint32_t)vxk::kGroupCapMax;
+    // The split sort defaults to the capacity whose kernel fits four
+    // work-groups on a CU.  With the default group bits a group holds 2048
+    // records or fewer on average, and 2560 is 11 standard deviations above
+    // 2048; larger groups take the fallback.
+    P.cap = t->group_cap ? t->group_cap : (uint32_t)(P.fused ? vxk::kGroupCapMax : vxk::kGroupCapFast);
     if (P.cap < 64 || P.cap > (uint32_t)vxk::kGroupCapMax)
         return fail(VX_ERR_UNSUPPORTED, "group_cap must be in [64, 3072]");
     P.cb = t->match_chunk_bits ? t->match_chunk_bits : (uint32_t)vxk::kMatchChunkBitsMax;

@@ -15,6 +15,9 @@ namespace vxk {
 
 constexpr int kMaxDigitBits = 11;     // widest partition digit (LDS histograms)
 constexpr int kGroupCapMax = 3072;    // records a sort group may hold in LDS
+// Default group capacity: the sort kernel for it fits four work-groups
+// on a CU (LDS and 64 VGPRs), against three for kGroupCapMax.
+constexpr int kGroupCapFast = 2560;
 constexpr uint32_t kFallbackMax = 1u << 20;  // largest group the fallback sorts
 constexpr int kMatchChunkBitsMax = 11;  // match chunk = 2^bits records (LDS capacity 2048)
 // Hash fused with the first partition pass: sub-tiles of 256 * 8 nonces,

@@ -613,7 +613,7 @@ __device__ __forceinline__ uint64_t pairs_in_range(const uint64_t *keys, uint32_
 // one's global loads behind the others' LDS work (better, measured, than
 // prefetching into registers at two per CU).
 template <int BLOCK, int CAPMAX>
-__global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *keys, uint32_t *nonces, GroupIn in,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CAPMAX <= kGroupCapFast ? 8 : 1))) void k_groupsort(uint64_t *keys, uint32_t *nonces, GroupIn in,
                                                      const uint32_t *__restrict__ gstart,
                                                      uint32_t G, uint32_t cap,
                                                      uint32_t *__restrict__ offsets,
@@ -625,7 +625,9 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *keys, uint32_t *n
     constexpr int ITEMS = CAPMAX / BLOCK;
     __shared__ uint64_t s_keys[CAPMAX];
     __shared__ uint32_t s_nonces[CAPMAX];
-    __shared__ uint32_t s_start[kSubBins + 1];
+    constexpr int NW2 = kSubBins / 2;  // two 16-bit sub-bin counters per word
+    static_assert(CAPMAX < 65536 && NW2 % BLOCK == 0, "packed counters");
+    __shared__ uint32_t s_start[NW2 + 1];
     __shared__ uint64_t s_wave[BLOCK / 64 + 1];
     __shared__ uint32_t s_tk[2];  // alternate, so a slow reader never sees the next ticket
     uint32_t *s_wave32 = reinterpret_cast<uint32_t *>(s_wave);
@@ -660,22 +662,43 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *keys, uint32_t *n
                 ovf_list[i] = g;
             }
         } else {
-            for (uint32_t i = tid; i < kSubBins; i += BLOCK) s_start[i] = 0;
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                const uint32_t e = j * BLOCK + tid;
-                if (e < n) slot[j] = atomicAdd(&s_start[(uint32_t)(k[j] >> sb_shift) & (kSubBins - 1)], 1u);
-            }
-            __syncthreads();
-            vxd::lds_exclusive_scan<BLOCK>(s_start, kSubBins, s_wave32);
-            if (tid == 0) s_start[kSubBins] = n;
+            for (uint32_t i = tid; i < NW2; i += BLOCK) s_start[i] = 0;
+            if (tid == 0) s_start[NW2] = n;  // start of the sub-bin past the last
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) {
                 const uint32_t e = j * BLOCK + tid;
                 if (e < n) {
-                    const uint32_t q = s_start[(uint32_t)(k[j] >> sb_shift) & (kSubBins - 1)] + slot[j];
+                    const uint32_t sb = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
+                    const uint32_t sh = (sb & 1u) << 4;
+                    slot[j] = (atomicAdd(&s_start[sb >> 1], 1u << sh) >> sh) & 0xFFFFu;
+                }
+            }
+            __syncthreads();
+            {
+                constexpr int PERW = NW2 / BLOCK;
+                uint32_t w[PERW], sum = 0;
+#pragma unroll
+                for (int i = 0; i < PERW; ++i) {
+                    w[i] = s_start[tid * PERW + i];
+                    sum += (w[i] & 0xFFFFu) + (w[i] >> 16);
+                }
+                uint32_t total;
+                uint32_t run = vxd::block_exclusive_scan<BLOCK>(sum, s_wave32, &total);
+#pragma unroll
+                for (int i = 0; i < PERW; ++i) {
+                    const uint32_t lo16 = w[i] & 0xFFFFu;
+                    s_start[tid * PERW + i] = run | ((run + lo16) << 16);
+                    run += lo16 + (w[i] >> 16);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t e = j * BLOCK + tid;
+                if (e < n) {
+                    const uint32_t sbq = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
+                    const uint32_t q = ((s_start[sbq >> 1] >> ((sbq & 1u) << 4)) & 0xFFFFu) + slot[j];
                     s_keys[q] = k[j];
                     s_nonces[q] = nn[j];
                 }
@@ -687,7 +710,9 @@ __global__ __launch_bounds__(BLOCK) void k_groupsort(uint64_t *keys, uint32_t *n
                 const uint32_t e = j * BLOCK + tid;
                 if (e < n) {
                     const uint32_t sb = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
-                    const uint32_t b0 = s_start[sb], b1 = s_start[sb + 1];
+                    const uint32_t b0 = (s_start[sb >> 1] >> ((sb & 1u) << 4)) & 0xFFFFu;
+                    const uint32_t sb1 = sb + 1;
+                    const uint32_t b1 = (s_start[sb1 >> 1] >> ((sb1 & 1u) << 4)) & 0xFFFFu;
                     uint32_t r = 0;
                     for (uint32_t x = b0; x < b1; ++x) r += rec_less(s_keys[x], s_nonces[x], k[j], nn[j]);
                     slot[j] = b0 + r;
@@ -1707,13 +1732,22 @@ hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint64_t *in
                             const uint32_t *in_lo, const uint32_t *gstart, uint32_t G, uint32_t cap,
                             uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count, uint32_t *ovf_list, uint64_t T,
                             uint8_t *pcnt, uint32_t g0, uint32_t gcount, uint32_t *ticket, hipStream_t s) {
-    static const uint32_t resident = resident_grid(k_groupsort<kSortBlock, kGroupCapMax>, kSortBlock);
-    const uint32_t grid = min(gcount, resident);
+    // Group capacities up to kGroupCapFast take the kernel that fits four
+    // work-groups on a CU; larger ones the 3072-record kernel (three).
+    static const uint32_t resident_fast = resident_grid(k_groupsort<kSortBlock, kGroupCapFast>, kSortBlock);
+    static const uint32_t resident_max = resident_grid(k_groupsort<kSortBlock, kGroupCapMax>, kSortBlock);
+    const bool fast = cap <= (uint32_t)kGroupCapFast;
+    const uint32_t grid = min(gcount, fast ? resident_fast : resident_max);
     if (grid == 0) return hipSuccess;
     const GroupIn in{in_keys, in_nonces, in_lo};
-    hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapMax>), dim3(grid), dim3(kSortBlock), 0, s,
-                       keys, nonces, in, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T, pcnt, g0,
-                       gcount, ticket);
+    if (fast)
+        hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapFast>), dim3(grid), dim3(kSortBlock), 0, s,
+                           keys, nonces, in, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T, pcnt, g0,
+                           gcount, ticket);
+    else
+        hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapMax>), dim3(grid), dim3(kSortBlock), 0, s,
+                           keys, nonces, in, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T, pcnt, g0,
+                           gcount, ticket);
     return hipGetLastError();
 }
 

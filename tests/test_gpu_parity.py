@@ -150,6 +150,42 @@ def test_bucket_sort_and_match_crowded(vx, T):
     assert np.array_equal(vx.t2_records(t2, ref_cnt), ref_t2)
 
 
+@pytest.mark.parametrize("cap", [0, 2600, 3072])
+def test_group_sizes_around_the_lds_capacities(vx, cap):
+    """Sort groups of exactly 2560 (the default capacity), 2561, 2800 and
+    3072 records (the largest capacity): the four-per-CU kernel, the
+    3072-record kernel and the fallback share the groups by capacity, with
+    the same outputs."""
+    k, gb = 14, 3
+    sizes = [2561, 3072, 2800, 2560, 2048, 1800, 1000]
+    sizes.append((1 << k) - sum(sizes))
+    rng = np.random.default_rng(11)
+    # 16 buckets per group, so that buckets and sub-bins are crowded
+    mid = rng.integers(0, 1 << 21, size=(len(sizes), 16), dtype=np.uint64)
+    parts = []
+    for g, s in enumerate(sizes):
+        a = ((np.uint64(g) << np.uint64(61)) | (mid[g][rng.integers(0, 16, size=s)] << np.uint64(40)) |
+             rng.integers(0, 1 << 40, size=s, dtype=np.uint64))
+        a[:3] = a[3:6]  # equal keys (the nonce breaks the tie)
+        parts.append(a)
+    keys = np.concatenate(parts)
+    rng.shuffle(keys)
+    T = 1 << 36
+    ref_t1k, ref_t1n, ref_off = oracle.bucket_sort(k, keys)
+    ref_t2, ref_cnt = oracle.match_table2(KEY0, T, ref_t1k, ref_t1n, ref_off, threads=8)
+    t = vx.make_tuning(group_bits=gb, group_cap=cap)
+    t1k, t1n, off, ws = vx.bucket_sort(KEY0, k, _to_dev(keys, np.int64), tuning=t)
+    torch.cuda.synchronize()
+    assert vx.device_status(ws) == 0
+    assert np.array_equal(vx.u64(t1k), ref_t1k)
+    assert np.array_equal(vx.u32(t1n), ref_t1n)
+    assert np.array_equal(vx.u32(off), ref_off)
+    t2, cnt = vx.match_table2(KEY0, k, t1k, t1n, off, threshold=T, t2_capacity=ref_cnt + 5)
+    torch.cuda.synchronize()
+    assert vx.t2_count(cnt) == ref_cnt
+    assert np.array_equal(vx.t2_records(t2, ref_cnt), ref_t2)
+
+
 def test_match_from_oracle_table1(vx):
     """vx_match_table2 on an oracle-built Table 1."""
     k = 18
