@@ -396,9 +396,8 @@ __global__ __launch_bounds__(BLOCK) void k_colscan(const uint32_t *__restrict__ 
 // ---------------------------------------------------------------------------
 // Partition scatter: each tile streams its records in sub-tiles of
 // BLOCK * ITEMS, ranks them by digit in LDS and writes every digit's run
-// contiguously at the tile's running cursor for that digit.  The next
-// sub-tile's loads are issued before the current one's LDS work and stores,
-// so a lone work-group per CU still keeps HBM reads in flight.
+// contiguously at the tile's running cursor for that digit.  A sub-tile's
+// loads are all issued before the first is waited for.
 //
 // CLAIM: instead of cursors from a histogram scan, every sub-tile claims
 // room for its digit runs with one global atomic per digit in fixed-size
@@ -466,17 +465,12 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ 
             }
         }
     };
-    uint64_t nk[ITEMS];
-    uint32_t nn[ITEMS];
-    if (lo < hi) load(lo, nk, nn);
+    // No register prefetch of the next sub-tile: it measured neutral, and
+    // its registers are better spent on larger sub-tiles.
     for (uint64_t base = lo; base < hi; base += SUB) {
         uint64_t k[ITEMS];
         uint32_t n[ITEMS], slot[ITEMS];
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            k[j] = nk[j];
-            n[j] = nn[j];
-        }
+        load(base, k, n);
         for (uint32_t d = tid; d < nd; d += BLOCK) s_start[d] = 0;
         __syncthreads();
 #pragma unroll
@@ -484,9 +478,6 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ 
             const uint64_t idx = base + (uint64_t)j * BLOCK + tid;
             if (idx < hi) slot[j] = atomicAdd(&s_start[(uint32_t)(k[j] >> shift) & mask], 1u);
         }
-        // Prefetch the next sub-tile.
-        const uint64_t nbase = base + SUB;
-        if (nbase < hi) load(nbase, nk, nn);
         __syncthreads();
         // Claim mode: thread d claims digit d's room; the atomic is in
         // flight during the scan and the LDS layout.
@@ -1715,7 +1706,12 @@ hipError_t launch_scatter_claim(const uint64_t *in_keys, const uint32_t *in_nonc
         hipLaunchKernelGGL((k_scatter<512, 8, 64, true>), dim3(nseg * q), dim3(512), 0, s, in_keys, in_nonces,
                            out_keys, out_nonces, nullptr, g, shift, bits, c);
     else
-        hipLaunchKernelGGL((k_scatter<1024, 8, 512, true>), dim3(nseg * q), dim3(1024), 0, s, in_keys, in_nonces,
+        // 12288-record sub-tiles (148 KB of LDS, one work-group per CU):
+        // runs of about 96 records per 7-bit digit, which write faster than
+        // the 64 of 8192-record sub-tiles (k=31: 23.6 against 24.6 ms for
+        // two passes), while 4096-record sub-tiles at twice the occupancy
+        // were slower still (28.4 ms).
+        hipLaunchKernelGGL((k_scatter<1024, 12, 512, true>), dim3(nseg * q), dim3(1024), 0, s, in_keys, in_nonces,
                            out_keys, out_nonces, nullptr, g, shift, bits, c);
     return hipGetLastError();
 }
