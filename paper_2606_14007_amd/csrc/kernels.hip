@@ -465,18 +465,36 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ 
             }
         }
     };
-    // No register prefetch of the next sub-tile: it measured neutral, and
-    // its registers are better spent on larger sub-tiles.
+    // The histogram-based scatter (a lone 8192-record work-group per CU)
+    // loads the next sub-tile into registers before the current one's LDS
+    // work and stores.  The claiming scatter does not: there the prefetch
+    // measured neutral, and its registers went into larger sub-tiles.
+    constexpr bool PREFETCH = !CLAIM;
+    uint64_t nk[ITEMS];
+    uint32_t nn[ITEMS];
+    if (PREFETCH && lo < hi) load(lo, nk, nn);
     for (uint64_t base = lo; base < hi; base += SUB) {
         uint64_t k[ITEMS];
         uint32_t n[ITEMS], slot[ITEMS];
-        load(base, k, n);
+        if (PREFETCH) {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                k[j] = nk[j];
+                n[j] = nn[j];
+            }
+        } else {
+            load(base, k, n);
+        }
         for (uint32_t d = tid; d < nd; d += BLOCK) s_start[d] = 0;
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const uint64_t idx = base + (uint64_t)j * BLOCK + tid;
             if (idx < hi) slot[j] = atomicAdd(&s_start[(uint32_t)(k[j] >> shift) & mask], 1u);
+        }
+        if (PREFETCH) {
+            const uint64_t nbase = base + SUB;
+            if (nbase < hi) load(nbase, nk, nn);
         }
         __syncthreads();
         // Claim mode: thread d claims digit d's room; the atomic is in
