@@ -177,7 +177,7 @@ __global__ __launch_bounds__(BLOCK) void k_hash_filter(Key key, uint64_t n, uint
 // ---------------------------------------------------------------------------
 
 template <int BLOCK, int ITEMS, int MAXD>
-__global__ __launch_bounds__(BLOCK) void k_hash_scatter(Key key, uint64_t n, uint64_t per_wg, uint32_t bits,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXD <= 64 ? 6 : 1))) void k_hash_scatter(Key key, uint64_t n, uint64_t per_wg, uint32_t bits,
                                                         uint32_t R, uint64_t *__restrict__ out_keys,
                                                         uint32_t *__restrict__ out_nonces,
                                                         uint32_t *__restrict__ fill,
@@ -1591,10 +1591,11 @@ hipError_t launch_hash_filter(const uint32_t key_words[8], uint64_t n, uint32_t 
     return hipGetLastError();
 }
 
-uint32_t hash_scatter_grid() {
+uint32_t hash_scatter_grid(bool small) {
     static const uint32_t g = resident_grid(k_hash_scatter<kHashBlock, kHashScatterItems, kHashScatterMaxDigits>,
                                             kHashBlock);
-    return g;
+    static const uint32_t g64 = resident_grid(k_hash_scatter<kHashBlock, kHashScatterItems, 64>, kHashBlock);
+    return small ? g64 : g;
 }
 
 hipError_t launch_hash_scatter(const uint32_t key_words[8], uint64_t n, uint32_t bits, uint32_t R, uint64_t *keys,
@@ -1604,11 +1605,18 @@ hipError_t launch_hash_scatter(const uint32_t key_words[8], uint64_t n, uint32_t
     for (int i = 0; i < 8; ++i) key.w[i] = key_words[i];
     constexpr uint64_t SUB = (uint64_t)kHashBlock * kHashScatterItems;
     const uint64_t nsub = (n + SUB - 1) / SUB;
-    const uint32_t grid = hash_scatter_grid();
+    // Up to 64 digits (the first digit of three-pass plots, k >= 29) the
+    // kernel's LDS and 80 VGPRs fit six work-groups per CU instead of five.
+    const bool small = bits <= 6;
+    const uint32_t grid = hash_scatter_grid(small);
     const uint64_t per = (nsub + grid - 1) / grid;
     const uint32_t used = (uint32_t)((nsub + per - 1) / per);
-    hipLaunchKernelGGL((k_hash_scatter<kHashBlock, kHashScatterItems, kHashScatterMaxDigits>), dim3(used),
-                       dim3(kHashBlock), 0, s, key, n, per, bits, R, keys, nonces, fill, status);
+    if (small)
+        hipLaunchKernelGGL((k_hash_scatter<kHashBlock, kHashScatterItems, 64>), dim3(used),
+                           dim3(kHashBlock), 0, s, key, n, per, bits, R, keys, nonces, fill, status);
+    else
+        hipLaunchKernelGGL((k_hash_scatter<kHashBlock, kHashScatterItems, kHashScatterMaxDigits>), dim3(used),
+                           dim3(kHashBlock), 0, s, key, n, per, bits, R, keys, nonces, fill, status);
     return hipGetLastError();
 }
 
