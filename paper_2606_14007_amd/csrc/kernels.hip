@@ -1605,8 +1605,9 @@ hipError_t launch_hash_scatter(const uint32_t key_words[8], uint64_t n, uint32_t
     for (int i = 0; i < 8; ++i) key.w[i] = key_words[i];
     constexpr uint64_t SUB = (uint64_t)kHashBlock * kHashScatterItems;
     const uint64_t nsub = (n + SUB - 1) / SUB;
-    // Up to 64 digits (the first digit of three-pass plots, k >= 29) the
-    // kernel's LDS and 80 VGPRs fit six work-groups per CU instead of five.
+    // Up to 64 digits (the first digit of three-pass plots, k >= 29, and of
+    // small plots) the kernel's LDS and 80 VGPRs fit six work-groups per CU
+    // instead of five.
     const bool small = bits <= 6;
     const uint32_t grid = hash_scatter_grid(small);
     const uint64_t per = (nsub + grid - 1) / grid;
