@@ -109,9 +109,13 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     // whole table, where short runs cost the most, so it takes no more than
     // 7 bits once three passes are needed (7-7-6 at k=31).  When the hash
     // kernel does the first pass (see below), that digit stays at 8 bits or
-    // less, and 6 with three passes (6-7-7 at k=31): it files sub-tiles of
-    // only 2048 records, so narrower digits keep its runs longer (measured
-    // at k=28 and k=31).
+    // less, and at most 6 with three passes: it files sub-tiles of only
+    // 2048 records, so narrower digits keep its runs longer (measured at
+    // k=28 and k=31).  With three passes up to G = 20 both later digits take
+    // 7 bits, the width the claiming scatter writes fastest, and the hash the
+    // rest: 4-7-7 at k=29, 5-7-7 at k=30, 6-7-7 at k=31 (6-6-6 and 6-7-6
+    // were 0.4 and 0.5 ms slower at k=29 and k=30; 5-7-8 and 5-8-7 1.2 ms
+    // slower at k=31).
     //
     // A pipelined plot (see run_pipelined; opt-in) instead keeps the later
     // passes at 6 bits, whose scatter fits on a CU next to two match
@@ -137,6 +141,8 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
         d0 = (P.G + 1) / 2;
         if (hs_ok) d0 = std::min(d0, 8u);
         d1 = P.G - d0; d2 = 0;
+    } else if (hs_ok && P.G <= 20) {
+        d0 = P.G - 14; d1 = 7; d2 = 7;
     } else {
         d0 = hs_ok ? 6 : 7; d1 = (P.G - d0 + 1) / 2; d2 = P.G - d0 - d1;
     }

@@ -34,7 +34,7 @@ def vx():
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("k", [27, 29])  # two passes (8-8), three passes (6-6-6)
+@pytest.mark.parametrize("k", [27, 29])  # two passes (8-8), three passes (4-7-7)
 def test_full_bit_exact(vx, k):
     print(f"k={k}: GPU plot", flush=True)
     b = vx.plot(KEY0, k)
