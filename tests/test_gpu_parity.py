@@ -67,6 +67,18 @@ def test_hash_table1_k20_several_keys(vx):
         assert np.array_equal(vx.u64(out), oracle.hash_table1(key, 20, threads=8))
 
 
+def test_device_h1_equals_published_keyed_vector(vx):
+    """The device's Table-1 hash of nonce 0x03020100 (bytes 00 01 02 03) under
+    the key of the BLAKE3 authors' test vectors is their published
+    keyed_hash digest, first 8 bytes read big-endian (no oracle involved)."""
+    from conftest import golden_lines
+    vec = {(int(n), m): bytes.fromhex(h) for n, m, h in golden_lines("blake3_test_vectors.txt")}
+    key = b"whats the Elvish word for friend"
+    out = vx.hash_table1(key, 26)
+    torch.cuda.synchronize()
+    assert int(vx.u64(out[0x03020100:0x03020101])[0]) == int.from_bytes(vec[(4, "keyed_hash")][:8], "big")
+
+
 @pytest.mark.parametrize("k", [1, 3, 9, 12, 13, 15, 17, 20, 21, 22, 24])
 def test_plot_default_threshold(vx, k):
     b = vx.plot(KEY0, k)
