@@ -198,9 +198,12 @@ vx_status vx_plot_with_events(const vx_plot_params *params, const vx_plot_buffer
  * same workspace run one after another in list order (so one workspace per
  * lane suffices); other buffers must not overlap.  Each output equals
  * vx_plot(params[i], buffers[i]).  tuning is NULL (built-in defaults per k)
- * or an array of n entries.  All plots are validated before anything is
- * enqueued.  The lane streams are shared per device: batches on one device
- * must not be captured from two threads at once. */
+ * or an array of n entries.  All plots (parameters, buffers, workspaces) are
+ * validated before anything is enqueued.  The status word of each workspace
+ * (vx_read_status) is cleared once per batch and then collects the device
+ * status bits of every plot that used it.  The lane streams are shared per
+ * device: batches on one device must not be captured from two threads at
+ * once. */
 vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buffers,
                         uint32_t n, const vx_tuning *tuning, void *stream);
 

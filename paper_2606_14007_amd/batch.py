@@ -15,7 +15,7 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _native as N
-from .plotter import PlotBuffers, _dev, _stream
+from .plotter import PlotBuffers, PlotOverflow, _dev, _stream, t2_count
 
 LANES = 4
 
@@ -83,9 +83,33 @@ def alloc_batch(specs, tunings=None, lanes: int = LANES, device=None) -> Batch:
     return Batch(list(specs), params, tunings, plots, lane_of, workspaces)
 
 
-def plot_batch(batch: Batch, stream=None) -> Batch:
-    """Enqueue the whole batch (vx_plot_batch) on `stream`."""
+def check(batch: Batch, stream=None) -> List[int]:
+    """Waits for the batch on `stream` and raises PlotOverflow if any plot's
+    Table 2 outgrew its capacity or any workspace's device status word is
+    non-zero (vx_plot_batch leaves in each workspace the status bits of every
+    plot that used it).  Returns |Table 2| per plot."""
+    sh = _stream(stream)
+    bad = []
+    for lane, ws in enumerate(batch.workspaces):
+        st = N.vx_read_status(ws.data_ptr(), sh)
+        if st:
+            plots = [i for i, l in enumerate(batch.lane_of_plot) if l == lane]
+            bad.append(f"device status {st:#x} in the workspace of plots {plots}")
+    counts = [t2_count(b) for b in batch.plots]
+    for i, (c, b) in enumerate(zip(counts, batch.plots)):
+        if c > b.t2_capacity:
+            bad.append(f"plot {i} (k={b.k}): Table 2 holds {c} records, capacity {b.t2_capacity}")
+    if bad:
+        raise PlotOverflow("batch: " + "; ".join(bad))
+    return counts
+
+
+def plot_batch(batch: Batch, stream=None, check_result: bool = False) -> Batch:
+    """Enqueue the whole batch (vx_plot_batch) on `stream`; check_result=True
+    also waits for it and raises on overflow (check)."""
     N.vx_plot_batch(batch.params, [b.native() for b in batch.plots], batch.tunings, _stream(stream))
+    if check_result:
+        check(batch, stream)
     return batch
 
 
@@ -105,8 +129,10 @@ def capture(batch: Batch) -> Batch:
     return batch
 
 
-def replay(batch: Batch) -> Batch:
+def replay(batch: Batch, check_result: bool = False) -> Batch:
     if batch.graph is None:
         raise RuntimeError("batch was not captured")
     batch.graph.replay()
+    if check_result:
+        check(batch)
     return batch

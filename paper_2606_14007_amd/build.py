@@ -36,24 +36,7 @@ def build(verbose: bool = False) -> str:
     if verbose and msgs:
         print("\n".join(msgs))
     os.replace(tmp, LIB)
-    build_probe(verbose)
     return LIB
-
-
-PROBE = os.path.join(PKG, "copy_probe")
-
-
-def build_probe(verbose: bool = False) -> str:
-    """The HBM copy-ceiling program (csrc/copy_probe.hip), a standalone binary."""
-    tmp = PROBE + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           os.path.join(CSRC, "copy_probe.hip"), "-o", tmp]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError("hipcc failed (copy_probe):\n" + r.stdout + r.stderr)
-    os.replace(tmp, PROBE)
-    return PROBE
 
 
 if __name__ == "__main__":

@@ -506,18 +506,19 @@ vx_status run_group_sort(const Plan &P, const Layout &L, void *ws, uint64_t *t1_
     const uint32_t *gstart = at<uint32_t>(ws, L.gstart[last]);
     uint32_t *ovf_list = at<uint32_t>(ws, L.ovf_list) + g0;
     const uint64_t *in_k = nullptr;
-    const uint32_t *in_n = nullptr, *in_lo = nullptr;
+    const uint32_t *in_n = nullptr, *in_lo = nullptr, *in_hi = nullptr;
     if (P.hs) {
         const PassBufs B = pass_bufs(P, L, ws, nullptr, t1_keys, t1_nonces, last);
         in_k = B.out_k;
         in_n = B.out_n;
         in_lo = at<uint32_t>(ws, L.seg_lo[last]);
+        in_hi = at<uint32_t>(ws, L.seg_hi[last]);
     }
-    VX_HIP(vxk::launch_groupsort(t1_keys, t1_nonces, in_k, in_n, in_lo, gstart, P.G, P.cap, offsets, (uint32_t)P.n,
+    VX_HIP(vxk::launch_groupsort(t1_keys, t1_nonces, in_k, in_n, in_lo, in_hi, gstart, P.G, P.cap, offsets, (uint32_t)P.n,
                                  hdr + kHdrOvf + slot, ovf_list, P.T, pcnt, g0, gcount,
                                  hdr + kHdrSortTicket + slot, s),
            "group sort");
-    VX_HIP(vxk::launch_group_fallback(t1_keys, t1_nonces, in_k, in_n, in_lo, at<uint64_t>(ws, L.scr_keys),
+    VX_HIP(vxk::launch_group_fallback(t1_keys, t1_nonces, in_k, in_n, in_lo, in_hi, at<uint64_t>(ws, L.scr_keys),
                                       at<uint32_t>(ws, L.scr_nonces), gstart, P.G, offsets, hdr + kHdrOvf + slot,
                                       ovf_list, hdr + kHdrStatus, P.T, pcnt, s),
            "group sort fallback");
@@ -1022,12 +1023,11 @@ vx_status lanes_for_current_device(Lanes **out) {
     return VX_OK;
 }
 
-// pipelined: the plan's slices may run on a second stream (vx_plot); batch
-// lanes run every plot on its lane alone.
-vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, const vx_tuning *tuning,
-                    hipEvent_t *ev, void *stream, bool pipelined) {
-    Plan P;
-    vx_status st = make_plan(params, tuning, &P);
+// Every check of a whole plot's arguments (vx_plot, and each plot of
+// vx_plot_batch before anything is enqueued); fills the plan and layout.
+vx_status check_plot(const vx_plot_params *params, const vx_plot_buffers *b, const vx_tuning *tuning, Plan *P,
+                     Layout *L) {
+    vx_status st = make_plan(params, tuning, P);
     if (st != VX_OK) return st;
     if (!b) return fail(VX_ERR_INVALID_ARG, "buffers is NULL");
     if (!b->t1_keys || !b->t1_nonces || !b->bucket_offsets || !b->t2_count || (b->t2_capacity && !b->t2))
@@ -1035,13 +1035,29 @@ vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, cons
     if (!aligned(b->t1_keys, 8) || !aligned(b->t1_nonces, 4) || !aligned(b->bucket_offsets, 4) ||
         !aligned(b->t2_count, 8) || (b->t2 && !aligned(b->t2, 16)))
         return fail(VX_ERR_INVALID_ARG, "misaligned buffer");
-    Layout L = layout(P, VX_CALL_PLOT);
-    if ((st = check_ws(L, b->workspace, b->workspace_bytes)) != VX_OK) return st;
+    *L = layout(*P, VX_CALL_PLOT);
+    return check_ws(*L, b->workspace, b->workspace_bytes);
+}
+
+// pipelined: the plan's slices may run on a second stream (vx_plot); batch
+// lanes run every plot on its lane alone, and keep the workspace's status
+// word (cleared once per workspace by vx_plot_batch), so that it collects
+// the status of every plot that used the workspace.
+vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, const vx_tuning *tuning,
+                    hipEvent_t *ev, void *stream, bool pipelined, bool keep_status = false) {
+    Plan P;
+    Layout L;
+    vx_status st = check_plot(params, b, tuning, &P, &L);
+    if (st != VX_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     void *ws = b->workspace;
     uint64_t *keys_no = at<uint64_t>(ws, L.keys_no);
     uint32_t *hdr = at<uint32_t>(ws, L.header);
-    VX_HIP(vxk::launch_reset(hdr, kHeaderWords, s), "reset");
+    static_assert(kHdrStatus == 0, "the status word leads the header");
+    if (keep_status)
+        VX_HIP(vxk::launch_reset(hdr + 1, kHeaderWords - 1, s), "reset");
+    else
+        VX_HIP(vxk::launch_reset(hdr, kHeaderWords, s), "reset");
     for (uint32_t i = 0; P.hs && i < P.npass; ++i)
         VX_HIP(vxk::launch_fill_u32(at<uint32_t>(ws, L.fill[i]), 1ull << (P.pre[i] + P.D[i]), 0u, s), "reset");
     VX_HIP(mark(ev, 0, s), "event");
@@ -1122,10 +1138,9 @@ vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buf
     std::vector<uint64_t> work(n);
     for (uint32_t i = 0; i < n; ++i) {
         Plan P;
-        vx_status st = make_plan(&params[i], tuning ? &tuning[i] : nullptr, &P);
+        Layout L;
+        vx_status st = check_plot(&params[i], &buffers[i], tuning ? &tuning[i] : nullptr, &P, &L);
         if (st != VX_OK) return st;
-        Layout L = layout(P, VX_CALL_PLOT);
-        if ((st = check_ws(L, buffers[i].workspace, buffers[i].workspace_bytes)) != VX_OK) return st;
         work[i] = P.n;
     }
     if (n == 0) return VX_OK;
@@ -1168,9 +1183,18 @@ vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buf
     for (uint32_t i = 0; i < n; ++i) used[lane_of_chain[chain_of[i]]] = true;
     for (int l = 0; l < kBatchLanes; ++l)
         if (used[l]) VX_HIP(hipStreamWaitEvent(ln->s[l], ln->fork, 0), "batch fork wait");
+    // Each workspace's status word is cleared once, before its first plot;
+    // the plots then leave it alone, so afterwards it holds the status bits
+    // of every plot that used that workspace.
+    std::vector<bool> cleared(chain_ws.size(), false);
     for (uint32_t i = 0; i < n; ++i) {
-        const int l = lane_of_chain[chain_of[i]];
-        st = plot_impl(&params[i], &buffers[i], tuning ? &tuning[i] : nullptr, nullptr, ln->s[l], false);
+        const int c = chain_of[i];
+        const int l = lane_of_chain[c];
+        if (!cleared[c]) {
+            VX_HIP(vxk::launch_reset(static_cast<uint32_t *>(buffers[i].workspace), 1, ln->s[l]), "batch status");
+            cleared[c] = true;
+        }
+        st = plot_impl(&params[i], &buffers[i], tuning ? &tuning[i] : nullptr, nullptr, ln->s[l], false, true);
         if (st != VX_OK) break;
     }
     // Join every used lane back into the caller's stream, also on failure, so

@@ -78,13 +78,15 @@ hipError_t launch_scatter_claim(const uint64_t *in_keys, const uint32_t *in_nonc
 hipError_t launch_region_bounds(uint32_t *fill, uint32_t r0, uint32_t nregions, uint32_t R, uint32_t *seg_lo,
                                 uint32_t *seg_hi, hipStream_t s);
 // Group sorts write group g to keys / nonces at gstart[g].  They read it in
-// place, or (in_keys != NULL) from record in_lo[g] of in_keys / in_nonces.
+// place, or (in_keys != NULL) from records [in_lo[g], in_hi[g]) of in_keys /
+// in_nonces.
 hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint64_t *in_keys, const uint32_t *in_nonces,
-                            const uint32_t *in_lo, const uint32_t *gstart, uint32_t G, uint32_t cap,
+                            const uint32_t *in_lo, const uint32_t *in_hi, const uint32_t *gstart, uint32_t G, uint32_t cap,
                             uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count, uint32_t *ovf_list, uint64_t T,
                             uint8_t *pcnt, uint32_t g0, uint32_t gcount, uint32_t *ticket, hipStream_t s);
 hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, const uint64_t *in_keys,
-                                 const uint32_t *in_nonces, const uint32_t *in_lo, uint64_t *scr_keys,
+                                 const uint32_t *in_nonces, const uint32_t *in_lo, const uint32_t *in_hi,
+                                 uint64_t *scr_keys,
                                  uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G,
                                  uint32_t *offsets, const uint32_t *ovf_count, const uint32_t *ovf_list,
                                  uint32_t *status, uint64_t T, uint8_t *pcnt, hipStream_t s);

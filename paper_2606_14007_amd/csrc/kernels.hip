@@ -413,13 +413,43 @@ struct Claim {
     uint32_t *status;
 };
 
-// Where a group sort reads group g: keys / nonces from record lo[g] of the
-// input regions, or (keys == NULL) in place at the group's own start.
+// Where a group sort reads group g: keys / nonces from records
+// [lo[g], hi[g]) of the input regions, or (keys == NULL) in place at the
+// group's own start.
 struct GroupIn {
     const uint64_t *keys;
     const uint32_t *nonces;
     const uint32_t *lo;
+    const uint32_t *hi;
 };
+
+// Records of group g and where its Table-1 slice ends.  In place, the group
+// is [gstart[g], gstart[g + 1]).  Gathered from a region, it holds that
+// region's (clamped) fill: without overflow this equals the difference of
+// the group starts; after a region overflowed, the difference of the last
+// group of a segment also counts the records the segment lost, so the group
+// takes only its own region's records and leaves the rest of its slice as a
+// hole (see zero_holes).  Either way every read stays inside the group's
+// region and every write below gstart[g + 1] <= the table size.
+__device__ __forceinline__ uint32_t group_records(const GroupIn &in, const uint32_t *gstart, uint32_t g,
+                                                  uint32_t lo) {
+    const uint32_t n = gstart[g + 1] - lo;
+    return in.keys ? min(n, in.hi[g] - in.lo[g]) : n;
+}
+
+// After a region overflow (VXK_DEV_STATUS_REGION_OVERFLOW) Table 1 is
+// incomplete: the hole of group g, [lo + n, gstart[g + 1]), and, after the
+// last group, the records past the placed total up to n_total are never
+// written.  Their pair-count bytes are zeroed so that the match never takes
+// partners from them (a count byte only reaches records of its own group).
+__device__ __forceinline__ void zero_holes(uint8_t *pcnt, const uint32_t *gstart, uint32_t g, uint32_t G,
+                                           uint32_t lo, uint32_t n, uint32_t n_total) {
+    if (!pcnt) return;
+    const uint32_t end = gstart[g + 1];
+    for (uint32_t i = lo + n + threadIdx.x; i < end; i += blockDim.x) pcnt[i] = 0;
+    if (g == (1u << G) - 1)
+        for (uint32_t i = end + threadIdx.x; i < n_total; i += blockDim.x) pcnt[i] = 0;
+}
 
 template <int BLOCK, int ITEMS, int MAXD, bool CLAIM>
 __global__ __launch_bounds__(BLOCK) void k_scatter(const uint64_t *__restrict__ in_keys,
@@ -585,15 +615,10 @@ __device__ __forceinline__ uint32_t pairs_after(const uint64_t *keys, uint32_t e
     return c;
 }
 
-// Adds the Table-2 pairs owned by the sorted run keys[0..n) (global records
-// [lo, lo + n)) to the counters of the fixed match chunks those records fall
-// in (chunk = record index >> chunk_bits).  Integer sums, so the order of the
-// atomic adds does not matter.
-// Pairs owned by records [e_lo, e_hi) of a sorted run keys[0..n) (the run
-// ends at a bucket boundary), counted with a two-pointer walk: the last
-// partner of a record never precedes the previous record's last partner.
-// Pairs of records [e_lo, e_hi) of a sorted run keys[0, n), by a two-pointer
-// walk.  pc (may be NULL) receives each record's count as one byte, with
+// Table-2 pairs owned by records [e_lo, e_hi) of a sorted run keys[0, n)
+// that ends at a bucket boundary, counted with a two-pointer walk (the last
+// partner of a record never precedes the previous record's last partner).
+// pc (may be NULL) receives each record's count as one byte, with
 // kPairCountEscape standing for "that many or more".
 __device__ __forceinline__ uint64_t pairs_in_range(const uint64_t *keys, uint32_t e_lo, uint32_t e_hi,
                                                    uint32_t n, uint64_t T, uint8_t *pc) {
@@ -650,7 +675,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CAPMAX <=
         const uint32_t t = s_tk[it & 1];
         if (t >= gcount) break;
         const uint32_t g = g0 + t;
-        const uint32_t lo = gstart[g], n = gstart[g + 1] - lo;
+        const uint32_t lo = gstart[g], n = group_records(in, gstart, g, lo);
+        if (in.keys) zero_holes(pcnt, gstart, g, G, lo, n, n_total);
         const uint64_t *src_k = in.keys ? in.keys + in.lo[g] : keys + lo;
         const uint32_t *src_n = in.keys ? in.nonces + in.lo[g] : nonces + lo;
         uint64_t k[ITEMS];
@@ -799,7 +825,7 @@ __global__ __launch_bounds__(BLOCK) void k_group_fallback(
     const uint32_t cnt = *ovf_count;
     for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
         const uint32_t g = ovf_list[i];
-        const uint32_t lo = gstart[g], hi = gstart[g + 1], n = hi - lo;
+        const uint32_t lo = gstart[g], n = group_records(in, gstart, g, lo);
         if (n > fb_max) {
             if (tid == 0) atomicOr(status, (uint32_t)VXK_DEV_STATUS_GROUP_TOO_LARGE);
             continue;
@@ -1752,7 +1778,7 @@ hipError_t launch_region_bounds(uint32_t *fill, uint32_t r0, uint32_t nregions, 
 }
 
 hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint64_t *in_keys, const uint32_t *in_nonces,
-                            const uint32_t *in_lo, const uint32_t *gstart, uint32_t G, uint32_t cap,
+                            const uint32_t *in_lo, const uint32_t *in_hi, const uint32_t *gstart, uint32_t G, uint32_t cap,
                             uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count, uint32_t *ovf_list, uint64_t T,
                             uint8_t *pcnt, uint32_t g0, uint32_t gcount, uint32_t *ticket, hipStream_t s) {
     // Group capacities up to kGroupCapFast take the kernel that fits four
@@ -1762,7 +1788,7 @@ hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint64_t *in
     const bool fast = cap <= (uint32_t)kGroupCapFast;
     const uint32_t grid = min(gcount, fast ? resident_fast : resident_max);
     if (grid == 0) return hipSuccess;
-    const GroupIn in{in_keys, in_nonces, in_lo};
+    const GroupIn in{in_keys, in_nonces, in_lo, in_hi};
     if (fast)
         hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapFast>), dim3(grid), dim3(kSortBlock), 0, s,
                            keys, nonces, in, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T, pcnt, g0,
@@ -1775,11 +1801,12 @@ hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint64_t *in
 }
 
 hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, const uint64_t *in_keys,
-                                 const uint32_t *in_nonces, const uint32_t *in_lo, uint64_t *scr_keys,
+                                 const uint32_t *in_nonces, const uint32_t *in_lo, const uint32_t *in_hi,
+                                 uint64_t *scr_keys,
                                  uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G,
                                  uint32_t *offsets, const uint32_t *ovf_count, const uint32_t *ovf_list,
                                  uint32_t *status, uint64_t T, uint8_t *pcnt, hipStream_t s) {
-    const GroupIn in{in_keys, in_nonces, in_lo};
+    const GroupIn in{in_keys, in_nonces, in_lo, in_hi};
     hipLaunchKernelGGL(k_group_fallback<kFallbackBlock>, dim3(kFallbackGrid), dim3(kFallbackBlock), 0,
                        s, keys, nonces, in, scr_keys, scr_nonces, gstart, G, offsets, ovf_count, ovf_list,
                        (uint32_t)kFallbackMax, status, T, pcnt);

@@ -98,15 +98,38 @@ def alloc_plot(k: int, threshold: int | None = None, t2_capacity: int | None = N
     )
 
 
+class PlotOverflow(RuntimeError):
+    """A plot's Table 2 held more records than its capacity, or the device
+    status word reported a condition (a region overflow, a group the sort
+    could not place): the tables are incomplete."""
+
+
+def check_plot(buffers: PlotBuffers, stream=None, what: str = "plot") -> int:
+    """Synchronises `stream` (default: the current stream) and raises
+    PlotOverflow if |Table 2| exceeds the capacity or the workspace's device
+    status word is non-zero; returns |Table 2|."""
+    status = N.vx_read_status(buffers.workspace.data_ptr(), _stream(stream))
+    cnt = t2_count(buffers)
+    if cnt > buffers.t2_capacity:
+        raise PlotOverflow(f"{what}: Table 2 holds {cnt} records, capacity {buffers.t2_capacity}")
+    if status:
+        raise PlotOverflow(f"{what}: device status {status:#x}")
+    return cnt
+
+
 def plot(key: bytes, k: int, threshold: int | None = None, buffers: PlotBuffers | None = None,
-         tuning: N.VxTuning | None = None, stream=None) -> PlotBuffers:
-    """Enqueue one whole plot (vx_plot); returns the buffers holding it."""
+         tuning: N.VxTuning | None = None, stream=None, check: bool = False) -> PlotBuffers:
+    """Enqueue one whole plot (vx_plot); returns the buffers holding it.
+    check=True waits for it and raises PlotOverflow on a Table-2 overflow or
+    a device status (check_plot)."""
     p = N.make_params(key, k, threshold)
     if buffers is None:
         buffers = alloc_plot(k, p.match_threshold, tuning=tuning)
     if buffers.k != k:
         raise ValueError("buffers were allocated for another k")
     N.vx_plot(p, buffers.native(), tuning, _stream(stream))
+    if check:
+        check_plot(buffers, stream)
     return buffers
 
 
@@ -282,7 +305,12 @@ def u32(t: torch.Tensor) -> np.ndarray:
 
 
 def t2_records(t2: torch.Tensor, count: int) -> np.ndarray:
-    n = min(int(count), t2.shape[0])
+    """The first `count` Table-2 records as a structured array.  Raises
+    PlotOverflow if count exceeds the buffer (the device counted records it
+    had no room to write)."""
+    n = int(count)
+    if n > t2.shape[0]:
+        raise PlotOverflow(f"Table 2 holds {n} records, capacity {t2.shape[0]}")
     return t2[:n].detach().cpu().numpy().view(T2_DTYPE).reshape(-1)
 
 

@@ -37,6 +37,7 @@ class Job:
     bypassed: int = 0
     handle: object = None
     result: object = None
+    error: Optional[str] = None     # set when the device reported a problem with this job
 
     @property
     def latency(self) -> float:
@@ -46,21 +47,22 @@ class Job:
 class Executor:
     """What the scheduler needs from a device."""
 
-    def footprint(self, k: int) -> int:
+    def footprint(self, job: Job) -> int:
         raise NotImplementedError
 
     def submit(self, job: Job, slot: int):
         raise NotImplementedError
 
-    def poll(self, handle) -> bool:
+    def poll(self, job: Job) -> bool:
+        """True once the job is done; may set job.error."""
         raise NotImplementedError
 
     def release(self, job: Job) -> None:
         raise NotImplementedError
 
-    def can_admit(self, k: int, resident: int, budget: int) -> bool:
-        """Whether a job of size k may start now (default: bytes fit the budget)."""
-        return resident + self.footprint(k) <= budget
+    def can_admit(self, job: Job, resident: int, budget: int) -> bool:
+        """Whether the job may start now (default: its bytes fit the budget)."""
+        return resident + self.footprint(job) <= budget
 
 
 @dataclass
@@ -87,7 +89,15 @@ class Stats:
         out: Dict[int, list] = {}
         for j in self.jobs:
             out.setdefault(j.k, []).append(j.latency)
-        return {k: {"n": len(v), "p50_ms": sorted(v)[len(v) // 2] * 1e3} for k, v in sorted(out.items())}
+        res = {}
+        for k, v in sorted(out.items()):
+            v = sorted(v)
+            res[k] = {"n": len(v), "p50_ms": v[len(v) // 2] * 1e3,
+                      "p99_ms": v[min(len(v) - 1, max(0, math.ceil(0.99 * len(v)) - 1))] * 1e3}
+        return res
+
+    def failed(self) -> List[Job]:
+        return [j for j in self.jobs if j.error]
 
 
 class Server:
@@ -108,7 +118,7 @@ class Server:
     def run(self, jobs: Sequence[Job]) -> Stats:
         """Serve `jobs` (arrival times relative to now) to completion."""
         for j in jobs:
-            if self.ex.footprint(j.k) > self.budget:
+            if self.ex.footprint(j) > self.budget:
                 raise ValueError(f"job {j.jid} (k={j.k}) can never fit the budget")
         pending = sorted(jobs, key=lambda j: (j.arrival, j.jid))
         waiting: List[Job] = []
@@ -128,22 +138,22 @@ class Server:
             # completions
             progressed = False
             for slot, job in list(running.items()):
-                if self.ex.poll(job.handle):
+                if self.ex.poll(job):
                     job.finished = self.clock() - t0
                     del running[slot]
                     free_slots.append(slot)
                     if self.on_done:
                         self.on_done(job)
                     self.ex.release(job)
-                    resident -= self.ex.footprint(job.k)
+                    resident -= self.ex.footprint(job)
                     done.append(job)
                     progressed = True
             # admissions, in arrival order with bounded backfill
             i = 0
             while free_slots and i < len(waiting):
                 job = waiting[i]
-                need = self.ex.footprint(job.k)
-                if self.ex.can_admit(job.k, resident, self.budget):
+                need = self.ex.footprint(job)
+                if self.ex.can_admit(job, resident, self.budget):
                     slot = free_slots.pop(0)
                     job.admitted = self.clock() - t0
                     job.handle = self.ex.submit(job, slot)
@@ -158,7 +168,7 @@ class Server:
                 if job.bypassed >= self.max_bypass:
                     break
                 for later in waiting[i + 1:]:
-                    if self.ex.can_admit(later.k, resident, self.budget):
+                    if self.ex.can_admit(later, resident, self.budget):
                         job.bypassed += 1
                         break
                 i += 1
@@ -233,31 +243,34 @@ class GpuExecutor(Executor):
         self.arena = Arena(budget_bytes)
         self.mem = torch.empty(self.arena.size, dtype=torch.uint8, device=self.device)
         self.tuning_for_k = tuning_for_k or (lambda k: None)
-        self._fp: Dict[int, int] = {}
-        self._layout: Dict[int, tuple] = {}
+        self._layout: Dict[tuple, tuple] = {}
 
-    def _plan(self, k: int):
-        if k not in self._layout:
-            N = self.N
-            p = N.make_params(bytes(32), k)
-            cap = N.vx_t2_capacity_hint(k, p.match_threshold)
+    def _plan(self, k: int, threshold: Optional[int]):
+        """Arena layout of one job: keyed by k and the job's threshold, which
+        sets its Table-2 capacity."""
+        N = self.N
+        T = N.vx_default_threshold(k) if threshold is None else int(threshold)
+        if (k, T) not in self._layout:
+            p = N.make_params(bytes(32), k, T)
+            cap = N.vx_t2_capacity_hint(k, T)
             ws = N.vx_workspace_bytes(p, N.VX_CALL_PLOT, self.tuning_for_k(k))
+            if ws == 0:
+                raise ValueError(f"invalid plot k={k}")
             n = 1 << k
-            parts = [("t1_keys", n * 8), ("t1_nonces", n * 4), ("bucket_offsets", (N.VX_NUM_BUCKETS + 1) * 4),
-                     ("t2", cap * 16), ("t2_count", 8), ("workspace", ws)]
+            parts = [("workspace", ws), ("t1_keys", n * 8), ("t1_nonces", n * 4),
+                     ("bucket_offsets", (N.VX_NUM_BUCKETS + 1) * 4), ("t2", cap * 16), ("t2_count", 8)]
             offs, at = {}, 0
             for name, nb in parts:
                 offs[name] = (at, nb)
                 at += -(-nb // 256) * 256
-            self._layout[k] = (offs, at, cap)
-            self._fp[k] = at
-        return self._layout[k]
+            self._layout[(k, T)] = (offs, at, cap)
+        return self._layout[(k, T)]
 
-    def footprint(self, k: int) -> int:
-        return self._plan(k)[1]
+    def footprint(self, job: Job) -> int:
+        return self._plan(job.k, job.threshold)[1]
 
-    def can_admit(self, k: int, resident: int, budget: int) -> bool:
-        return self.arena.can_alloc(self.footprint(k))
+    def can_admit(self, job: Job, resident: int, budget: int) -> bool:
+        return self.arena.can_alloc(self.footprint(job))
 
     def _view(self, base: int, off_nb, dtype, shape=None):
         off, nb = off_nb
@@ -266,7 +279,7 @@ class GpuExecutor(Executor):
 
     def submit(self, job: Job, slot: int):
         torch, N = self.torch, self.N
-        offs, total, cap = self._plan(job.k)
+        offs, total, cap = self._plan(job.k, job.threshold)
         base = self.arena.alloc(total)
         if base is None:
             raise RuntimeError("arena full: admission and allocation disagree")
@@ -286,10 +299,20 @@ class GpuExecutor(Executor):
         ev.record(s)
         job.result = buf
         job._arena = (base, total)
+        job._stream = s
         return ev
 
-    def poll(self, handle) -> bool:
-        return handle.query()
+    def poll(self, job: Job) -> bool:
+        """Done once the job's event has passed; then its Table-2 count and
+        device status word are read (the stream is idle, so this does not
+        wait) and a problem is recorded in job.error."""
+        if not job.handle.query():
+            return False
+        try:
+            self.P.check_plot(job.result, job._stream, what=f"job {job.jid} (k={job.k})")
+        except self.P.PlotOverflow as e:
+            job.error = str(e)
+        return True
 
     def release(self, job: Job) -> None:
         base, total = job._arena

@@ -111,3 +111,4 @@ def test_region_pct_limits():
     small = vx.vx_workspace_bytes(p, vx.VX_CALL_PLOT, vx.make_tuning(group_bits=12, region_pct=25))
     assert 0 < small < base
     assert vx.vx_workspace_bytes(p, vx.VX_CALL_PLOT, vx.make_tuning(region_pct=1001)) == 0
+

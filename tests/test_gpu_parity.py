@@ -270,3 +270,39 @@ def test_region_overflow_is_reported(vx):
     assert vx.device_status(st.data) & N.VX_DEV_STATUS_REGION_OVERFLOW
     b = vx.plot(KEY0, k, threshold=0, tuning=vx.make_tuning(group_bits=12))
     _assert_plot_equal(vx, b, oracle.plot(KEY0, k, threshold=0))
+
+
+@pytest.mark.parametrize("tun", [dict(group_bits=12), dict(group_bits=14, pass1_bits=4, pass2_bits=5)])
+@pytest.mark.parametrize("pct", [25, 60])
+def test_region_overflow_with_matching_stays_bounded(vx, tun, pct):
+    """Overflowing regions with the default threshold, so that the match
+    walks the table: a gathered group holds only its own region's records,
+    the holes that overflow leaves in Table 1 carry zero pair counts, and
+    the plot finishes with the status bit set.  Table 1 is pre-filled with a
+    sentinel, so the records the plot placed are known: each is a genuine
+    (H1(nonce), nonce) record, no nonce is placed twice, and every Table-2
+    record pairs two placed nonces with the right hash."""
+    from paper_2606_14007_amd import _native as N
+    k = 16
+    tuning = vx.make_tuning(region_pct=pct, **tun)
+    b = vx.alloc_plot(k, tuning=tuning)
+    b.t1_keys.fill_(-1)
+    b.t1_nonces.fill_(-1)
+    vx.plot(KEY0, k, buffers=b, tuning=tuning)
+    torch.cuda.synchronize()
+    assert vx.device_status(b.workspace) & N.VX_DEV_STATUS_REGION_OVERFLOW
+    keys, nonces = vx.u64(b.t1_keys), vx.u32(b.t1_nonces)
+    placed = nonces != 0xFFFFFFFF
+    assert 0 < placed.sum() < 1 << k
+    pn = nonces[placed]
+    assert len(np.unique(pn)) == len(pn) and np.all(pn < (1 << k))
+    assert np.array_equal(keys[placed], oracle.h1_many(KEY0, pn))
+    offs = vx.u32(b.bucket_offsets)
+    assert np.all(np.diff(offs.astype(np.int64)) >= 0) and offs[-1] == 1 << k
+    cnt = vx.t2_count(b)
+    assert 0 <= cnt <= b.t2_capacity
+    t2 = vx.t2_records(b.t2, cnt)
+    ok = set(pn.tolist())
+    for r in t2[:2000]:
+        assert int(r["nonce_a"]) in ok and int(r["nonce_b"]) in ok
+        assert int(r["hash2"]) == oracle.h2(KEY0, int(r["nonce_a"]), int(r["nonce_b"]))

@@ -33,8 +33,8 @@ class FakeExecutor(Executor):
         self.peak = 0
         self.order = []
 
-    def footprint(self, k):
-        return (1 << k) * self.fp
+    def footprint(self, job):
+        return (1 << job.k) * self.fp
 
     def _advance(self):
         now = self.clock.now()
@@ -49,12 +49,13 @@ class FakeExecutor(Executor):
         self._advance()
         h = object()
         self.running[h] = 2.0 ** (job.k - 20) * 1e-3
-        self.resident += self.footprint(job.k)
+        self.resident += self.footprint(job)
         self.peak = max(self.peak, self.resident)
         self.order.append(job.jid)
         return h
 
-    def poll(self, h):
+    def poll(self, job):
+        h = job.handle
         self._advance()
         if self.running[h] <= 0:
             del self.running[h]
@@ -62,7 +63,7 @@ class FakeExecutor(Executor):
         return False
 
     def release(self, job):
-        self.resident -= self.footprint(job.k)
+        self.resident -= self.footprint(job)
 
 
 def _run(jobs, slots, budget, **kw):
@@ -143,3 +144,37 @@ def test_arena_first_fit_and_coalescing():
     a.release(0, 4 * A)
     a.release(z, 4 * A)
     assert a.free == [(0, 10 * A)]
+
+
+def test_gpu_executor_sizes_table2_from_each_jobs_threshold():
+    """The arena layout of a job depends on its threshold: a wider threshold
+    gets the larger Table-2 capacity it needs (host-side planning only)."""
+    from paper_2606_14007_amd import _native as N
+    from paper_2606_14007_amd.serve import GpuExecutor
+    ex = GpuExecutor.__new__(GpuExecutor)   # planning needs no device
+    ex.N = N
+    ex.tuning_for_k = lambda k: None
+    ex._layout = {}
+    k = 28                                  # default threshold 2^36
+    plain = Job(0, k, bytes(32), 0.0)
+    wide = Job(1, k, bytes(32), 0.0, threshold=1 << 38)
+    assert ex.footprint(wide) > ex.footprint(plain)
+    offs, total, cap = ex._plan(k, 1 << 38)
+    assert cap == N.vx_t2_capacity_hint(k, 1 << 38)
+    assert offs["t2"][1] == cap * 16 and total == ex.footprint(wide)
+    assert ex._plan(k, None)[2] == N.vx_t2_capacity_hint(k, N.vx_default_threshold(k))
+
+
+def test_failed_jobs_are_reported():
+    class Failing(FakeExecutor):
+        def poll(self, job):
+            done = super().poll(job)
+            if done and job.jid % 7 == 3:
+                job.error = "device status 0x4"
+            return done
+
+    c = Clock()
+    ex = Failing(c)
+    jobs = jobs_from_arrivals(serving_arrivals(30, rate_per_s=500.0, k_lo=16, k_hi=20))
+    st = Server(ex, 1 << 40, slots=2, clock=c.now, sleep=c.sleep).run(jobs)
+    assert [j.jid for j in st.failed()] == [j for j in range(30) if j % 7 == 3]
