@@ -68,31 +68,88 @@ def load_traffic(kernel: str, k: int):
     return rec["fetch"] + rec["write"]
 
 
-def cpu_baseline(k_sample: int, target_k: int):
+def host_info() -> dict:
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    mem = None
+    try:
+        for ln in open("/proc/meminfo"):
+            if ln.startswith("MemTotal:"):
+                mem = round(int(ln.split()[1]) / 2**20, 1)
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)), "cpu_model": model,
+            "host_mem_gib": mem}
+
+
+def cpu_baseline(k_sample: int, target_k: int) -> dict:
+    """The plain oracle (C, shares no code with the HIP path) on the host:
+    a full k_sample plot on one pinned core, then its thread-split variant
+    on every usable core.  Each stage is scaled to target_k: hashing and
+    match + H2 by the growth of their work (2^(target_k - k_sample) nonces,
+    the |Table 2| ratio of the default thresholds), the bucket + sort stage
+    by 2^d * target_k / k_sample (n log n; the insertion sort inside a
+    bucket grows faster, so this favours the CPU)."""
     import oracle
     from vx_inputs import derive_key
-    log(f"cpu baseline: plain oracle, full k={k_sample} plot, 1 thread ...")
-    t0 = time.perf_counter()
-    secs, t2n = oracle.plot_timed(derive_key(0), k_sample, threads=1)
-    wall = time.perf_counter() - t0
-    scale = 2.0 ** (target_k - k_sample)
-    est = sum(secs) * scale
-    log(f"cpu baseline: stages {['%.2f' % s for s in secs]} s, |T2|={t2n}, "
-        f"scaled x{scale:.0f} -> {est:.1f} s per k={target_k} plot")
+    key = derive_key(0)
+    info = host_info()
+    cpus = sorted(os.sched_getaffinity(0))
+    d = target_k - k_sample
+
+    def t2_expect(k):
+        n = 2.0 ** k
+        lam = n / 2.0 ** 24
+        t = min(1.0, 2.0 ** (64 - k) / 2.0 ** 40)
+        return n * lam * t * (1 - t / 2)
+
+    scale = [2.0 ** d, 2.0 ** d * target_k / k_sample, t2_expect(target_k) / t2_expect(k_sample)]
+
+    def run(threads):
+        t0 = time.perf_counter()
+        secs, t2n, written = oracle.plot_timed(key, k_sample, threads=threads)
+        wall = time.perf_counter() - t0
+        if written != t2n:
+            raise RuntimeError("oracle Table-2 buffer too small: the timing would skip H2 hashes")
+        est = sum(a * b for a, b in zip(secs, scale))
+        log(f"cpu baseline, {threads} thread(s): stages {['%.2f' % x for x in secs]} s at k={k_sample} "
+            f"(|T2|={t2n}, {wall:.1f} s wall) -> {est:.1f} s per k={target_k} plot")
+        return secs, est, t2n
+
+    log(f"cpu baseline: plain oracle, full k={k_sample} plot; host {info}")
+    old = os.sched_getaffinity(0)
+    os.sched_setaffinity(0, {cpus[0]})   # this thread only: the single-thread oracle runs in it
+    try:
+        s1, e1, t2n = run(1)
+    finally:
+        os.sched_setaffinity(0, old)
+    sm, em, _ = run(len(cpus))
+    stage_names = ["hash", "bucket+sort", "match+H2"]
     return {
-        "value": round(est, 2), "unit": "s", "cores": 1, "kind": "oracle",
-        "sample": (f"full k={k_sample} plot of the same seeded key on 1 host thread "
-                   f"({wall:.1f} s wall: hash {secs[0]:.2f} s, bucket+sort {secs[1]:.2f} s, "
-                   f"match+H2 {secs[2]:.2f} s); each stage scaled by 2^{target_k - k_sample} "
-                   f"to k={target_k} (linear; the in-bucket insertion sort grows faster, so "
-                   f"this favours the CPU)"),
+        "value": round(em, 2), "unit": "s", "cores": len(cpus), "kind": "oracle",
+        "sample": (f"full k={k_sample} plot of the same seeded key (2^{k_sample} H1 + {t2n} H2 hashes, "
+                   f"insertion sort per bucket), thread-split oracle on {len(cpus)} host threads, each "
+                   f"stage scaled to k={target_k}: hash x{scale[0]:.0f}, bucket+sort "
+                   f"x{scale[1]:.1f} (n log n; favours the CPU), match+H2 x{scale[2]:.2f} (|T2|)"),
+        "stages_s": {n: round(x, 3) for n, x in zip(stage_names, sm)},
+        "single_thread": {"value": round(e1, 2), "unit": "s", "cores": 1,
+                          "stages_s": {n: round(x, 3) for n, x in zip(stage_names, s1)}},
+        "host": info,
     }
 
 
-def bench_batched(args) -> dict:
-    """32 plots, k uniform in 22..29, independent keys (SplitMix64 seed 4):
-    plots/hour of one batched launch (eager, and replayed as a HIP graph)
-    against the same plots one at a time through vx_plot."""
+def batched_compare(reps: int, autotuned: bool = False) -> dict:
+    """The batched workload (32 plots, k uniform in 22..29, keys from
+    SplitMix64 seed 4): the same plots one at a time through vx_plot, against
+    one vx_plot_batch, eager and replayed as a HIP graph.  Every run is
+    checked for overflow and device status; returns times and plots/hour."""
     import torch
     import paper_2606_14007_amd as vx
     from paper_2606_14007_amd import autotune, batch as B
@@ -100,7 +157,7 @@ def bench_batched(args) -> dict:
 
     specs = batched_plan(32)
     tunings = None
-    if args.autotune:
+    if autotuned:
         cache = autotune.load_cache()
         tun = [autotune.tuned(s.k, cache) for s in specs]
         tunings = [autotune.to_native(t) if t else vx.make_tuning() for t in tun]
@@ -116,7 +173,7 @@ def bench_batched(args) -> dict:
         for p, nb in zip(params, nbs):
             vx.vx_plot(p, nb, None, sh)   # plain path, default tuning, one at a time
 
-    def timed(fn, reps):
+    def timed(fn):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -125,36 +182,54 @@ def bench_batched(args) -> dict:
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps
 
-    reps = max(1, args.steps)
-    t_seq = timed(sequential, reps)
+    t_seq = timed(sequential)
+    for i, b in enumerate(bt.plots):
+        vx.check_plot(b, what=f"sequential plot {i}")
     log(f"sequential: {t_seq * 1e3:.1f} ms for {len(specs)} plots")
-    t_bat = timed(lambda: B.plot_batch(bt), reps)
+    t_bat = timed(lambda: B.plot_batch(bt))
+    B.check(bt)
     log(f"batched (eager): {t_bat * 1e3:.1f} ms")
     B.capture(bt)
-    t_graph = timed(lambda: B.replay(bt), reps)
+    t_graph = timed(lambda: B.replay(bt))
+    B.check(bt)
     log(f"batched (graph replay): {t_graph * 1e3:.1f} ms")
-    for b in bt.plots:
-        if vx.t2_count(b) > b.t2_capacity:
-            raise RuntimeError("Table 2 overflow in batch")
     n = len(specs)
     best = min(t_bat, t_graph)
-    return {
-        "metric": "mixed-k plots/hour batched vs plain",
-        "value": round(n * 3600.0 / best, 1),
-        "unit": "plots/h",
-        "n_gpus": 1, "steps": reps, "warmup": 1,
-        "ms_per_step": round(best * 1e3, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "batched: 32 plots, k uniform in 22..29, keys from SplitMix64 "
-                               "seed 4, default thresholds", "ks": [s.k for s in specs],
-                   "lanes": B.LANES, "autotuned": bool(args.autotune),
-                   "parallelism": "single GPU"},
+    out = {
+        "ks": [s.k for s in specs], "footprint_gib": round(bt.footprint_bytes() / 2**30, 1),
+        "sequential_ms": round(t_seq * 1e3, 3), "batched_eager_ms": round(t_bat * 1e3, 3),
+        "batched_graph_ms": round(t_graph * 1e3, 3), "best_ms": round(best * 1e3, 3),
         "sequential_plots_per_hour": round(n * 3600.0 / t_seq, 1),
+        "batched_plots_per_hour": round(n * 3600.0 / best, 1),
         "batched_eager_plots_per_hour": round(n * 3600.0 / t_bat, 1),
         "batched_graph_plots_per_hour": round(n * 3600.0 / t_graph, 1),
         "speedup_vs_sequential": round(t_seq / best, 3),
-        "records": sum(1 << s.k for s in specs),
+        "records": sum(1 << s.k for s in specs), "lanes": B.LANES, "autotuned": autotuned,
+    }
+    del bt
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_batched(args) -> dict:
+    """32 plots, k uniform in 22..29, independent keys (SplitMix64 seed 4):
+    plots/hour of one batched launch (eager, and replayed as a HIP graph)
+    against the same plots one at a time through vx_plot."""
+    reps = max(1, args.steps)
+    r = batched_compare(reps, bool(args.autotune))
+    return {
+        "metric": "mixed-k plots/hour batched vs plain",
+        "value": r["batched_plots_per_hour"],
+        "unit": "plots/h",
+        "n_gpus": 1, "steps": reps, "warmup": 1,
+        "ms_per_step": r["best_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "batched: 32 plots, k uniform in 22..29, keys from SplitMix64 "
+                               "seed 4, default thresholds", "ks": r["ks"],
+                   "lanes": r["lanes"], "autotuned": r["autotuned"], "parallelism": "single GPU"},
+        **{k: v for k, v in r.items() if k not in ("ks", "lanes", "autotuned")},
     }
 
 
@@ -424,8 +499,13 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--k", type=int, default=31)
-    ap.add_argument("--cpu-sample-k", type=int, default=25)
+    ap.add_argument("--cpu-sample-k", type=int, default=27)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning", default="",
+                    help="k31: implementation parameters as name=value,... (vx_tuning fields; "
+                         "none changes any output), e.g. fused_sort_match=1")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="k31: skip the batched-vs-sequential part of the line")
     ap.add_argument("--workload", choices=["k31", "batched", "serving", "egress", "chunked"], default="k31",
                     help="k31: one whole plot (the default line); batched: the 32-plot mix; "
                          "serving: Poisson requests through the continuous-batching server; "
@@ -472,7 +552,11 @@ def main() -> int:
     torch.cuda.set_device(dev)
     log(f"device: {torch.cuda.get_device_name(0)}; k={k}; allocating "
         f"{vx.footprint_bytes(k, T) / 2**30:.1f} GiB")
-    bufs = vx.alloc_plot(k, T, device=dev)
+    tun = None
+    if args.tuning:
+        tun = vx.make_tuning(**{kv.split("=")[0]: int(kv.split("=")[1]) for kv in args.tuning.split(",")})
+        log(f"tuning: {args.tuning}")
+    bufs = vx.alloc_plot(k, T, tuning=tun, device=dev)
     params = vx.make_params(key, k, T)
     nb = bufs.native()
     stream = torch.cuda.current_stream()
@@ -488,7 +572,7 @@ def main() -> int:
         del src, dst
 
     for i in range(args.warmup):
-        vx.vx_plot(params, nb, None, sh)
+        vx.vx_plot(params, nb, tun, sh)
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
     status = vx.device_status(bufs.workspace)
@@ -505,14 +589,12 @@ def main() -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for row in events:
-        vx.vx_plot_with_events(params, nb, [e.cuda_event for e in row], None, sh)
+        vx.vx_plot_with_events(params, nb, [e.cuda_event for e in row], tun, sh)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log(f"timed {args.steps} plots in {t1 - t0:.3f} s")
 
-    t2n = vx.t2_count(bufs)
-    if t2n > bufs.t2_capacity:
-        raise RuntimeError(f"Table 2 overflow: {t2n} > {bufs.t2_capacity}")
+    t2n = vx.check_plot(bufs, what=f"k={k} plot")   # raises on Table-2 overflow or a device status
     n = 1 << k
     stage_ms = {s: 0.0 for s in STAGES}
     for row in events:
@@ -523,8 +605,13 @@ def main() -> int:
     plot_s = ms_per_step / 1000.0
 
     # Rooflines per stage (algorithmic work per launch / event-measured time).
-    h1_ops = opcount.valu_per_h1() * n
-    h2_ops = opcount.valu_per_h2() * t2n
+    # VALU work in two forms: algorithmic 32-bit ops (every add, xor and
+    # rotate one op), the unit of the target, and vector instructions (a
+    # three-input add is one), what the kernels issue.
+    h1_ops = opcount.ops_per_h1() * n
+    h2_ops = opcount.ops_per_h2() * t2n
+    h1_ins = opcount.valu_per_h1() * n
+    h2_ins = opcount.valu_per_h2() * t2n
     valu_peak = opcount.MI355X_VALU_LANE_OPS_PER_S
     hbm_peak = opcount.MI355X_HBM_BYTES_PER_S
     npass = vx.vx_partition_passes(vx.make_params(derive_key(0), k))
@@ -546,12 +633,13 @@ def main() -> int:
         sec = stage_ms[s] / 1000.0
         ent = {"ms": round(stage_ms[s], 3), "kernel": kernel_of[s]}
         if sec > 0:
-            if s == "hash":
-                ent.update(bound="alu", achieved=h1_ops / sec / 1e12, peak=valu_peak / 1e12,
-                           unit="T lane-ops/s")
-            elif s == "match_emit":
-                ent.update(bound="alu", achieved=h2_ops / sec / 1e12, peak=valu_peak / 1e12,
-                           unit="T lane-ops/s")
+            if s in ("hash", "match_emit"):
+                ops, ins = (h1_ops, h1_ins) if s == "hash" else (h2_ops, h2_ins)
+                ent.update(bound="alu", achieved=ops / sec / 1e12, peak=valu_peak / 1e12,
+                           unit="T lane-ops/s",
+                           instruction_form={"achieved": round(ins / sec / 1e12, 2),
+                                             "frac": round(ins / sec / valu_peak, 4),
+                                             "per_hash": opcount.valu_per_h1()})
             elif algo_bytes[s]:
                 ent.update(bound="hbm", achieved=algo_bytes[s] / sec / 1e9, peak=hbm_peak / 1e9,
                            unit="GB/s")
@@ -562,13 +650,26 @@ def main() -> int:
     dom = max(STAGES, key=lambda s: stage_ms[s])
     d = stages[dom]
     traffic = load_traffic(kernel_of[dom], k)
+    alu = d.get("bound") == "alu"
     roofline = {"bound": d.get("bound"), "achieved": d.get("achieved"), "peak": d.get("peak"),
-                "unit": "TOP/s" if d.get("bound") == "alu" else "GB/s",
+                "unit": "TOP/s" if alu else "GB/s",
                 "frac": d.get("frac"), "traffic": traffic, "kernel": d["kernel"], "stage": dom,
                 "work_per_launch": (h1_ops if dom == "hash" else h2_ops if dom == "match_emit"
                                     else algo_bytes.get(dom)),
-                "work_unit": ("VALU lane-instructions (%d per hash)" % opcount.valu_per_h1()
-                              if d.get("bound") == "alu" else "bytes")}
+                "work_unit": ("algorithmic 32-bit ops (%d per Table-1 hash, %d per Table-2 hash)"
+                              % (opcount.ops_per_h1(), opcount.ops_per_h2()) if alu else "bytes")}
+    if alu:
+        roofline["instruction_form"] = dict(d["instruction_form"], unit="T VALU lane-instructions/s")
+
+    # The other two parts of the metric: Blake3 hashes/s (above) and mixed-k
+    # plots/hour batched against plain, measured after the k=31 buffers are freed.
+    del bufs, nb
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    batched = None
+    if not args.no_batched:
+        log("batched mix: 32 plots, k 22..29 (seed 4), sequential vs vx_plot_batch ...")
+        batched = batched_compare(reps=3)
 
     out = {
         "metric": "K=31 plot seconds" if k == 31 else f"K={k} plot seconds",
@@ -594,6 +695,11 @@ def main() -> int:
         "stages": stages,
         "roofline": roofline,
     }
+    if batched:
+        out["batched_plots_per_hour"] = batched["batched_plots_per_hour"]
+        out["sequential_plots_per_hour"] = batched["sequential_plots_per_hour"]
+        out["batched_speedup_vs_sequential"] = batched["speedup_vs_sequential"]
+        out["batched"] = batched
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_k, k)
     print(json.dumps(out), flush=True)

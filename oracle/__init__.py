@@ -209,19 +209,27 @@ def plot(key: bytes, k: int, threshold: int | None = None, threads: int = 1) -> 
     return Plot(k, T, keys, t1k, t1n, off, t2)
 
 
-def plot_timed(key: bytes, k: int, threads: int = 1, threshold: int | None = None):
-    """Per-stage wall seconds (hash, bucket+sort, match+H2) and |T2|."""
+def plot_timed(key: bytes, k: int, threads: int = 1, threshold: int | None = None,
+               t2_capacity: int | None = None):
+    """Per-stage wall seconds (hash, bucket+sort, match+H2), |T2| and the
+    number of Table-2 records written (each of them hashed: H2 is only
+    computed for records that have room, so a timing is complete only when
+    the two counts agree).  The default capacity, 2^k + 2^16, holds |T2| of
+    the default threshold at every k (about 2^k (1 - 2^(23 - k)) pairs for
+    k > 24, 2^(2k - 25) below)."""
     n = 1 << k
     T = default_threshold(k) if threshold is None else int(threshold)
+    cap = n + (1 << 16) if t2_capacity is None else int(t2_capacity)
     keys = np.empty(n, np.uint64)
     t1k = np.empty(n, np.uint64)
     t1n = np.empty(n, np.uint32)
     off = np.empty(NBUCKETS + 1, np.uint32)
+    t2 = np.empty(cap, T2_DTYPE)
     secs = (C.c_double * 3)()
     total = lib().or_plot_timed(_key(key), k, T, _p(keys, C.c_uint64), _p(t1k, C.c_uint64),
-                                _p(t1n, C.c_uint32), _p(off, C.c_uint32), None, 0, threads,
-                                secs)
-    return [secs[0], secs[1], secs[2]], int(total)
+                                _p(t1n, C.c_uint32), _p(off, C.c_uint32), t2.ctypes.data_as(C.c_void_p),
+                                cap, threads, secs)
+    return [secs[0], secs[1], secs[2]], int(total), min(int(total), cap)
 
 
 @dataclass

@@ -131,7 +131,7 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
             return fail(VX_ERR_UNSUPPORTED, "staged plots use the fused hash and the split sort and match");
         P.slices = 1;
     }
-    const bool hs_ok = (!records || staged >= 0) && !t->separate_hash && !P.fused;
+    const bool hs_ok = (!records || staged >= 0) && !t->separate_hash;
     uint32_t d0, d1, d2;
     if (P.G <= 9) {
         d0 = P.G; d1 = 0; d2 = 0;
@@ -181,7 +181,7 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     // work-groups on a CU.  With the default group bits a group holds 2048
     // records or fewer on average, and 2560 is 11 standard deviations above
     // 2048; larger groups take the fallback.
-    P.cap = t->group_cap ? t->group_cap : (uint32_t)(P.fused ? vxk::kGroupCapMax : vxk::kGroupCapFast);
+    P.cap = t->group_cap ? t->group_cap : (uint32_t)vxk::kGroupCapFast;
     if (P.cap < 64 || P.cap > (uint32_t)vxk::kGroupCapMax)
         return fail(VX_ERR_UNSUPPORTED, "group_cap must be in [64, 3072]");
     P.cb = t->match_chunk_bits ? t->match_chunk_bits : (uint32_t)vxk::kMatchChunkBitsMax;
@@ -1099,11 +1099,21 @@ vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, cons
         VX_HIP(vxk::launch_zero_u64(words, 1u << P.G, s), "zero look-back words");
         VX_HIP(mark(ev, 4, s), "event");
         VX_HIP(mark(ev, 5, s), "event");
-        VX_HIP(vxk::launch_sort_match(P.key_words, b->t1_keys, b->t1_nonces, at<uint64_t>(ws, L.scr_keys),
-                                      at<uint32_t>(ws, L.scr_nonces), at<uint32_t>(ws, L.gstart[P.npass - 1]),
-                                      P.G, P.cap, b->bucket_offsets, (uint32_t)P.n, P.T, hdr + kHdrFusedTicket,
-                                      words, hdr + kHdrStatus, b->t2, b->t2_capacity, b->t2_count,
-                                      kLookbackSpinLimit, s),
+        const uint32_t last = P.npass - 1;
+        const uint64_t *in_k = nullptr;
+        const uint32_t *in_n = nullptr, *in_lo = nullptr, *in_hi = nullptr;
+        if (P.hs) {
+            const PassBufs B = pass_bufs(P, L, ws, nullptr, b->t1_keys, b->t1_nonces, last);
+            in_k = B.out_k;
+            in_n = B.out_n;
+            in_lo = at<uint32_t>(ws, L.seg_lo[last]);
+            in_hi = at<uint32_t>(ws, L.seg_hi[last]);
+        }
+        VX_HIP(vxk::launch_group_match(P.key_words, b->t1_keys, b->t1_nonces, in_k, in_n, in_lo, in_hi,
+                                       at<uint64_t>(ws, L.scr_keys), at<uint32_t>(ws, L.scr_nonces),
+                                       at<uint32_t>(ws, L.gstart[last]), P.G, P.cap, b->bucket_offsets,
+                                       (uint32_t)P.n, P.T, hdr + kHdrFusedTicket, words, hdr + kHdrStatus, b->t2,
+                                       b->t2_capacity, b->t2_count, kLookbackSpinLimit, s),
                "sort + match");
         VX_HIP(mark(ev, 6, s), "event");
     }

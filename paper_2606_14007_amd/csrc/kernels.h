@@ -102,11 +102,15 @@ hipError_t launch_scan_range(const uint64_t *counts, uint64_t *bases, uint32_t n
                              const uint32_t *r_lo, const uint32_t *r_hi, uint32_t last, uint64_t *acc,
                              uint64_t *t2_count, hipStream_t s);
 hipError_t launch_zero_u64(uint64_t *p, uint32_t n, hipStream_t s);
-hipError_t launch_sort_match(const uint32_t key_words[8], uint64_t *keys, uint32_t *nonces, uint64_t *scr_keys,
-                             uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G, uint32_t cap,
-                             uint32_t *offsets, uint32_t n_total, uint64_t T, uint32_t *ticket,
-                             uint64_t *words, uint32_t *dev_status, void *t2, uint64_t t2cap,
-                             uint64_t *t2_count, uint32_t spin_limit, hipStream_t s);
+// Fused group sort + match + Table-2 hash of all 2^G groups (look-back
+// words[2^G] zero at launch, *ticket zero at launch).  Groups are read in
+// place or, with in_keys, gathered from records [in_lo[g], in_hi[g]).
+hipError_t launch_group_match(const uint32_t key_words[8], uint64_t *keys, uint32_t *nonces, const uint64_t *in_keys,
+                              const uint32_t *in_nonces, const uint32_t *in_lo, const uint32_t *in_hi,
+                              uint64_t *scr_keys, uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G,
+                              uint32_t cap, uint32_t *offsets, uint32_t n_total, uint64_t T, uint32_t *ticket,
+                              uint64_t *words, uint32_t *dev_status, void *t2, uint64_t t2cap, uint64_t *t2_count,
+                              uint32_t spin_limit, hipStream_t s);
 hipError_t launch_scan_u64(const uint64_t *in, uint32_t n, uint64_t *out, uint64_t *part,
                            uint64_t *total, hipStream_t s);
 uint32_t scan_parts(uint32_t n);

@@ -639,6 +639,89 @@ __device__ __forceinline__ uint64_t pairs_in_range(const uint64_t *keys, uint32_
     return total;
 }
 
+// Sorts the n <= CAPMAX records of a group, loaded lane-strided into k[] /
+// nn[] (item j of thread t is record j * BLOCK + t), into s_keys / s_nonces
+// by (key, nonce): a counting sort on the kSubBinBits key bits below the
+// group prefix (sb_shift), with two 16-bit counters per LDS word in s_start
+// (kSubBins / 2 + 1 words), then an exact rank inside each (tiny) sub-bin.
+// Every thread of the work-group calls it; it ends with a barrier, after
+// which s_start is free.
+template <int BLOCK, int CAPMAX>
+__device__ __forceinline__ void lds_sort_group(const uint64_t (&k)[CAPMAX / BLOCK], const uint32_t (&nn)[CAPMAX / BLOCK],
+                                               uint32_t n, uint32_t sb_shift, uint64_t *s_keys,
+                                               uint32_t *s_nonces, uint32_t *s_start, uint32_t *s_wave32) {
+    constexpr int ITEMS = CAPMAX / BLOCK;
+    constexpr int NW2 = kSubBins / 2;
+    const uint32_t tid = threadIdx.x;
+    uint32_t slot[ITEMS];
+    for (uint32_t i = tid; i < NW2; i += BLOCK) s_start[i] = 0;
+    if (tid == 0) s_start[NW2] = n;  // start of the sub-bin past the last
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t e = j * BLOCK + tid;
+        if (e < n) {
+            const uint32_t sb = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
+            const uint32_t sh = (sb & 1u) << 4;
+            slot[j] = (atomicAdd(&s_start[sb >> 1], 1u << sh) >> sh) & 0xFFFFu;
+        }
+    }
+    __syncthreads();
+    {
+        constexpr int PERW = NW2 / BLOCK;
+        uint32_t w[PERW], sum = 0;
+#pragma unroll
+        for (int i = 0; i < PERW; ++i) {
+            w[i] = s_start[tid * PERW + i];
+            sum += (w[i] & 0xFFFFu) + (w[i] >> 16);
+        }
+        uint32_t total;
+        uint32_t run = vxd::block_exclusive_scan<BLOCK>(sum, s_wave32, &total);
+#pragma unroll
+        for (int i = 0; i < PERW; ++i) {
+            const uint32_t lo16 = w[i] & 0xFFFFu;
+            s_start[tid * PERW + i] = run | ((run + lo16) << 16);
+            run += lo16 + (w[i] >> 16);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t e = j * BLOCK + tid;
+        if (e < n) {
+            const uint32_t sbq = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
+            const uint32_t q = ((s_start[sbq >> 1] >> ((sbq & 1u) << 4)) & 0xFFFFu) + slot[j];
+            s_keys[q] = k[j];
+            s_nonces[q] = nn[j];
+        }
+    }
+    __syncthreads();
+    // Exact rank inside the sub-bin; slot[] is reused for the final position.
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t e = j * BLOCK + tid;
+        if (e < n) {
+            const uint32_t sb = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
+            const uint32_t b0 = (s_start[sb >> 1] >> ((sb & 1u) << 4)) & 0xFFFFu;
+            const uint32_t sb1 = sb + 1;
+            const uint32_t b1 = (s_start[sb1 >> 1] >> ((sb1 & 1u) << 4)) & 0xFFFFu;
+            uint32_t r = 0;
+            for (uint32_t x = b0; x < b1; ++x) r += rec_less(s_keys[x], s_nonces[x], k[j], nn[j]);
+            slot[j] = b0 + r;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t e = j * BLOCK + tid;
+        if (e < n) {
+            s_keys[slot[j]] = k[j];
+            s_nonces[slot[j]] = nn[j];
+        }
+    }
+    __syncthreads();
+}
+
 // Persistent: each work-group takes groups of [g0, g0 + gcount) from a
 // ticket counter (*ticket, zero at launch) until none is left, so work-groups
 // that start late -- while another stream's kernel holds part of the device
@@ -680,7 +763,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CAPMAX <=
         const uint64_t *src_k = in.keys ? in.keys + in.lo[g] : keys + lo;
         const uint32_t *src_n = in.keys ? in.nonces + in.lo[g] : nonces + lo;
         uint64_t k[ITEMS];
-        uint32_t nn[ITEMS], slot[ITEMS];
+        uint32_t nn[ITEMS];
         if (n <= cap && n > 0) {
             // Clamped, unconditional loads: a wave issues all before waiting.
 #pragma unroll
@@ -697,72 +780,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CAPMAX <=
                 ovf_list[i] = g;
             }
         } else {
-            for (uint32_t i = tid; i < NW2; i += BLOCK) s_start[i] = 0;
-            if (tid == 0) s_start[NW2] = n;  // start of the sub-bin past the last
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                const uint32_t e = j * BLOCK + tid;
-                if (e < n) {
-                    const uint32_t sb = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
-                    const uint32_t sh = (sb & 1u) << 4;
-                    slot[j] = (atomicAdd(&s_start[sb >> 1], 1u << sh) >> sh) & 0xFFFFu;
-                }
-            }
-            __syncthreads();
-            {
-                constexpr int PERW = NW2 / BLOCK;
-                uint32_t w[PERW], sum = 0;
-#pragma unroll
-                for (int i = 0; i < PERW; ++i) {
-                    w[i] = s_start[tid * PERW + i];
-                    sum += (w[i] & 0xFFFFu) + (w[i] >> 16);
-                }
-                uint32_t total;
-                uint32_t run = vxd::block_exclusive_scan<BLOCK>(sum, s_wave32, &total);
-#pragma unroll
-                for (int i = 0; i < PERW; ++i) {
-                    const uint32_t lo16 = w[i] & 0xFFFFu;
-                    s_start[tid * PERW + i] = run | ((run + lo16) << 16);
-                    run += lo16 + (w[i] >> 16);
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                const uint32_t e = j * BLOCK + tid;
-                if (e < n) {
-                    const uint32_t sbq = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
-                    const uint32_t q = ((s_start[sbq >> 1] >> ((sbq & 1u) << 4)) & 0xFFFFu) + slot[j];
-                    s_keys[q] = k[j];
-                    s_nonces[q] = nn[j];
-                }
-            }
-            __syncthreads();
-            // Exact rank inside the sub-bin; slot[] is reused for the final position.
-#pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                const uint32_t e = j * BLOCK + tid;
-                if (e < n) {
-                    const uint32_t sb = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
-                    const uint32_t b0 = (s_start[sb >> 1] >> ((sb & 1u) << 4)) & 0xFFFFu;
-                    const uint32_t sb1 = sb + 1;
-                    const uint32_t b1 = (s_start[sb1 >> 1] >> ((sb1 & 1u) << 4)) & 0xFFFFu;
-                    uint32_t r = 0;
-                    for (uint32_t x = b0; x < b1; ++x) r += rec_less(s_keys[x], s_nonces[x], k[j], nn[j]);
-                    slot[j] = b0 + r;
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                const uint32_t e = j * BLOCK + tid;
-                if (e < n) {
-                    s_keys[slot[j]] = k[j];
-                    s_nonces[slot[j]] = nn[j];
-                }
-            }
-            __syncthreads();
+            lds_sort_group<BLOCK, CAPMAX>(k, nn, n, sb_shift, s_keys, s_nonces, s_start, s_wave32);
             // Write the group out, with each record's pair count (one byte):
             // lane-strided records keep LDS reads and stores contiguous; a
             // record tests its next four records with independent reads (no
@@ -1188,22 +1206,33 @@ __global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *_
 }
 
 // ---------------------------------------------------------------------------
-// Fused group sort + match + Table-2 hash (the plot path).
+// Fused group sort + match + Table-2 hash (the plot's tail; paper sec. III-A
+// fuses the sort and the match of a bucket in one block).
 //
 // A persistent work-group takes sort groups in increasing order from a
-// ticket counter.  For each group it sorts the records in LDS (as
-// k_groupsort), writes them to Table 1 with the group's bucket offsets,
-// counts every record's pairs, and obtains the group's Table-2 base with a
-// decoupled look-back over the groups before it (single-pass scan, Merrill
-// and Garland 2016): it publishes its own count first, then sums published
-// counts backwards until it meets a published inclusive prefix.  Tickets are
-// handed out in order to running work-groups and every work-group publishes
-// its count before it waits, so the waits always end; the wait is still
-// bounded and sets a status bit if the bound is hit.  Then the group's pairs
-// are expanded into an LDS list and hashed one pair per lane.  Sorting and
-// hashing of different work-groups overlap on each CU, and Table 1 is read
-// once.  Groups above the LDS capacity are sorted and matched from global
-// memory by the same work-group (slow path, never taken by BLAKE3 keys).
+// ticket counter.  For group g it
+//  1. gathers the group's records from its partition region (or reads them
+//     in place), sorts them in LDS (lds_sort_group) and writes the group's
+//     Table-1 slice and bucket offsets;
+//  2. counts each record's pairs from the sorted keys in LDS -- exactly,
+//     because partners never leave a group (groups end at bucket
+//     boundaries);
+//  3. publishes the group's pair total and obtains its Table-2 base with a
+//     decoupled look-back over the totals of the groups before it
+//     (single-pass scan, Merrill and Garland 2016): it publishes its own
+//     total first, then sums published totals backwards until it meets a
+//     published inclusive prefix.  Tickets are handed out in order to
+//     running work-groups and every work-group publishes its total before it
+//     waits, so the waits always end; the wait is still bounded and sets a
+//     status bit if the bound is hit;
+//  4. expands the pairs into LDS (each slot names its first record) and
+//     hashes them one pair per lane, writing Table 2 at base + slot.
+// The work-groups resident on a CU are at different steps, so the sorts'
+// memory and LDS work runs beside the hashes' vector work.  Table 1 is read
+// once (from the regions) and never read back, and only the pair totals
+// cross work-groups.  Groups above the LDS capacity are sorted and matched by
+// the same work-group in global memory (slow path; never taken by BLAKE3 keys
+// at the default group bits).
 // ---------------------------------------------------------------------------
 
 constexpr uint64_t kLbAgg = 1ull << 62;     // word holds the group's own count
@@ -1267,214 +1296,227 @@ __device__ uint64_t lookback(const uint64_t *words, uint32_t g, uint32_t spin_li
     return prefix;
 }
 
-// Writes the pairs of records [e0, e0 + ITEMS) of a sorted LDS run that fall
-// in slots [w, w + PW) into the pair list (slot - w); my_off is the slot of
-// the first pair of record e0.  Partners are found by the same forward scan
-// that counted them.
-template <int ITEMS>
-__device__ __forceinline__ void expand_pairs(const uint64_t *s_keys, const uint32_t *s_nonces, uint32_t e0,
-                                             uint32_t n, uint64_t T, uint64_t my_off, uint64_t w,
-                                             uint32_t PW, uint32_t *s_pa, uint32_t *s_pb) {
-    uint64_t off = my_off;
-    for (uint32_t e = e0; e < min(e0 + ITEMS, n) && off < w + PW; ++e) {
-        const uint64_t ki = s_keys[e];
-        const uint32_t bi = (uint32_t)(ki >> 40);
-        const uint32_t na = s_nonces[e];
-        uint32_t j = e + 1;
-        for (; j < n; ++j) {
-            const uint64_t kj = s_keys[j];
-            if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
-            const uint64_t q = off + (j - e - 1);
-            if (q >= w && q < w + PW) {
-                s_pa[q - w] = na;
-                s_pb[q - w] = s_nonces[j];
-            }
+// Oversized group (n > the LDS capacity): rank sort in global memory, the
+// records compared in LDS-staged tiles of CAPMAX records (s_keys / s_nonces),
+// written to keys / nonces [lo, lo + n), then the group's bucket offsets.
+// src: the group's records (its region, or a scratch copy).  All threads
+// call it; it ends with a barrier.
+template <int BLOCK, int CAPMAX>
+__device__ void slow_sort_group(const uint64_t *src_k, const uint32_t *src_n, uint32_t n, uint64_t *keys,
+                                uint32_t *nonces, uint32_t lo, uint32_t g, uint32_t G, uint32_t *offsets,
+                                uint64_t *s_keys, uint32_t *s_nonces) {
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t e0 = 0; e0 < n; e0 += BLOCK) {
+        const uint32_t e = e0 + tid;
+        const bool valid = e < n;
+        uint64_t mk = 0;
+        uint32_t mn = 0, r = 0;
+        if (valid) {
+            mk = src_k[e];
+            mn = src_n[e];
         }
-        off += j - e - 1;
+        for (uint32_t t0 = 0; t0 < n; t0 += CAPMAX) {
+            const uint32_t m = min((uint32_t)CAPMAX, n - t0);
+            __syncthreads();
+            for (uint32_t x = tid; x < m; x += BLOCK) {
+                s_keys[x] = src_k[t0 + x];
+                s_nonces[x] = src_n[t0 + x];
+            }
+            __syncthreads();
+            if (valid)
+                for (uint32_t x = 0; x < m; ++x) r += rec_less(s_keys[x], s_nonces[x], mk, mn);
+        }
+        if (valid) {
+            keys[lo + r] = mk;
+            nonces[lo + r] = mn;
+        }
     }
+    __syncthreads();
+    const uint32_t nbg = 1u << (VXK_BUCKET_BITS - G);
+    const uint32_t bfirst = g << (VXK_BUCKET_BITS - G);
+    for (uint32_t bl = tid; bl < nbg; bl += BLOCK) {
+        uint32_t a = 0, c = n;
+        while (a < c) {
+            const uint32_t mid = (a + c) >> 1;
+            if ((uint32_t)(keys[lo + mid] >> 40) < bfirst + bl) a = mid + 1; else c = mid;
+        }
+        offsets[bfirst + bl] = lo + a;
+    }
+    __syncthreads();
 }
 
-template <int BLOCK, int CAPMAX, int PW>
-__global__ __launch_bounds__(BLOCK) void k_sort_match(
-    Key key, uint64_t *__restrict__ keys, uint32_t *__restrict__ nonces,
-    uint64_t *__restrict__ scr_keys, uint32_t *__restrict__ scr_nonces,
-    const uint32_t *__restrict__ gstart, uint32_t G, uint32_t cap,
-    uint32_t *__restrict__ offsets, uint32_t n_total, uint64_t T, uint32_t *__restrict__ ticket,
-    uint64_t *__restrict__ words, uint32_t *__restrict__ dev_status, uint4 *__restrict__ t2,
-    uint64_t t2cap, uint64_t *__restrict__ t2_count, uint32_t spin_limit, uint32_t fb_max) {
+template <int BLOCK, int CAPMAX, int SLOTS>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_group_match(
+    Key key, uint64_t *__restrict__ keys, uint32_t *__restrict__ nonces, GroupIn in,
+    uint64_t *__restrict__ scr_keys, uint32_t *__restrict__ scr_nonces, const uint32_t *__restrict__ gstart,
+    uint32_t G, uint32_t cap, uint32_t *__restrict__ offsets, uint32_t n_total, uint64_t T,
+    uint32_t *__restrict__ ticket, uint64_t *__restrict__ words, uint32_t *__restrict__ dev_status,
+    uint4 *__restrict__ t2, uint64_t t2cap, uint64_t *__restrict__ t2_count, uint32_t spin_limit,
+    uint32_t fb_max) {
     constexpr int ITEMS = CAPMAX / BLOCK;
-    static_assert(kSubBins * 4 >= PW * 8, "pair list reuses the sub-bin area");
-    static_assert(CAPMAX >= PW, "hashes of one window reuse the key area");
-    __shared__ uint64_t s_keys[CAPMAX];
+    constexpr int NW2 = kSubBins / 2;
+    static_assert(CAPMAX % BLOCK == 0 && CAPMAX < 65536, "records are indexed by 16 bits");
+    static_assert(CAPMAX * 4 + SLOTS * 2 <= CAPMAX * 8, "first slots and the slot window fit the key area");
+    static_assert(CAPMAX <= 2 * (NW2 + 1), "16-bit pair counts fit the sub-bin area");
+    __shared__ uint64_t s_keys[CAPMAX];      // steps 1-2: sorted keys; step 4: s_first + s_slot
     __shared__ uint32_t s_nonces[CAPMAX];
-    __shared__ uint32_t s_start[kSubBins + 1];
+    __shared__ uint32_t s_start[NW2 + 1];    // step 1: sub-bin counters; steps 2-3: s_cnt
     __shared__ uint64_t s_wave[BLOCK / 64 + 1];
-    __shared__ uint32_t s_first[2 * (BLOCK / 64)];
-    __shared__ uint32_t s_g;
+    __shared__ uint32_t s_lb[2 * (BLOCK / 64)];
+    __shared__ uint32_t s_tk[2];  // alternate, so a slow reader never sees the next ticket
     uint32_t *s_wave32 = reinterpret_cast<uint32_t *>(s_wave);
-    uint32_t *s_pa = s_start;
-    uint32_t *s_pb = s_start + PW;
-    const uint32_t tid = threadIdx.x;
+    uint16_t *s_cnt = reinterpret_cast<uint16_t *>(s_start);   // pairs owned by each sorted record
+    uint32_t *s_first = reinterpret_cast<uint32_t *>(s_keys);  // first slot of each record
+    uint16_t *s_slot = reinterpret_cast<uint16_t *>(s_keys) + 2 * CAPMAX;  // record of each window slot
+    const uint32_t tid0 = threadIdx.x;
     const uint32_t ngroups = 1u << G;
     const uint32_t sb_shift = 64u - G - kSubBinBits;
     const uint32_t nbg = 1u << (VXK_BUCKET_BITS - G);
-    while (true) {
-        if (tid == 0) s_g = atomicAdd(ticket, 1u);
+    if (blockIdx.x == 0 && tid0 == 0) offsets[VXK_NUM_BUCKETS] = n_total;
+    for (uint32_t it = 0;; ++it) {
+        // Opaque per group, so that the compiler recomputes thread-derived
+        // addresses instead of holding them in registers across the loop (the
+        // kernel then fits 80 VGPRs, three work-groups per CU).
+        uint32_t tid = tid0;
+        asm volatile("" : "+v"(tid));
+        if (tid == 0) s_tk[it & 1] = atomicAdd(ticket, 1u);
         __syncthreads();
-        const uint32_t g = s_g;
+        const uint32_t g = s_tk[it & 1];
         if (g >= ngroups) break;
-        const uint32_t lo = gstart[g], hi = gstart[g + 1], n = hi - lo;
+        const uint32_t lo = gstart[g], n = group_records(in, gstart, g, lo);
+        const uint64_t *src_k = in.keys ? in.keys + in.lo[g] : keys + lo;
+        const uint32_t *src_n = in.keys ? in.nonces + in.lo[g] : nonces + lo;
         const bool fast = n <= cap;
-        if (g == ngroups - 1 && tid == 0) offsets[VXK_NUM_BUCKETS] = n_total;
-        const uint32_t bfirst = g << (VXK_BUCKET_BITS - G);
+        uint64_t mine = 0;  // pairs owned by this thread's records
         if (fast) {
-            for (uint32_t i = tid; i < kSubBins; i += BLOCK) s_start[i] = 0;
-            __syncthreads();
             uint64_t k[ITEMS];
-            uint32_t nn[ITEMS], slot[ITEMS];
+            uint32_t nn[ITEMS];
+            if (n > 0) {
 #pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                const uint32_t e = j * BLOCK + tid;
-                if (e < n) {
-                    k[j] = keys[lo + e];
-                    nn[j] = nonces[lo + e];
-                    slot[j] = atomicAdd(&s_start[(uint32_t)(k[j] >> sb_shift) & (kSubBins - 1)], 1u);
+                for (int j = 0; j < ITEMS; ++j) {
+                    const uint32_t e = j * BLOCK + tid;
+                    const uint32_t ec = e < n ? e : n - 1;
+                    k[j] = src_k[ec];
+                    nn[j] = src_n[ec];
                 }
             }
-            __syncthreads();
-            vxd::lds_exclusive_scan<BLOCK>(s_start, kSubBins, s_wave32);
-            if (tid == 0) s_start[kSubBins] = n;
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                const uint32_t e = j * BLOCK + tid;
-                if (e < n) {
-                    const uint32_t q = s_start[(uint32_t)(k[j] >> sb_shift) & (kSubBins - 1)] + slot[j];
-                    s_keys[q] = k[j];
-                    s_nonces[q] = nn[j];
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                const uint32_t e = j * BLOCK + tid;
-                if (e < n) {
-                    const uint32_t sb = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
-                    const uint32_t b0 = s_start[sb], b1 = s_start[sb + 1];
-                    uint32_t r = 0;
-                    for (uint32_t x = b0; x < b1; ++x) r += rec_less(s_keys[x], s_nonces[x], k[j], nn[j]);
-                    slot[j] = b0 + r;
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                const uint32_t e = j * BLOCK + tid;
-                if (e < n) {
-                    s_keys[slot[j]] = k[j];
-                    s_nonces[slot[j]] = nn[j];
-                }
-            }
-            __syncthreads();
+            lds_sort_group<BLOCK, CAPMAX>(k, nn, n, sb_shift, s_keys, s_nonces, s_start, s_wave32);
+            // Write the group out and count each record's pairs: lane-strided
+            // records keep LDS and global accesses contiguous; a record tests
+            // its next four records with independent reads and walks on only
+            // past four partners.
             for (uint32_t e = tid; e < n; e += BLOCK) {
-                keys[lo + e] = s_keys[e];
+                const uint64_t ki = s_keys[e];
+                keys[lo + e] = ki;
                 nonces[lo + e] = s_nonces[e];
+                const uint32_t bi = (uint32_t)(ki >> 40);
+                uint64_t kn[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) kn[r] = e + 1 + r < n ? s_keys[e + 1 + r] : ~0ull;
+                uint32_t c = 0;
+                bool go = true;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    go = go && e + 1 + r < n && (uint32_t)(kn[r] >> 40) == bi && kn[r] - ki < T;
+                    c += go ? 1u : 0u;
+                }
+                if (c == 4)
+                    for (uint32_t j = e + 5; j < n; ++j) {
+                        const uint64_t kj = s_keys[j];
+                        if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
+                        ++c;
+                    }
+                s_cnt[e] = (uint16_t)c;
             }
+            const uint32_t bfirst = g << (VXK_BUCKET_BITS - G);
             for (uint32_t bl = tid; bl < nbg; bl += BLOCK) {
+                const uint32_t b = bfirst + bl;
                 uint32_t a = 0, c = n;
                 while (a < c) {
                     const uint32_t mid = (a + c) >> 1;
-                    if ((uint32_t)(s_keys[mid] >> 40) < bfirst + bl) a = mid + 1; else c = mid;
+                    if ((uint32_t)(s_keys[mid] >> 40) < b) a = mid + 1; else c = mid;
                 }
-                offsets[bfirst + bl] = lo + a;
+                offsets[b] = lo + a;
+            }
+            __syncthreads();
+            // Canonical slots: thread t owns records [t * ITEMS, t * ITEMS + ITEMS).
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t e = tid * ITEMS + i;
+                if (e < n) mine += s_cnt[e];
             }
         } else if (n <= fb_max) {
-            // Slow path: rank sort through scratch, all in global memory.
-            for (uint32_t e = tid; e < n; e += BLOCK) {
-                scr_keys[lo + e] = keys[lo + e];
-                scr_nonces[lo + e] = nonces[lo + e];
-            }
-            __syncthreads();
-            for (uint32_t e = tid; e < n; e += BLOCK) {
-                const uint64_t mk = scr_keys[lo + e];
-                const uint32_t mn = scr_nonces[lo + e];
-                uint32_t r = 0;
-                for (uint32_t x = 0; x < n; ++x) r += rec_less(scr_keys[lo + x], scr_nonces[lo + x], mk, mn);
-                keys[lo + r] = mk;
-                nonces[lo + r] = mn;
-            }
-            __syncthreads();
-            for (uint32_t bl = tid; bl < nbg; bl += BLOCK) {
-                uint32_t a = 0, c = n;
-                while (a < c) {
-                    const uint32_t mid = (a + c) >> 1;
-                    if ((uint32_t)(keys[lo + mid] >> 40) < bfirst + bl) a = mid + 1; else c = mid;
+            // Slow path: the group's records, as a scratch copy when in place.
+            if (!in.keys) {
+                for (uint32_t e = tid; e < n; e += BLOCK) {
+                    scr_keys[lo + e] = keys[lo + e];
+                    scr_nonces[lo + e] = nonces[lo + e];
                 }
-                offsets[bfirst + bl] = lo + a;
+                src_k = scr_keys + lo;
+                src_n = scr_nonces + lo;
+                __syncthreads();
             }
+            slow_sort_group<BLOCK, CAPMAX>(src_k, src_n, n, keys, nonces, lo, g, G, offsets, s_keys, s_nonces);
+            for (uint32_t e = tid; e < n; e += BLOCK) mine += pairs_after(keys + lo, e, n, T);
         } else {
             if (tid == 0) atomicOr(dev_status, (uint32_t)VXK_DEV_STATUS_GROUP_TOO_LARGE);
         }
-        const bool counted = fast || n <= fb_max;
-        // Pair counts.  Fast path: this thread owns records [e0, e0 + ITEMS)
-        // of the sorted group in LDS; slow path: records tid, tid + BLOCK, ...
-        const uint32_t e0 = tid * ITEMS;
-        uint64_t mine = 0;
-        if (fast) {
-            for (uint32_t e = e0; e < min(e0 + ITEMS, n); ++e) mine += pairs_after(s_keys, e, n, T);
-        } else if (counted) {
-            for (uint32_t e = tid; e < n; e += BLOCK) mine += pairs_after(keys + lo, e, n, T);
-        }
         uint64_t ctot;
         const uint64_t my_off = vxd::block_exclusive_scan<BLOCK>(mine, s_wave, &ctot);
-        // Publish this group's count at once, so that later groups can pass
-        // it in their look-back while this one keeps working.
+        // Publish this group's total at once, so that later groups can pass it
+        // in their look-back while this one keeps working.
         if (tid == 0) lb_store(&words[g], kLbAgg | ctot);
-        if (fast && ctot <= PW) {
-            // Common case, one window: expand and hash the pairs into LDS
-            // first (the hashes overwrite the key area, no longer needed),
-            // then look back -- by now the groups before this one have
-            // published -- and write the records out.
-            expand_pairs<ITEMS>(s_keys, s_nonces, tid * ITEMS, n, T, my_off, 0, PW, s_pa, s_pb);
-            __syncthreads();
-            uint64_t *s_h = s_keys;
-#pragma unroll 1
-            for (uint32_t q = tid; q < (uint32_t)ctot; q += BLOCK) s_h[q] = vxd::h2(key, s_pa[q], s_pb[q]);
-            __syncthreads();  // hashes visible to the writers below (the look-back may not sync)
-            const uint64_t base = lookback<BLOCK>(words, g, spin_limit, dev_status, s_first, s_wave);
-            if (tid == 0) {
-                lb_store(&words[g], kLbPrefix | (base + ctot));
-                if (g == ngroups - 1) *t2_count = base + ctot;
-            }
-            for (uint32_t q = tid; q < (uint32_t)ctot; q += BLOCK) {
-                const uint64_t idx = base + q;
-                const uint64_t h = s_h[q];
-                if (idx < t2cap) t2[idx] = make_uint4(s_pa[q], s_pb[q], (uint32_t)h, (uint32_t)(h >> 32));
-            }
-        } else {
-        const uint64_t base = lookback<BLOCK>(words, g, spin_limit, dev_status, s_first, s_wave);
+        const uint64_t base = lookback<BLOCK>(words, g, spin_limit, dev_status, s_lb, s_wave);
         if (tid == 0) {
             lb_store(&words[g], kLbPrefix | (base + ctot));
             if (g == ngroups - 1) *t2_count = base + ctot;
         }
-        if (fast) {
-            for (uint64_t w = 0; w < ctot; w += PW) {
-                expand_pairs<ITEMS>(s_keys, s_nonces, tid * ITEMS, n, T, my_off, w, PW, s_pa, s_pb);
-                __syncthreads();
-                const uint32_t lim = (uint32_t)((ctot - w) < PW ? (ctot - w) : PW);
+        if (fast && ctot) {
+            // A group's pairs fit 32 bits (at most CAPMAX^2 / 2).  First slot of
+            // each record, then the slots in windows of SLOTS (one window unless
+            // the keys are crowded); counts are re-read from LDS per window,
+            // which keeps the hash loop's live registers few.
+            const uint32_t tot = (uint32_t)ctot, off = (uint32_t)my_off;
+            {
+                uint32_t r = off;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint32_t e = tid * ITEMS + i;
+                    if (e < n) {
+                        s_first[e] = r;
+                        r += s_cnt[e];
+                    }
+                }
+            }
 #pragma unroll 1
-                for (uint32_t q = tid; q < lim; q += BLOCK) {
-                    const uint32_t a = s_pa[q], b = s_pb[q];
-                    const uint64_t h = vxd::h2(key, a, b);
-                    const uint64_t idx = base + w + q;
-                    if (idx < t2cap) t2[idx] = make_uint4(a, b, (uint32_t)h, (uint32_t)(h >> 32));
+            for (uint32_t w0 = 0; w0 < tot; w0 += SLOTS) {
+                const uint32_t w1 = min(w0 + (uint32_t)SLOTS, tot);
+                uint32_t f = off;
+#pragma unroll 1
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint32_t e = tid * ITEMS + i;
+                    const uint32_t c = e < n ? (uint32_t)s_cnt[e] : 0u;
+                    const uint32_t a = max(f, w0), b = min(f + c, w1);
+                    for (uint32_t q = a; q < b; ++q) s_slot[q - w0] = (uint16_t)e;
+                    f += c;
+                }
+                __syncthreads();
+                const uint32_t nq = w1 - w0;
+                uint4 *out = t2 + base + w0;
+                const uint64_t room = base + w0 < t2cap ? t2cap - (base + w0) : 0;
+#pragma unroll 1
+                for (uint32_t qr = tid; qr < nq; qr += BLOCK) {
+                    const uint32_t e = s_slot[qr];
+                    const uint32_t j = e + 1 + (w0 + qr - s_first[e]);
+                    const uint32_t na = s_nonces[e], nb = s_nonces[j];
+                    const uint64_t h = vxd::h2(key, na, nb);
+                    if (qr < room) out[qr] = make_uint4(na, nb, (uint32_t)h, (uint32_t)(h >> 32));
                 }
                 __syncthreads();
             }
-        } else if (counted) {
-            // Slow path: one thread per record, pairs in canonical order by a
-            // sequential walk of the records (rare; correctness only).
-            __syncthreads();
+        } else if (!fast && ctot) {
+            // Slow path: pairs in canonical order by one thread's sequential
+            // walk (rare; correctness only).
             if (tid == 0) {
                 uint64_t idx = base;
                 for (uint32_t e = 0; e < n; ++e) {
@@ -1487,7 +1529,6 @@ __global__ __launch_bounds__(BLOCK) void k_sort_match(
                     }
                 }
             }
-        }
         }
         __syncthreads();
     }
@@ -1605,7 +1646,6 @@ constexpr int kFallbackGrid = 256;
 constexpr int kMatchBlock = 512;
 constexpr int kMatchCap = 2048;
 constexpr int kMatchSlots = 4096;
-constexpr int kMatchWindow = 2048;
 
 hipError_t launch_hash_filter(const uint32_t key_words[8], uint64_t n, uint32_t tiles, uint64_t chunk,
                               uint32_t pbits, uint32_t prefix, uint64_t *keys, uint32_t *nonces, uint64_t cap,
@@ -1869,20 +1909,33 @@ hipError_t launch_match_emit(const uint32_t key_words[8], const uint64_t *keys, 
     return hipGetLastError();
 }
 
-hipError_t launch_sort_match(const uint32_t key_words[8], uint64_t *keys, uint32_t *nonces, uint64_t *scr_keys,
-                             uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G, uint32_t cap,
-                             uint32_t *offsets, uint32_t n_total, uint64_t T, uint32_t *ticket,
-                             uint64_t *words, uint32_t *dev_status, void *t2, uint64_t t2cap,
-                             uint64_t *t2_count, uint32_t spin_limit, hipStream_t s) {
+hipError_t launch_group_match(const uint32_t key_words[8], uint64_t *keys, uint32_t *nonces, const uint64_t *in_keys,
+                              const uint32_t *in_nonces, const uint32_t *in_lo, const uint32_t *in_hi,
+                              uint64_t *scr_keys, uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G,
+                              uint32_t cap, uint32_t *offsets, uint32_t n_total, uint64_t T, uint32_t *ticket,
+                              uint64_t *words, uint32_t *dev_status, void *t2, uint64_t t2cap, uint64_t *t2_count,
+                              uint32_t spin_limit, hipStream_t s) {
     Key key;
     for (int i = 0; i < 8; ++i) key.w[i] = key_words[i];
-    static const uint32_t resident =
-        resident_grid(k_sort_match<kSortBlock, kGroupCapMax, kMatchWindow>, kSortBlock);
-    const uint32_t grid = min(1u << G, resident);
-    hipLaunchKernelGGL((k_sort_match<kSortBlock, kGroupCapMax, kMatchWindow>), dim3(grid), dim3(kSortBlock),
-                       0, s, key, keys, nonces, scr_keys, scr_nonces, gstart, G, cap, offsets, n_total, T,
-                       ticket, words, dev_status, (uint4 *)t2, t2cap, t2_count, spin_limit,
-                       (uint32_t)kFallbackMax);
+    const GroupIn in{in_keys, in_nonces, in_lo, in_hi};
+    // Group capacities up to kGroupCapFast take the kernel that fits four
+    // work-groups on a CU; larger ones the 3072-record kernel.
+    static const uint32_t resident_fast =
+        resident_grid(k_group_match<kSortBlock, kGroupCapFast, kMatchSlots>, kSortBlock);
+    static const uint32_t resident_max =
+        resident_grid(k_group_match<kSortBlock, kGroupCapMax, kMatchSlots>, kSortBlock);
+    const bool fast = cap <= (uint32_t)kGroupCapFast;
+    const uint32_t grid = min(1u << G, fast ? resident_fast : resident_max);
+    if (fast)
+        hipLaunchKernelGGL((k_group_match<kSortBlock, kGroupCapFast, kMatchSlots>), dim3(grid), dim3(kSortBlock), 0,
+                           s, key, keys, nonces, in, scr_keys, scr_nonces, gstart, G, cap, offsets, n_total, T,
+                           ticket, words, dev_status, (uint4 *)t2, t2cap, t2_count, spin_limit,
+                           (uint32_t)kFallbackMax);
+    else
+        hipLaunchKernelGGL((k_group_match<kSortBlock, kGroupCapMax, kMatchSlots>), dim3(grid), dim3(kSortBlock), 0,
+                           s, key, keys, nonces, in, scr_keys, scr_nonces, gstart, G, cap, offsets, n_total, T,
+                           ticket, words, dev_status, (uint4 *)t2, t2cap, t2_count, spin_limit,
+                           (uint32_t)kFallbackMax);
     return hipGetLastError();
 }
 

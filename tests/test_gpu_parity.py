@@ -273,7 +273,7 @@ def test_region_overflow_is_reported(vx):
 
 
 @pytest.mark.parametrize("tun", [dict(group_bits=12), dict(group_bits=14, pass1_bits=4, pass2_bits=5)])
-@pytest.mark.parametrize("pct", [25, 60])
+@pytest.mark.parametrize("pct", [10, 25])
 def test_region_overflow_with_matching_stays_bounded(vx, tun, pct):
     """Overflowing regions with the default threshold, so that the match
     walks the table: a gathered group holds only its own region's records,
