@@ -332,8 +332,9 @@ def bench_egress(args) -> dict:
 def bench_serving(args) -> dict:
     """Poisson plot requests (SplitMix64 seed 5), k uniform in 22..30, at
     about 80% of the plain one-at-a-time service rate; continuous batching
-    (4 slots, HBM-footprint admission) against a FIFO one-at-a-time server on
-    the same arrivals."""
+    (4 slots, HBM-footprint admission, jobs of k >= --big-k one at a time
+    beside the smaller ones) against the same without size classes and a
+    FIFO one-at-a-time server, all on the same arrivals."""
     import torch
     from paper_2606_14007_amd import serve
     from vx_inputs import serving_arrivals
@@ -348,21 +349,24 @@ def bench_serving(args) -> dict:
     arrivals = serving_arrivals(args.requests, rate)
     budget = int(args.budget_gb * 2**30)
 
-    def run(slots, max_bypass):
+    def run(label, slots, max_bypass, **kw):
         ex = serve.GpuExecutor(slots=slots, budget_bytes=budget)
-        st = serve.Server(ex, budget, slots=slots, max_bypass=max_bypass).run(
+        st = serve.Server(ex, budget, slots=slots, max_bypass=max_bypass, **kw).run(
             serve.jobs_from_arrivals(arrivals))
         del ex
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
+        if st.failed():
+            raise RuntimeError(f"{label}: {len(st.failed())} jobs reported a device problem")
+        log(f"{label}: p50 {st.percentile(50) * 1e3:.1f} ms, p99 {st.percentile(99) * 1e3:.1f} ms, "
+            f"{st.plots_per_hour():.0f} plots/h, peak resident {st.max_resident / 2**30:.1f} GiB, "
+            f"max concurrent {st.max_concurrent}")
         return st
 
-    cb = run(4, 8)
-    log(f"continuous batching: p50 {cb.percentile(50) * 1e3:.1f} ms, p99 {cb.percentile(99) * 1e3:.1f} ms, "
-        f"{cb.plots_per_hour():.0f} plots/h, peak resident {cb.max_resident / 2**30:.1f} GiB")
-    fifo = run(1, 0)
-    log(f"FIFO one at a time:  p50 {fifo.percentile(50) * 1e3:.1f} ms, p99 {fifo.percentile(99) * 1e3:.1f} ms, "
-        f"{fifo.plots_per_hour():.0f} plots/h")
+    cb = run(f"continuous batching, size classes (k >= {args.big_k}: one at a time)", 4, 8,
+             big_k=args.big_k, max_big=1)
+    flat = run("continuous batching, one class", 4, 8)
+    fifo = run("FIFO one at a time", 1, 0)
     return {
         "metric": "plot serving plots/hour (continuous batching, p50/p99 latency) vs FIFO",
         "value": round(cb.plots_per_hour(), 1),
@@ -373,9 +377,13 @@ def bench_serving(args) -> dict:
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"serving: {args.requests} Poisson requests (seed 5), k uniform in "
                                f"{k_lo}..{k_hi}, rate {rate:.1f}/s = 80% of the plain service rate",
-                   "slots": 4, "budget_gib": args.budget_gb, "parallelism": "single GPU"},
+                   "slots": 4, "big_k": args.big_k, "max_big": 1, "budget_gib": args.budget_gb,
+                   "parallelism": "single GPU"},
         "p50_latency_ms": round(cb.percentile(50) * 1e3, 2),
         "p99_latency_ms": round(cb.percentile(99) * 1e3, 2),
+        "one_class_p50_latency_ms": round(flat.percentile(50) * 1e3, 2),
+        "one_class_p99_latency_ms": round(flat.percentile(99) * 1e3, 2),
+        "one_class_plots_per_hour": round(flat.plots_per_hour(), 1),
         "fifo_p50_latency_ms": round(fifo.percentile(50) * 1e3, 2),
         "fifo_p99_latency_ms": round(fifo.percentile(99) * 1e3, 2),
         "fifo_plots_per_hour": round(fifo.plots_per_hour(), 1),
@@ -383,7 +391,9 @@ def bench_serving(args) -> dict:
         "max_concurrent": cb.max_concurrent,
         "plain_ms_per_k": {k: round(t * 1e3, 3) for k, t in per_k.items()},
         "p50_ms_per_k": {k: round(v["p50_ms"], 2) for k, v in cb.by_k().items()},
+        "p99_ms_per_k": {k: round(v["p99_ms"], 2) for k, v in cb.by_k().items()},
         "fifo_p50_ms_per_k": {k: round(v["p50_ms"], 2) for k, v in fifo.by_k().items()},
+        "fifo_p99_ms_per_k": {k: round(v["p99_ms"], 2) for k, v in fifo.by_k().items()},
     }
 
 
@@ -512,7 +522,9 @@ def main() -> int:
                          "egress: Table 2 streamed to plot files; chunked: one plot in chunks")
     ap.add_argument("--chunk-k", type=int, default=32, help="chunked: k of the plot")
     ap.add_argument("--chunk-bits", type=int, default=1, help="chunked: 2^c chunks")
-    ap.add_argument("--requests", type=int, default=400, help="serving: number of requests")
+    ap.add_argument("--requests", type=int, default=1000, help="serving: number of requests")
+    ap.add_argument("--big-k", type=int, default=28,
+                    help="serving: jobs with k at or above this run one at a time")
     ap.add_argument("--egress-k", type=int, default=28, help="egress: k of every plot")
     ap.add_argument("--egress-dir", default=None, help="egress: write plot files here (default: discard)")
     ap.add_argument("--egress-slots", type=int, default=4, help="egress: pinned staging buffers")

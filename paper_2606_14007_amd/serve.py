@@ -13,6 +13,14 @@ go first ("backfill"), which keeps the GPU busy without letting a large job
 starve: a job that has been passed over `max_bypass` times blocks backfill
 until it runs.
 
+Size classes (optional): jobs with k >= `big_k` are "big" and at most
+`max_big` of them run at once, in arrival order among themselves; smaller
+jobs take the other slots.  Running every job beside every other stretches
+the largest jobs the most (the device is shared, and a large plot already
+fills it), which raises the tail latency above a one-at-a-time server's;
+keeping the big jobs one at a time bounds their stretch to the small jobs'
+share of the work, while small jobs still skip the queue of big ones.
+
 The scheduler is written against a small executor interface (footprint /
 submit / poll / release) so that the same loop drives the GPU executor
 below or a simulated one in CPU tests.
@@ -104,9 +112,12 @@ class Server:
     def __init__(self, executor: Executor, budget_bytes: int, slots: int = 4,
                  max_bypass: int = 8, clock: Callable[[], float] = time.perf_counter,
                  sleep: Callable[[float], None] = time.sleep,
-                 on_done: Optional[Callable[[Job], None]] = None):
+                 on_done: Optional[Callable[[Job], None]] = None,
+                 big_k: Optional[int] = None, max_big: int = 1):
         if slots < 1:
             raise ValueError("need at least one slot")
+        if big_k is not None and max_big < 1:
+            raise ValueError("max_big must be at least 1")
         self.ex = executor
         self.budget = int(budget_bytes)
         self.slots = slots
@@ -114,6 +125,11 @@ class Server:
         self.clock = clock
         self.sleep = sleep
         self.on_done = on_done
+        self.big_k = big_k
+        self.max_big = max_big
+
+    def _big(self, job: Job) -> bool:
+        return self.big_k is not None and job.k >= self.big_k
 
     def run(self, jobs: Sequence[Job]) -> Stats:
         """Serve `jobs` (arrival times relative to now) to completion."""
@@ -149,15 +165,20 @@ class Server:
                     done.append(job)
                     progressed = True
             # admissions, in arrival order with bounded backfill
+            n_big = sum(1 for j in running.values() if self._big(j))
             i = 0
             while free_slots and i < len(waiting):
                 job = waiting[i]
                 need = self.ex.footprint(job)
+                if self._big(job) and n_big >= self.max_big:
+                    i += 1          # its class is full: waits for a big job to finish
+                    continue
                 if self.ex.can_admit(job, resident, self.budget):
                     slot = free_slots.pop(0)
                     job.admitted = self.clock() - t0
                     job.handle = self.ex.submit(job, slot)
                     running[slot] = job
+                    n_big += self._big(job)
                     resident += need
                     max_resident = max(max_resident, resident)
                     max_conc = max(max_conc, len(running))
@@ -168,7 +189,8 @@ class Server:
                 if job.bypassed >= self.max_bypass:
                     break
                 for later in waiting[i + 1:]:
-                    if self.ex.can_admit(later, resident, self.budget):
+                    if (not (self._big(later) and n_big >= self.max_big)
+                            and self.ex.can_admit(later, resident, self.budget)):
                         job.bypassed += 1
                         break
                 i += 1

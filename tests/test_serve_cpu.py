@@ -178,3 +178,64 @@ def test_failed_jobs_are_reported():
     jobs = jobs_from_arrivals(serving_arrivals(30, rate_per_s=500.0, k_lo=16, k_hi=20))
     st = Server(ex, 1 << 40, slots=2, clock=c.now, sleep=c.sleep).run(jobs)
     assert [j.jid for j in st.failed()] == [j for j in range(30) if j % 7 == 3]
+
+
+class ClassCounting(FakeExecutor):
+    """Records how many jobs with k >= big_k ran at once and their order."""
+
+    def __init__(self, clock, big_k, **kw):
+        super().__init__(clock, **kw)
+        self.big_k = big_k
+        self.big_now = 0
+        self.big_peak = 0
+        self.big_order = []
+
+    def submit(self, job, slot):
+        h = super().submit(job, slot)
+        if job.k >= self.big_k:
+            self.big_now += 1
+            self.big_peak = max(self.big_peak, self.big_now)
+            self.big_order.append(job.jid)
+        return h
+
+    def release(self, job):
+        super().release(job)
+        if job.k >= self.big_k:
+            self.big_now -= 1
+
+
+@pytest.mark.parametrize("max_big", [1, 2])
+def test_size_classes_cap_big_jobs_and_keep_their_order(max_big):
+    c = Clock()
+    ex = ClassCounting(c, big_k=20, parallel=1.0)
+    jobs = jobs_from_arrivals(serving_arrivals(300, rate_per_s=300.0, k_lo=14, k_hi=22))
+    st = Server(ex, 1 << 40, slots=4, clock=c.now, sleep=c.sleep, big_k=20, max_big=max_big).run(jobs)
+    assert len(st.jobs) == 300
+    assert ex.big_peak == max_big
+    assert ex.big_order == sorted(ex.big_order)
+    assert st.max_concurrent <= 4
+
+
+def test_size_classes_beat_fifo_at_both_percentiles():
+    """The serving mix in miniature (sizes 2^-6 .. 2^2 ms, a 64x spread as
+    k = 22..30 has 256x) at about 80% load on a device shared evenly by
+    running jobs: with one big job at a time, small jobs skip the queue of
+    big ones (a far lower median) and the tail stays below FIFO's."""
+    mean = sum(2.0 ** (k - 20) for k in range(14, 23)) / 9 * 1e-3
+    arr = serving_arrivals(1000, rate_per_s=0.8 / mean, k_lo=14, k_hi=22)
+
+    def run(slots, **kw):
+        c = Clock()
+        return Server(FakeExecutor(c, parallel=1.0), 1 << 40, slots=slots, clock=c.now,
+                      sleep=c.sleep, **kw).run(jobs_from_arrivals(arr))
+
+    fifo = run(1, max_bypass=0)
+    classes = run(4, big_k=20, max_big=1)
+    assert classes.percentile(50) < 0.5 * fifo.percentile(50)
+    assert classes.percentile(99) < fifo.percentile(99)
+    assert classes.plots_per_hour() >= 0.99 * fifo.plots_per_hour()
+
+
+def test_size_classes_reject_zero_big_slots():
+    with pytest.raises(ValueError):
+        Server(FakeExecutor(Clock()), 1 << 40, big_k=20, max_big=0)
