@@ -33,6 +33,18 @@ def vx():
     return m
 
 
+@pytest.fixture(autouse=True)
+def _release_device_memory():
+    """Each test here holds up to ~250 GB; hand the cached blocks back
+    between tests so the next one finds the whole HBM free."""
+    yield
+    import gc
+    gc.collect()
+    if torch.cuda.is_available():
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
+
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("k", [27, 29])  # two passes (8-8), three passes (4-7-7)
 def test_full_bit_exact(vx, k):
@@ -197,7 +209,10 @@ def test_k32_in_two_chunks_sampled_and_properties(vx, mode):
     else:
         b = vx.alloc_chunk(k, c)
     seen = torch.zeros(1 << k, dtype=torch.bool, device=dev)
-    rank = torch.empty(1 << k, dtype=torch.int64, device=dev)  # nonce -> position in its chunk
+    # nonce -> position in its chunk, stored as int32 offset by -2^31 (a chunk
+    # holds fewer than 2^32 records; the shift keeps the order)
+    rank = torch.empty(1 << k, dtype=torch.int32, device=dev)
+    OFS = 1 << 31
     step = 1 << 28
     total_m = 0
     t1_pos = t2_pos = 0
@@ -230,7 +245,7 @@ def test_k32_in_two_chunks_sampled_and_properties(vx, mode):
             ni = non[lo:lo + step].long() & 0xFFFFFFFF
             assert not bool(seen[ni].any())
             seen[ni] = True
-            rank[ni] = torch.arange(lo, min(lo + step, m), dtype=torch.int64, device=dev)
+            rank[ni] = (torch.arange(lo, min(lo + step, m), dtype=torch.int64, device=dev) - OFS).int()
 
         print(f"k=32: chunk {r}: bucket offsets", flush=True)
         counts = torch.zeros(1 << 24, dtype=torch.int64, device=dev)
@@ -259,12 +274,12 @@ def test_k32_in_two_chunks_sampled_and_properties(vx, mode):
         print(f"k=32: chunk {r}: Table-2 validity and canonical order", flush=True)
         t2 = b.t2[:cnt]
         prev = None
-        ra_parts = []
+        ra_all = torch.empty(cnt, dtype=torch.int32, device=dev)  # ra - 2^31 of every record
         for lo in range(0, cnt, step):
             rec = t2[lo:lo + step]
             na = (rec[:, 0] & 0xFFFFFFFF).long()
             nb = ((rec[:, 0] >> 32) & 0xFFFFFFFF).long()
-            ra, rb = rank[na], rank[nb]
+            ra, rb = rank[na].long() + OFS, rank[nb].long() + OFS
             assert bool(seen[na].all()) and bool(seen[nb].all())
             assert bool(torch.all((ra < m) & (rb < m)))
             ka, kb = keys[ra], keys[rb]
@@ -277,9 +292,8 @@ def test_k32_in_two_chunks_sampled_and_properties(vx, mode):
             if prev is not None:
                 assert int(comp[0]) > prev
             prev = int(comp[-1])
-            ra_parts.append(ra)
-        ra_all = torch.cat(ra_parts)
-        del ra_parts
+            ra_all[lo:lo + step] = (ra - OFS).int()
+            del rec, na, nb, ra, rb, ka, kb, d, comp
 
         print(f"k=32: chunk {r}: sampled buckets against the oracle", flush=True)
         mine = [(i, bk) for i, bk in enumerate(s.buckets) if b0 <= bk < b1]
@@ -293,8 +307,10 @@ def test_k32_in_two_chunks_sampled_and_properties(vx, mode):
             assert np.array_equal(vx.u32(non[a:e]), s.t1_nonces[t1_pos:t1_pos + nbk])
             t1_pos += nbk
             pc = int(s.pair_counts[i])
-            p_lo = int(torch.searchsorted(ra_all, torch.tensor([a], device=dev), side="left"))
-            p_hi = int(torch.searchsorted(ra_all, torch.tensor([e], device=dev), side="left"))
+            p_lo = int(torch.searchsorted(ra_all, torch.tensor([a - OFS], dtype=torch.int32, device=dev),
+                                          side="left"))
+            p_hi = int(torch.searchsorted(ra_all, torch.tensor([e - OFS], dtype=torch.int32, device=dev),
+                                          side="left"))
             assert p_hi - p_lo == pc
             got = vx.t2_records(t2[p_lo:p_hi], pc)
             assert np.array_equal(got, s.t2[t2_pos:t2_pos + pc])
