@@ -207,6 +207,26 @@ vx_status vx_plot_with_events(const vx_plot_params *params, const vx_plot_buffer
 vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buffers,
                         uint32_t n, const vx_tuning *tuning, void *stream);
 
+/* Bytes of the workspace array that libvx holds on each device for
+ * vx_plot_noalloc (enough for k <= 22 at the default tuning). */
+#define VX_NOALLOC_WORKSPACE_BYTES (128u << 20)
+
+/* vx_plot for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * workspace is a fixed array of VX_NOALLOC_WORKSPACE_BYTES that the library
+ * holds on each device it runs on, from the first call on that device until
+ * the process ends; the call itself allocates nothing.  buffers->workspace
+ * must be NULL and workspace_bytes 0; the other buffers are the caller's, as
+ * for vx_plot, and the outputs equal vx_plot's.  A plot whose workspace
+ * (vx_workspace_bytes) exceeds the array returns VX_ERR_WORKSPACE and
+ * enqueues nothing.  d_status: NULL, or one caller-owned device u32 that
+ * receives the plot's device status word (VX_DEV_STATUS_*) at its end.
+ * Every call on one device shares that device's array: calls that can
+ * overlap on one device (other streams, other host threads) race and must
+ * be serialised by the caller. */
+vx_status vx_plot_noalloc(const vx_plot_params *params, const vx_plot_buffers *buffers,
+                          const vx_tuning *tuning, uint32_t *d_status, void *stream);
+
 /* ------------------------------------------------------------------------
  * Chunked plots.  A plot can be made in 2^chunk_bits chunks of its bucket
  * space: chunk r holds the buckets whose top chunk_bits bits equal r

@@ -16,7 +16,8 @@ from ._native import (VX_BUCKET_BITS, VX_CALL_BUCKET_SORT, VX_CALL_MATCH, VX_CAL
                       vx_egress_create, vx_egress_submit, vx_egress_wait, vx_egress_bytes,
                       vx_egress_destroy, vx_chunk_capacity_hint, vx_chunk_workspace_bytes,
                       vx_plot_chunk, vx_stage_bytes, vx_stage_plot, vx_staged_chunk_workspace_bytes,
-                      vx_plot_staged_chunk, vx_egress_submit_chunk)
+                      vx_plot_staged_chunk, vx_egress_submit_chunk, vx_plot_noalloc,
+                      VX_NOALLOC_WORKSPACE_BYTES)
 from .plotter import (T2_DTYPE, ChunkBuffers, PlotBuffers, PlotOverflow, Stage, alloc_chunk, alloc_plot,
                       alloc_stage, check_plot,
                       alloc_staged_chunk, bucket_sort, device_status, plot_staged_chunk, stage_plot, staged_chunks,

@@ -79,6 +79,8 @@ SYMBOLS = [
                                       C.POINTER(VxTuning), C.POINTER(C.c_void_p), C.c_void_p]),
     ("vx_plot_batch", C.c_int, [C.POINTER(VxPlotParams), C.POINTER(VxPlotBuffers), C.c_uint32,
                                 C.POINTER(VxTuning), C.c_void_p]),
+    ("vx_plot_noalloc", C.c_int, [C.POINTER(VxPlotParams), C.POINTER(VxPlotBuffers), C.POINTER(VxTuning),
+                                  C.c_void_p, C.c_void_p]),
     ("vx_read_status", C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.c_void_p]),
     ("vx_last_error", C.c_char_p, []),
     ("vx_chunk_capacity_hint", C.c_uint64, [C.c_uint32, C.c_uint32, C.c_uint64, C.POINTER(C.c_uint64)]),
@@ -216,6 +218,16 @@ def vx_plot_batch(params_list, buffers_list, tunings=None, stream: int = 0) -> N
     B = (VxPlotBuffers * n)(*buffers_list)
     T = None if tunings is None else (VxTuning * n)(*tunings)
     _check(lib().vx_plot_batch(P, B, n, T, stream), "vx_plot_batch")
+
+
+VX_NOALLOC_WORKSPACE_BYTES = 128 << 20
+
+
+def vx_plot_noalloc(params: VxPlotParams, buffers: VxPlotBuffers, tuning=None, d_status: int = 0,
+                    stream: int = 0) -> None:
+    """buffers.workspace must be 0 (the library's own array is used)."""
+    _check(lib().vx_plot_noalloc(C.byref(params), C.byref(buffers), _tref(tuning), d_status or None, stream),
+           "vx_plot_noalloc")
 
 
 def vx_read_status(d_ws: int, stream: int = 0) -> int:

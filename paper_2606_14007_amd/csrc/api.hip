@@ -1218,6 +1218,84 @@ vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buf
     return st;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// vx_plot_noalloc: vx_plot whose workspace is a fixed array the library
+// holds on every device it runs on, for callers that cannot allocate.  In
+// host code the array's name is no device address: every host use goes
+// through the address hipGetSymbolAddress gives for the current device.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[VX_NOALLOC_WORKSPACE_BYTES];
+
+namespace {
+
+struct ScratchSlot {
+    bool ready = false;
+    void *ptr = nullptr;
+};
+
+ScratchSlot g_scratch[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// The current device's copy of `scratch`, looked up once per device.
+vx_status scratch_for_current_device(void **out) {
+    int dev = 0;
+    VX_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(VX_ERR_UNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> guard(g_scratch_mu);
+    ScratchSlot &sl = g_scratch[dev];
+    if (!sl.ready) {
+        void *p = nullptr;
+        VX_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!p || !aligned(p, 256)) return fail(VX_ERR_DEVICE, "the library's workspace array has no usable address");
+        sl.ptr = p;
+        sl.ready = true;
+    }
+    *out = sl.ptr;
+    return VX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vx_status vx_plot_noalloc(const vx_plot_params *params, const vx_plot_buffers *buffers, const vx_tuning *tuning,
+                          uint32_t *d_status, void *stream) {
+    if (!buffers) return fail(VX_ERR_INVALID_ARG, "buffers is NULL");
+    if (buffers->workspace || buffers->workspace_bytes)
+        return fail(VX_ERR_INVALID_ARG,
+                    "vx_plot_noalloc uses the library's own workspace: buffers->workspace must be NULL and "
+                    "workspace_bytes 0");
+    if (d_status && !aligned(d_status, 4)) return fail(VX_ERR_INVALID_ARG, "misaligned d_status");
+    Plan P;
+    vx_status st = make_plan(params, tuning, &P);
+    if (st != VX_OK) return st;
+    const size_t need = layout(P, VX_CALL_PLOT).total;
+    if (need > (size_t)VX_NOALLOC_WORKSPACE_BYTES) {
+        char msg[200];
+        snprintf(msg, sizeof(msg),
+                 "this plot needs %zu workspace bytes; vx_plot_noalloc holds %zu (k <= 22 at the default "
+                 "tuning)", need, (size_t)VX_NOALLOC_WORKSPACE_BYTES);
+        return fail(VX_ERR_WORKSPACE, msg);
+    }
+    void *ws = nullptr;
+    st = scratch_for_current_device(&ws);
+    if (st != VX_OK) return st;
+    vx_plot_buffers b = *buffers;
+    b.workspace = ws;
+    b.workspace_bytes = VX_NOALLOC_WORKSPACE_BYTES;
+    // No pipelining: its second stream would be created on first use.
+    st = plot_impl(params, &b, tuning, nullptr, stream, false);
+    if (st != VX_OK) return st;
+    if (d_status)
+        VX_HIP(hipMemcpyAsync(d_status, ws, sizeof(uint32_t), hipMemcpyDeviceToDevice, (hipStream_t)stream),
+               "status copy");
+    g_err[0] = 0;
+    return VX_OK;
+}
+
 vx_status vx_read_status(const void *d_workspace, uint32_t *h_status, void *stream) {
     if (!d_workspace || !h_status) return fail(VX_ERR_INVALID_ARG, "NULL pointer");
     hipStream_t s = (hipStream_t)stream;

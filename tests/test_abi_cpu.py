@@ -112,3 +112,21 @@ def test_region_pct_limits():
     assert 0 < small < base
     assert vx.vx_workspace_bytes(p, vx.VX_CALL_PLOT, vx.make_tuning(region_pct=1001)) == 0
 
+
+
+def test_noalloc_checks_on_host():
+    """vx_plot_noalloc refuses, before any device work, a plot whose workspace
+    exceeds the library's array (k = 23 at the default tuning) and a caller
+    workspace; k = 22 fits."""
+    assert vx.vx_workspace_bytes(vx.make_params(bytes(32), 22), vx.VX_CALL_PLOT) <= vx.VX_NOALLOC_WORKSPACE_BYTES
+    p = vx.make_params(bytes(32), 23)
+    assert vx.vx_workspace_bytes(p, vx.VX_CALL_PLOT) > vx.VX_NOALLOC_WORKSPACE_BYTES
+    b = N.VxPlotBuffers()
+    b.t1_keys, b.t1_nonces, b.bucket_offsets, b.t2_count = 256, 512, 1024, 2048
+    with pytest.raises(vx.VxError) as e:
+        vx.vx_plot_noalloc(p, b)
+    assert e.value.status == N.VX_ERR_WORKSPACE
+    b.workspace, b.workspace_bytes = 4096, 1 << 20
+    with pytest.raises(vx.VxError) as e:
+        vx.vx_plot_noalloc(vx.make_params(bytes(32), 12), b)
+    assert e.value.status == N.VX_ERR_INVALID_ARG
