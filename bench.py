@@ -626,16 +626,24 @@ def main() -> int:
     h2_ins = opcount.valu_per_h2() * t2n
     valu_peak = opcount.MI355X_VALU_LANE_OPS_PER_S
     hbm_peak = opcount.MI355X_HBM_BYTES_PER_S
-    npass = vx.vx_partition_passes(vx.make_params(derive_key(0), k))
+    npass = vx.vx_partition_passes(params, tun)
+    hslices = vx.vx_hash_slices(params, tun)
     # With two or more passes the hash kernel also does the first pass (its
-    # stage is then only the region scan); a one-pass plot hashes alone.
+    # stage is then only the region scan); a one-pass plot hashes alone.  A
+    # plot hashed in slices also does the second pass in the hash launches.
     fused_first = npass >= 2
+    in_hash = 0 if not fused_first else (2 if hslices > 1 else 1)
     kernel_of = dict(KERNEL_OF_STAGE)
     if not fused_first:
         kernel_of.update(hash="k_hash_table1", partition1="k_digit_hist + k_scatter (pass 1)")
+    if hslices > 1:
+        kernel_of.update(hash=f"k_hash_pass x{hslices + 1} (hash in {hslices} slices + the second pass)",
+                         partition1="k_region_scan_slices + k_region_bounds + k_colscan (pass 2 is in the hash)",
+                         partition2="k_scatter claiming regions + k_region_bounds + k_colscan (third pass)")
     algo_bytes = {
         "partition1": 0 if fused_first else n * (8 + 12),  # read key, write key+nonce
-        "partition2": (npass - 1) * n * (12 + 12),  # each later pass reads and writes key+nonce
+        # each later pass reads and writes key+nonce
+        "partition2": max(0, npass - max(in_hash, 1)) * n * (12 + 12),
         # read and write key+nonce, offsets, one pair-count byte per record
         "group_sort": n * (12 + 12 + 1) + (vx.VX_NUM_BUCKETS + 1) * 4,
         "chunk_sums": n * 1,                     # read the count bytes
@@ -697,8 +705,8 @@ def main() -> int:
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": f"k={k} single plot", "k": k, "nonces": n, "key_seed": 0,
-                   "threshold": f"2^{64 - k}", "buckets": 1 << 24,
-                   "parallelism": "single GPU"},
+                   "threshold": f"2^{64 - k}", "buckets": 1 << 24, "partition_passes": npass,
+                   "hash_slices": hslices, "parallelism": "single GPU"},
         "blake3_hashes_per_s": round((n + t2n) / plot_s, 1),
         "plots_per_hour": round(3600.0 / plot_s, 1),
         "table2_records": t2n,

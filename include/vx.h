@@ -125,6 +125,10 @@ typedef struct {
                                   the default (0 = 100).  The one exception to "no output
                                   changes": below 100 regions can overflow, which sets
                                   VX_DEV_STATUS_REGION_OVERFLOW (for tests of that report) */
+    uint32_t hash_slices;      /* vx_plot: 1 = hash the plot in one launch; 2..16 = hash it in that
+                                  many nonce slices, each launch filing the previous slice's records
+                                  by the second digit beside the next slice's hash (plots whose two
+                                  leading digits fit 7 bits each); 0 = the default for k */
 } vx_tuning;
 
 enum { VX_CALL_BUCKET_SORT = 1, VX_CALL_MATCH = 2, VX_CALL_PLOT = 3 };
@@ -141,6 +145,13 @@ size_t vx_workspace_bytes(const vx_plot_params *params, int which_call, const vx
  * what a caller needs to account the bytes a sort moves.  No device work.
  * Returns 0 for invalid params or tuning. */
 uint32_t vx_partition_passes(const vx_plot_params *params, const vx_tuning *tuning);
+
+/* Nonce slices in which vx_plot hashes a plot with these params and tuning
+ * (may be NULL): 1 = one launch; s >= 2 = s launches, each filing the
+ * previous slice's records by the second digit beside its own hash, so the
+ * first two partition passes are done by then.  No device work.  Returns 0
+ * for invalid params or tuning. */
+uint32_t vx_hash_slices(const vx_plot_params *params, const vx_tuning *tuning);
 
 /* A Table-2 capacity that holds |Table 2| of a k-plot with threshold T with
  * overwhelming probability (expectation plus a generous margin). */

@@ -45,6 +45,14 @@ constexpr uint32_t kMaxSlices = 16;
 // partition's work-groups do not share CUs in practice), and the pipelined
 // plot was slower than the sequential one, so pipelining is opt-in.
 constexpr uint32_t kDefaultSlices = 1;
+// A plot hashed in slices files each slice's records by the second digit
+// beside the next slice's hash (run_sliced_front).
+constexpr uint32_t kMaxHashSlices = 16;
+// Measured (one box, median plot time, 1 / 4 / 8 / 16 slices): k=31 112.7 /
+// 110.2 / 108.6 / 107.9 ms, k=30 57.9 / 55.3 / 54.5 / 54.0 ms; at k <= 29
+// the sliced digits (a seven-bit second digit, hence a third pass below
+// k = 29) made plots slower (k=29 29.5 -> 34.0 ms, k=28 13.8 -> 18.4 ms).
+uint32_t default_hash_slices(uint32_t k) { return k >= 30 ? 16 : 1; }
 
 struct Plan {
     uint32_t k = 0;
@@ -63,7 +71,8 @@ struct Plan {
     bool fused = false;      // plot: one fused sort + match kernel instead of two
     uint32_t slices = 1;     // plot: pipeline slices of the passes after the first (1 = none)
     bool hs = false;         // plot: region passes (the hash does the first; see make_plan)
-    uint32_t R[kMaxPasses] = {};  // hs: records per region of each pass
+    uint32_t R[kMaxPasses] = {};  // hs: records per region of each pass (pass 0: per hash slice)
+    uint32_t hq = 1;         // plot: nonce slices of the hash (>= 2: see run_sliced_front)
     int staged = -1;         // >= 0: one chunk (of 2^staged) of a staged plot; see vx_stage_plot
 };
 
@@ -132,27 +141,62 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
         P.slices = 1;
     }
     const bool hs_ok = (!records || staged >= 0) && !t->separate_hash;
+    if (t->hash_slices > kMaxHashSlices) return fail(VX_ERR_UNSUPPORTED, "hash_slices must be at most 16");
+    // Hash slices: whole plots whose first two digits fit the sliced
+    // kernel's 7 bits; the pipelined tail keeps its own split.
+    uint32_t hq = t->hash_slices ? t->hash_slices : default_hash_slices(P.k);
+    if (records || staged >= 0 || t->separate_hash || P.slices > 1 || P.G < 2 ||
+        P.G > 2u * vxk::kHashPassMaxBits + (uint32_t)vxk::kHashPassMaxBits)
+        hq = 1;
+    // The digits of the passes for hq hash slices (see below).
+    auto split = [&](uint32_t q, uint32_t &d0, uint32_t &d1, uint32_t &d2) -> vx_status {
+        if (q > 1) {
+            // Both digits of the sliced kernel take at most 7 bits.  Up to 14
+            // group bits they are the only passes; above, the third (a
+            // claiming scatter of its own) takes 7 bits and the hash the rest.
+            if (P.G <= 2u * vxk::kHashPassMaxBits) {
+                d0 = (P.G + 1) / 2; d1 = P.G - d0; d2 = 0;
+            } else {
+                d1 = vxk::kHashPassMaxBits;
+                d2 = std::min<uint32_t>(vxk::kHashPassMaxBits, P.G - d1 - 1);
+                d0 = P.G - d1 - d2;
+            }
+        } else if (P.G <= 9) {
+            d0 = P.G; d1 = 0; d2 = 0;
+        } else if (P.slices > 1 && P.G >= 13) {
+            d0 = P.G - 12; d1 = 6; d2 = 6;
+        } else if (P.G <= 17) {
+            d0 = (P.G + 1) / 2;
+            if (hs_ok) d0 = std::min(d0, 8u);
+            d1 = P.G - d0; d2 = 0;
+        } else if (hs_ok && P.G <= 20) {
+            d0 = P.G - 14; d1 = 7; d2 = 7;
+        } else {
+            d0 = hs_ok ? 6 : 7; d1 = (P.G - d0 + 1) / 2; d2 = P.G - d0 - d1;
+        }
+        if (t->pass1_bits || t->pass2_bits) {
+            d0 = t->pass1_bits ? t->pass1_bits : d0;
+            if (d0 > P.G) return fail(VX_ERR_UNSUPPORTED, "pass1_bits must be at most group_bits");
+            const uint32_t rest = P.G - d0;
+            if (t->pass2_bits)
+                d1 = t->pass2_bits;
+            else if (q > 1)
+                d1 = std::min<uint32_t>(rest, vxk::kHashPassMaxBits);
+            else
+                d1 = rest <= (uint32_t)vxk::kMaxDigitBits ? rest : (rest + 1) / 2;
+            if (d1 > rest) return fail(VX_ERR_UNSUPPORTED, "pass1_bits + pass2_bits must be at most group_bits");
+            d2 = rest - d1;
+        }
+        return VX_OK;
+    };
     uint32_t d0, d1, d2;
-    if (P.G <= 9) {
-        d0 = P.G; d1 = 0; d2 = 0;
-    } else if (P.slices > 1 && P.G >= 13) {
-        d0 = P.G - 12; d1 = 6; d2 = 6;
-    } else if (P.G <= 17) {
-        d0 = (P.G + 1) / 2;
-        if (hs_ok) d0 = std::min(d0, 8u);
-        d1 = P.G - d0; d2 = 0;
-    } else if (hs_ok && P.G <= 20) {
-        d0 = P.G - 14; d1 = 7; d2 = 7;
-    } else {
-        d0 = hs_ok ? 6 : 7; d1 = (P.G - d0 + 1) / 2; d2 = P.G - d0 - d1;
-    }
-    if (t->pass1_bits || t->pass2_bits) {
-        d0 = t->pass1_bits ? t->pass1_bits : d0;
-        if (d0 > P.G) return fail(VX_ERR_UNSUPPORTED, "pass1_bits must be at most group_bits");
-        const uint32_t rest = P.G - d0;
-        d1 = t->pass2_bits ? t->pass2_bits : (rest <= (uint32_t)vxk::kMaxDigitBits ? rest : (rest + 1) / 2);
-        if (d1 > rest) return fail(VX_ERR_UNSUPPORTED, "pass1_bits + pass2_bits must be at most group_bits");
-        d2 = rest - d1;
+    st = split(hq, d0, d1, d2);
+    if (st != VX_OK) return st;
+    if (hq > 1 && (!hs_ok || d0 > (uint32_t)vxk::kHashPassMaxBits || d1 == 0 ||
+                   d1 > (uint32_t)vxk::kHashPassMaxBits || (P.n >> d0) < hq)) {
+        hq = 1;  // beyond the sliced kernel: the plot hashes in one launch
+        st = split(hq, d0, d1, d2);
+        if (st != VX_OK) return st;
     }
     const uint32_t ds[kMaxPasses] = {d0, d1, d2};
     P.npass = 0;
@@ -217,6 +261,20 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
         if (t->region_pct) P.R[i] = std::max<uint32_t>(1, (uint32_t)((uint64_t)P.R[i] * t->region_pct / 100));
         if (bits < cbits || ((uint64_t)P.R[i] << (bits - cbits)) >= (1ull << 32)) P.hs = false;
     }
+    // Hash slices need the region passes, two or more passes, and both
+    // leading digits within the sliced kernel's width; otherwise the plot
+    // hashes in one launch.  Slice s hashes nonces [s * n / hq, (s + 1) * n /
+    // hq) into 2^D[0] regions of its own, of R[0] records each.
+    if (hq > 1 && P.hs && P.npass >= 2 && P.D[0] <= (uint32_t)vxk::kHashPassMaxBits &&
+        P.D[1] <= (uint32_t)vxk::kHashPassMaxBits && (P.n >> P.D[0]) >= hq) {
+        const double mean = (double)(((P.n + hq - 1) / hq + (1ull << P.D[0]) - 1) >> P.D[0]);
+        uint32_t r0 = (uint32_t)(mean + 8.0 * std::sqrt(mean)) + vxk::kHashScatterSub;
+        if (t->region_pct) r0 = std::max<uint32_t>(1, (uint32_t)((uint64_t)r0 * t->region_pct / 100));
+        if (((uint64_t)r0 * hq << P.D[0]) < (1ull << 32)) {
+            P.hq = hq;
+            P.R[0] = r0;
+        }
+    }
     if (staged >= 0 && !P.hs)
         return fail(VX_ERR_UNSUPPORTED,
                     "staged plots need two or more partition passes, a first digit of at most 8 bits and at "
@@ -246,7 +304,7 @@ struct Layout {
 };
 
 // Workspace header: u32 words zeroed at the start of every call.
-constexpr uint32_t kHeaderWords = 64;
+constexpr uint32_t kHeaderWords = 96;
 constexpr uint32_t kHdrStatus = 0;       // device status bits
 constexpr uint32_t kHdrFusedTicket = 2;  // group ticket of the fused sort + match
 constexpr uint32_t kHdrAcc = 4;          // u64 (words 4, 5): Table-2 records of the slices scanned so far
@@ -254,7 +312,8 @@ constexpr uint32_t kHdrChunkCount = 6;   // u64 (words 6, 7): records a chunk's 
 constexpr uint32_t kHdrOvf = 8;          // per slice: oversized groups found
 constexpr uint32_t kHdrSortTicket = 8 + kMaxSlices;       // per slice: group ticket of the sort
 constexpr uint32_t kHdrEmitTicket = 8 + 2 * kMaxSlices;   // per slice: chunk ticket of the match
-static_assert(kHdrEmitTicket + kMaxSlices <= kHeaderWords, "header holds every slice's words");
+constexpr uint32_t kHdrHashPassTicket = 8 + 3 * kMaxSlices;  // per launch of a sliced hash
+static_assert(kHdrHashPassTicket + kMaxHashSlices + 1 <= kHeaderWords, "header holds every slice's words");
 constexpr uint32_t kLookbackSpinLimit = 1u << 20;
 
 constexpr int kCallChunk = 4;        // internal: the workspace of vx_plot_chunk
@@ -290,7 +349,7 @@ Layout layout(const Plan &P, int which) {
     const uint32_t cbits = staged ? (uint32_t)P.staged : 0;
     uint64_t cap_even = staged ? 0 : P.n, cap_odd = staged ? 0 : P.n;
     for (uint32_t i = staged ? 1 : 0; hs && i < P.npass; ++i) {
-        const uint64_t c = (uint64_t)P.R[i] << (P.pre[i] + P.D[i] - cbits);
+        const uint64_t c = ((uint64_t)P.R[i] << (P.pre[i] + P.D[i] - cbits)) * (i == 0 ? P.hq : 1);
         uint64_t &m = (i % 2 == 0) ? cap_even : cap_odd;
         m = std::max(m, c);
     }
@@ -298,7 +357,7 @@ Layout layout(const Plan &P, int which) {
     if (hs) L.reg_nonces = take(cap_even * 4);
     for (uint32_t i = 0; hs && i < P.npass; ++i) {
         const size_t nr = (size_t)1 << (P.pre[i] + P.D[i]);
-        L.fill[i] = take(nr * 4);
+        L.fill[i] = take(nr * 4 * (i == 0 ? P.hq : 1));
         L.seg_lo[i] = take(nr * 4);
         L.seg_hi[i] = take(nr * 4);
     }
@@ -421,6 +480,25 @@ PassBufs pass_bufs(const Plan &P, const Layout &L, void *ws, const uint64_t *key
     return B;
 }
 
+// After a region pass i >= 1 over input segments [sa, sb): the clamp of its
+// regions' counts into their bounds, and their scan (one row per segment, on
+// top of the segments' bases) into the group starts.
+vx_status claimed_regions(const Plan &P, const Layout &L, void *ws, uint32_t i, uint32_t sa, uint32_t sb,
+                          hipStream_t s, uint32_t origin = 0) {
+    const uint32_t nd = 1u << P.D[i];
+    const uint32_t nseg = sb - sa;
+    const uint32_t *base = at<uint32_t>(ws, L.gstart[i - 1]) + sa;
+    uint32_t *off = at<uint32_t>(ws, L.off[i]) + (size_t)sa * P.Q[i] * nd;
+    uint32_t *gst = at<uint32_t>(ws, L.gstart[i]) + (size_t)sa * nd;
+    uint32_t *fill = at<uint32_t>(ws, L.fill[i]) + (size_t)sa * nd;
+    VX_HIP(vxk::launch_region_bounds(fill, (sa - origin) * nd, nseg * nd, P.R[i],
+                                     at<uint32_t>(ws, L.seg_lo[i]) + sa * nd,
+                                     at<uint32_t>(ws, L.seg_hi[i]) + sa * nd, s),
+           "pass regions");
+    VX_HIP(vxk::launch_colscan(fill, off, nseg, 1, nd, base, gst, nseg * nd, (uint32_t)P.n, s), "pass scan");
+    return VX_OK;
+}
+
 // Pass i >= 1 over its input segments [sa, sb) (the groups of pass i - 1).
 // A region-pass plan (P.hs) reads the previous pass's regions and claims
 // room in its own: the scatter, the clamp of the region counts, and their
@@ -447,12 +525,7 @@ vx_status run_pass(const Plan &P, const Layout &L, void *ws, const PassBufs &B, 
         VX_HIP(vxk::launch_scatter_claim(B.in_k, B.in_n, B.out_k + first, B.out_n + first, seg, seg_end, nseg, q,
                                          shift, P.D[i], fill, P.R[i], at<uint32_t>(ws, L.header) + kHdrStatus, s),
                "pass scatter");
-        VX_HIP(vxk::launch_region_bounds(fill, (sa - origin) * nd, nseg * nd, P.R[i],
-                                         at<uint32_t>(ws, L.seg_lo[i]) + sa * nd,
-                                         at<uint32_t>(ws, L.seg_hi[i]) + sa * nd, s),
-               "pass regions");
-        VX_HIP(vxk::launch_colscan(fill, off, nseg, 1, nd, base, gst, nseg * nd, (uint32_t)P.n, s), "pass scan");
-        return VX_OK;
+        return claimed_regions(P, L, ws, i, sa, sb, s, origin);
     }
     uint32_t *hist = at<uint32_t>(ws, L.hist[i]) + (size_t)sa * q * nd;
     VX_HIP(vxk::launch_hist_segments(B.in_k, base, nullptr, nseg, q, shift, P.D[i], hist, s), "pass histogram");
@@ -469,7 +542,10 @@ vx_status run_pass(const Plan &P, const Layout &L, void *ws, const PassBufs &B, 
 vx_status run_partition(const Plan &P, const Layout &L, void *ws, const uint64_t *keys_no,
                         bool hist_done, uint64_t *t1_keys, uint32_t *t1_nonces, uint32_t npass_run,
                         hipStream_t s, hipEvent_t *ev, const uint32_t *nonces_in = nullptr) {
-    for (uint32_t i = P.hs ? 1 : 0; i < npass_run; ++i) {
+    // A sliced hash (P.hq > 1) has done the first two passes.
+    const uint32_t first = P.hs ? (P.hq > 1 ? 2 : 1) : 0;
+    if (first >= npass_run) VX_HIP(mark(ev, 3, s), "event");
+    for (uint32_t i = first; i < npass_run; ++i) {
         const PassBufs B = pass_bufs(P, L, ws, keys_no, t1_keys, t1_nonces, i, nonces_in);
         if (i == 0) {
             uint32_t *hist = at<uint32_t>(ws, L.hist[0]), *off = at<uint32_t>(ws, L.off[0]);
@@ -489,7 +565,69 @@ vx_status run_partition(const Plan &P, const Layout &L, void *ws, const uint64_t
         }
         VX_HIP(mark(ev, i == 0 ? 2 : 3, s), "event");
     }
-    if (npass_run == 1) VX_HIP(mark(ev, 3, s), "event");
+    if (npass_run == 1 && first < npass_run) VX_HIP(mark(ev, 3, s), "event");
+    return VX_OK;
+}
+
+// The hash and the first two partition passes of a plot hashed in P.hq
+// nonce slices.  Launch i hashes slice i and files it by the first digit
+// into its own regions, while its other work-groups file the regions of
+// slice i - 1 (written by launch i - 1) by the second digit into the plot's
+// second-pass regions, shared by all slices.  Then the first digit's group
+// starts over all slices, and the second pass's region bounds and group
+// starts.
+vx_status run_sliced_front(const Plan &P, const Layout &L, void *ws, hipStream_t s, hipEvent_t *ev) {
+    uint32_t *hdr = at<uint32_t>(ws, L.header);
+    const uint32_t nd0 = 1u << P.D[0];
+    uint64_t *reg_k = at<uint64_t>(ws, L.keys_no);
+    uint32_t *reg_n = at<uint32_t>(ws, L.reg_nonces);
+    uint32_t *fill0 = at<uint32_t>(ws, L.fill[0]);
+    const uint64_t slice_recs = (uint64_t)nd0 * P.R[0];
+    const uint32_t per = (P.R[0] + vxk::kHashScatterSub - 1) / vxk::kHashScatterSub;
+    for (uint32_t i = 0; i <= P.hq; ++i) {
+        vxk::HashPassList W;
+        memset(&W, 0, sizeof(W));
+        if (i < P.hq) {
+            vxk::HashSliceDesc &H = W.h[W.nh++];
+            memcpy(H.key, P.key_words, sizeof(H.key));
+            H.nonce0 = P.n * i / P.hq;
+            H.n = P.n * (i + 1) / P.hq - H.nonce0;
+            H.keys = reg_k + i * slice_recs;
+            H.nonces = reg_n + i * slice_recs;
+            H.fill = fill0 + (size_t)i * nd0;
+            H.status = hdr + kHdrStatus;
+            H.bits = P.D[0];
+            H.R = P.R[0];
+            H.items = (uint32_t)((H.n + vxk::kHashScatterSub - 1) / vxk::kHashScatterSub);
+            W.h_items += H.items;
+        }
+        if (i >= 1) {
+            vxk::PassSliceDesc &Q = W.p[W.np++];
+            Q.keys = reg_k + (i - 1) * slice_recs;
+            Q.nonces = reg_n + (i - 1) * slice_recs;
+            Q.fill = fill0 + (size_t)(i - 1) * nd0;
+            Q.out_keys = at<uint64_t>(ws, L.scr_keys);
+            Q.out_nonces = at<uint32_t>(ws, L.scr_nonces);
+            Q.out_fill = at<uint32_t>(ws, L.fill[1]);
+            Q.status = hdr + kHdrStatus;
+            Q.R_in = P.R[0];
+            Q.per = per;
+            Q.shift = 64 - P.D[0] - P.D[1];
+            Q.bits = P.D[1];
+            Q.R_out = P.R[1];
+            Q.items = nd0 * per;
+            W.p_items += Q.items;
+        }
+        const uint64_t nt = (uint64_t)W.h_items + W.p_items;
+        W.h_frac = ((uint64_t)W.h_items << 32) / nt + ((((uint64_t)W.h_items << 32) % nt) ? 1 : 0);
+        VX_HIP(vxk::launch_hash_pass(W, hdr + kHdrHashPassTicket + i, s), "sliced hash");
+    }
+    VX_HIP(mark(ev, 1, s), "event");
+    VX_HIP(vxk::launch_region_scan_slices(fill0, P.hq, nd0, P.R[0], at<uint32_t>(ws, L.gstart[0]), s),
+           "region scan");
+    vx_status st = claimed_regions(P, L, ws, 1, 0, nd0, s);
+    if (st != VX_OK) return st;
+    VX_HIP(mark(ev, 2, s), "event");
     return VX_OK;
 }
 
@@ -497,10 +635,18 @@ vx_status run_partition(const Plan &P, const Layout &L, void *ws, const uint64_t
 // into Table 1, with their bucket offsets; `slot` picks the slice's header
 // words.  Groups are sorted in place, or (region-pass plans) gathered from
 // the last pass's regions.  pcnt (may be NULL): the sort also stores every
-// record's pair count (one byte) while the group is in LDS.
+// record's pair count (one byte) while the group is in LDS.  sums: it also
+// adds the counts up per match chunk (L.mcount, zeroed here first), so that
+// the match needs no pass over the count bytes; only when the sorted groups
+// hold every record of the table.
 vx_status run_group_sort(const Plan &P, const Layout &L, void *ws, uint64_t *t1_keys, uint32_t *t1_nonces,
                          uint32_t *offsets, uint8_t *pcnt, uint32_t g0, uint32_t gcount, uint32_t slot,
-                         hipStream_t s) {
+                         hipStream_t s, bool sums = false) {
+    uint64_t *csum = nullptr;
+    if (sums && pcnt) {
+        csum = at<uint64_t>(ws, L.mcount);
+        VX_HIP(vxk::launch_zero_u64(csum, match_chunks(P), s), "zero chunk sums");
+    }
     uint32_t *hdr = at<uint32_t>(ws, L.header);
     const uint32_t last = P.npass - 1;
     const uint32_t *gstart = at<uint32_t>(ws, L.gstart[last]);
@@ -516,29 +662,31 @@ vx_status run_group_sort(const Plan &P, const Layout &L, void *ws, uint64_t *t1_
     }
     VX_HIP(vxk::launch_groupsort(t1_keys, t1_nonces, in_k, in_n, in_lo, in_hi, gstart, P.G, P.cap, offsets, (uint32_t)P.n,
                                  hdr + kHdrOvf + slot, ovf_list, P.T, pcnt, g0, gcount,
-                                 hdr + kHdrSortTicket + slot, s),
+                                 hdr + kHdrSortTicket + slot, csum, P.cb, s),
            "group sort");
     VX_HIP(vxk::launch_group_fallback(t1_keys, t1_nonces, in_k, in_n, in_lo, in_hi, at<uint64_t>(ws, L.scr_keys),
                                       at<uint32_t>(ws, L.scr_nonces), gstart, P.G, offsets, hdr + kHdrOvf + slot,
-                                      ovf_list, hdr + kHdrStatus, P.T, pcnt, s),
+                                      ovf_list, hdr + kHdrStatus, P.T, pcnt, csum, P.cb, s),
            "group sort fallback");
     return VX_OK;
 }
 
 // Match and Table-2 hashing of the chunks owned by records [*r_lo, *r_hi)
-// (NULL: all), whose count bytes are in the workspace: chunk sums, Table-2
-// bases (a device scan over all chunks when unsliced, else a ranged scan that
-// carries the running total), then the match kernel.
+// (NULL: all), whose count bytes are in the workspace: chunk sums (unless
+// sums_ready: the sort or the match count made them), Table-2 bases (a
+// device scan over all chunks when unsliced, else a ranged scan that carries
+// the running total), then the match kernel.
 vx_status run_match(const Plan &P, const Layout &L, void *ws, const uint64_t *t1_keys,
                     const uint32_t *t1_nonces, vx_t2_record *t2, uint64_t cap, uint64_t *t2_count,
                     const uint32_t *r_lo, const uint32_t *r_hi, uint32_t last, uint32_t slot, uint32_t wg_per_cu,
-                    hipStream_t s, hipEvent_t *ev = nullptr) {
+                    hipStream_t s, hipEvent_t *ev = nullptr, bool sums_ready = false) {
     uint32_t *hdr = at<uint32_t>(ws, L.header);
     uint64_t *cnt = at<uint64_t>(ws, L.mcount), *base = at<uint64_t>(ws, L.mbase);
     uint8_t *pcnt = at<uint8_t>(ws, L.pcnt);
     const uint32_t nch = match_chunks(P);
-    VX_HIP(vxk::launch_chunk_sums(pcnt, t1_keys, (uint32_t)P.n, P.cb, P.T, cnt, r_lo, r_hi, last, nch, s),
-           "chunk pair sums");
+    if (!sums_ready)
+        VX_HIP(vxk::launch_chunk_sums(pcnt, t1_keys, (uint32_t)P.n, P.cb, P.T, cnt, r_lo, r_hi, last, nch, s),
+               "chunk pair sums");
     if (!r_lo) {
         VX_HIP(vxk::launch_scan_u64(cnt, nch, base, at<uint64_t>(ws, L.mpart), t2_count, s), "match scan");
     } else {
@@ -712,6 +860,12 @@ uint32_t vx_partition_passes(const vx_plot_params *params, const vx_tuning *tuni
     return P.npass;
 }
 
+uint32_t vx_hash_slices(const vx_plot_params *params, const vx_tuning *tuning) {
+    Plan P;
+    if (make_plan(params, tuning, &P) != VX_OK) return 0;
+    return P.hq;
+}
+
 uint64_t vx_t2_capacity_hint(uint32_t k, uint64_t threshold) {
     if (k < 1 || k > 31) return 0;
     // Expected pairs per record for uniform keys: neighbours within T inside
@@ -783,7 +937,7 @@ vx_status vx_match_table2(const vx_plot_params *params, const uint64_t *d_t1_key
                                    at<uint8_t>(d_workspace, L.pcnt), s),
            "match count");
     st = run_match(P, L, d_workspace, d_t1_keys, d_t1_nonces, d_t2, t2_capacity, d_t2_count, nullptr, nullptr, 1,
-                   0, 0, s);
+                   0, 0, s, nullptr, true);
     if (st == VX_OK) g_err[0] = 0;
     return st;
 }
@@ -859,11 +1013,11 @@ vx_status vx_plot_chunk(const vx_plot_params *params, uint32_t chunk_bits, uint3
     const uint32_t g0 = own ? chunk << (P.G - chunk_bits) : 0;
     const uint32_t gn = own ? 1u << (P.G - chunk_bits) : 1u << P.G;
     st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, at<uint8_t>(ws, L.pcnt), g0, gn, 0,
-                        s);
+                        s, true);
     if (st == VX_OK && own) st = fill_outside_offsets(b->bucket_offsets, chunk_bits, chunk, m, s);
     if (st == VX_OK)
         st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, nullptr, nullptr, 1,
-                       0, 0, s);
+                       0, 0, s, nullptr, true);
     if (st == VX_OK) g_err[0] = 0;
     return st;
 }
@@ -971,12 +1125,12 @@ vx_status vx_plot_staged_chunk(const vx_plot_params *params, uint32_t chunk_bits
     }
     const uint32_t gsh = P.G - P.D[0];
     st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, at<uint8_t>(ws, L.pcnt),
-                        d_first << gsh, ndc << gsh, 0, s);
+                        d_first << gsh, ndc << gsh, 0, s, true);
     if (st != VX_OK) return st;
     // Buckets before the chunk start at 0, those after it (and the end) at m.
     if ((st = fill_outside_offsets(b->bucket_offsets, chunk_bits, chunk, m, s)) != VX_OK) return st;
     st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, nullptr, nullptr, 1, 0,
-                   0, s);
+                   0, s, nullptr, true);
     if (st == VX_OK) g_err[0] = 0;
     return st;
 }
@@ -1059,9 +1213,14 @@ vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, cons
     else
         VX_HIP(vxk::launch_reset(hdr, kHeaderWords, s), "reset");
     for (uint32_t i = 0; P.hs && i < P.npass; ++i)
-        VX_HIP(vxk::launch_fill_u32(at<uint32_t>(ws, L.fill[i]), 1ull << (P.pre[i] + P.D[i]), 0u, s), "reset");
+        VX_HIP(vxk::launch_fill_u32(at<uint32_t>(ws, L.fill[i]), (1ull << (P.pre[i] + P.D[i])) * (i == 0 ? P.hq : 1),
+                                    0u, s),
+               "reset");
     VX_HIP(mark(ev, 0, s), "event");
-    if (P.hs) {
+    if (P.hs && P.hq > 1) {
+        st = run_sliced_front(P, L, ws, s, ev);
+        if (st != VX_OK) return st;
+    } else if (P.hs) {
         // Hash + first partition pass in one kernel, then the regions' bounds.
         VX_HIP(vxk::launch_hash_scatter(P.key_words, P.n, P.D[0], P.R[0], keys_no, at<uint32_t>(ws, L.reg_nonces),
                                         at<uint32_t>(ws, L.fill[0]), hdr + kHdrStatus, s),
@@ -1087,11 +1246,11 @@ vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, cons
         st = run_partition(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, P.npass, s, ev);
         if (st != VX_OK) return st;
         st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, at<uint8_t>(ws, L.pcnt), 0,
-                            1u << P.G, 0, s);
+                            1u << P.G, 0, s, true);
         if (st != VX_OK) return st;
         VX_HIP(mark(ev, 4, s), "event");
         st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, nullptr, nullptr,
-                       1, 0, 0, s, ev);
+                       1, 0, 0, s, ev, true);
     } else {
         st = run_partition(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, P.npass, s, ev);
         if (st != VX_OK) return st;

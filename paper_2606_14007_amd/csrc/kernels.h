@@ -29,6 +29,48 @@ constexpr uint32_t kHashScatterSub = 256u * kHashScatterItems;
 constexpr int kClaimMaxBits = 9;  // widest digit of a claiming scatter
 
 hipError_t launch_reset(uint32_t *words, uint32_t n, hipStream_t s);
+
+// Hash of nonce slices beside the next partition pass of slices hashed in an
+// earlier launch (k_hash_pass).  Items are sub-tiles of kHashScatterSub
+// records.
+struct HashSliceDesc {       // hash nonces [nonce0, nonce0 + n), file them by the first digit
+    uint32_t key[8];         // plot key, little-endian words
+    uint64_t nonce0, n;
+    uint64_t *keys;          // region d of the slice: records [d * R, (d + 1) * R)
+    uint32_t *nonces;
+    uint32_t *fill;          // records filed per region (zero before the slice's launch)
+    uint32_t *status;        // device status word of the plot
+    uint32_t bits, R;        // first-digit bits (<= 7), region capacity
+    uint32_t items;          // ceil(n / kHashScatterSub)
+    uint32_t pad;
+};
+struct PassSliceDesc {       // file the regions of a hashed slice by the next digit
+    const uint64_t *keys;    // nin regions of R_in records
+    const uint32_t *nonces;
+    const uint32_t *fill;    // their fills (clamped to R_in)
+    uint64_t *out_keys;      // region r * 2^bits + d of the output: [region * R_out, + R_out)
+    uint32_t *out_nonces;
+    uint32_t *out_fill;      // shared by every slice of the plot (zero before its first slice)
+    uint32_t *status;
+    uint32_t R_in, per;      // per: sub-tiles per input region = ceil(R_in / kHashScatterSub)
+    uint32_t shift, bits;    // digit = (key >> shift) & (2^bits - 1), bits <= 7
+    uint32_t R_out;
+    uint32_t items;          // nin * per
+};
+constexpr int kHashPassMaxSlices = 8;
+struct HashPassList {
+    HashSliceDesc h[kHashPassMaxSlices];
+    PassSliceDesc p[kHashPassMaxSlices];
+    uint32_t nh, np;
+    uint32_t h_items, p_items;  // totals over the lists
+    uint64_t h_frac;            // ceil(h_items * 2^32 / (h_items + p_items))
+};
+constexpr int kHashPassMaxBits = 7;
+// One launch over the list; *ticket zero at launch.
+hipError_t launch_hash_pass(const HashPassList &L, uint32_t *ticket, hipStream_t s);
+// gstart[d] (d <= nd) of the first digit over a sliced hash's regions.
+hipError_t launch_region_scan_slices(const uint32_t *fill, uint32_t slices, uint32_t nd, uint32_t R,
+                                     uint32_t *gstart, hipStream_t s);
 // Chunked plots: hash all n nonces, keep keys whose top pbits bits are
 // `prefix`; *count (zero at launch) receives how many (records past cap are
 // not written).
@@ -83,13 +125,15 @@ hipError_t launch_region_bounds(uint32_t *fill, uint32_t r0, uint32_t nregions, 
 hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint64_t *in_keys, const uint32_t *in_nonces,
                             const uint32_t *in_lo, const uint32_t *in_hi, const uint32_t *gstart, uint32_t G, uint32_t cap,
                             uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count, uint32_t *ovf_list, uint64_t T,
-                            uint8_t *pcnt, uint32_t g0, uint32_t gcount, uint32_t *ticket, hipStream_t s);
+                            uint8_t *pcnt, uint32_t g0, uint32_t gcount, uint32_t *ticket, uint64_t *csum,
+                            uint32_t cb, hipStream_t s);
 hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, const uint64_t *in_keys,
                                  const uint32_t *in_nonces, const uint32_t *in_lo, const uint32_t *in_hi,
                                  uint64_t *scr_keys,
                                  uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G,
                                  uint32_t *offsets, const uint32_t *ovf_count, const uint32_t *ovf_list,
-                                 uint32_t *status, uint64_t T, uint8_t *pcnt, hipStream_t s);
+                                 uint32_t *status, uint64_t T, uint8_t *pcnt, uint64_t *csum, uint32_t cb,
+                                 hipStream_t s);
 hipError_t launch_match_count(const uint64_t *keys, uint32_t n_total, uint32_t chunk_bits, uint64_t T,
                               uint64_t *counts, uint8_t *pcnt, hipStream_t s);
 // Ranged launches: the records [*r_lo, *r_hi) (device words; NULL = all

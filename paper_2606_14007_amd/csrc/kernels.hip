@@ -296,6 +296,184 @@ __global__ __launch_bounds__(BLOCK) void k_region_scan(const uint32_t *__restric
 }
 
 // ---------------------------------------------------------------------------
+// Hash of nonce slices beside the next partition pass of slices hashed
+// before, in one persistent launch.
+//
+// The hash is bound by the vector ALUs and leaves memory nearly idle; a
+// partition pass is bound by memory and LDS and leaves the ALUs nearly idle.
+// A plot hashed in slices runs, in launch i, the hash (and first-digit
+// filing) of slice i beside the next-digit filing of the regions of slice
+// i - 1, which launch i - 1 wrote (stream order makes them visible; no item
+// waits on another).  Work-groups take items of both kinds from one ticket
+// counter, interleaved in proportion to their numbers, so that every CU
+// holds both kinds at once.  Both kinds share one LDS layout: a sub-tile of
+// SUB records is ranked by digit with LDS atomics, each digit's run claims
+// room in its region with one global atomic, and the runs are written
+// contiguously.  A list may hold slices of several plots (a batch).
+// ---------------------------------------------------------------------------
+
+template <int BLOCK, int ITEMS, int MAXD>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_hash_pass(HashPassList L,
+                                                                                     uint32_t *__restrict__ ticket) {
+    constexpr uint32_t SUB = BLOCK * ITEMS;
+    constexpr int PER = (MAXD + 63) / 64;  // digits per lane of the one-wave scan
+    static_assert(MAXD <= BLOCK, "one thread per digit claims its region room");
+    __shared__ uint64_t s_keys[SUB];
+    __shared__ uint32_t s_non[SUB];
+    __shared__ uint32_t s_cnt[MAXD];      // digit counts of the sub-tile
+    __shared__ uint32_t s_pos[MAXD + 1];  // their exclusive prefix
+    __shared__ uint32_t s_claim[MAXD];
+    __shared__ uint32_t s_tk[2];  // alternate, so a slow reader never sees the next ticket
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint64_t NT = (uint64_t)L.h_items + L.p_items;
+    if (tid < MAXD) s_cnt[tid] = 0;
+    if (tid == 0) s_tk[0] = atomicAdd(ticket, 1u);
+    __syncthreads();
+    for (uint32_t it = 0;; ++it) {
+        const uint64_t t = s_tk[it & 1];
+        if (t >= NT) break;
+        // Position t is a hash item when the proportional count of hash
+        // items, a(t) = floor(t * h_frac / 2^32), grows across it.
+        const uint64_t a0 = (t * L.h_frac) >> 32, a1 = ((t + 1) * L.h_frac) >> 32;
+        uint64_t k[ITEMS];
+        uint32_t nv[ITEMS], slot[ITEMS];
+        uint32_t m, shift, mask, R, region0;
+        uint32_t *fill, *ononces, *status;
+        uint64_t *okeys;
+        if (a1 > a0) {
+            uint32_t x = (uint32_t)a0, s = 0;
+            while (s + 1 < L.nh && x >= L.h[s].items) x -= L.h[s].items, ++s;
+            const HashSliceDesc &H = L.h[s];
+            Key key;
+#pragma unroll
+            for (int w = 0; w < 8; ++w) key.w[w] = H.key[w];
+            const uint64_t base = (uint64_t)x * SUB;
+            m = (uint32_t)(H.n - base < SUB ? H.n - base : SUB);
+            shift = 64u - H.bits;
+            mask = (1u << H.bits) - 1u;
+            R = H.R;
+            region0 = 0;
+            fill = H.fill;
+            okeys = H.keys;
+            ononces = H.nonces;
+            status = H.status;
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                // As in k_hash_table1: keep the nonce opaque to the optimiser.
+                uint32_t nonce = (uint32_t)(H.nonce0 + base) + (uint32_t)(j * BLOCK) + tid;
+                asm volatile("" : "+v"(nonce));
+                k[j] = vxd::h1(key, nonce);
+                nv[j] = nonce;
+            }
+        } else {
+            uint32_t x = (uint32_t)(t - a0), s = 0;
+            while (s + 1 < L.np && x >= L.p[s].items) x -= L.p[s].items, ++s;
+            const PassSliceDesc &P = L.p[s];
+            const uint32_t r = x / P.per, lo = (x % P.per) * SUB;
+            const uint32_t f = min(P.fill[r], P.R_in);
+            m = lo < f ? min(SUB, f - lo) : 0u;
+            shift = P.shift;
+            mask = (1u << P.bits) - 1u;
+            R = P.R_out;
+            region0 = r << P.bits;
+            fill = P.out_fill;
+            okeys = P.out_keys;
+            ononces = P.out_nonces;
+            status = P.status;
+            if (m) {
+                // Clamped, unconditional loads: a wave issues all before waiting.
+                const uint64_t src = (uint64_t)r * P.R_in + lo;
+#pragma unroll
+                for (int j = 0; j < ITEMS; ++j) {
+                    const uint32_t e = j * BLOCK + tid;
+                    const uint64_t ic = src + (e < m ? e : m - 1);
+                    k[j] = P.keys[ic];
+                    nv[j] = P.nonces[ic];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+            if (j * BLOCK + tid < m) slot[j] = atomicAdd(&s_cnt[(uint32_t)(k[j] >> shift) & mask], 1u);
+        if (tid == 0) s_tk[(it + 1) & 1] = atomicAdd(ticket, 1u);
+        __syncthreads();
+        // Claim room in the regions (thread d <-> digit d); the atomics are in
+        // flight during the scan and the LDS layout.  Wave 0 scans the counts.
+        const uint32_t nd = mask + 1u;
+        uint32_t claim = 0;
+        if (tid < nd) {
+            const uint32_t c = s_cnt[tid];
+            if (c) claim = atomicAdd(&fill[region0 + tid], c);
+        }
+        if (tid < 64) {
+            uint32_t v[PER], sum = 0;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const uint32_t d = lane * PER + q;
+                v[q] = d < nd ? s_cnt[d] : 0u;
+                sum += v[q];
+            }
+            const uint32_t inc = vxd::wave_inclusive_scan(sum);
+            uint32_t run = inc - sum;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const uint32_t d = lane * PER + q;
+                if (d < nd) s_pos[d] = run;
+                run += v[q];
+            }
+        }
+        __syncthreads();
+        // The counts are consumed: clear them for the next item (its atomics
+        // come after the next barrier).
+        if (tid < nd) s_cnt[tid] = 0;
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+            if (j * BLOCK + tid < m) {
+                const uint32_t p = s_pos[(uint32_t)(k[j] >> shift) & mask] + slot[j];
+                s_keys[p] = k[j];
+                s_non[p] = nv[j];
+            }
+        if (tid < nd) s_claim[tid] = claim;
+        __syncthreads();
+        // No barrier after the write-out: the next item's LDS layout waits for
+        // the barrier after its ranking, which every thread reaches only once
+        // its reads here are done.
+        for (uint32_t e = tid; e < m; e += BLOCK) {
+            const uint64_t kk = s_keys[e];
+            const uint32_t d = (uint32_t)(kk >> shift) & mask;
+            const uint32_t r = s_claim[d] + (e - s_pos[d]);
+            if (r < R) {
+                const uint64_t g = (uint64_t)(region0 + d) * R + r;
+                okeys[g] = kk;
+                ononces[g] = s_non[e];
+            } else {
+                atomicOr(status, (uint32_t)VXK_DEV_STATUS_REGION_OVERFLOW);
+            }
+        }
+    }
+}
+
+// Starts of the first digit's groups after a plot hashed in `slices`
+// slices: gstart[d] = records of digits below d over all slices, each
+// slice's region d holding min(fill[s * nd + d], R); gstart[nd] = all.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_region_scan_slices(const uint32_t *__restrict__ fill, uint32_t slices,
+                                                              uint32_t nd, uint32_t R,
+                                                              uint32_t *__restrict__ gstart) {
+    __shared__ uint32_t s[kMaxDigits];
+    __shared__ uint32_t s_wave[BLOCK / 64 + 1];
+    for (uint32_t d = threadIdx.x; d < nd; d += BLOCK) {
+        uint32_t c = 0;
+        for (uint32_t q = 0; q < slices; ++q) c += min(fill[q * nd + d], R);
+        s[d] = c;
+    }
+    __syncthreads();
+    const uint32_t total = vxd::lds_exclusive_scan<BLOCK>(s, (int)nd, s_wave);
+    for (uint32_t d = threadIdx.x; d < nd; d += BLOCK) gstart[d] = s[d];
+    if (threadIdx.x == 0) gstart[nd] = total;
+}
+
+// ---------------------------------------------------------------------------
 // Digit histogram per tile
 // ---------------------------------------------------------------------------
 
@@ -619,11 +797,15 @@ __device__ __forceinline__ uint32_t pairs_after(const uint64_t *keys, uint32_t e
 // that ends at a bucket boundary, counted with a two-pointer walk (the last
 // partner of a record never precedes the previous record's last partner).
 // pc (may be NULL) receives each record's count as one byte, with
-// kPairCountEscape standing for "that many or more".
+// kPairCountEscape standing for "that many or more".  csum (may be NULL)
+// receives the counts summed per match chunk of Table 1 (chunk c = records
+// [c << cb, (c + 1) << cb)), the run starting at Table-1 index `at`.
 __device__ __forceinline__ uint64_t pairs_in_range(const uint64_t *keys, uint32_t e_lo, uint32_t e_hi,
-                                                   uint32_t n, uint64_t T, uint8_t *pc) {
-    uint64_t total = 0;
-    uint32_t reach = e_lo;
+                                                   uint32_t n, uint64_t T, uint8_t *pc,
+                                                   unsigned long long *csum = nullptr, uint32_t cb = 0,
+                                                   uint32_t at = 0) {
+    uint64_t total = 0, part = 0;
+    uint32_t reach = e_lo, chunk = (at + e_lo) >> cb;
     for (uint32_t e = e_lo; e < e_hi; ++e) {
         const uint64_t ki = keys[e];
         const uint32_t bi = (uint32_t)(ki >> 40);
@@ -635,7 +817,16 @@ __device__ __forceinline__ uint64_t pairs_in_range(const uint64_t *keys, uint32_
         }
         total += reach - e;
         if (pc) pc[e] = (uint8_t)min(reach - e, kPairCountEscape);
+        if (csum) {
+            if ((at + e) >> cb != chunk) {
+                if (part) atomicAdd(&csum[chunk], (unsigned long long)part);
+                chunk = (at + e) >> cb;
+                part = 0;
+            }
+            part += reach - e;
+        }
     }
+    if (csum && part) atomicAdd(&csum[chunk], (unsigned long long)part);
     return total;
 }
 
@@ -738,8 +929,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CAPMAX <=
                                                      uint32_t *__restrict__ ovf_count,
                                                      uint32_t *__restrict__ ovf_list, uint64_t T,
                                                      uint8_t *__restrict__ pcnt, uint32_t g0,
-                                                     uint32_t gcount, uint32_t *__restrict__ ticket) {
+                                                     uint32_t gcount, uint32_t *__restrict__ ticket,
+                                                     unsigned long long *__restrict__ csum, uint32_t cb) {
     constexpr int ITEMS = CAPMAX / BLOCK;
+    // Pair sums of the match chunks a group overlaps (at most CAPMAX / 64 + 2
+    // for chunks of 64 records or more).
+    constexpr int NCS = CAPMAX / 64 + 2;
+    __shared__ uint32_t s_csum[NCS];
     __shared__ uint64_t s_keys[CAPMAX];
     __shared__ uint32_t s_nonces[CAPMAX];
     constexpr int NW2 = kSubBins / 2;  // two 16-bit sub-bin counters per word
@@ -764,6 +960,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CAPMAX <=
         const uint32_t *src_n = in.keys ? in.nonces + in.lo[g] : nonces + lo;
         uint64_t k[ITEMS];
         uint32_t nn[ITEMS];
+        if (csum)
+            for (uint32_t i = tid; i < (uint32_t)NCS; i += BLOCK) s_csum[i] = 0;  // read after the sort's barriers
         if (n <= cap && n > 0) {
             // Clamped, unconditional loads: a wave issues all before waiting.
 #pragma unroll
@@ -785,29 +983,46 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CAPMAX <=
             // lane-strided records keep LDS reads and stores contiguous; a
             // record tests its next four records with independent reads (no
             // chain of dependent loads) and walks on only past four partners.
-            for (uint32_t e = tid; e < n; e += BLOCK) {
-                const uint64_t ki = s_keys[e];
-                keys[lo + e] = ki;
-                nonces[lo + e] = s_nonces[e];
-                if (pcnt) {
-                    const uint32_t bi = (uint32_t)(ki >> 40);
-                    uint64_t kn[4];
+            // With csum, every wave also adds its 64 consecutive records'
+            // exact counts into the (at most two) match chunks they fall in.
+            const uint32_t c_lo = lo >> cb;
+            for (uint32_t e0 = 0; e0 < n; e0 += BLOCK) {
+                const uint32_t e = e0 + tid;
+                uint32_t cnt_e = 0;
+                if (e < n) {
+                    const uint64_t ki = s_keys[e];
+                    keys[lo + e] = ki;
+                    nonces[lo + e] = s_nonces[e];
+                    if (pcnt) {
+                        const uint32_t bi = (uint32_t)(ki >> 40);
+                        uint64_t kn[4];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) kn[r] = e + 1 + r < n ? s_keys[e + 1 + r] : ~0ull;
-                    uint32_t c = 0;
-                    bool go = true;
+                        for (int r = 0; r < 4; ++r) kn[r] = e + 1 + r < n ? s_keys[e + 1 + r] : ~0ull;
+                        uint32_t c = 0;
+                        bool go = true;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        go = go && e + 1 + r < n && (uint32_t)(kn[r] >> 40) == bi && kn[r] - ki < T;
-                        c += go ? 1u : 0u;
-                    }
-                    if (c == 4)
-                        for (uint32_t j = e + 5; j < n; ++j) {
-                            const uint64_t kj = s_keys[j];
-                            if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
-                            ++c;
+                        for (int r = 0; r < 4; ++r) {
+                            go = go && e + 1 + r < n && (uint32_t)(kn[r] >> 40) == bi && kn[r] - ki < T;
+                            c += go ? 1u : 0u;
                         }
-                    pcnt[lo + e] = (uint8_t)min(c, kPairCountEscape);
+                        if (c == 4)
+                            for (uint32_t j = e + 5; j < n; ++j) {
+                                const uint64_t kj = s_keys[j];
+                                if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
+                                ++c;
+                            }
+                        pcnt[lo + e] = (uint8_t)min(c, kPairCountEscape);
+                        cnt_e = c;
+                    }
+                }
+                if (csum) {
+                    const uint32_t ca = (lo + e0 + (tid & ~63u)) >> cb;  // the wave's first chunk
+                    const uint32_t va = ((lo + e) >> cb) == ca ? cnt_e : 0u;
+                    const uint32_t sa = vxd::wave_sum(va), sb = vxd::wave_sum(cnt_e - va);
+                    if ((tid & 63u) == 0) {
+                        if (sa) atomicAdd(&s_csum[ca - c_lo], sa);
+                        if (sb) atomicAdd(&s_csum[ca + 1 - c_lo], sb);
+                    }
                 }
             }
             // offsets[b] for the group's buckets: first record with bucket >= b.
@@ -822,6 +1037,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CAPMAX <=
                 offsets[b] = lo + a;
             }
             __syncthreads();
+            if (csum && n) {  // the chunks of records [lo, lo + n)
+                const uint32_t nch = ((lo + n - 1) >> cb) - c_lo + 1;
+                for (uint32_t i = tid; i < nch; i += BLOCK)
+                    if (s_csum[i]) atomicAdd(&csum[c_lo + i], (unsigned long long)s_csum[i]);
+            }
         }
     }
 }
@@ -836,7 +1056,7 @@ __global__ __launch_bounds__(BLOCK) void k_group_fallback(
     uint32_t *scr_nonces, const uint32_t *__restrict__ gstart, uint32_t G,
     uint32_t *__restrict__ offsets, const uint32_t *__restrict__ ovf_count,
     const uint32_t *__restrict__ ovf_list, uint32_t fb_max, uint32_t *__restrict__ status,
-    uint64_t T, uint8_t *__restrict__ pcnt) {
+    uint64_t T, uint8_t *__restrict__ pcnt, unsigned long long *__restrict__ csum, uint32_t cb) {
     __shared__ uint64_t s_k[BLOCK];
     __shared__ uint32_t s_n[BLOCK];
     const uint32_t tid = threadIdx.x;
@@ -904,7 +1124,7 @@ __global__ __launch_bounds__(BLOCK) void k_group_fallback(
         if (pcnt && n) {
             const uint32_t per = (n + BLOCK - 1) / BLOCK;
             const uint32_t r0 = min(tid * per, n), r1 = min(r0 + per, n);
-            pairs_in_range(keys + lo, r0, r1, n, T, pcnt + lo);
+            pairs_in_range(keys + lo, r0, r1, n, T, pcnt + lo, csum, cb, lo);
         }
         __syncthreads();
     }
@@ -1687,6 +1907,30 @@ hipError_t launch_hash_scatter(const uint32_t key_words[8], uint64_t n, uint32_t
     return hipGetLastError();
 }
 
+hipError_t launch_hash_pass(const HashPassList &L, uint32_t *ticket, hipStream_t s) {
+    static_assert(1 << kHashPassMaxBits <= kHashBlock, "one thread per digit");
+    if (L.nh > (uint32_t)kHashPassMaxSlices || L.np > (uint32_t)kHashPassMaxSlices) return hipErrorInvalidValue;
+    for (uint32_t i = 0; i < L.nh; ++i)
+        if (L.h[i].bits < 1 || L.h[i].bits > (uint32_t)kHashPassMaxBits) return hipErrorInvalidValue;
+    for (uint32_t i = 0; i < L.np; ++i)
+        if (L.p[i].bits < 1 || L.p[i].bits > (uint32_t)kHashPassMaxBits || L.p[i].per < 1) return hipErrorInvalidValue;
+    const uint64_t nt = (uint64_t)L.h_items + L.p_items;
+    if (nt == 0) return hipSuccess;
+    static const uint32_t grid =
+        resident_grid(k_hash_pass<kHashBlock, kHashScatterItems, 1 << kHashPassMaxBits>, kHashBlock);
+    const uint32_t used = nt < grid ? (uint32_t)nt : grid;
+    hipLaunchKernelGGL((k_hash_pass<kHashBlock, kHashScatterItems, 1 << kHashPassMaxBits>), dim3(used),
+                       dim3(kHashBlock), 0, s, L, ticket);
+    return hipGetLastError();
+}
+
+hipError_t launch_region_scan_slices(const uint32_t *fill, uint32_t slices, uint32_t nd, uint32_t R,
+                                     uint32_t *gstart, hipStream_t s) {
+    hipLaunchKernelGGL(k_region_scan_slices<kColBlock>, dim3(1), dim3(kColBlock), 0, s, fill, slices, nd, R,
+                       gstart);
+    return hipGetLastError();
+}
+
 hipError_t launch_region_scan(const uint32_t *fill, uint32_t nd, uint32_t R, uint32_t *seg_lo, uint32_t *seg_hi,
                               uint32_t *gstart, hipStream_t s) {
     hipLaunchKernelGGL(k_region_scan<kColBlock>, dim3(1), dim3(kColBlock), 0, s, fill, nd, R, seg_lo, seg_hi,
@@ -1820,7 +2064,8 @@ hipError_t launch_region_bounds(uint32_t *fill, uint32_t r0, uint32_t nregions, 
 hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint64_t *in_keys, const uint32_t *in_nonces,
                             const uint32_t *in_lo, const uint32_t *in_hi, const uint32_t *gstart, uint32_t G, uint32_t cap,
                             uint32_t *offsets, uint32_t n_total, uint32_t *ovf_count, uint32_t *ovf_list, uint64_t T,
-                            uint8_t *pcnt, uint32_t g0, uint32_t gcount, uint32_t *ticket, hipStream_t s) {
+                            uint8_t *pcnt, uint32_t g0, uint32_t gcount, uint32_t *ticket, uint64_t *csum, uint32_t cb,
+                            hipStream_t s) {
     // Group capacities up to kGroupCapFast take the kernel that fits four
     // work-groups on a CU; larger ones the 3072-record kernel (three).
     static const uint32_t resident_fast = resident_grid(k_groupsort<kSortBlock, kGroupCapFast>, kSortBlock);
@@ -1832,11 +2077,11 @@ hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint64_t *in
     if (fast)
         hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapFast>), dim3(grid), dim3(kSortBlock), 0, s,
                            keys, nonces, in, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T, pcnt, g0,
-                           gcount, ticket);
+                           gcount, ticket, reinterpret_cast<unsigned long long *>(csum), cb);
     else
         hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapMax>), dim3(grid), dim3(kSortBlock), 0, s,
                            keys, nonces, in, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T, pcnt, g0,
-                           gcount, ticket);
+                           gcount, ticket, reinterpret_cast<unsigned long long *>(csum), cb);
     return hipGetLastError();
 }
 
@@ -1845,11 +2090,12 @@ hipError_t launch_group_fallback(uint64_t *keys, uint32_t *nonces, const uint64_
                                  uint64_t *scr_keys,
                                  uint32_t *scr_nonces, const uint32_t *gstart, uint32_t G,
                                  uint32_t *offsets, const uint32_t *ovf_count, const uint32_t *ovf_list,
-                                 uint32_t *status, uint64_t T, uint8_t *pcnt, hipStream_t s) {
+                                 uint32_t *status, uint64_t T, uint8_t *pcnt, uint64_t *csum, uint32_t cb,
+                                 hipStream_t s) {
     const GroupIn in{in_keys, in_nonces, in_lo, in_hi};
     hipLaunchKernelGGL(k_group_fallback<kFallbackBlock>, dim3(kFallbackGrid), dim3(kFallbackBlock), 0,
                        s, keys, nonces, in, scr_keys, scr_nonces, gstart, G, offsets, ovf_count, ovf_list,
-                       (uint32_t)kFallbackMax, status, T, pcnt);
+                       (uint32_t)kFallbackMax, status, T, pcnt, reinterpret_cast<unsigned long long *>(csum), cb);
     return hipGetLastError();
 }
 

@@ -130,3 +130,26 @@ def test_noalloc_checks_on_host():
     with pytest.raises(vx.VxError) as e:
         vx.vx_plot_noalloc(vx.make_params(bytes(32), 12), b)
     assert e.value.status == N.VX_ERR_INVALID_ARG
+
+
+def test_hash_slices_take_their_own_plan():
+    """A sliced hash keeps one set of first-pass regions per slice, so its
+    workspace differs from the one-launch plan's; plans outside the sliced
+    kernel's reach (a first digit over 7 bits, too many slices) fall back
+    to one launch and need the same workspace as the plain plan."""
+    from paper_2606_14007_amd import _native as N
+    p = N.make_params(bytes(range(32)), 16)
+    ws = lambda **t: N.vx_workspace_bytes(p, N.VX_CALL_PLOT, N.make_tuning(**t))
+    hq = lambda **t: N.vx_hash_slices(p, N.make_tuning(**t))
+    for t in (dict(), dict(group_bits=12), dict(group_bits=15), dict(group_bits=14),
+              dict(group_bits=13, pass1_bits=3), dict(group_bits=20)):
+        assert hq(hash_slices=4, **t) == 4, t
+        assert ws(hash_slices=4, **t) != ws(hash_slices=1, **t), t
+    # beyond the sliced kernel: a first digit of 8 bits, one pass, too few records per region
+    for t in (dict(group_bits=16, pass1_bits=8), dict(group_bits=9, pass1_bits=9), dict(group_bits=1)):
+        assert hq(hash_slices=4, **t) == 1, t
+        assert ws(hash_slices=4, **t) == ws(hash_slices=1, **t), t
+    assert hq(hash_slices=16, group_bits=14) == 16
+    assert N.vx_hash_slices(N.make_params(bytes(range(32)), 3), N.make_tuning(hash_slices=8, group_bits=2)) == 1
+    assert hq(hash_slices=17) == 0 and ws(hash_slices=17) == 0  # invalid tuning
+    assert N.vx_hash_slices(p) >= 1

@@ -85,6 +85,15 @@ def test_plot_default_threshold(vx, k):
     _assert_plot_equal(vx, b, oracle.plot(KEY0, k, threads=8))
 
 
+@pytest.mark.parametrize("k,hq", [(20, 2), (20, 7), (22, 8), (24, 4), (24, 16)])
+def test_plot_sliced_hash(vx, k, hq):
+    """The plot hashed in nonce slices, each slice's second pass beside the
+    next slice's hash, with the default group bits (two passes up to k=25,
+    three above)."""
+    b = vx.plot(KEY0, k, tuning=vx.make_tuning(hash_slices=hq))
+    _assert_plot_equal(vx, b, oracle.plot(KEY0, k, threads=8))
+
+
 @pytest.mark.parametrize("k,T", [(14, 1 << 44), (16, 1 << 42), (18, 1 << 41), (12, 0),
                                  (16, (1 << 64) - 1)])
 def test_plot_thresholds(vx, k, T):
@@ -116,6 +125,14 @@ TUNINGS = [
     dict(group_bits=16, pipeline_slices=16, group_cap=64),   # 16 slices, oversized groups
     dict(group_bits=15, pipeline_slices=5, match_chunk_bits=6),  # many small chunks per slice
     dict(group_bits=9, pipeline_slices=4),    # one pass: nothing to pipeline
+    dict(hash_slices=2),                      # sliced hash, both passes in its launches (3-2)
+    dict(hash_slices=3, group_bits=12),       # uneven slices, 6-6
+    dict(hash_slices=8, group_bits=15),       # 1-7-7: a claiming third pass after the slices
+    dict(hash_slices=16, group_bits=14),      # sixteen slices, 7-7
+    dict(hash_slices=4, group_bits=13, pass1_bits=3),    # 3-7-3
+    dict(hash_slices=5, group_bits=16, fused_sort_match=1),  # sliced hash, fused tail
+    dict(hash_slices=2, group_bits=20),       # 6-7-7 (the k=31 split), tiny groups
+    dict(hash_slices=4, group_cap=64),        # sliced hash, oversized groups
 ]
 
 
@@ -272,7 +289,8 @@ def test_region_overflow_is_reported(vx):
     _assert_plot_equal(vx, b, oracle.plot(KEY0, k, threshold=0))
 
 
-@pytest.mark.parametrize("tun", [dict(group_bits=12), dict(group_bits=14, pass1_bits=4, pass2_bits=5)])
+@pytest.mark.parametrize("tun", [dict(group_bits=12), dict(group_bits=14, pass1_bits=4, pass2_bits=5),
+                                 dict(group_bits=12, hash_slices=4), dict(group_bits=16, hash_slices=3)])
 @pytest.mark.parametrize("pct", [10, 25])
 def test_region_overflow_with_matching_stays_bounded(vx, tun, pct):
     """Overflowing regions with the default threshold, so that the match
