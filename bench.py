@@ -145,7 +145,7 @@ def cpu_baseline(k_sample: int, target_k: int) -> dict:
     }
 
 
-def batched_compare(reps: int, autotuned: bool = False) -> dict:
+def batched_compare(reps: int, autotuned: bool = False, shared_hash: bool = False) -> dict:
     """The batched workload (32 plots, k uniform in 22..29, keys from
     SplitMix64 seed 4): the same plots one at a time through vx_plot, against
     one vx_plot_batch, eager and replayed as a HIP graph.  Every run is
@@ -162,6 +162,11 @@ def batched_compare(reps: int, autotuned: bool = False) -> dict:
         tun = [autotune.tuned(s.k, cache) for s in specs]
         tunings = [autotune.to_native(t) if t else vx.make_tuning() for t in tun]
         log(f"autotuned plots: {sum(t is not None for t in tun)}/{len(tun)}")
+    if shared_hash:
+        # every plot may share hash launches with the others (device work list)
+        tunings = tunings or [vx.make_tuning() for _ in specs]
+        for t in tunings:
+            t.batch_shared_hash = 1
     bt = B.alloc_batch(specs, tunings=tunings)
     log(f"batched: {len(specs)} plots, k={sorted(s.k for s in specs)}, "
         f"{bt.footprint_bytes() / 2**30:.1f} GiB on the device")
@@ -205,6 +210,7 @@ def batched_compare(reps: int, autotuned: bool = False) -> dict:
         "batched_graph_plots_per_hour": round(n * 3600.0 / t_graph, 1),
         "speedup_vs_sequential": round(t_seq / best, 3),
         "records": sum(1 << s.k for s in specs), "lanes": B.LANES, "autotuned": autotuned,
+        "shared_hash": shared_hash,
     }
     del bt
     torch.cuda.synchronize()
@@ -217,7 +223,7 @@ def bench_batched(args) -> dict:
     plots/hour of one batched launch (eager, and replayed as a HIP graph)
     against the same plots one at a time through vx_plot."""
     reps = max(1, args.steps)
-    r = batched_compare(reps, bool(args.autotune))
+    r = batched_compare(reps, bool(args.autotune), bool(args.shared_hash))
     return {
         "metric": "mixed-k plots/hour batched vs plain",
         "value": r["batched_plots_per_hour"],
@@ -532,6 +538,8 @@ def main() -> int:
     ap.add_argument("--budget-gb", type=float, default=250.0, help="serving: HBM budget (GiB)")
     ap.add_argument("--autotune", action="store_true",
                     help="batched: use the cached autotuned tuning per k")
+    ap.add_argument("--shared-hash", action="store_true",
+                    help="batched: let plots share hash launches (device work list) instead of lanes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 2 GiB device-to-device copy (known bytes) so that "
                          "HBM byte counters can be scaled against it")
@@ -628,6 +636,7 @@ def main() -> int:
     hbm_peak = opcount.MI355X_HBM_BYTES_PER_S
     npass = vx.vx_partition_passes(params, tun)
     hslices = vx.vx_hash_slices(params, tun)
+    tslices = vx.vx_tail_slices(params, tun)
     # With two or more passes the hash kernel also does the first pass (its
     # stage is then only the region scan); a one-pass plot hashes alone.  A
     # plot hashed in slices also does the second pass in the hash launches.
@@ -640,10 +649,16 @@ def main() -> int:
         kernel_of.update(hash=f"k_hash_pass x{hslices + 1} (hash in {hslices} slices + the second pass)",
                          partition1="k_region_scan_slices + k_region_bounds + k_colscan (pass 2 is in the hash)",
                          partition2="k_scatter claiming regions + k_region_bounds + k_colscan (third pass)")
+    in_tail = 1 if tslices > 1 and npass == 3 else 0
+    if tslices > 1:
+        kernel_of.update(match_emit=(f"k_pipe x{tslices + 1 + in_tail} ("
+                                     + ("third pass + " if in_tail else "")
+                                     + f"group sort + match + H2, pipelined over {tslices} slices)"),
+                         group_sort="(in the pipelined tail)", chunk_sums="(sums made by the sort)")
     algo_bytes = {
         "partition1": 0 if fused_first else n * (8 + 12),  # read key, write key+nonce
         # each later pass reads and writes key+nonce
-        "partition2": max(0, npass - max(in_hash, 1)) * n * (12 + 12),
+        "partition2": max(0, npass - max(in_hash, 1) - in_tail) * n * (12 + 12),
         # read and write key+nonce, offsets, one pair-count byte per record
         "group_sort": n * (12 + 12 + 1) + (vx.VX_NUM_BUCKETS + 1) * 4,
         "chunk_sums": n * 1,                     # read the count bytes
@@ -706,7 +721,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"k={k} single plot", "k": k, "nonces": n, "key_seed": 0,
                    "threshold": f"2^{64 - k}", "buckets": 1 << 24, "partition_passes": npass,
-                   "hash_slices": hslices, "parallelism": "single GPU"},
+                   "hash_slices": hslices, "tail_slices": tslices, "parallelism": "single GPU"},
         "blake3_hashes_per_s": round((n + t2n) / plot_s, 1),
         "plots_per_hour": round(3600.0 / plot_s, 1),
         "table2_records": t2n,

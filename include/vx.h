@@ -129,6 +129,17 @@ typedef struct {
                                   many nonce slices, each launch filing the previous slice's records
                                   by the second digit beside the next slice's hash (plots whose two
                                   leading digits fit 7 bits each); 0 = the default for k */
+    uint32_t tail_slices;      /* vx_plot: 1 = the third partition pass, the sort and the match as
+                                  separate kernels; 2..16 = pipelined over that many slices of the
+                                  second pass's regions, one persistent launch per step running the
+                                  third pass of one slice, the sort of the previous and the match of
+                                  the one before (plots with region passes, group_cap <= 2560 and
+                                  digits of at most 7 bits after the second); 0 = the default for k */
+    uint32_t batch_shared_hash; /* vx_plot_batch: nonzero lets this plot's hash launches (and its
+                                  second and third partition passes) be shared with other plots of
+                                  the batch that ask for it -- one persistent launch per step over a
+                                  device work list of slices of several plots; 0 (default) runs the
+                                  plot on its own, on one of the batch's lanes */
 } vx_tuning;
 
 enum { VX_CALL_BUCKET_SORT = 1, VX_CALL_MATCH = 2, VX_CALL_PLOT = 3 };
@@ -152,6 +163,12 @@ uint32_t vx_partition_passes(const vx_plot_params *params, const vx_tuning *tuni
  * first two partition passes are done by then.  No device work.  Returns 0
  * for invalid params or tuning. */
 uint32_t vx_hash_slices(const vx_plot_params *params, const vx_tuning *tuning);
+
+/* Slices over which vx_plot pipelines the work after the first two
+ * partition passes (the third pass, the sort and the match, in one
+ * persistent launch per step): 1 = not pipelined.  No device work.  Returns
+ * 0 for invalid params or tuning. */
+uint32_t vx_tail_slices(const vx_plot_params *params, const vx_tuning *tuning);
 
 /* A Table-2 capacity that holds |Table 2| of a k-plot with threshold T with
  * overwhelming probability (expectation plus a generous margin). */

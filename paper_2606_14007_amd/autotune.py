@@ -1,12 +1,15 @@
 """Autotuner for the plot's implementation parameters (vx_tuning).
 
-For a given k it times a small set of candidate tunings -- sort-group size,
-match-chunk size, hash fused with the first pass or not -- on the current
-GPU and keeps the fastest.
-No candidate changes any output (they only move work between kernels), so
-picking by time is safe.  Results are cached in JSON keyed by GPU
-architecture and k (tuning_cache.json next to this file, or the path in
-VX_TUNING_CACHE).
+For a given k it searches the tunables that shape the plot's kernels -- the
+hash's nonce slices (each slice's second partition pass runs beside the next
+slice's hash), the first partition digit's width, the sort-group bits (how
+finely the partition passes cut the bucket space), the sort group's LDS
+capacity and the match chunk -- one at a time from the built-in default
+(coordinate descent: each tunable's alternatives are timed with the others
+at their best so far) and keeps the fastest.  No candidate changes any
+output (they only move work between kernels), so picking by time is safe.
+Results are cached in JSON keyed by GPU architecture and k
+(tuning_cache.json next to this file, or the path in VX_TUNING_CACHE).
 """
 from __future__ import annotations
 
@@ -24,7 +27,8 @@ CACHE_PATH = os.environ.get("VX_TUNING_CACHE",
                             os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                          "tuning_cache.json"))
 FIELDS = ("group_bits", "pass1_bits", "group_cap", "h1_tiles", "match_chunk_bits", "pass2_bits",
-          "fused_sort_match", "pipeline_slices", "separate_hash", "region_pct")
+          "fused_sort_match", "pipeline_slices", "separate_hash", "region_pct", "hash_slices", "tail_slices",
+          "batch_shared_hash")
 
 
 def arch() -> str:
@@ -34,16 +38,25 @@ def arch() -> str:
     return getattr(props, "gcnArchName", props.name).split(":")[0]
 
 
+def axes(k: int) -> List[tuple]:
+    """The tunables searched for k, each with its alternatives (0 = the
+    built-in default for k)."""
+    gb = [g for g in (k - 12, k - 11, k - 10) if 1 <= g <= 21]
+    return [
+        ("hash_slices", [0, 1, 4, 16]),            # hash work per launch (slices)
+        ("group_bits", [0] + gb),                  # sort groups = bucket-partition granularity
+        ("pass1_bits", [0, 4, 5, 6, 7, 8]),        # first partition digit
+        ("group_cap", [0, 3072]),                  # sort group capacity in LDS
+        ("match_chunk_bits", [0, 10]),             # match chunk (records)
+    ]
+
+
 def candidates(k: int) -> List[Dict[str, int]]:
-    out = []
-    for gb in (k - 12, k - 11, k - 10):
-        if not 1 <= gb <= 20:
-            continue
-        for cb in (10, 11):
-            # the hash with the first partition pass fused in (default), or
-            # the two as separate kernels
-            for sep in (0, 1):
-                out.append({"group_bits": gb, "match_chunk_bits": cb, "separate_hash": sep})
+    """Every single-axis variant of the default (the first round of the
+    search); used by tests and as a quick list."""
+    out = [{}]
+    for name, vals in axes(k):
+        out += [{name: v} for v in vals if v]
     return out
 
 
@@ -53,7 +66,12 @@ def to_native(d: Optional[Dict[str, int]]) -> Optional[N.VxTuning]:
     return N.make_tuning(**{f: int(d.get(f, 0)) for f in FIELDS})
 
 
-def _time_plot(k: int, tuning: N.VxTuning, reps: int, key: bytes) -> float:
+def valid(k: int, d: Dict[str, int]) -> bool:
+    p = N.make_params(bytes(32), k)
+    return N.vx_workspace_bytes(p, N.VX_CALL_PLOT, to_native(d) or N.make_tuning()) > 0
+
+
+def _time_plot(k: int, tuning, reps: int, key: bytes) -> float:
     b = alloc_plot(k, tuning=tuning)
     p = N.make_params(key, k)
     nb = b.native()
@@ -70,17 +88,29 @@ def _time_plot(k: int, tuning: N.VxTuning, reps: int, key: bytes) -> float:
 
 
 def tune(k: int, reps: int = 3, key: bytes = bytes(range(32)), verbose: bool = False) -> Dict:
-    best, best_t, results = None, float("inf"), []
-    for cand in candidates(k):
-        t = _time_plot(k, to_native(cand), reps, key)
-        results.append((cand, t))
-        if verbose:
-            print(f"k={k} {cand} {t * 1e3:.3f} ms", flush=True)
-        if t < best_t:
-            best, best_t = cand, t
-    default_t = _time_plot(k, None, reps, key)
-    return {"tuning": best, "ms": best_t * 1e3, "default_ms": default_t * 1e3,
-            "tried": len(results)}
+    """Coordinate descent over axes(k) from the default."""
+    seen: Dict[str, float] = {}
+
+    def timed(d):
+        tag = json.dumps(d, sort_keys=True)
+        if tag not in seen:
+            seen[tag] = _time_plot(k, to_native(d), reps, key)
+            if verbose:
+                print(f"k={k} {d} {seen[tag] * 1e3:.3f} ms", flush=True)
+        return seen[tag]
+
+    best: Dict[str, int] = {}
+    best_t = timed(best)
+    default_t = best_t
+    for name, vals in axes(k):
+        for v in vals:
+            cand = {**best, name: v} if v else {q: w for q, w in best.items() if q != name}
+            if cand == best or not valid(k, cand):
+                continue
+            t = timed(cand)
+            if t < best_t:
+                best, best_t = cand, t
+    return {"tuning": best or None, "ms": best_t * 1e3, "default_ms": default_t * 1e3, "tried": len(seen)}
 
 
 def load_cache(path: str = CACHE_PATH) -> Dict:
@@ -101,7 +131,7 @@ def tuned(k: int, cache: Optional[Dict] = None) -> Optional[Dict[str, int]]:
     """Cached tuning for k on this GPU (None = built-in defaults)."""
     cache = load_cache() if cache is None else cache
     rec = cache.get(arch(), {}).get(str(k))
-    if rec and rec.get("ms", 0) < rec.get("default_ms", 0):
+    if rec and rec.get("tuning") and rec.get("ms", 0) < rec.get("default_ms", 0):
         return rec["tuning"]
     return None
 

@@ -48,11 +48,21 @@ constexpr uint32_t kDefaultSlices = 1;
 // A plot hashed in slices files each slice's records by the second digit
 // beside the next slice's hash (run_sliced_front).
 constexpr uint32_t kMaxHashSlices = 16;
-// Measured (one box, median plot time, 1 / 4 / 8 / 16 slices): k=31 112.7 /
-// 110.2 / 108.6 / 107.9 ms, k=30 57.9 / 55.3 / 54.5 / 54.0 ms; at k <= 29
-// the sliced digits (a seven-bit second digit, hence a third pass below
-// k = 29) made plots slower (k=29 29.5 -> 34.0 ms, k=28 13.8 -> 18.4 ms).
-uint32_t default_hash_slices(uint32_t k) { return k >= 30 ? 16 : 1; }
+// Each hash slice's first-pass fill counters start on a 256-byte line of
+// their own: a slice's hash claims room with atomics on them while the next
+// launch reads them, and two slices sharing a line (16 counters at k = 29)
+// made every other launch of a k=29 plot twice as slow.
+inline uint32_t slice_fill_stride(uint32_t d0) { return ((1u << d0) + 63u) & ~63u; }
+// Measured (one box, median plot time, 1 / 4 / 16 slices): k=31 114.0 /
+// 108.8 / 103.8 ms, k=30 57.8 / 55.0 / 53.4, k=29 29.2 / 27.5 / 26.9,
+// k=27 6.63 / 6.26 / 6.37, k=26 3.25 / 3.13 / 3.43, k=25 1.73 / 1.62 / 2.06;
+// at k=28 the sliced split needs a third pass (13.6 / 13.9 / 13.8), and
+// below k=25 the hash is too short to hide a pass.
+uint32_t default_hash_slices(uint32_t k) { return k >= 29 ? 16 : (k >= 25 && k <= 27 ? 4 : 1); }
+// A plot's work after its first two partition passes can be pipelined over
+// slices (run_pipe_tail).
+constexpr uint32_t kMaxTailSlices = 16;
+uint32_t default_tail_slices(uint32_t /*k*/) { return 1; }
 
 struct Plan {
     uint32_t k = 0;
@@ -73,6 +83,7 @@ struct Plan {
     bool hs = false;         // plot: region passes (the hash does the first; see make_plan)
     uint32_t R[kMaxPasses] = {};  // hs: records per region of each pass (pass 0: per hash slice)
     uint32_t hq = 1;         // plot: nonce slices of the hash (>= 2: see run_sliced_front)
+    uint32_t zt = 1;         // plot: slices of the pipelined tail (>= 2: see run_pipe_tail)
     int staged = -1;         // >= 0: one chunk (of 2^staged) of a staged plot; see vx_stage_plot
 };
 
@@ -142,8 +153,9 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     }
     const bool hs_ok = (!records || staged >= 0) && !t->separate_hash;
     if (t->hash_slices > kMaxHashSlices) return fail(VX_ERR_UNSUPPORTED, "hash_slices must be at most 16");
+    if (t->tail_slices > kMaxTailSlices) return fail(VX_ERR_UNSUPPORTED, "tail_slices must be at most 16");
     // Hash slices: whole plots whose first two digits fit the sliced
-    // kernel's 7 bits; the pipelined tail keeps its own split.
+    // kernel's 8 bits; the pipelined tail keeps its own split.
     uint32_t hq = t->hash_slices ? t->hash_slices : default_hash_slices(P.k);
     if (records || staged >= 0 || t->separate_hash || P.slices > 1 || P.G < 2 ||
         P.G > 2u * vxk::kHashPassMaxBits + (uint32_t)vxk::kHashPassMaxBits)
@@ -151,20 +163,27 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     // The digits of the passes for hq hash slices (see below).
     auto split = [&](uint32_t q, uint32_t &d0, uint32_t &d1, uint32_t &d2) -> vx_status {
         if (q > 1) {
-            // Both digits of the sliced kernel take at most 7 bits.  Up to 14
-            // group bits they are the only passes; above, the third (a
-            // claiming scatter of its own) takes 7 bits and the hash the rest.
+            // Both digits of the sliced kernel take at most 8 bits.  Up to 16
+            // group bits they are the only passes; above, the second and the
+            // third (a claiming scatter of its own) take 7 bits, the width
+            // those scatters write fastest, and the hash the rest.
             if (P.G <= 2u * vxk::kHashPassMaxBits) {
                 d0 = (P.G + 1) / 2; d1 = P.G - d0; d2 = 0;
             } else {
-                d1 = vxk::kHashPassMaxBits;
-                d2 = std::min<uint32_t>(vxk::kHashPassMaxBits, P.G - d1 - 1);
+                d1 = 7;
+                d2 = std::min<uint32_t>(7, P.G - d1 - 1);
                 d0 = P.G - d1 - d2;
             }
         } else if (P.G <= 9) {
             d0 = P.G; d1 = 0; d2 = 0;
         } else if (P.slices > 1 && P.G >= 13) {
             d0 = P.G - 12; d1 = 6; d2 = 6;
+        } else if (hs_ok && P.G <= 13) {
+            // The hash kernel files its first digit behind the ALU-bound
+            // hash, so small plots give it 8 bits and the claiming scatter
+            // the rest (autotuned: k=22 0.27 against 0.33 ms with 6-5, k=23
+            // 0.44 against 0.48 ms with 6-6).
+            d0 = std::min(8u, P.G - 1); d1 = P.G - d0; d2 = 0;
         } else if (P.G <= 17) {
             d0 = (P.G + 1) / 2;
             if (hs_ok) d0 = std::min(d0, 8u);
@@ -275,6 +294,17 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
             P.R[0] = r0;
         }
     }
+    // The pipelined tail: whole plots with region passes, the split sort (of
+    // the 2560-record kernel) and match, and a third digit (if any) within
+    // the filing kernel's 7 bits; slices cut the second pass's regions.
+    {
+        const uint32_t zt = t->tail_slices ? t->tail_slices : default_tail_slices(P.k);
+        const uint32_t n1 = P.npass >= 2 ? 1u << (P.pre[1] + P.D[1]) : 0;
+        if (zt > 1 && !records && staged < 0 && !P.fused && P.slices == 1 && P.hs && P.npass >= 2 &&
+            P.cap <= (uint32_t)vxk::kGroupCapFast && (P.npass < 3 || P.D[2] <= (uint32_t)vxk::kPipeMaxBits) &&
+            n1 >= zt)
+            P.zt = zt;
+    }
     if (staged >= 0 && !P.hs)
         return fail(VX_ERR_UNSUPPORTED,
                     "staged plots need two or more partition passes, a first digit of at most 8 bits and at "
@@ -300,11 +330,12 @@ struct Layout {
     // hs, per pass: u32[2^(pre + D)] region fill counts and bounds
     size_t fill[kMaxPasses] = {}, seg_lo[kMaxPasses] = {}, seg_hi[kMaxPasses] = {};
     size_t mpart = 0;             // u64[scan parts]
+    size_t pipelist = 0;          // the work list of a k_pipe launch (plot)
     size_t total = 0;
 };
 
 // Workspace header: u32 words zeroed at the start of every call.
-constexpr uint32_t kHeaderWords = 96;
+constexpr uint32_t kHeaderWords = 128;
 constexpr uint32_t kHdrStatus = 0;       // device status bits
 constexpr uint32_t kHdrFusedTicket = 2;  // group ticket of the fused sort + match
 constexpr uint32_t kHdrAcc = 4;          // u64 (words 4, 5): Table-2 records of the slices scanned so far
@@ -313,7 +344,10 @@ constexpr uint32_t kHdrOvf = 8;          // per slice: oversized groups found
 constexpr uint32_t kHdrSortTicket = 8 + kMaxSlices;       // per slice: group ticket of the sort
 constexpr uint32_t kHdrEmitTicket = 8 + 2 * kMaxSlices;   // per slice: chunk ticket of the match
 constexpr uint32_t kHdrHashPassTicket = 8 + 3 * kMaxSlices;  // per launch of a sliced hash
-static_assert(kHdrHashPassTicket + kMaxHashSlices + 1 <= kHeaderWords, "header holds every slice's words");
+constexpr uint32_t kHdrPipeTicket = kHdrHashPassTicket + kMaxHashSlices + 1;  // per launch of a pipelined tail
+constexpr uint32_t kHdrBatchTicket = kHdrPipeTicket + kMaxTailSlices + 2;  // fused launches of a batch
+constexpr uint32_t kBatchTicketWords = kHeaderWords - kHdrBatchTicket;
+static_assert(kBatchTicketWords >= 21, "a batch round needs up to 21 launches per plot");
 constexpr uint32_t kLookbackSpinLimit = 1u << 20;
 
 constexpr int kCallChunk = 4;        // internal: the workspace of vx_plot_chunk
@@ -357,7 +391,7 @@ Layout layout(const Plan &P, int which) {
     if (hs) L.reg_nonces = take(cap_even * 4);
     for (uint32_t i = 0; hs && i < P.npass; ++i) {
         const size_t nr = (size_t)1 << (P.pre[i] + P.D[i]);
-        L.fill[i] = take(nr * 4 * (i == 0 ? P.hq : 1));
+        L.fill[i] = take(i == 0 && P.hq > 1 ? (size_t)slice_fill_stride(P.D[0]) * P.hq * 4 : nr * 4);
         L.seg_lo[i] = take(nr * 4);
         L.seg_hi[i] = take(nr * 4);
     }
@@ -380,6 +414,7 @@ Layout layout(const Plan &P, int which) {
         L.mcount = take((size_t)nch * 8);
         L.mbase = take((size_t)nch * 8);
         L.mpart = take((size_t)vxk::scan_parts(nch) * 8);
+        if (which == VX_CALL_PLOT && !chunk && !staged) L.pipelist = take(sizeof(vxk::PipeList));
         L.pcnt = take(align_up(P.n, 4));
     }
     L.total = at;
@@ -539,11 +574,15 @@ vx_status run_pass(const Plan &P, const Layout &L, void *ws, const PassBufs &B, 
 // Partition passes [0, npass_run).  Pass 0 reads the nonce-order keys (its
 // histogram comes from the hash kernel in a plot, or from a histogram pass
 // over caller keys).
+// The passes a plot's hash launches file: none (a separate hash), the first
+// (the hash kernel's own), or the first two (sliced or fused launches).
+uint32_t hash_passes(const Plan &P) { return P.hs ? (P.hq > 1 ? 2 : 1) : 0; }
+
 vx_status run_partition(const Plan &P, const Layout &L, void *ws, const uint64_t *keys_no,
                         bool hist_done, uint64_t *t1_keys, uint32_t *t1_nonces, uint32_t npass_run,
-                        hipStream_t s, hipEvent_t *ev, const uint32_t *nonces_in = nullptr) {
-    // A sliced hash (P.hq > 1) has done the first two passes.
-    const uint32_t first = P.hs ? (P.hq > 1 ? 2 : 1) : 0;
+                        hipStream_t s, hipEvent_t *ev, const uint32_t *nonces_in = nullptr,
+                        uint32_t first = UINT32_MAX) {
+    if (first == UINT32_MAX) first = hash_passes(P);
     if (first >= npass_run) VX_HIP(mark(ev, 3, s), "event");
     for (uint32_t i = first; i < npass_run; ++i) {
         const PassBufs B = pass_bufs(P, L, ws, keys_no, t1_keys, t1_nonces, i, nonces_in);
@@ -576,56 +615,91 @@ vx_status run_partition(const Plan &P, const Layout &L, void *ws, const uint64_t
 // second-pass regions, shared by all slices.  Then the first digit's group
 // starts over all slices, and the second pass's region bounds and group
 // starts.
+// Slice i of a plan whose hash files two passes (P.hs, two or more passes,
+// both digits within the sliced kernel's width; P.hq slices, one when the
+// plan is not sliced): its hash (first digit, into the slice's own regions)
+// and its second pass (over those regions, into the plot's second-pass
+// regions).
+bool front_fusable(const Plan &P) {
+    return P.hs && P.npass >= 2 && P.D[0] <= (uint32_t)vxk::kHashPassMaxBits &&
+           P.D[1] <= (uint32_t)vxk::kHashPassMaxBits;
+}
+
+uint32_t front_fill_stride(const Plan &P) { return P.hq > 1 ? slice_fill_stride(P.D[0]) : 1u << P.D[0]; }
+
+vxk::HashSliceDesc hash_slice(const Plan &P, const Layout &L, void *ws, uint32_t i) {
+    vxk::HashSliceDesc H;
+    memset(&H, 0, sizeof(H));
+    const uint64_t slice_recs = ((uint64_t)P.R[0]) << P.D[0];
+    memcpy(H.key, P.key_words, sizeof(H.key));
+    H.nonce0 = P.n * i / P.hq;
+    H.n = P.n * (i + 1) / P.hq - H.nonce0;
+    H.keys = at<uint64_t>(ws, L.keys_no) + i * slice_recs;
+    H.nonces = at<uint32_t>(ws, L.reg_nonces) + i * slice_recs;
+    H.fill = at<uint32_t>(ws, L.fill[0]) + (size_t)i * front_fill_stride(P);
+    H.status = at<uint32_t>(ws, L.header) + kHdrStatus;
+    H.bits = P.D[0];
+    H.R = P.R[0];
+    H.items = (uint32_t)((H.n + vxk::kHashScatterSub - 1) / vxk::kHashScatterSub);
+    return H;
+}
+
+vxk::PassSliceDesc pass_slice(const Plan &P, const Layout &L, void *ws, uint32_t i) {
+    vxk::PassSliceDesc Q;
+    memset(&Q, 0, sizeof(Q));
+    const uint64_t slice_recs = ((uint64_t)P.R[0]) << P.D[0];
+    const uint32_t per = (P.R[0] + vxk::kHashScatterSub - 1) / vxk::kHashScatterSub;
+    Q.keys = at<uint64_t>(ws, L.keys_no) + i * slice_recs;
+    Q.nonces = at<uint32_t>(ws, L.reg_nonces) + i * slice_recs;
+    Q.fill = at<uint32_t>(ws, L.fill[0]) + (size_t)i * front_fill_stride(P);
+    Q.out_keys = at<uint64_t>(ws, L.scr_keys);
+    Q.out_nonces = at<uint32_t>(ws, L.scr_nonces);
+    Q.out_fill = at<uint32_t>(ws, L.fill[1]);
+    Q.status = at<uint32_t>(ws, L.header) + kHdrStatus;
+    Q.R_in = P.R[0];
+    Q.per = per;
+    Q.shift = 64 - P.D[0] - P.D[1];
+    Q.bits = P.D[1];
+    Q.R_out = P.R[1];
+    Q.items = (1u << P.D[0]) * per;
+    return Q;
+}
+
+// Proportions of a launch's two kinds of items (k_hash_pass).
+void set_frac(vxk::HashPassList &W) {
+    const uint64_t nt = (uint64_t)W.h_items + W.p_items;
+    const uint64_t num = (uint64_t)W.h_items << 32;
+    W.h_frac = nt ? num / nt + (num % nt ? 1 : 0) : 0;
+}
+
+// After every slice's second pass: the first digit's group starts over all
+// slices, then the second pass's region bounds and group starts.
+vx_status finish_front(const Plan &P, const Layout &L, void *ws, hipStream_t s) {
+    const uint32_t nd0 = 1u << P.D[0];
+    VX_HIP(vxk::launch_region_scan_slices(at<uint32_t>(ws, L.fill[0]), P.hq, front_fill_stride(P), nd0, P.R[0],
+                                          at<uint32_t>(ws, L.gstart[0]), s),
+           "region scan");
+    return claimed_regions(P, L, ws, 1, 0, nd0, s);
+}
+
 vx_status run_sliced_front(const Plan &P, const Layout &L, void *ws, hipStream_t s, hipEvent_t *ev) {
     uint32_t *hdr = at<uint32_t>(ws, L.header);
-    const uint32_t nd0 = 1u << P.D[0];
-    uint64_t *reg_k = at<uint64_t>(ws, L.keys_no);
-    uint32_t *reg_n = at<uint32_t>(ws, L.reg_nonces);
-    uint32_t *fill0 = at<uint32_t>(ws, L.fill[0]);
-    const uint64_t slice_recs = (uint64_t)nd0 * P.R[0];
-    const uint32_t per = (P.R[0] + vxk::kHashScatterSub - 1) / vxk::kHashScatterSub;
     for (uint32_t i = 0; i <= P.hq; ++i) {
         vxk::HashPassList W;
         memset(&W, 0, sizeof(W));
         if (i < P.hq) {
-            vxk::HashSliceDesc &H = W.h[W.nh++];
-            memcpy(H.key, P.key_words, sizeof(H.key));
-            H.nonce0 = P.n * i / P.hq;
-            H.n = P.n * (i + 1) / P.hq - H.nonce0;
-            H.keys = reg_k + i * slice_recs;
-            H.nonces = reg_n + i * slice_recs;
-            H.fill = fill0 + (size_t)i * nd0;
-            H.status = hdr + kHdrStatus;
-            H.bits = P.D[0];
-            H.R = P.R[0];
-            H.items = (uint32_t)((H.n + vxk::kHashScatterSub - 1) / vxk::kHashScatterSub);
-            W.h_items += H.items;
+            W.h[W.nh++] = hash_slice(P, L, ws, i);
+            W.h_items += W.h[0].items;
         }
         if (i >= 1) {
-            vxk::PassSliceDesc &Q = W.p[W.np++];
-            Q.keys = reg_k + (i - 1) * slice_recs;
-            Q.nonces = reg_n + (i - 1) * slice_recs;
-            Q.fill = fill0 + (size_t)(i - 1) * nd0;
-            Q.out_keys = at<uint64_t>(ws, L.scr_keys);
-            Q.out_nonces = at<uint32_t>(ws, L.scr_nonces);
-            Q.out_fill = at<uint32_t>(ws, L.fill[1]);
-            Q.status = hdr + kHdrStatus;
-            Q.R_in = P.R[0];
-            Q.per = per;
-            Q.shift = 64 - P.D[0] - P.D[1];
-            Q.bits = P.D[1];
-            Q.R_out = P.R[1];
-            Q.items = nd0 * per;
-            W.p_items += Q.items;
+            W.p[W.np++] = pass_slice(P, L, ws, i - 1);
+            W.p_items += W.p[0].items;
         }
-        const uint64_t nt = (uint64_t)W.h_items + W.p_items;
-        W.h_frac = ((uint64_t)W.h_items << 32) / nt + ((((uint64_t)W.h_items << 32) % nt) ? 1 : 0);
+        set_frac(W);
         VX_HIP(vxk::launch_hash_pass(W, hdr + kHdrHashPassTicket + i, s), "sliced hash");
     }
     VX_HIP(mark(ev, 1, s), "event");
-    VX_HIP(vxk::launch_region_scan_slices(fill0, P.hq, nd0, P.R[0], at<uint32_t>(ws, L.gstart[0]), s),
-           "region scan");
-    vx_status st = claimed_regions(P, L, ws, 1, 0, nd0, s);
+    vx_status st = finish_front(P, L, ws, s);
     if (st != VX_OK) return st;
     VX_HIP(mark(ev, 2, s), "event");
     return VX_OK;
@@ -638,7 +712,9 @@ vx_status run_sliced_front(const Plan &P, const Layout &L, void *ws, hipStream_t
 // record's pair count (one byte) while the group is in LDS.  sums: it also
 // adds the counts up per match chunk (L.mcount, zeroed here first), so that
 // the match needs no pass over the count bytes; only when the sorted groups
-// hold every record of the table.
+// hold every record of the table.  (The reductions cost the sort more than
+// the separate pass over the count bytes takes, measured at k=31: 15.6 ms
+// against 12.9 + 0.8 ms; the pipelined tail uses them, the rest does not.)
 vx_status run_group_sort(const Plan &P, const Layout &L, void *ws, uint64_t *t1_keys, uint32_t *t1_nonces,
                          uint32_t *offsets, uint8_t *pcnt, uint32_t g0, uint32_t gcount, uint32_t slot,
                          hipStream_t s, bool sums = false) {
@@ -699,6 +775,116 @@ vx_status run_match(const Plan &P, const Layout &L, void *ws, const uint64_t *t1
                                   r_lo, r_hi, last, nch, wg_per_cu, hdr + kHdrEmitTicket + slot, s),
            "match emit");
     VX_HIP(mark(ev, 6, s), "event");
+    return VX_OK;
+}
+
+// The plot's work after its first two partition passes, software-pipelined
+// over P.zt slices of the second pass's regions (of the groups, when there
+// are only two passes).  Launch i of k_pipe files slice i by the third
+// digit, sorts slice i - 1 and matches slice i - 2 (fewer stages without a
+// third pass); between launches come the third pass's region bounds and
+// group starts of slice i, the fallback sort of slice i - 1's oversized
+// groups, and the Table-2 bases of the match chunks that slice i - 1 owns
+// (a ranged scan carrying the running total; the last one stores |T2|).
+// The sort adds each chunk's pair count (csum), so no pass over the count
+// bytes is needed.  A slice's groups end at bucket boundaries, so a chunk's
+// partners lie in its own slice or an earlier one, all sorted by then.
+vx_status run_pipe_tail(const Plan &P, const Layout &L, void *ws, const vx_plot_buffers *b, hipStream_t s) {
+    uint32_t *hdr = at<uint32_t>(ws, L.header);
+    const uint32_t last = P.npass - 1;
+    const bool p3 = P.npass == 3;
+    const uint32_t N1 = 1u << (P.pre[1] + P.D[1]);
+    const uint32_t Z = P.zt;
+    const uint32_t gper = p3 ? 1u << P.D[2] : 1u;
+    const uint32_t *gst1 = at<uint32_t>(ws, L.gstart[1]);
+    uint64_t *csum = at<uint64_t>(ws, L.mcount), *base = at<uint64_t>(ws, L.mbase);
+    uint8_t *pcnt = at<uint8_t>(ws, L.pcnt);
+    uint32_t *ovf_list = at<uint32_t>(ws, L.ovf_list);
+    VX_HIP(vxk::launch_zero_u64(csum, match_chunks(P), s), "zero chunk sums");
+    const PassBufs Bl = pass_bufs(P, L, ws, nullptr, b->t1_keys, b->t1_nonces, last);
+    const PassBufs B2 = pass_bufs(P, L, ws, nullptr, b->t1_keys, b->t1_nonces, p3 ? 2 : last);
+    const uint32_t per = (P.R[1] + vxk::kPipeSub - 1) / vxk::kPipeSub;
+    vxk::PipeList *dl = at<vxk::PipeList>(ws, L.pipelist);
+    const uint32_t off_s = p3 ? 1 : 0, off_m = off_s + 1;
+    auto cut = [&](uint32_t j) { return (uint32_t)((uint64_t)N1 * j / Z); };
+    const vxk::SortArgs sa{b->t1_keys, b->t1_nonces,
+                           vxk::GroupIn{Bl.out_k, Bl.out_n, at<uint32_t>(ws, L.seg_lo[last]),
+                                        at<uint32_t>(ws, L.seg_hi[last])},
+                           at<uint32_t>(ws, L.gstart[last]), b->bucket_offsets, nullptr, nullptr, pcnt,
+                           reinterpret_cast<unsigned long long *>(csum), P.T, P.G, P.cap, (uint32_t)P.n, P.cb};
+    vxk::MatchArgs ma{{}, b->t1_keys, b->t1_nonces, pcnt, base, reinterpret_cast<uint4 *>(b->t2), b->t2_capacity,
+                      P.T, (uint32_t)P.n, P.cb};
+    memcpy(ma.key, P.key_words, sizeof(ma.key));
+    for (uint32_t i = 0; i < Z + off_m; ++i) {
+        vxk::PipeList W;
+        memset(&W, 0, sizeof(W));
+        if (p3 && i < Z) {  // the third pass over slice i
+            const uint32_t a = cut(i), e = cut(i + 1);
+            vxk::PassSliceDesc &Q = W.p[W.n[1]++];
+            Q.keys = B2.in_k + (uint64_t)a * P.R[1];
+            Q.nonces = B2.in_n + (uint64_t)a * P.R[1];
+            Q.fill = at<uint32_t>(ws, L.fill[1]) + a;
+            Q.out_keys = B2.out_k;
+            Q.out_nonces = B2.out_n;
+            Q.out_fill = at<uint32_t>(ws, L.fill[2]);
+            Q.status = hdr + kHdrStatus;
+            Q.R_in = P.R[1];
+            Q.per = per;
+            Q.shift = 64 - P.pre[2] - P.D[2];
+            Q.bits = P.D[2];
+            Q.R_out = P.R[2];
+            Q.items = (e - a) * per;
+            Q.r0 = a;
+            W.items[1] += Q.items;
+        }
+        if (i >= off_s && i - off_s < Z) {  // the sort of slice j
+            const uint32_t j = i - off_s, a = cut(j), e = cut(j + 1);
+            vxk::PipeSortDesc &D = W.s[W.n[2]++];
+            D.a = sa;
+            D.a.ovf_count = hdr + kHdrOvf + j;
+            D.a.ovf_list = ovf_list + a * gper;
+            D.g0 = a * gper;
+            D.items = (e - a) * gper;
+            W.items[2] += D.items;
+        }
+        if (i >= off_m) {  // the match of slice j
+            const uint32_t j = i - off_m, a = cut(j), e = cut(j + 1);
+            vxk::PipeMatchDesc &M = W.m[W.n[3]++];
+            M.a = ma;
+            M.r_lo = gst1 + a;
+            M.r_hi = gst1 + e;
+            M.last = j + 1 == Z;
+            // The slice's records fit its second-pass regions; its chunks are
+            // at most one more than its records fill.
+            const uint64_t maxrec = std::min<uint64_t>(P.n, (uint64_t)(e - a) * P.R[1]);
+            M.items = (uint32_t)(maxrec >> P.cb) + 2;
+            W.items[3] += M.items;
+        }
+        uint64_t rest = (uint64_t)W.items[0] + W.items[1] + W.items[2] + W.items[3];
+        for (int r = 0; r < 3; ++r) {
+            const uint64_t num = (uint64_t)W.items[r] << 32;
+            W.frac[r] = rest ? num / rest + (num % rest ? 1 : 0) : 0;
+            rest -= W.items[r];
+        }
+        VX_HIP(vxk::launch_pipe(W, dl, hdr + kHdrPipeTicket + i, s), "pipelined tail");
+        if (p3 && i < Z) {
+            vx_status st = claimed_regions(P, L, ws, 2, cut(i), cut(i + 1), s);
+            if (st != VX_OK) return st;
+        }
+        if (i >= off_s && i - off_s < Z) {
+            const uint32_t j = i - off_s, a = cut(j), e = cut(j + 1);
+            VX_HIP(vxk::launch_group_fallback(b->t1_keys, b->t1_nonces, Bl.out_k, Bl.out_n,
+                                              at<uint32_t>(ws, L.seg_lo[last]), at<uint32_t>(ws, L.seg_hi[last]),
+                                              at<uint64_t>(ws, L.scr_keys), at<uint32_t>(ws, L.scr_nonces),
+                                              at<uint32_t>(ws, L.gstart[last]), P.G, b->bucket_offsets,
+                                              hdr + kHdrOvf + j, ovf_list + a * gper, hdr + kHdrStatus, P.T, pcnt,
+                                              csum, P.cb, s),
+                   "group sort fallback");
+            VX_HIP(vxk::launch_scan_range(csum, base, (uint32_t)P.n, P.cb, gst1 + a, gst1 + e, j + 1 == Z,
+                                          reinterpret_cast<uint64_t *>(hdr + kHdrAcc), b->t2_count, s),
+                   "match scan");
+        }
+    }
     return VX_OK;
 }
 
@@ -866,6 +1052,12 @@ uint32_t vx_hash_slices(const vx_plot_params *params, const vx_tuning *tuning) {
     return P.hq;
 }
 
+uint32_t vx_tail_slices(const vx_plot_params *params, const vx_tuning *tuning) {
+    Plan P;
+    if (make_plan(params, tuning, &P) != VX_OK) return 0;
+    return P.zt;
+}
+
 uint64_t vx_t2_capacity_hint(uint32_t k, uint64_t threshold) {
     if (k < 1 || k > 31) return 0;
     // Expected pairs per record for uniform keys: neighbours within T inside
@@ -1013,11 +1205,11 @@ vx_status vx_plot_chunk(const vx_plot_params *params, uint32_t chunk_bits, uint3
     const uint32_t g0 = own ? chunk << (P.G - chunk_bits) : 0;
     const uint32_t gn = own ? 1u << (P.G - chunk_bits) : 1u << P.G;
     st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, at<uint8_t>(ws, L.pcnt), g0, gn, 0,
-                        s, true);
+                        s);
     if (st == VX_OK && own) st = fill_outside_offsets(b->bucket_offsets, chunk_bits, chunk, m, s);
     if (st == VX_OK)
         st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, nullptr, nullptr, 1,
-                       0, 0, s, nullptr, true);
+                       0, 0, s);
     if (st == VX_OK) g_err[0] = 0;
     return st;
 }
@@ -1125,12 +1317,12 @@ vx_status vx_plot_staged_chunk(const vx_plot_params *params, uint32_t chunk_bits
     }
     const uint32_t gsh = P.G - P.D[0];
     st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, at<uint8_t>(ws, L.pcnt),
-                        d_first << gsh, ndc << gsh, 0, s, true);
+                        d_first << gsh, ndc << gsh, 0, s);
     if (st != VX_OK) return st;
     // Buckets before the chunk start at 0, those after it (and the end) at m.
     if ((st = fill_outside_offsets(b->bucket_offsets, chunk_bits, chunk, m, s)) != VX_OK) return st;
     st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, nullptr, nullptr, 1, 0,
-                   0, s, nullptr, true);
+                   0, s);
     if (st == VX_OK) g_err[0] = 0;
     return st;
 }
@@ -1197,6 +1389,26 @@ vx_status check_plot(const vx_plot_params *params, const vx_plot_buffers *b, con
 // lanes run every plot on its lane alone, and keep the workspace's status
 // word (cleared once per workspace by vx_plot_batch), so that it collects
 // the status of every plot that used the workspace.
+// The header words (the status word too, unless keep_status) and the
+// region fill counts of a plot, cleared before its first kernel.
+vx_status plot_reset(const Plan &P, const Layout &L, void *ws, bool keep_status, hipStream_t s) {
+    uint32_t *hdr = at<uint32_t>(ws, L.header);
+    static_assert(kHdrStatus == 0, "the status word leads the header");
+    if (keep_status)
+        VX_HIP(vxk::launch_reset(hdr + 1, kHeaderWords - 1, s), "reset");
+    else
+        VX_HIP(vxk::launch_reset(hdr, kHeaderWords, s), "reset");
+    for (uint32_t i = 0; P.hs && i < P.npass; ++i)
+        VX_HIP(vxk::launch_fill_u32(at<uint32_t>(ws, L.fill[i]),
+                                    i == 0 ? (uint64_t)front_fill_stride(P) * P.hq : 1ull << (P.pre[i] + P.D[i]), 0u,
+                                    s),
+               "reset");
+    return VX_OK;
+}
+
+vx_status plot_tail(const Plan &P, const Layout &L, const vx_plot_buffers *b, hipEvent_t *ev, hipStream_t s,
+                    bool pipelined, uint32_t front_passes);
+
 vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, const vx_tuning *tuning,
                     hipEvent_t *ev, void *stream, bool pipelined, bool keep_status = false) {
     Plan P;
@@ -1207,15 +1419,7 @@ vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, cons
     void *ws = b->workspace;
     uint64_t *keys_no = at<uint64_t>(ws, L.keys_no);
     uint32_t *hdr = at<uint32_t>(ws, L.header);
-    static_assert(kHdrStatus == 0, "the status word leads the header");
-    if (keep_status)
-        VX_HIP(vxk::launch_reset(hdr + 1, kHeaderWords - 1, s), "reset");
-    else
-        VX_HIP(vxk::launch_reset(hdr, kHeaderWords, s), "reset");
-    for (uint32_t i = 0; P.hs && i < P.npass; ++i)
-        VX_HIP(vxk::launch_fill_u32(at<uint32_t>(ws, L.fill[i]), (1ull << (P.pre[i] + P.D[i])) * (i == 0 ? P.hq : 1),
-                                    0u, s),
-               "reset");
+    if ((st = plot_reset(P, L, ws, keep_status, s)) != VX_OK) return st;
     VX_HIP(mark(ev, 0, s), "event");
     if (P.hs && P.hq > 1) {
         st = run_sliced_front(P, L, ws, s, ev);
@@ -1237,22 +1441,45 @@ vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, cons
                "hash");
         VX_HIP(mark(ev, 1, s), "event");
     }
+    st = plot_tail(P, L, b, ev, s, pipelined, hash_passes(P));
+    if (st == VX_OK) g_err[0] = 0;
+    return st;
+}
+
+// Everything after the hash (and the passes it files): the remaining
+// partition passes, the sort, the match and Table-2 hash.
+vx_status plot_tail(const Plan &P, const Layout &L, const vx_plot_buffers *b, hipEvent_t *ev, hipStream_t s,
+                    bool pipelined, uint32_t front_passes) {
+    vx_status st = VX_OK;
+    void *ws = b->workspace;
+    uint64_t *keys_no = at<uint64_t>(ws, L.keys_no);
+    uint32_t *hdr = at<uint32_t>(ws, L.header);
     if (!P.fused && pipelined && P.slices > 1) {
-        st = run_partition(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, 1, s, ev);
+        st = run_partition(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, 1, s, ev, nullptr, front_passes);
         if (st == VX_OK) st = run_pipelined(P, L, ws, b, keys_no, s, ev);
+    } else if (!P.fused && P.zt > 1) {
+        // Passes before the third as separate kernels, then the pipelined tail.
+        st = run_partition(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, std::min(P.npass, 2u), s, ev, nullptr,
+                           front_passes);
+        if (st != VX_OK) return st;
+        VX_HIP(mark(ev, 4, s), "event");
+        VX_HIP(mark(ev, 5, s), "event");
+        st = run_pipe_tail(P, L, ws, b, s);
+        if (st != VX_OK) return st;
+        VX_HIP(mark(ev, 6, s), "event");
     } else if (!P.fused) {
         // Separate kernels: the sort stores each record's pair count while
         // the groups are in LDS, then the match kernel reads nonces and counts.
-        st = run_partition(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, P.npass, s, ev);
+        st = run_partition(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, P.npass, s, ev, nullptr, front_passes);
         if (st != VX_OK) return st;
         st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, at<uint8_t>(ws, L.pcnt), 0,
-                            1u << P.G, 0, s, true);
+                            1u << P.G, 0, s);
         if (st != VX_OK) return st;
         VX_HIP(mark(ev, 4, s), "event");
         st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, nullptr, nullptr,
-                       1, 0, 0, s, ev, true);
+                       1, 0, 0, s, ev);
     } else {
-        st = run_partition(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, P.npass, s, ev);
+        st = run_partition(P, L, ws, keys_no, true, b->t1_keys, b->t1_nonces, P.npass, s, ev, nullptr, front_passes);
         if (st != VX_OK) return st;
         uint64_t *words = at<uint64_t>(ws, L.lbwords);
         VX_HIP(vxk::launch_zero_u64(words, 1u << P.G, s), "zero look-back words");
@@ -1276,7 +1503,6 @@ vx_status plot_impl(const vx_plot_params *params, const vx_plot_buffers *b, cons
                "sort + match");
         VX_HIP(mark(ev, 6, s), "event");
     }
-    if (st == VX_OK) g_err[0] = 0;
     return st;
 }
 
@@ -1304,13 +1530,11 @@ vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buf
                         const vx_tuning *tuning, void *stream) {
     if (n && (!params || !buffers)) return fail(VX_ERR_INVALID_ARG, "NULL params or buffers");
     // Validate everything before enqueuing anything.
-    std::vector<uint64_t> work(n);
+    std::vector<Plan> plan(n);
+    std::vector<Layout> lay(n);
     for (uint32_t i = 0; i < n; ++i) {
-        Plan P;
-        Layout L;
-        vx_status st = check_plot(&params[i], &buffers[i], tuning ? &tuning[i] : nullptr, &P, &L);
+        vx_status st = check_plot(&params[i], &buffers[i], tuning ? &tuning[i] : nullptr, &plan[i], &lay[i]);
         if (st != VX_OK) return st;
-        work[i] = P.n;
     }
     if (n == 0) return VX_OK;
     hipStream_t s = (hipStream_t)stream;
@@ -1319,9 +1543,9 @@ vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buf
     if (st != VX_OK) return st;
     // Plots that share a workspace form one chain (run in list order); chains
     // go, largest first, to the least loaded lane.
-    std::vector<int> chain_of(n, -1);
     std::vector<const void *> chain_ws;
     std::vector<uint64_t> chain_work;
+    std::vector<std::vector<uint32_t>> chain_plots;
     for (uint32_t i = 0; i < n; ++i) {
         int c = -1;
         for (size_t j = 0; j < chain_ws.size(); ++j)
@@ -1330,14 +1554,16 @@ vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buf
             c = (int)chain_ws.size();
             chain_ws.push_back(buffers[i].workspace);
             chain_work.push_back(0);
+            chain_plots.emplace_back();
         }
-        chain_of[i] = c;
-        chain_work[c] += work[i];
+        chain_plots[c].push_back(i);
+        chain_work[c] += plan[i].n;
     }
-    std::vector<int> order(chain_ws.size());
-    for (size_t j = 0; j < order.size(); ++j) order[j] = (int)j;
+    const size_t nchains = chain_ws.size();
+    std::vector<int> order(nchains);
+    for (size_t j = 0; j < nchains; ++j) order[j] = (int)j;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return chain_work[x] > chain_work[y]; });
-    std::vector<int> lane_of_chain(chain_ws.size(), 0);
+    std::vector<int> lane_of_chain(nchains, 0);
     uint64_t load[kBatchLanes] = {};
     for (int c : order) {
         int best = 0;
@@ -1346,25 +1572,184 @@ vx_status vx_plot_batch(const vx_plot_params *params, const vx_plot_buffers *buf
         lane_of_chain[c] = best;
         load[best] += chain_work[c];
     }
+    size_t rounds = 0;
+    for (auto &v : chain_plots) rounds = std::max(rounds, v.size());
     std::lock_guard<std::mutex> guard(ln->mu);
+    // Every lane starts behind the work already on the caller's stream.
     VX_HIP(hipEventRecord(ln->fork, s), "batch fork");
     bool used[kBatchLanes] = {};
-    for (uint32_t i = 0; i < n; ++i) used[lane_of_chain[chain_of[i]]] = true;
+    for (size_t c = 0; c < nchains; ++c) used[lane_of_chain[c]] = true;
     for (int l = 0; l < kBatchLanes; ++l)
         if (used[l]) VX_HIP(hipStreamWaitEvent(ln->s[l], ln->fork, 0), "batch fork wait");
     // Each workspace's status word is cleared once, before its first plot;
     // the plots then leave it alone, so afterwards it holds the status bits
     // of every plot that used that workspace.
-    std::vector<bool> cleared(chain_ws.size(), false);
-    for (uint32_t i = 0; i < n; ++i) {
-        const int c = chain_of[i];
-        const int l = lane_of_chain[c];
-        if (!cleared[c]) {
-            VX_HIP(vxk::launch_reset(static_cast<uint32_t *>(buffers[i].workspace), 1, ln->s[l]), "batch status");
-            cleared[c] = true;
+    auto clear_status = [&](uint32_t i, hipStream_t on) -> vx_status {
+        VX_HIP(vxk::launch_reset(static_cast<uint32_t *>(buffers[i].workspace), 1, on), "batch status");
+        return VX_OK;
+    };
+    // Round r takes the r-th plot of every chain (different workspaces).
+    // Plots that ask for it (batch_shared_hash) and whose hash files two
+    // passes share fused launches on the caller's stream (k_hash_pass over a
+    // device work list): launch u hashes the
+    // slices of unit u -- slices of one or more plots, large ones alone,
+    // small ones packed up to 2^27 nonces -- while its other work-groups
+    // file by the second digit the slices of unit u - 1 and, by the third,
+    // parts of plots whose second pass is complete.  The third pass of a
+    // plot needs all of its second, so only another plot's hash can hide it.
+    // As soon as a plot's passes are done, its sort and match go to its
+    // lane.  The other plots run whole on their lanes.
+    std::vector<int> chain_of(n, -1);
+    for (size_t c = 0; c < nchains; ++c)
+        for (uint32_t i : chain_plots[c]) chain_of[i] = (int)c;
+    auto hand_over = [&](uint32_t i, uint32_t passes_done) -> vx_status {
+        const int l = lane_of_chain[chain_of[i]];
+        VX_HIP(hipEventRecord(ln->fork, s), "batch hand-over");
+        VX_HIP(hipStreamWaitEvent(ln->s[l], ln->fork, 0), "batch hand-over wait");
+        return plot_tail(plan[i], lay[i], &buffers[i], nullptr, ln->s[l], false, passes_done);
+    };
+    for (size_t r = 0; r < rounds && st == VX_OK; ++r) {
+        std::vector<uint32_t> F;
+        for (size_t c = 0; c < nchains; ++c) {
+            if (r >= chain_plots[c].size()) continue;
+            const uint32_t i = chain_plots[c][r];
+            const vx_tuning *ti = tuning ? &tuning[i] : nullptr;
+            if (ti && ti->batch_shared_hash && front_fusable(plan[i])) {
+                F.push_back(i);
+                continue;
+            }
+            const hipStream_t lane = ln->s[lane_of_chain[c]];
+            if (r == 0 && (st = clear_status(i, lane)) != VX_OK) break;
+            if ((st = plot_impl(&params[i], &buffers[i], tuning ? &tuning[i] : nullptr, nullptr, lane, false, true)) !=
+                VX_OK)
+                break;
         }
-        st = plot_impl(&params[i], &buffers[i], tuning ? &tuning[i] : nullptr, nullptr, ln->s[l], false, true);
+        if (st != VX_OK || F.empty()) continue;
+        // The caller's stream waits for the lanes of these plots' chains
+        // (their previous plots' tails).
+        if (r > 0)
+            for (uint32_t i : F) {
+                const int l = lane_of_chain[chain_of[i]];
+                VX_HIP(hipEventRecord(ln->join[l], ln->s[l]), "batch round");
+                VX_HIP(hipStreamWaitEvent(s, ln->join[l], 0), "batch round wait");
+            }
+        std::stable_sort(F.begin(), F.end(), [&](uint32_t x, uint32_t y) { return plan[x].n > plan[y].n; });
+        for (uint32_t i : F) {
+            if (r == 0 && (st = clear_status(i, s)) != VX_OK) break;
+            if ((st = plot_reset(plan[i], lay[i], buffers[i].workspace, true, s)) != VX_OK) break;
+        }
         if (st != VX_OK) break;
+        // Units of slices (at most four, so that third-pass parts fit beside
+        // the previous unit's second passes in one list).
+        struct SliceRef {
+            uint32_t plot, slice;
+        };
+        constexpr size_t kUnitMax = 4, kPartsPerPlot = 4;
+        std::vector<std::vector<SliceRef>> units;
+        uint64_t unit_nonces = 0;
+        for (uint32_t i : F) {
+            const Plan &P = plan[i];
+            const uint64_t per_slice = (P.n + P.hq - 1) / P.hq;
+            for (uint32_t q = 0; q < P.hq; ++q) {
+                if (units.empty() || units.back().size() == kUnitMax ||
+                    unit_nonces + per_slice > std::max<uint64_t>(1ull << 27, per_slice)) {
+                    units.emplace_back();
+                    unit_nonces = 0;
+                }
+                units.back().push_back({i, q});
+                unit_nonces += per_slice;
+            }
+        }
+        // Third-pass parts waiting for a launch, and how many of each plot's
+        // are still to be filed.
+        struct Part {
+            uint32_t plot, a, e;  // the plot's second-pass regions [a, e)
+        };
+        std::vector<Part> pending;
+        std::vector<uint32_t> parts_left(n, 0);
+        const uint32_t U = (uint32_t)units.size();
+        for (uint32_t u = 0; st == VX_OK && (u <= U || !pending.empty()); ++u) {
+            vxk::HashPassList W;
+            memset(&W, 0, sizeof(W));
+            if (u < U)
+                for (const SliceRef &x : units[u]) {
+                    W.h[W.nh] = hash_slice(plan[x.plot], lay[x.plot], buffers[x.plot].workspace, x.slice);
+                    W.h_items += W.h[W.nh++].items;
+                }
+            if (u >= 1 && u <= U)
+                for (const SliceRef &x : units[u - 1]) {
+                    W.p[W.np] = pass_slice(plan[x.plot], lay[x.plot], buffers[x.plot].workspace, x.slice);
+                    W.p_items += W.p[W.np++].items;
+                }
+            std::vector<Part> taken;
+            while (!pending.empty() && W.np < (uint32_t)vxk::kHashPassMaxSlices) {
+                const Part pt = pending.front();
+                pending.erase(pending.begin());
+                const Plan &P = plan[pt.plot];
+                const Layout &L = lay[pt.plot];
+                void *ws = buffers[pt.plot].workspace;
+                const PassBufs B2 = pass_bufs(P, L, ws, nullptr, buffers[pt.plot].t1_keys,
+                                              buffers[pt.plot].t1_nonces, 2);
+                vxk::PassSliceDesc &Q = W.p[W.np++];
+                memset(&Q, 0, sizeof(Q));
+                const uint32_t per = (P.R[1] + vxk::kHashScatterSub - 1) / vxk::kHashScatterSub;
+                Q.keys = B2.in_k + (uint64_t)pt.a * P.R[1];
+                Q.nonces = B2.in_n + (uint64_t)pt.a * P.R[1];
+                Q.fill = at<uint32_t>(ws, L.fill[1]) + pt.a;
+                Q.out_keys = B2.out_k;
+                Q.out_nonces = B2.out_n;
+                Q.out_fill = at<uint32_t>(ws, L.fill[2]);
+                Q.status = at<uint32_t>(ws, L.header) + kHdrStatus;
+                Q.R_in = P.R[1];
+                Q.per = per;
+                Q.shift = 64 - P.pre[2] - P.D[2];
+                Q.bits = P.D[2];
+                Q.R_out = P.R[2];
+                Q.items = (pt.e - pt.a) * per;
+                Q.r0 = pt.a;
+                W.p_items += Q.items;
+                taken.push_back(pt);
+            }
+            set_frac(W);
+            // A zeroed ticket word: one of the batch words of one of the
+            // round's plots' headers (a plot brings at most 16 slices and 4
+            // third-pass parts, so the launches fit 21 words per plot).
+            const uint32_t owner = F[u % F.size()];
+            const uint32_t word = u / (uint32_t)F.size();
+            if (word >= kBatchTicketWords) {
+                st = fail(VX_ERR_UNSUPPORTED, "batch: too many fused launches in one round");
+                break;
+            }
+            uint32_t *ticket = at<uint32_t>(buffers[owner].workspace, lay[owner].header) + kHdrBatchTicket + word;
+            VX_HIP(vxk::launch_hash_pass(W, ticket, s), "batch hash");
+            // Plots whose second pass finished in this launch: their group
+            // starts, then (three passes) their third pass in later launches,
+            // else their sort and match on their lane.
+            if (u >= 1 && u <= U)
+                for (const SliceRef &x : units[u - 1]) {
+                    const uint32_t i = x.plot;
+                    if (x.slice + 1 != plan[i].hq) continue;
+                    if ((st = finish_front(plan[i], lay[i], buffers[i].workspace, s)) != VX_OK) break;
+                    const Plan &P = plan[i];
+                    if (P.npass == 3 && P.zt == 1 && P.D[2] <= (uint32_t)vxk::kHashPassMaxBits) {
+                        const uint32_t N1 = 1u << (P.pre[1] + P.D[1]);
+                        const uint32_t parts = (uint32_t)std::min<size_t>(kPartsPerPlot, N1);
+                        for (uint32_t q = 0; q < parts; ++q)
+                            pending.push_back({i, (uint32_t)((uint64_t)N1 * q / parts),
+                                               (uint32_t)((uint64_t)N1 * (q + 1) / parts)});
+                        parts_left[i] = parts;
+                    } else if ((st = hand_over(i, 2)) != VX_OK) {
+                        break;
+                    }
+                }
+            for (const Part &pt : taken)
+                if (--parts_left[pt.plot] == 0) {
+                    const uint32_t i = pt.plot;
+                    const uint32_t N1 = 1u << (plan[i].pre[1] + plan[i].D[1]);
+                    if ((st = claimed_regions(plan[i], lay[i], buffers[i].workspace, 2, 0, N1, s)) != VX_OK) break;
+                    if ((st = hand_over(i, 3)) != VX_OK) break;
+                }
+        }
     }
     // Join every used lane back into the caller's stream, also on failure, so
     // the caller's stream never runs ahead of work already enqueued.

@@ -40,7 +40,7 @@ struct HashSliceDesc {       // hash nonces [nonce0, nonce0 + n), file them by t
     uint32_t *nonces;
     uint32_t *fill;          // records filed per region (zero before the slice's launch)
     uint32_t *status;        // device status word of the plot
-    uint32_t bits, R;        // first-digit bits (<= 7), region capacity
+    uint32_t bits, R;        // first-digit bits (<= kHashPassMaxBits), region capacity
     uint32_t items;          // ceil(n / kHashScatterSub)
     uint32_t pad;
 };
@@ -53,9 +53,11 @@ struct PassSliceDesc {       // file the regions of a hashed slice by the next d
     uint32_t *out_fill;      // shared by every slice of the plot (zero before its first slice)
     uint32_t *status;
     uint32_t R_in, per;      // per: sub-tiles per input region = ceil(R_in / kHashScatterSub)
-    uint32_t shift, bits;    // digit = (key >> shift) & (2^bits - 1), bits <= 7
+    uint32_t shift, bits;    // digit = (key >> shift) & (2^bits - 1), bits <= kHashPassMaxBits
     uint32_t R_out;
     uint32_t items;          // nin * per
+    uint32_t r0;             // first input region's index in the plot's second-pass regions
+    uint32_t pad;
 };
 constexpr int kHashPassMaxSlices = 8;
 struct HashPassList {
@@ -65,12 +67,78 @@ struct HashPassList {
     uint32_t h_items, p_items;  // totals over the lists
     uint64_t h_frac;            // ceil(h_items * 2^32 / (h_items + p_items))
 };
-constexpr int kHashPassMaxBits = 7;
+constexpr int kHashPassMaxBits = 8;  // widest digit of a sliced hash's two passes
+constexpr int kPipeMaxBits = 7;      // widest digit of k_pipe's filing items
+
+// Where a group's records come from: in place (keys == NULL) or records
+// [lo[g], hi[g]) of keys / nonces (the last partition pass's regions).
+struct GroupIn {
+    const uint64_t *keys;
+    const uint32_t *nonces;
+    const uint32_t *lo;
+    const uint32_t *hi;
+};
+
+// What one group sort needs besides the group's index (one plot).
+struct SortArgs {
+    uint64_t *keys;               // Table 1
+    uint32_t *nonces;
+    GroupIn in;
+    const uint32_t *gstart;
+    uint32_t *offsets;
+    uint32_t *ovf_count, *ovf_list;
+    uint8_t *pcnt;                // may be NULL
+    unsigned long long *csum;     // may be NULL
+    uint64_t T;
+    uint32_t G, cap, n_total, cb;
+};
+
+// What one match chunk needs besides the chunk's index (one plot).
+struct MatchArgs {
+    uint32_t key[8];
+    const uint64_t *keys;       // Table 1
+    const uint32_t *nonces;
+    const uint8_t *pcnt;        // pair count of every record (one byte)
+    const uint64_t *chunk_base; // Table-2 index of each chunk's first pair
+    uint4 *t2;
+    uint64_t cap;
+    uint64_t T;
+    uint32_t n_total, cb;
+};
+
+// One launch of a software-pipelined plot or batch (k_pipe): lists of
+// hash slices (H), partition-pass slices (P), group ranges to sort (S) and
+// record ranges to match (M), whose inputs earlier launches finished.
+constexpr int kPipeMaxLists = 4;
+constexpr int kPipeBlock = 512;
+constexpr uint32_t kPipeSub = 4096;  // records of a filing sub-tile (H and P items)
+struct PipeSortDesc {
+    SortArgs a;
+    uint32_t g0, items;      // groups [g0, g0 + items)
+};
+struct PipeMatchDesc {
+    MatchArgs a;
+    const uint32_t *r_lo, *r_hi;  // the chunks owned by records [*r_lo, *r_hi) (to the end when last)
+    uint32_t last;
+    uint32_t items;               // an upper bound of their number
+};
+struct PipeList {
+    HashSliceDesc h[kPipeMaxLists];
+    PassSliceDesc p[kPipeMaxLists];
+    PipeSortDesc s[kPipeMaxLists];
+    PipeMatchDesc m[kPipeMaxLists];
+    uint32_t n[4];       // descriptors of each kind: H, P, S, M
+    uint32_t items[4];   // items of each kind
+    uint64_t frac[3];    // ceil(items[r] * 2^32 / (items of kinds >= r)), r = 0..2
+};
+// One launch over the list, which is first stored at d_list (device memory,
+// free again once the launch is done); *ticket zero at launch.
+hipError_t launch_pipe(const PipeList &L, PipeList *d_list, uint32_t *ticket, hipStream_t s);
 // One launch over the list; *ticket zero at launch.
 hipError_t launch_hash_pass(const HashPassList &L, uint32_t *ticket, hipStream_t s);
 // gstart[d] (d <= nd) of the first digit over a sliced hash's regions.
-hipError_t launch_region_scan_slices(const uint32_t *fill, uint32_t slices, uint32_t nd, uint32_t R,
-                                     uint32_t *gstart, hipStream_t s);
+hipError_t launch_region_scan_slices(const uint32_t *fill, uint32_t slices, uint32_t stride, uint32_t nd,
+                                     uint32_t R, uint32_t *gstart, hipStream_t s);
 // Chunked plots: hash all n nonces, keep keys whose top pbits bits are
 // `prefix`; *count (zero at launch) receives how many (records past cap are
 // not written).

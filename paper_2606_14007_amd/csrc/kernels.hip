@@ -35,6 +35,11 @@ namespace vxk {
 using vxd::Key;
 
 constexpr int kMaxDigits = 1 << kMaxDigitBits;
+// Match kernels: work-groups of 512 threads, chunks of up to 2048 records,
+// windows of 4096 Table-2 slots.
+constexpr int kMatchBlock = 512;
+constexpr int kMatchCap = 2048;
+constexpr int kMatchSlots = 4096;
 
 struct TileGeom {
     // mode 0: tile t covers [t * chunk, min((t + 1) * chunk, n)).
@@ -312,19 +317,150 @@ __global__ __launch_bounds__(BLOCK) void k_region_scan(const uint32_t *__restric
 // contiguously.  A list may hold slices of several plots (a batch).
 // ---------------------------------------------------------------------------
 
-template <int BLOCK, int ITEMS, int MAXD>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_hash_pass(HashPassList L,
-                                                                                     uint32_t *__restrict__ ticket) {
-    constexpr uint32_t SUB = BLOCK * ITEMS;
+// Files a sub-tile of m <= BLOCK * ITEMS records, held lane-strided in k[] /
+// nv[] (item j of thread t is record j * BLOCK + t), by their digit
+// (key >> shift) & mask: ranks them with LDS atomics on cnt[], claims room
+// for each digit's run in region region0 + d (capacity R) with one global
+// atomic on fill[], lays the sub-tile out digit by digit in LDS and writes
+// every run contiguously.  cnt[] must be zero on entry and is zero again on
+// return.  before_barrier() runs between the ranking and the first barrier.
+// No barrier follows the write-out: a caller's next LDS layout must come
+// after a barrier that every thread reaches only once its reads here are
+// done.
+template <int BLOCK, int ITEMS, int MAXD, typename F>
+__device__ __forceinline__ void file_records(const uint64_t (&k)[ITEMS], const uint32_t (&nv)[ITEMS], uint32_t m,
+                                             uint32_t shift, uint32_t mask, uint32_t *fill, uint32_t region0,
+                                             uint32_t R, uint64_t *okeys, uint32_t *ononces, uint32_t *status,
+                                             uint64_t *s_keys, uint32_t *s_non, uint32_t *s_cnt, uint32_t *s_pos,
+                                             uint32_t *s_claim, F before_barrier) {
     constexpr int PER = (MAXD + 63) / 64;  // digits per lane of the one-wave scan
     static_assert(MAXD <= BLOCK, "one thread per digit claims its region room");
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    uint32_t slot[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+        if (j * BLOCK + tid < m) slot[j] = atomicAdd(&s_cnt[(uint32_t)(k[j] >> shift) & mask], 1u);
+    before_barrier();
+    __syncthreads();
+    // Claim room in the regions (thread d <-> digit d); the atomics are in
+    // flight during the scan and the LDS layout.  Wave 0 scans the counts.
+    const uint32_t nd = mask + 1u;
+    uint32_t claim = 0;
+    if (tid < nd) {
+        const uint32_t c = s_cnt[tid];
+        if (c) claim = atomicAdd(&fill[region0 + tid], c);
+    }
+    if (tid < 64) {
+        uint32_t v[PER], sum = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t d = lane * PER + q;
+            v[q] = d < nd ? s_cnt[d] : 0u;
+            sum += v[q];
+        }
+        const uint32_t inc = vxd::wave_inclusive_scan(sum);
+        uint32_t run = inc - sum;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t d = lane * PER + q;
+            if (d < nd) s_pos[d] = run;
+            run += v[q];
+        }
+    }
+    __syncthreads();
+    // The counts are consumed: clear them for the next sub-tile (its atomics
+    // come after the next barrier).
+    if (tid < nd) s_cnt[tid] = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+        if (j * BLOCK + tid < m) {
+            const uint32_t p = s_pos[(uint32_t)(k[j] >> shift) & mask] + slot[j];
+            s_keys[p] = k[j];
+            s_non[p] = nv[j];
+        }
+    if (tid < nd) s_claim[tid] = claim;
+    __syncthreads();
+    for (uint32_t e = tid; e < m; e += BLOCK) {
+        const uint64_t kk = s_keys[e];
+        const uint32_t d = (uint32_t)(kk >> shift) & mask;
+        const uint32_t r = s_claim[d] + (e - s_pos[d]);
+        if (r < R) {
+            const uint64_t g = (uint64_t)(region0 + d) * R + r;
+            okeys[g] = kk;
+            ononces[g] = s_non[e];
+        } else {
+            atomicOr(status, (uint32_t)VXK_DEV_STATUS_REGION_OVERFLOW);
+        }
+    }
+}
+
+// Sub-tile x of a hash slice: hashes its nonces into k[] / nv[]; returns
+// the number of records (the last sub-tile may be short).
+template <int BLOCK, int ITEMS>
+__device__ __forceinline__ uint32_t hash_subtile(const HashSliceDesc &H, uint32_t x, uint64_t (&k)[ITEMS],
+                                                 uint32_t (&nv)[ITEMS]) {
+    constexpr uint32_t SUB = BLOCK * ITEMS;
+    Key key;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) key.w[w] = H.key[w];
+    const uint64_t base = (uint64_t)x * SUB;
+    const uint32_t m = (uint32_t)(H.n - base < SUB ? H.n - base : SUB);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        // As in k_hash_table1: keep the nonce opaque to the optimiser.
+        uint32_t nonce = (uint32_t)(H.nonce0 + base) + (uint32_t)(j * BLOCK) + threadIdx.x;
+        asm volatile("" : "+v"(nonce));
+        k[j] = vxd::h1(key, nonce);
+        nv[j] = nonce;
+    }
+    return m;
+}
+
+// Sub-tile x of a pass over a slice's regions: loads region x / per's
+// records [(x % per) * SUB, ...) (clamped, unconditional loads: a wave
+// issues all before waiting); returns the number of records, and the
+// region in *r.
+template <int BLOCK, int ITEMS>
+__device__ __forceinline__ uint32_t load_subtile(const PassSliceDesc &P, uint32_t x, uint64_t (&k)[ITEMS],
+                                                 uint32_t (&nv)[ITEMS], uint32_t *r_out) {
+    constexpr uint32_t SUB = BLOCK * ITEMS;
+    const uint32_t r = x / P.per, lo = (x % P.per) * SUB;
+    const uint32_t f = min(P.fill[r], P.R_in);
+    const uint32_t m = lo < f ? min(SUB, f - lo) : 0u;
+    *r_out = r;
+    if (m) {
+        const uint64_t src = (uint64_t)r * P.R_in + lo;
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t e = j * BLOCK + threadIdx.x;
+            const uint64_t ic = src + (e < m ? e : m - 1);
+            k[j] = P.keys[ic];
+            nv[j] = P.nonces[ic];
+        }
+    }
+    return m;
+}
+
+// Position t of a launch's ticket order belongs to the first list while
+// floor(t * frac / 2^32) grows across it (frac = ceil(n1 * 2^32 / n));
+// returns whether it does, with the item index in the chosen list.
+__device__ __forceinline__ bool take_first(uint64_t t, uint64_t frac, uint64_t &idx) {
+    const uint64_t a0 = (t * frac) >> 32, a1 = ((t + 1) * frac) >> 32;
+    idx = a1 > a0 ? a0 : t - a0;
+    return a1 > a0;
+}
+
+template <int BLOCK, int ITEMS, int MAXD>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXD <= 128 ? 6 : 1))) void k_hash_pass(HashPassList L,
+                                                                                     uint32_t *__restrict__ ticket) {
+    constexpr uint32_t SUB = BLOCK * ITEMS;
     __shared__ uint64_t s_keys[SUB];
     __shared__ uint32_t s_non[SUB];
     __shared__ uint32_t s_cnt[MAXD];      // digit counts of the sub-tile
     __shared__ uint32_t s_pos[MAXD + 1];  // their exclusive prefix
     __shared__ uint32_t s_claim[MAXD];
     __shared__ uint32_t s_tk[2];  // alternate, so a slow reader never sees the next ticket
-    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t tid = threadIdx.x;
     const uint64_t NT = (uint64_t)L.h_items + L.p_items;
     if (tid < MAXD) s_cnt[tid] = 0;
     if (tid == 0) s_tk[0] = atomicAdd(ticket, 1u);
@@ -332,23 +468,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
     for (uint32_t it = 0;; ++it) {
         const uint64_t t = s_tk[it & 1];
         if (t >= NT) break;
-        // Position t is a hash item when the proportional count of hash
-        // items, a(t) = floor(t * h_frac / 2^32), grows across it.
-        const uint64_t a0 = (t * L.h_frac) >> 32, a1 = ((t + 1) * L.h_frac) >> 32;
+        uint64_t idx;
+        const bool hrole = take_first(t, L.h_frac, idx);
         uint64_t k[ITEMS];
-        uint32_t nv[ITEMS], slot[ITEMS];
+        uint32_t nv[ITEMS];
         uint32_t m, shift, mask, R, region0;
         uint32_t *fill, *ononces, *status;
         uint64_t *okeys;
-        if (a1 > a0) {
-            uint32_t x = (uint32_t)a0, s = 0;
+        if (hrole) {
+            uint32_t x = (uint32_t)idx, s = 0;
             while (s + 1 < L.nh && x >= L.h[s].items) x -= L.h[s].items, ++s;
             const HashSliceDesc &H = L.h[s];
-            Key key;
-#pragma unroll
-            for (int w = 0; w < 8; ++w) key.w[w] = H.key[w];
-            const uint64_t base = (uint64_t)x * SUB;
-            m = (uint32_t)(H.n - base < SUB ? H.n - base : SUB);
+            m = hash_subtile<BLOCK, ITEMS>(H, x, k, nv);
             shift = 64u - H.bits;
             mask = (1u << H.bits) - 1u;
             R = H.R;
@@ -357,114 +488,42 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
             okeys = H.keys;
             ononces = H.nonces;
             status = H.status;
-#pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                // As in k_hash_table1: keep the nonce opaque to the optimiser.
-                uint32_t nonce = (uint32_t)(H.nonce0 + base) + (uint32_t)(j * BLOCK) + tid;
-                asm volatile("" : "+v"(nonce));
-                k[j] = vxd::h1(key, nonce);
-                nv[j] = nonce;
-            }
         } else {
-            uint32_t x = (uint32_t)(t - a0), s = 0;
+            uint32_t x = (uint32_t)idx, s = 0;
             while (s + 1 < L.np && x >= L.p[s].items) x -= L.p[s].items, ++s;
             const PassSliceDesc &P = L.p[s];
-            const uint32_t r = x / P.per, lo = (x % P.per) * SUB;
-            const uint32_t f = min(P.fill[r], P.R_in);
-            m = lo < f ? min(SUB, f - lo) : 0u;
+            uint32_t r;
+            m = load_subtile<BLOCK, ITEMS>(P, x, k, nv, &r);
             shift = P.shift;
             mask = (1u << P.bits) - 1u;
             R = P.R_out;
-            region0 = r << P.bits;
+            region0 = (P.r0 + r) << P.bits;
             fill = P.out_fill;
             okeys = P.out_keys;
             ononces = P.out_nonces;
             status = P.status;
-            if (m) {
-                // Clamped, unconditional loads: a wave issues all before waiting.
-                const uint64_t src = (uint64_t)r * P.R_in + lo;
-#pragma unroll
-                for (int j = 0; j < ITEMS; ++j) {
-                    const uint32_t e = j * BLOCK + tid;
-                    const uint64_t ic = src + (e < m ? e : m - 1);
-                    k[j] = P.keys[ic];
-                    nv[j] = P.nonces[ic];
-                }
-            }
         }
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j)
-            if (j * BLOCK + tid < m) slot[j] = atomicAdd(&s_cnt[(uint32_t)(k[j] >> shift) & mask], 1u);
-        if (tid == 0) s_tk[(it + 1) & 1] = atomicAdd(ticket, 1u);
-        __syncthreads();
-        // Claim room in the regions (thread d <-> digit d); the atomics are in
-        // flight during the scan and the LDS layout.  Wave 0 scans the counts.
-        const uint32_t nd = mask + 1u;
-        uint32_t claim = 0;
-        if (tid < nd) {
-            const uint32_t c = s_cnt[tid];
-            if (c) claim = atomicAdd(&fill[region0 + tid], c);
-        }
-        if (tid < 64) {
-            uint32_t v[PER], sum = 0;
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const uint32_t d = lane * PER + q;
-                v[q] = d < nd ? s_cnt[d] : 0u;
-                sum += v[q];
-            }
-            const uint32_t inc = vxd::wave_inclusive_scan(sum);
-            uint32_t run = inc - sum;
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const uint32_t d = lane * PER + q;
-                if (d < nd) s_pos[d] = run;
-                run += v[q];
-            }
-        }
-        __syncthreads();
-        // The counts are consumed: clear them for the next item (its atomics
-        // come after the next barrier).
-        if (tid < nd) s_cnt[tid] = 0;
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j)
-            if (j * BLOCK + tid < m) {
-                const uint32_t p = s_pos[(uint32_t)(k[j] >> shift) & mask] + slot[j];
-                s_keys[p] = k[j];
-                s_non[p] = nv[j];
-            }
-        if (tid < nd) s_claim[tid] = claim;
-        __syncthreads();
-        // No barrier after the write-out: the next item's LDS layout waits for
-        // the barrier after its ranking, which every thread reaches only once
-        // its reads here are done.
-        for (uint32_t e = tid; e < m; e += BLOCK) {
-            const uint64_t kk = s_keys[e];
-            const uint32_t d = (uint32_t)(kk >> shift) & mask;
-            const uint32_t r = s_claim[d] + (e - s_pos[d]);
-            if (r < R) {
-                const uint64_t g = (uint64_t)(region0 + d) * R + r;
-                okeys[g] = kk;
-                ononces[g] = s_non[e];
-            } else {
-                atomicOr(status, (uint32_t)VXK_DEV_STATUS_REGION_OVERFLOW);
-            }
-        }
+        // The next ticket is fetched before the first barrier and read after
+        // the last one.
+        file_records<BLOCK, ITEMS, MAXD>(k, nv, m, shift, mask, fill, region0, R, okeys, ononces, status, s_keys,
+                                         s_non, s_cnt, s_pos, s_claim, [&]() {
+                                             if (tid == 0) s_tk[(it + 1) & 1] = atomicAdd(ticket, 1u);
+                                         });
     }
 }
 
 // Starts of the first digit's groups after a plot hashed in `slices`
 // slices: gstart[d] = records of digits below d over all slices, each
-// slice's region d holding min(fill[s * nd + d], R); gstart[nd] = all.
+// slice's region d holding min(fill[s * stride + d], R); gstart[nd] = all.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_region_scan_slices(const uint32_t *__restrict__ fill, uint32_t slices,
-                                                              uint32_t nd, uint32_t R,
+                                                              uint32_t stride, uint32_t nd, uint32_t R,
                                                               uint32_t *__restrict__ gstart) {
     __shared__ uint32_t s[kMaxDigits];
     __shared__ uint32_t s_wave[BLOCK / 64 + 1];
     for (uint32_t d = threadIdx.x; d < nd; d += BLOCK) {
         uint32_t c = 0;
-        for (uint32_t q = 0; q < slices; ++q) c += min(fill[q * nd + d], R);
+        for (uint32_t q = 0; q < slices; ++q) c += min(fill[q * stride + d], R);
         s[d] = c;
     }
     __syncthreads();
@@ -594,12 +653,6 @@ struct Claim {
 // Where a group sort reads group g: keys / nonces from records
 // [lo[g], hi[g]) of the input regions, or (keys == NULL) in place at the
 // group's own start.
-struct GroupIn {
-    const uint64_t *keys;
-    const uint32_t *nonces;
-    const uint32_t *lo;
-    const uint32_t *hi;
-};
 
 // Records of group g and where its Table-1 slice ends.  In place, the group
 // is [gstart[g], gstart[g + 1]).  Gathered from a region, it holds that
@@ -913,136 +966,156 @@ __device__ __forceinline__ void lds_sort_group(const uint64_t (&k)[CAPMAX / BLOC
     __syncthreads();
 }
 
+
+// LDS of one group sort.
+template <int BLOCK, int CAPMAX>
+struct SortLds {
+    static constexpr int NCS = CAPMAX / 64 + 2;  // match chunks a group overlaps (chunks of >= 64 records)
+    static constexpr int NW2 = kSubBins / 2;     // two 16-bit sub-bin counters per word
+    uint64_t keys[CAPMAX];
+    uint32_t nonces[CAPMAX];
+    uint32_t start[NW2 + 1];
+    uint64_t wave[BLOCK / 64 + 1];
+    uint32_t csum[NCS];
+};
+
+// Sorts group g into Table 1 with its bucket offsets and, with pcnt, each
+// record's pair count (one byte) and (with csum) the counts summed per match
+// chunk.  A group over the capacity goes to the overflow list for the
+// fallback.  Run by the whole work-group; LDS is free again once every
+// thread has returned.
+template <int BLOCK, int CAPMAX>
+__device__ __forceinline__ void sort_one_group(uint32_t g, const SortArgs &A, SortLds<BLOCK, CAPMAX> &S) {
+    constexpr int ITEMS = CAPMAX / BLOCK;
+    constexpr int NCS = SortLds<BLOCK, CAPMAX>::NCS;
+    static_assert(CAPMAX < 65536 && SortLds<BLOCK, CAPMAX>::NW2 % BLOCK == 0, "packed counters");
+    uint64_t *s_keys = S.keys;
+    uint32_t *s_nonces = S.nonces;
+    uint32_t *s_csum = S.csum;
+    uint32_t *s_wave32 = reinterpret_cast<uint32_t *>(S.wave);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t sb_shift = 64u - A.G - kSubBinBits;
+    const uint32_t nbg = 1u << (VXK_BUCKET_BITS - A.G);
+    uint64_t *keys = A.keys;
+    uint32_t *nonces = A.nonces;
+    const GroupIn &in = A.in;
+    const uint32_t *gstart = A.gstart;
+    const uint32_t G = A.G, cap = A.cap, n_total = A.n_total, cb = A.cb;
+    uint32_t *offsets = A.offsets, *ovf_count = A.ovf_count, *ovf_list = A.ovf_list;
+    uint8_t *pcnt = A.pcnt;
+    unsigned long long *csum = A.csum;
+    const uint64_t T = A.T;
+    if (g == (1u << G) - 1 && tid == 0) offsets[VXK_NUM_BUCKETS] = n_total;
+    const uint32_t lo = gstart[g], n = group_records(in, gstart, g, lo);
+    if (in.keys) zero_holes(pcnt, gstart, g, G, lo, n, n_total);
+    const uint64_t *src_k = in.keys ? in.keys + in.lo[g] : keys + lo;
+    const uint32_t *src_n = in.keys ? in.nonces + in.lo[g] : nonces + lo;
+    uint64_t k[ITEMS];
+    uint32_t nn[ITEMS];
+    if (csum)
+        for (uint32_t i = tid; i < (uint32_t)NCS; i += BLOCK) s_csum[i] = 0;  // read after the sort's barriers
+    if (n <= cap && n > 0) {
+        // Clamped, unconditional loads: a wave issues all before waiting.
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t e = j * BLOCK + tid;
+            const uint32_t ec = e < n ? e : n - 1;
+            k[j] = src_k[ec];
+            nn[j] = src_n[ec];
+        }
+    }
+    if (n > cap) {
+        if (tid == 0) {
+            const uint32_t i = atomicAdd(ovf_count, 1u);
+            ovf_list[i] = g;
+        }
+    } else {
+        lds_sort_group<BLOCK, CAPMAX>(k, nn, n, sb_shift, s_keys, s_nonces, S.start, s_wave32);
+        // Write the group out, with each record's pair count (one byte):
+        // lane-strided records keep LDS reads and stores contiguous; a
+        // record tests its next four records with independent reads (no
+        // chain of dependent loads) and walks on only past four partners.
+        // With csum, every wave also adds its 64 consecutive records'
+        // exact counts into the (at most two) match chunks they fall in.
+        const uint32_t c_lo = lo >> cb;
+        for (uint32_t e0 = 0; e0 < n; e0 += BLOCK) {
+            const uint32_t e = e0 + tid;
+            uint32_t cnt_e = 0;
+            if (e < n) {
+                const uint64_t ki = s_keys[e];
+                keys[lo + e] = ki;
+                nonces[lo + e] = s_nonces[e];
+                if (pcnt) {
+                    const uint32_t bi = (uint32_t)(ki >> 40);
+                    uint64_t kn[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) kn[r] = e + 1 + r < n ? s_keys[e + 1 + r] : ~0ull;
+                    uint32_t c = 0;
+                    bool go = true;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        go = go && e + 1 + r < n && (uint32_t)(kn[r] >> 40) == bi && kn[r] - ki < T;
+                        c += go ? 1u : 0u;
+                    }
+                    if (c == 4)
+                        for (uint32_t j = e + 5; j < n; ++j) {
+                            const uint64_t kj = s_keys[j];
+                            if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
+                            ++c;
+                        }
+                    pcnt[lo + e] = (uint8_t)min(c, kPairCountEscape);
+                    cnt_e = c;
+                }
+            }
+            if (csum) {
+                const uint32_t ca = (lo + e0 + (tid & ~63u)) >> cb;  // the wave's first chunk
+                const uint32_t va = ((lo + e) >> cb) == ca ? cnt_e : 0u;
+                const uint32_t sa = vxd::wave_sum(va), sb = vxd::wave_sum(cnt_e - va);
+                if ((tid & 63u) == 0) {
+                    if (sa) atomicAdd(&s_csum[ca - c_lo], sa);
+                    if (sb) atomicAdd(&s_csum[ca + 1 - c_lo], sb);
+                }
+            }
+        }
+        // offsets[b] for the group's buckets: first record with bucket >= b.
+        const uint32_t bfirst = g << (VXK_BUCKET_BITS - G);
+        for (uint32_t bl = tid; bl < nbg; bl += BLOCK) {
+            const uint32_t b = bfirst + bl;
+            uint32_t a = 0, c = n;
+            while (a < c) {
+                const uint32_t mid = (a + c) >> 1;
+                if ((uint32_t)(s_keys[mid] >> 40) < b) a = mid + 1; else c = mid;
+            }
+            offsets[b] = lo + a;
+        }
+        __syncthreads();
+        if (csum && n) {  // the chunks of records [lo, lo + n)
+            const uint32_t nch = ((lo + n - 1) >> cb) - c_lo + 1;
+            for (uint32_t i = tid; i < nch; i += BLOCK)
+                if (s_csum[i]) atomicAdd(&csum[c_lo + i], (unsigned long long)s_csum[i]);
+        }
+    }
+}
+
 // Persistent: each work-group takes groups of [g0, g0 + gcount) from a
 // ticket counter (*ticket, zero at launch) until none is left, so work-groups
 // that start late -- while another stream's kernel holds part of the device
-// -- simply take fewer groups.  The kernel is kept under 80 VGPRs so that
-// three work-groups share each CU; their phases interleave, which hides each
-// one's global loads behind the others' LDS work (better, measured, than
-// prefetching into registers at two per CU).
+// -- simply take fewer groups.  The kernel is kept at 64 VGPRs or fewer so
+// that four work-groups share each CU; their phases interleave, which hides
+// each one's global loads behind the others' LDS work (better, measured,
+// than prefetching into registers at fewer work-groups per CU).
 template <int BLOCK, int CAPMAX>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CAPMAX <= kGroupCapFast ? 8 : 1))) void k_groupsort(uint64_t *keys, uint32_t *nonces, GroupIn in,
-                                                     const uint32_t *__restrict__ gstart,
-                                                     uint32_t G, uint32_t cap,
-                                                     uint32_t *__restrict__ offsets,
-                                                     uint32_t n_total,
-                                                     uint32_t *__restrict__ ovf_count,
-                                                     uint32_t *__restrict__ ovf_list, uint64_t T,
-                                                     uint8_t *__restrict__ pcnt, uint32_t g0,
-                                                     uint32_t gcount, uint32_t *__restrict__ ticket,
-                                                     unsigned long long *__restrict__ csum, uint32_t cb) {
-    constexpr int ITEMS = CAPMAX / BLOCK;
-    // Pair sums of the match chunks a group overlaps (at most CAPMAX / 64 + 2
-    // for chunks of 64 records or more).
-    constexpr int NCS = CAPMAX / 64 + 2;
-    __shared__ uint32_t s_csum[NCS];
-    __shared__ uint64_t s_keys[CAPMAX];
-    __shared__ uint32_t s_nonces[CAPMAX];
-    constexpr int NW2 = kSubBins / 2;  // two 16-bit sub-bin counters per word
-    static_assert(CAPMAX < 65536 && NW2 % BLOCK == 0, "packed counters");
-    __shared__ uint32_t s_start[NW2 + 1];
-    __shared__ uint64_t s_wave[BLOCK / 64 + 1];
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CAPMAX <= kGroupCapFast ? 8 : 1))) void k_groupsort(SortArgs A, uint32_t g0, uint32_t gcount,
+                                                                                                                          uint32_t *__restrict__ ticket) {
+    __shared__ SortLds<BLOCK, CAPMAX> S;
     __shared__ uint32_t s_tk[2];  // alternate, so a slow reader never sees the next ticket
-    uint32_t *s_wave32 = reinterpret_cast<uint32_t *>(s_wave);
     const uint32_t tid = threadIdx.x;
-    const uint32_t sb_shift = 64u - G - kSubBinBits;
-    const uint32_t nbg = 1u << (VXK_BUCKET_BITS - G);
-    if (blockIdx.x == 0 && tid == 0) offsets[VXK_NUM_BUCKETS] = n_total;
     for (uint32_t it = 0;; ++it) {
         if (tid == 0) s_tk[it & 1] = atomicAdd(ticket, 1u);
         __syncthreads();
         const uint32_t t = s_tk[it & 1];
         if (t >= gcount) break;
-        const uint32_t g = g0 + t;
-        const uint32_t lo = gstart[g], n = group_records(in, gstart, g, lo);
-        if (in.keys) zero_holes(pcnt, gstart, g, G, lo, n, n_total);
-        const uint64_t *src_k = in.keys ? in.keys + in.lo[g] : keys + lo;
-        const uint32_t *src_n = in.keys ? in.nonces + in.lo[g] : nonces + lo;
-        uint64_t k[ITEMS];
-        uint32_t nn[ITEMS];
-        if (csum)
-            for (uint32_t i = tid; i < (uint32_t)NCS; i += BLOCK) s_csum[i] = 0;  // read after the sort's barriers
-        if (n <= cap && n > 0) {
-            // Clamped, unconditional loads: a wave issues all before waiting.
-#pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                const uint32_t e = j * BLOCK + tid;
-                const uint32_t ec = e < n ? e : n - 1;
-                k[j] = src_k[ec];
-                nn[j] = src_n[ec];
-            }
-        }
-        if (n > cap) {
-            if (tid == 0) {
-                const uint32_t i = atomicAdd(ovf_count, 1u);
-                ovf_list[i] = g;
-            }
-        } else {
-            lds_sort_group<BLOCK, CAPMAX>(k, nn, n, sb_shift, s_keys, s_nonces, s_start, s_wave32);
-            // Write the group out, with each record's pair count (one byte):
-            // lane-strided records keep LDS reads and stores contiguous; a
-            // record tests its next four records with independent reads (no
-            // chain of dependent loads) and walks on only past four partners.
-            // With csum, every wave also adds its 64 consecutive records'
-            // exact counts into the (at most two) match chunks they fall in.
-            const uint32_t c_lo = lo >> cb;
-            for (uint32_t e0 = 0; e0 < n; e0 += BLOCK) {
-                const uint32_t e = e0 + tid;
-                uint32_t cnt_e = 0;
-                if (e < n) {
-                    const uint64_t ki = s_keys[e];
-                    keys[lo + e] = ki;
-                    nonces[lo + e] = s_nonces[e];
-                    if (pcnt) {
-                        const uint32_t bi = (uint32_t)(ki >> 40);
-                        uint64_t kn[4];
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) kn[r] = e + 1 + r < n ? s_keys[e + 1 + r] : ~0ull;
-                        uint32_t c = 0;
-                        bool go = true;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            go = go && e + 1 + r < n && (uint32_t)(kn[r] >> 40) == bi && kn[r] - ki < T;
-                            c += go ? 1u : 0u;
-                        }
-                        if (c == 4)
-                            for (uint32_t j = e + 5; j < n; ++j) {
-                                const uint64_t kj = s_keys[j];
-                                if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
-                                ++c;
-                            }
-                        pcnt[lo + e] = (uint8_t)min(c, kPairCountEscape);
-                        cnt_e = c;
-                    }
-                }
-                if (csum) {
-                    const uint32_t ca = (lo + e0 + (tid & ~63u)) >> cb;  // the wave's first chunk
-                    const uint32_t va = ((lo + e) >> cb) == ca ? cnt_e : 0u;
-                    const uint32_t sa = vxd::wave_sum(va), sb = vxd::wave_sum(cnt_e - va);
-                    if ((tid & 63u) == 0) {
-                        if (sa) atomicAdd(&s_csum[ca - c_lo], sa);
-                        if (sb) atomicAdd(&s_csum[ca + 1 - c_lo], sb);
-                    }
-                }
-            }
-            // offsets[b] for the group's buckets: first record with bucket >= b.
-            const uint32_t bfirst = g << (VXK_BUCKET_BITS - G);
-            for (uint32_t bl = tid; bl < nbg; bl += BLOCK) {
-                const uint32_t b = bfirst + bl;
-                uint32_t a = 0, c = n;
-                while (a < c) {
-                    const uint32_t mid = (a + c) >> 1;
-                    if ((uint32_t)(s_keys[mid] >> 40) < b) a = mid + 1; else c = mid;
-                }
-                offsets[b] = lo + a;
-            }
-            __syncthreads();
-            if (csum && n) {  // the chunks of records [lo, lo + n)
-                const uint32_t nch = ((lo + n - 1) >> cb) - c_lo + 1;
-                for (uint32_t i = tid; i < nch; i += BLOCK)
-                    if (s_csum[i]) atomicAdd(&csum[c_lo + i], (unsigned long long)s_csum[i]);
-            }
-        }
+        sort_one_group<BLOCK, CAPMAX>(g0 + t, A, S);
     }
 }
 
@@ -1297,131 +1370,262 @@ __global__ __launch_bounds__(BLOCK) void k_scan_range(const uint64_t *__restrict
 // k_match_emit).
 __device__ __noinline__ uint32_t load_nonce_slow(const uint32_t *nonces, uint32_t i) { return nonces[i]; }
 
+
 template <int BLOCK, int MCAP, int SLOTS>
-__global__ __launch_bounds__(BLOCK) void k_match_emit(Key key, const uint64_t *__restrict__ keys,
-                                                      const uint32_t *__restrict__ nonces,
-                                                      const uint8_t *__restrict__ pcnt,
-                                                      uint32_t n_total, uint32_t cb, uint64_t T,
-                                                      const uint64_t *__restrict__ chunk_base,
-                                                      uint4 *__restrict__ t2, uint64_t cap,
-                                                      const uint32_t *r_lo, const uint32_t *r_hi,
-                                                      uint32_t last, uint32_t *__restrict__ ticket) {
+struct MatchLds {
+    uint32_t nonces[MCAP];
+    uint64_t first[MCAP];  // first Table-2 slot of each record (chunk-relative)
+    uint32_t slot[SLOTS];  // record owning each slot of the window
+    uint64_t wave[BLOCK / 64 + 1];
+};
+
+// Loads chunk ci's nonces (pn, lane-strided) and thread t's word of count
+// bytes (records 4t .. 4t+3).
+template <int BLOCK, int ITEMS>
+__device__ __forceinline__ void match_load(const MatchArgs &A, uint32_t ci, uint32_t (&pn)[ITEMS], uint32_t &pc) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t c = ci << A.cb, m = min(1u << A.cb, A.n_total - c);
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t e = tid + i * BLOCK;
+        if (e < m) pn[i] = A.nonces[c + e];
+    }
+    if (tid * ITEMS < m) pc = *reinterpret_cast<const uint32_t *>(A.pcnt + c + tid * ITEMS);
+}
+
+// Match + Table-2 hash of chunk ci, whose nonces and count word the caller
+// loaded (match_load).  `between` runs once the chunk's counts are scanned
+// (the persistent kernel loads the next chunk there).  Run by the whole
+// work-group; LDS is free again once every thread has returned.
+template <int BLOCK, int MCAP, int SLOTS, typename F>
+__device__ __forceinline__ void match_one_chunk(uint32_t ci, const MatchArgs &A, MatchLds<BLOCK, MCAP, SLOTS> &S,
+                                                const uint32_t (&pn)[MCAP / BLOCK], uint32_t pc, F between) {
     constexpr int ITEMS = MCAP / BLOCK;
     static_assert(ITEMS == 4, "one 32-bit word of count bytes per thread");
-    __shared__ uint32_t s_nonces[MCAP];
-    __shared__ uint64_t s_first[MCAP];  // first Table-2 slot of each record (chunk-relative)
-    __shared__ uint32_t s_slot[SLOTS];  // record owning each slot of the window
-    __shared__ uint64_t s_wave[BLOCK / 64 + 1];
+    uint32_t *s_nonces = S.nonces;
+    uint64_t *s_first = S.first;
+    uint32_t *s_slot = S.slot;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t e0 = tid * ITEMS;
+    const uint32_t n_total = A.n_total;
+    const uint32_t c = ci << A.cb, m = min(1u << A.cb, n_total - c);
+    Key key;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) key.w[w] = A.key[w];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t e = tid + i * BLOCK;
+        if (e < m) s_nonces[e] = pn[i];
+    }
+    const uint32_t cw = pc;
+    const uint64_t base = A.chunk_base[ci];
+    uint32_t cnt[ITEMS];
+    uint64_t mine = 0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        uint32_t cc = 0;
+        if (e0 + i < m) {
+            cc = (cw >> (8 * i)) & 0xffu;
+            if (cc == kPairCountEscape) cc = pairs_after_global(A.keys, c + e0 + i, n_total, A.T);
+        }
+        cnt[i] = cc;
+        mine += cc;
+    }
+    uint64_t ctot;
+    const uint64_t run = vxd::block_exclusive_scan<BLOCK>(mine, S.wave, &ctot);
+    ctot = uniform_u64(ctot);  // same in every lane: keep it in scalar registers
+    between();
+    // A pair-free chunk skips the LDS writes below (it has no barrier after
+    // them before the next chunk).
+    const uint64_t run_end = run + mine;
+    if (ctot) {
+        const uint64_t w1 = SLOTS < ctot ? SLOTS : ctot;
+        uint64_t r = run;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            s_first[e0 + i] = r;
+            const uint64_t hi = r + cnt[i] < w1 ? r + cnt[i] : w1;
+            for (uint64_t q = r; q < hi; ++q) s_slot[q] = e0 + i;
+            r += cnt[i];
+        }
+    }
+    uint4 *out = A.t2 + base;
+    const uint64_t cap = A.cap;
+#pragma unroll 1
+    for (uint64_t w0 = 0; w0 < ctot;) {
+        const uint64_t w1 = w0 + SLOTS < ctot ? w0 + SLOTS : ctot;
+        __syncthreads();
+        const uint32_t nq = (uint32_t)(w1 - w0);
+#pragma unroll 1
+        for (uint32_t qr = tid; qr < nq; qr += BLOCK) {
+            const uint32_t e = s_slot[qr];
+            const uint64_t q = w0 + qr;
+            const uint32_t j = e + 1 + (uint32_t)(q - s_first[e]);
+            const uint32_t na = s_nonces[e];
+            // The partner is almost always in this chunk's LDS copy; an
+            // out-of-line load for the rest keeps the compiler from merging
+            // the two into a generic (flat) load per pair.
+            uint32_t nb;
+            if (__builtin_expect(j < m, 1))
+                nb = s_nonces[j];
+            else
+                nb = load_nonce_slow(A.nonces, c + j);
+            const uint64_t h = vxd::h2(key, na, nb);
+            if (base + q < cap) out[q] = make_uint4(na, nb, (uint32_t)h, (uint32_t)(h >> 32));
+        }
+        __syncthreads();
+        w0 = w1;
+        if (w0 < ctot) {  // next window (crowded keys only): runs from LDS
+            const uint64_t w2 = w0 + SLOTS < ctot ? w0 + SLOTS : ctot;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint64_t f = s_first[e0 + i];
+                const uint64_t g = i + 1 < ITEMS ? s_first[e0 + i + 1] : run_end;
+                const uint64_t lo = f > w0 ? f : w0;
+                const uint64_t hi = g < w2 ? g : w2;
+                for (uint64_t q = lo; q < hi; ++q) s_slot[q - w0] = e0 + i;
+            }
+        }
+    }
+}
+
+template <int BLOCK, int MCAP, int SLOTS>
+__global__ __launch_bounds__(BLOCK) void k_match_emit(MatchArgs A, const uint32_t *r_lo, const uint32_t *r_hi,
+                                                      uint32_t last, uint32_t *__restrict__ ticket) {
+    constexpr int ITEMS = MCAP / BLOCK;
+    __shared__ MatchLds<BLOCK, MCAP, SLOTS> S;
     __shared__ uint32_t s_tk[2];  // alternate, so a slow reader never sees the next ticket
     const uint32_t tid = threadIdx.x;
-    const uint32_t csize = 1u << cb;  // <= MCAP
-    const uint32_t e0 = tid * ITEMS;
     uint32_t c0, nchunks;  // this launch's chunks: [c0, nchunks)
-    chunk_range(r_lo, r_hi, last, cb, (n_total + csize - 1) >> cb, c0, nchunks);
+    chunk_range(r_lo, r_hi, last, A.cb, (A.n_total + (1u << A.cb) - 1) >> A.cb, c0, nchunks);
     if (tid == 0) s_tk[1] = atomicAdd(ticket, 1u);
     __syncthreads();
     uint32_t ci = c0 + s_tk[1];
     if (ci >= nchunks) return;
     uint32_t pn[ITEMS], pc = 0;
-    {
-        const uint32_t c = ci << cb, m = min(csize, n_total - c);
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t e = tid + i * BLOCK;
-            if (e < m) pn[i] = nonces[c + e];
-        }
-        if (e0 < m) pc = *reinterpret_cast<const uint32_t *>(pcnt + c + e0);
-    }
+    match_load<BLOCK, ITEMS>(A, ci, pn, pc);
     for (uint32_t it = 0;; ++it) {
-        const uint32_t c = ci << cb, m = min(csize, n_total - c);
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t e = tid + i * BLOCK;
-            if (e < m) s_nonces[e] = pn[i];
-        }
-        const uint32_t cw = pc;
         if (tid == 0) s_tk[it & 1] = atomicAdd(ticket, 1u);  // the next chunk, read after the scan
-        const uint64_t base = chunk_base[ci];
-        uint32_t cnt[ITEMS];
-        uint64_t mine = 0;
+        uint32_t cur[ITEMS];
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            uint32_t cc = 0;
-            if (e0 + i < m) {
-                cc = (cw >> (8 * i)) & 0xffu;
-                if (cc == kPairCountEscape) cc = pairs_after_global(keys, c + e0 + i, n_total, T);
-            }
-            cnt[i] = cc;
-            mine += cc;
-        }
-        uint64_t ctot;
-        const uint64_t run = vxd::block_exclusive_scan<BLOCK>(mine, s_wave, &ctot);
-        ctot = uniform_u64(ctot);  // same in every lane: keep it in scalar registers
+        for (int i = 0; i < ITEMS; ++i) cur[i] = pn[i];
+        const uint32_t cpc = pc;
+        uint32_t nci = 0;
+        bool more = false;
         // Prefetch the next chunk into registers while this one is hashed.
-        const uint32_t nci = c0 + s_tk[it & 1];
-        const bool more = nci < nchunks;
-        if (more) {
-            const uint32_t nc = nci << cb, nm = min(csize, n_total - nc);
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const uint32_t e = tid + i * BLOCK;
-                if (e < nm) pn[i] = nonces[nc + e];
-            }
-            if (e0 < nm) pc = *reinterpret_cast<const uint32_t *>(pcnt + nc + e0);
-        }
-        // A pair-free chunk skips the LDS writes below (it has no barrier
-        // after them before the next chunk).
-        const uint64_t run_end = run + mine;
-        if (ctot) {
-            const uint64_t w1 = SLOTS < ctot ? SLOTS : ctot;
-            uint64_t r = run;
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                s_first[e0 + i] = r;
-                const uint64_t hi = r + cnt[i] < w1 ? r + cnt[i] : w1;
-                for (uint64_t q = r; q < hi; ++q) s_slot[q] = e0 + i;
-                r += cnt[i];
-            }
-        }
-        uint4 *out = t2 + base;
-#pragma unroll 1
-        for (uint64_t w0 = 0; w0 < ctot;) {
-            const uint64_t w1 = w0 + SLOTS < ctot ? w0 + SLOTS : ctot;
-            __syncthreads();
-            const uint32_t nq = (uint32_t)(w1 - w0);
-#pragma unroll 1
-            for (uint32_t qr = tid; qr < nq; qr += BLOCK) {
-                const uint32_t e = s_slot[qr];
-                const uint64_t q = w0 + qr;
-                const uint32_t j = e + 1 + (uint32_t)(q - s_first[e]);
-                const uint32_t na = s_nonces[e];
-                // The partner is almost always in this chunk's LDS copy; an
-                // out-of-line load for the rest keeps the compiler from
-                // merging the two into a generic (flat) load per pair.
-                uint32_t nb;
-                if (__builtin_expect(j < m, 1))
-                    nb = s_nonces[j];
-                else
-                    nb = load_nonce_slow(nonces, c + j);
-                const uint64_t h = vxd::h2(key, na, nb);
-                if (base + q < cap) out[q] = make_uint4(na, nb, (uint32_t)h, (uint32_t)(h >> 32));
-            }
-            __syncthreads();
-            w0 = w1;
-            if (w0 < ctot) {  // next window (crowded keys only): runs from LDS
-                const uint64_t w2 = w0 + SLOTS < ctot ? w0 + SLOTS : ctot;
-#pragma unroll
-                for (int i = 0; i < ITEMS; ++i) {
-                    const uint64_t f = s_first[e0 + i];
-                    const uint64_t g = i + 1 < ITEMS ? s_first[e0 + i + 1] : run_end;
-                    const uint64_t lo = f > w0 ? f : w0;
-                    const uint64_t hi = g < w2 ? g : w2;
-                    for (uint64_t q = lo; q < hi; ++q) s_slot[q - w0] = e0 + i;
-                }
-            }
-        }
+        match_one_chunk<BLOCK, MCAP, SLOTS>(ci, A, S, cur, cpc, [&]() {
+            nci = c0 + s_tk[it & 1];
+            more = nci < nchunks;
+            if (more) match_load<BLOCK, ITEMS>(A, nci, pn, pc);
+        });
         if (!more) break;
         ci = nci;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One persistent launch of a software-pipelined plot (or batch of plots):
+// items of up to four kinds -- hash sub-tiles (H), partition-pass sub-tiles
+// (P), group sorts (S) and match chunks (M) -- from slices whose inputs
+// earlier launches finished (stream order makes them visible; no item
+// waits on another).  Work-groups take items from one ticket counter, the
+// kinds interleaved in proportion to their numbers, so that the vector-ALU
+// work (hash, match) and the memory and LDS work (passes, sort) of
+// different slices share every CU.  The kinds share one LDS area, so every
+// item starts behind a barrier; the filing counters have their own.
+// ---------------------------------------------------------------------------
+
+// The four kinds of k_pipe items, each out of line so that none keeps
+// another's values in registers.
+template <int BLOCK>
+struct PipeLds {
+    static constexpr int CAP = kGroupCapFast;
+    union Area {
+        struct {
+            uint64_t keys[kPipeSub];
+            uint32_t non[kPipeSub];
+        } f;
+        SortLds<BLOCK, CAP> s;
+        MatchLds<BLOCK, kMatchCap, kMatchSlots> m;
+    } a;
+    uint32_t cnt[1 << kPipeMaxBits];
+    uint32_t pos[(1 << kPipeMaxBits) + 1];
+    uint32_t claim[1 << kPipeMaxBits];
+};
+
+template <int BLOCK>
+__device__ __noinline__ void pipe_hash(const HashSliceDesc &H, uint32_t x, PipeLds<BLOCK> &S) {
+    constexpr int FI = kPipeSub / BLOCK;
+    uint64_t k[FI];
+    uint32_t nv[FI];
+    const uint32_t m = hash_subtile<BLOCK, FI>(H, x, k, nv);
+    file_records<BLOCK, FI, 1 << kPipeMaxBits>(k, nv, m, 64u - H.bits, (1u << H.bits) - 1u, H.fill, 0, H.R,
+                                                   H.keys, H.nonces, H.status, S.a.f.keys, S.a.f.non, S.cnt, S.pos,
+                                                   S.claim, [] {});
+}
+
+template <int BLOCK>
+__device__ __noinline__ void pipe_pass(const PassSliceDesc &P, uint32_t x, PipeLds<BLOCK> &S) {
+    constexpr int FI = kPipeSub / BLOCK;
+    uint64_t k[FI];
+    uint32_t nv[FI], r;
+    const uint32_t m = load_subtile<BLOCK, FI>(P, x, k, nv, &r);
+    file_records<BLOCK, FI, 1 << kPipeMaxBits>(k, nv, m, P.shift, (1u << P.bits) - 1u, P.out_fill,
+                                                   (P.r0 + r) << P.bits, P.R_out, P.out_keys, P.out_nonces, P.status,
+                                                   S.a.f.keys, S.a.f.non, S.cnt, S.pos, S.claim, [] {});
+}
+
+template <int BLOCK>
+__device__ __noinline__ void pipe_sort(const PipeSortDesc &D, uint32_t x, PipeLds<BLOCK> &S) {
+    sort_one_group<BLOCK, PipeLds<BLOCK>::CAP>(D.g0 + x, D.a, S.a.s);
+}
+
+template <int BLOCK>
+__device__ __noinline__ void pipe_match(const PipeMatchDesc &M, uint32_t x, PipeLds<BLOCK> &S) {
+    uint32_t c0, c1;
+    chunk_range(M.r_lo, M.r_hi, M.last, M.a.cb, (M.a.n_total + (1u << M.a.cb) - 1) >> M.a.cb, c0, c1);
+    const uint32_t ci = c0 + x;
+    if (ci >= c1) return;  // the item count is an upper bound
+    uint32_t pn[kMatchCap / BLOCK], pc = 0;
+    match_load<BLOCK, kMatchCap / BLOCK>(M.a, ci, pn, pc);
+    match_one_chunk<BLOCK, kMatchCap, kMatchSlots>(ci, M.a, S.a.m, pn, pc, [] {});
+}
+
+// The launch's list is read from device memory (k_store_list wrote it), so
+// the items' descriptors are passed on by address without copies.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_pipe(const PipeList *__restrict__ Lp,
+                                                                                uint32_t *__restrict__ ticket) {
+    const PipeList &L = *Lp;
+    __shared__ PipeLds<BLOCK> S;
+    __shared__ uint32_t s_tk[2];  // alternate, so a slow reader never sees the next ticket
+    const uint32_t tid = threadIdx.x;
+    const uint64_t NT = (uint64_t)L.items[0] + L.items[1] + L.items[2] + L.items[3];
+    if (tid < (1u << kPipeMaxBits)) S.cnt[tid] = 0;
+    for (uint32_t it = 0;; ++it) {
+        if (tid == 0) s_tk[it & 1] = atomicAdd(ticket, 1u);
+        __syncthreads();
+        const uint64_t t = s_tk[it & 1];
+        if (t >= NT) break;
+        uint64_t i1, i2, i3;
+        uint32_t d = 0;
+        if (take_first(t, L.frac[0], i1)) {
+            uint32_t x = (uint32_t)i1;
+            while (d + 1 < L.n[0] && x >= L.h[d].items) x -= L.h[d].items, ++d;
+            pipe_hash<BLOCK>(L.h[d], x, S);
+        } else if (take_first(i1, L.frac[1], i2)) {
+            uint32_t x = (uint32_t)i2;
+            while (d + 1 < L.n[1] && x >= L.p[d].items) x -= L.p[d].items, ++d;
+            pipe_pass<BLOCK>(L.p[d], x, S);
+        } else if (take_first(i2, L.frac[2], i3)) {
+            uint32_t x = (uint32_t)i3;
+            while (d + 1 < L.n[2] && x >= L.s[d].items) x -= L.s[d].items, ++d;
+            pipe_sort<BLOCK>(L.s[d], x, S);
+        } else {
+            uint32_t x = (uint32_t)i3;
+            while (d + 1 < L.n[3] && x >= L.m[d].items) x -= L.m[d].items, ++d;
+            pipe_match<BLOCK>(L.m[d], x, S);
+        }
     }
 }
 
@@ -1863,9 +2067,6 @@ constexpr int kColBlock = 1024;
 constexpr int kSortBlock = 512;
 constexpr int kFallbackBlock = 1024;
 constexpr int kFallbackGrid = 256;
-constexpr int kMatchBlock = 512;
-constexpr int kMatchCap = 2048;
-constexpr int kMatchSlots = 4096;
 
 hipError_t launch_hash_filter(const uint32_t key_words[8], uint64_t n, uint32_t tiles, uint64_t chunk,
                               uint32_t pbits, uint32_t prefix, uint64_t *keys, uint32_t *nonces, uint64_t cap,
@@ -1910,24 +2111,36 @@ hipError_t launch_hash_scatter(const uint32_t key_words[8], uint64_t n, uint32_t
 hipError_t launch_hash_pass(const HashPassList &L, uint32_t *ticket, hipStream_t s) {
     static_assert(1 << kHashPassMaxBits <= kHashBlock, "one thread per digit");
     if (L.nh > (uint32_t)kHashPassMaxSlices || L.np > (uint32_t)kHashPassMaxSlices) return hipErrorInvalidValue;
-    for (uint32_t i = 0; i < L.nh; ++i)
+    uint32_t bits = 1;
+    for (uint32_t i = 0; i < L.nh; ++i) {
         if (L.h[i].bits < 1 || L.h[i].bits > (uint32_t)kHashPassMaxBits) return hipErrorInvalidValue;
-    for (uint32_t i = 0; i < L.np; ++i)
+        bits = max(bits, L.h[i].bits);
+    }
+    for (uint32_t i = 0; i < L.np; ++i) {
         if (L.p[i].bits < 1 || L.p[i].bits > (uint32_t)kHashPassMaxBits || L.p[i].per < 1) return hipErrorInvalidValue;
+        bits = max(bits, L.p[i].bits);
+    }
     const uint64_t nt = (uint64_t)L.h_items + L.p_items;
     if (nt == 0) return hipSuccess;
-    static const uint32_t grid =
-        resident_grid(k_hash_pass<kHashBlock, kHashScatterItems, 1 << kHashPassMaxBits>, kHashBlock);
+    // Digits up to 7 bits take the kernel whose LDS fits six work-groups on
+    // a CU; 8-bit digits the one with room for 256 counters (five).
+    static const uint32_t grid7 = resident_grid(k_hash_pass<kHashBlock, kHashScatterItems, 128>, kHashBlock);
+    static const uint32_t grid8 = resident_grid(k_hash_pass<kHashBlock, kHashScatterItems, 256>, kHashBlock);
+    const uint32_t grid = bits <= 7 ? grid7 : grid8;
     const uint32_t used = nt < grid ? (uint32_t)nt : grid;
-    hipLaunchKernelGGL((k_hash_pass<kHashBlock, kHashScatterItems, 1 << kHashPassMaxBits>), dim3(used),
-                       dim3(kHashBlock), 0, s, L, ticket);
+    if (bits <= 7)
+        hipLaunchKernelGGL((k_hash_pass<kHashBlock, kHashScatterItems, 128>), dim3(used), dim3(kHashBlock), 0, s, L,
+                           ticket);
+    else
+        hipLaunchKernelGGL((k_hash_pass<kHashBlock, kHashScatterItems, 256>), dim3(used), dim3(kHashBlock), 0, s, L,
+                           ticket);
     return hipGetLastError();
 }
 
-hipError_t launch_region_scan_slices(const uint32_t *fill, uint32_t slices, uint32_t nd, uint32_t R,
-                                     uint32_t *gstart, hipStream_t s) {
-    hipLaunchKernelGGL(k_region_scan_slices<kColBlock>, dim3(1), dim3(kColBlock), 0, s, fill, slices, nd, R,
-                       gstart);
+hipError_t launch_region_scan_slices(const uint32_t *fill, uint32_t slices, uint32_t stride, uint32_t nd,
+                                     uint32_t R, uint32_t *gstart, hipStream_t s) {
+    hipLaunchKernelGGL(k_region_scan_slices<kColBlock>, dim3(1), dim3(kColBlock), 0, s, fill, slices, stride, nd,
+                       R, gstart);
     return hipGetLastError();
 }
 
@@ -2073,15 +2286,14 @@ hipError_t launch_groupsort(uint64_t *keys, uint32_t *nonces, const uint64_t *in
     const bool fast = cap <= (uint32_t)kGroupCapFast;
     const uint32_t grid = min(gcount, fast ? resident_fast : resident_max);
     if (grid == 0) return hipSuccess;
-    const GroupIn in{in_keys, in_nonces, in_lo, in_hi};
+    const SortArgs A{keys, nonces, GroupIn{in_keys, in_nonces, in_lo, in_hi}, gstart, offsets, ovf_count, ovf_list,
+                     pcnt, reinterpret_cast<unsigned long long *>(csum), T, G, cap, n_total, cb};
     if (fast)
-        hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapFast>), dim3(grid), dim3(kSortBlock), 0, s,
-                           keys, nonces, in, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T, pcnt, g0,
-                           gcount, ticket, reinterpret_cast<unsigned long long *>(csum), cb);
+        hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapFast>), dim3(grid), dim3(kSortBlock), 0, s, A, g0,
+                           gcount, ticket);
     else
-        hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapMax>), dim3(grid), dim3(kSortBlock), 0, s,
-                           keys, nonces, in, gstart, G, cap, offsets, n_total, ovf_count, ovf_list, T, pcnt, g0,
-                           gcount, ticket, reinterpret_cast<unsigned long long *>(csum), cb);
+        hipLaunchKernelGGL((k_groupsort<kSortBlock, kGroupCapMax>), dim3(grid), dim3(kSortBlock), 0, s, A, g0,
+                           gcount, ticket);
     return hipGetLastError();
 }
 
@@ -2149,9 +2361,30 @@ hipError_t launch_match_emit(const uint32_t key_words[8], const uint64_t *keys, 
     static const uint32_t per_cu = max(1u, resident / max(1u, (uint32_t)device_cus()));
     const uint32_t want = wg_per_cu ? min(wg_per_cu, per_cu) * (uint32_t)device_cus() : resident;
     const uint32_t grid = max(1u, min(max_chunks, want));
+    MatchArgs A{{}, keys, nonces, pcnt, chunk_base, (uint4 *)t2, cap, T, n_total, chunk_bits};
+    for (int i = 0; i < 8; ++i) A.key[i] = key_words[i];
     hipLaunchKernelGGL((k_match_emit<kMatchBlock, kMatchCap, kMatchSlots>), dim3(grid), dim3(kMatchBlock),
-                       0, s, key, keys, nonces, pcnt, n_total, chunk_bits, T, chunk_base, (uint4 *)t2, cap,
-                       r_lo, r_hi, last, ticket);
+                       0, s, A, r_lo, r_hi, last, ticket);
+    return hipGetLastError();
+}
+
+__global__ void k_store_list(PipeList L, PipeList *dst) {
+    if (threadIdx.x == 0) *dst = L;
+}
+
+hipError_t launch_pipe(const PipeList &L, PipeList *d_list, uint32_t *ticket, hipStream_t s) {
+    for (int r = 0; r < 4; ++r)
+        if (L.n[r] > (uint32_t)kPipeMaxLists) return hipErrorInvalidValue;
+    for (uint32_t i = 0; i < L.n[0]; ++i)
+        if (L.h[i].bits < 1 || L.h[i].bits > (uint32_t)kPipeMaxBits) return hipErrorInvalidValue;
+    for (uint32_t i = 0; i < L.n[1]; ++i)
+        if (L.p[i].bits < 1 || L.p[i].bits > (uint32_t)kPipeMaxBits || L.p[i].per < 1) return hipErrorInvalidValue;
+    const uint64_t nt = (uint64_t)L.items[0] + L.items[1] + L.items[2] + L.items[3];
+    if (nt == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_store_list, dim3(1), dim3(64), 0, s, L, d_list);
+    static const uint32_t grid = resident_grid(k_pipe<kPipeBlock>, kPipeBlock);
+    const uint32_t used = nt < grid ? (uint32_t)nt : grid;
+    hipLaunchKernelGGL(k_pipe<kPipeBlock>, dim3(used), dim3(kPipeBlock), 0, s, (const PipeList *)d_list, ticket);
     return hipGetLastError();
 }
 

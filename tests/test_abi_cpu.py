@@ -145,11 +145,32 @@ def test_hash_slices_take_their_own_plan():
               dict(group_bits=13, pass1_bits=3), dict(group_bits=20)):
         assert hq(hash_slices=4, **t) == 4, t
         assert ws(hash_slices=4, **t) != ws(hash_slices=1, **t), t
-    # beyond the sliced kernel: a first digit of 8 bits, one pass, too few records per region
-    for t in (dict(group_bits=16, pass1_bits=8), dict(group_bits=9, pass1_bits=9), dict(group_bits=1)):
+    # beyond the sliced kernel: a first digit of 9 bits, one pass, too few records per region
+    assert hq(hash_slices=4, group_bits=16, pass1_bits=8) == 4   # 8-bit digits: the wider kernel
+    for t in (dict(group_bits=18, pass1_bits=9), dict(group_bits=9, pass1_bits=9), dict(group_bits=1)):
         assert hq(hash_slices=4, **t) == 1, t
         assert ws(hash_slices=4, **t) == ws(hash_slices=1, **t), t
     assert hq(hash_slices=16, group_bits=14) == 16
     assert N.vx_hash_slices(N.make_params(bytes(range(32)), 3), N.make_tuning(hash_slices=8, group_bits=2)) == 1
     assert hq(hash_slices=17) == 0 and ws(hash_slices=17) == 0  # invalid tuning
     assert N.vx_hash_slices(p) >= 1
+
+
+def test_tail_slices_take_their_own_plan():
+    """The pipelined tail is planned only where its kernel applies: region
+    passes, at most 2560 records per group in LDS, a third digit of at most
+    7 bits, and no more slices than second-pass regions."""
+    from paper_2606_14007_amd import _native as N
+    p = N.make_params(bytes(range(32)), 16)
+    zt = lambda **t: N.vx_tail_slices(p, N.make_tuning(**t))
+    assert zt(tail_slices=4) == 1                         # k = 16: one pass by default
+    assert zt(tail_slices=4, group_bits=10) == 4
+    assert zt(tail_slices=4, group_bits=15) == 4
+    assert zt(tail_slices=16, group_bits=14) == 16
+    assert zt(tail_slices=4, group_bits=10, group_cap=3072) == 1      # the 3072-record sort kernel
+    assert zt(tail_slices=4, group_bits=10, fused_sort_match=1) == 1  # the fused tail
+    assert zt(tail_slices=4, group_bits=1) == 1           # one pass
+    assert zt(tail_slices=4, group_bits=20, pass1_bits=4, pass2_bits=7) == 1  # a 9-bit third digit
+    assert zt(tail_slices=16, group_bits=5) == 1          # four second-pass regions
+    assert zt(tail_slices=17) == 0                        # invalid tuning
+    assert N.vx_tail_slices(p) >= 1

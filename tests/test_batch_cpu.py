@@ -18,10 +18,19 @@ def test_lanes_single_lane():
     assert _assign_lanes([5, 3, 9], 1) == [0, 0, 0]
 
 
-def test_autotune_candidates_valid():
-    for k in (12, 22, 27, 31):
-        c = autotune.candidates(k)
-        assert c and all(1 <= d["group_bits"] <= 20 for d in c)
-        assert all(d["match_chunk_bits"] in (10, 11) for d in c)
-        t = autotune.to_native(c[0])
-        assert t.group_bits == c[0]["group_bits"]
+def test_autotune_searches_the_named_tunables():
+    """The search covers the hash's slices, the first digit, the group bits
+    (bucket-partition granularity), the sort group capacity and the match
+    chunk; its single-axis variants map onto vx_tuning fields, and those
+    the plan rejects are filtered out before any timing."""
+    for k in (22, 27, 29, 31):
+        names = [a for a, _ in autotune.axes(k)]
+        assert names == ["hash_slices", "group_bits", "pass1_bits", "group_cap", "match_chunk_bits"]
+        cands = autotune.candidates(k)
+        assert cands[0] == {} and len(cands) >= 10
+        for d in cands[1:]:
+            (f, v), = d.items()
+            assert getattr(autotune.to_native(d), f) == v
+        ok = [d for d in cands if autotune.valid(k, d)]
+        assert {} in ok and len(ok) >= 8
+    assert not autotune.valid(22, {"pass1_bits": 12})

@@ -95,3 +95,42 @@ def test_graph_replay_recomputes_every_time(vx, refs):
         for b, ref in zip(bt.plots, refs):
             _check(vx, b, ref)
         assert vx.t2_count(other) >= 0
+
+
+def test_batch_fused_fronts_mixed_plans(vx, refs):
+    """Plans whose hash files two passes and that ask for it share fused
+    hash launches across plots (a device work list of slices); the others
+    run whole on their lanes.  Two lanes, so workspaces are shared and the batch runs in
+    several rounds.  Mixed: sliced and one-launch fronts, three passes, a
+    pipelined tail, and one-pass plots."""
+    from paper_2606_14007_amd import batch as B
+    specs = _specs()  # k = 16, 10, 18, 13, 17, 12, 15, 14
+    tun = []
+    for i, s in enumerate(specs):
+        if i % 4 == 0:
+            tun.append(vx.make_tuning(group_bits=s.k - 5, hash_slices=3))
+        elif i % 4 == 1:
+            tun.append(vx.make_tuning(group_bits=max(10, s.k - 2), hash_slices=1, tail_slices=2))
+        elif i % 4 == 2:
+            tun.append(vx.make_tuning(group_bits=min(s.k + 2, 18), hash_slices=5))
+        else:
+            tun.append(None)
+    tun = [t if t is not None else vx.make_tuning() for t in tun]
+    for t in tun:
+        t.batch_shared_hash = 1
+    fused = [vx.vx_partition_passes(vx.make_params(s.key, s.k), t) >= 2 for s, t in zip(specs, tun)]
+    assert 2 <= sum(fused) < len(specs)
+    bt = B.alloc_batch(specs, tunings=tun, lanes=2)
+    B.plot_batch(bt, check_result=True)
+    torch.cuda.synchronize()
+    for b, ref in zip(bt.plots, refs):
+        _check(vx, b, ref)
+    B.capture(bt)
+    for r in range(2):
+        for b in bt.plots:
+            b.t1_keys.fill_(-1)
+            b.t2_count.zero_()
+        B.replay(bt, check_result=True)
+        torch.cuda.synchronize()
+        for b, ref in zip(bt.plots, refs):
+            _check(vx, b, ref)

@@ -85,12 +85,24 @@ def test_plot_default_threshold(vx, k):
     _assert_plot_equal(vx, b, oracle.plot(KEY0, k, threads=8))
 
 
-@pytest.mark.parametrize("k,hq", [(20, 2), (20, 7), (22, 8), (24, 4), (24, 16)])
+@pytest.mark.parametrize("k,hq", [(20, 2), (20, 7), (22, 8), (24, 4), (24, 16), (26, 4)])
 def test_plot_sliced_hash(vx, k, hq):
     """The plot hashed in nonce slices, each slice's second pass beside the
     next slice's hash, with the default group bits (two passes up to k=25,
     three above)."""
     b = vx.plot(KEY0, k, tuning=vx.make_tuning(hash_slices=hq))
+    _assert_plot_equal(vx, b, oracle.plot(KEY0, k, threads=8))
+
+
+@pytest.mark.parametrize("k,hq,zt,gb", [(20, 1, 4, 12), (22, 4, 8, 0), (24, 8, 16, 0), (22, 2, 8, 18),
+                                        (23, 16, 8, 20)])
+def test_plot_pipelined_tail(vx, k, hq, zt, gb):
+    """The third pass, the sort and the match pipelined over zt slices (one
+    persistent launch per step), after a one-launch or sliced hash; 18 and
+    20 group bits give three passes at these sizes."""
+    t = vx.make_tuning(hash_slices=hq, tail_slices=zt, group_bits=gb)
+    assert vx.vx_tail_slices(vx.make_params(KEY0, k), t) == zt
+    b = vx.plot(KEY0, k, tuning=t)
     _assert_plot_equal(vx, b, oracle.plot(KEY0, k, threads=8))
 
 
@@ -133,6 +145,15 @@ TUNINGS = [
     dict(hash_slices=5, group_bits=16, fused_sort_match=1),  # sliced hash, fused tail
     dict(hash_slices=2, group_bits=20),       # 6-7-7 (the k=31 split), tiny groups
     dict(hash_slices=4, group_cap=64),        # sliced hash, oversized groups
+    dict(hash_slices=6, group_bits=16),       # 8-8: the sliced kernel with 256 counters
+    dict(hash_slices=3, group_bits=17, pass1_bits=8, pass2_bits=8),  # 8-8-1
+    dict(tail_slices=2, group_bits=10),       # pipelined tail: sort + match over two slices
+    dict(tail_slices=4, group_bits=15, pass1_bits=5, pass2_bits=5),  # third pass, sort, match pipelined
+    dict(tail_slices=3, hash_slices=4, group_bits=20),  # sliced hash + pipelined tail, 6-7-7
+    dict(tail_slices=16, group_bits=14),      # sixteen slices of two-pass groups
+    dict(tail_slices=5, hash_slices=3, group_bits=12),  # uneven tail slices after a sliced hash
+    dict(tail_slices=4, group_bits=11, match_chunk_bits=6),  # small match chunks spanning slices
+    dict(tail_slices=4, group_cap=64, group_bits=14),   # oversized groups: fallback per slice
 ]
 
 
@@ -290,7 +311,8 @@ def test_region_overflow_is_reported(vx):
 
 
 @pytest.mark.parametrize("tun", [dict(group_bits=12), dict(group_bits=14, pass1_bits=4, pass2_bits=5),
-                                 dict(group_bits=12, hash_slices=4), dict(group_bits=16, hash_slices=3)])
+                                 dict(group_bits=12, hash_slices=4), dict(group_bits=18, hash_slices=3),
+                                 dict(group_bits=12, tail_slices=4), dict(group_bits=18, hash_slices=2, tail_slices=3)])
 @pytest.mark.parametrize("pct", [10, 25])
 def test_region_overflow_with_matching_stays_bounded(vx, tun, pct):
     """Overflowing regions with the default threshold, so that the match
