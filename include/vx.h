@@ -131,7 +131,7 @@ typedef struct {
                                   leading digits fit 7 bits each); 0 = the default for k */
     uint32_t tail_slices;      /* vx_plot: 1 = the third partition pass, the sort and the match as
                                   separate kernels; 2..16 = pipelined over that many slices of the
-                                  second pass's regions, one persistent launch per step running the
+                                  first pass's segments, one persistent launch per step running the
                                   third pass of one slice, the sort of the previous and the match of
                                   the one before (plots with region passes, group_cap <= 2560 and
                                   digits of at most 7 bits after the second); 0 = the default for k */

@@ -299,10 +299,9 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     // the filing kernel's 7 bits; slices cut the second pass's regions.
     {
         const uint32_t zt = t->tail_slices ? t->tail_slices : default_tail_slices(P.k);
-        const uint32_t n1 = P.npass >= 2 ? 1u << (P.pre[1] + P.D[1]) : 0;
         if (zt > 1 && !records && staged < 0 && !P.fused && P.slices == 1 && P.hs && P.npass >= 2 &&
             P.cap <= (uint32_t)vxk::kGroupCapFast && (P.npass < 3 || P.D[2] <= (uint32_t)vxk::kPipeMaxBits) &&
-            n1 >= zt)
+            (1u << P.D[0]) >= zt)
             P.zt = zt;
     }
     if (staged >= 0 && !P.hs)
@@ -806,7 +805,14 @@ vx_status run_pipe_tail(const Plan &P, const Layout &L, void *ws, const vx_plot_
     const uint32_t per = (P.R[1] + vxk::kPipeSub - 1) / vxk::kPipeSub;
     vxk::PipeList *dl = at<vxk::PipeList>(ws, L.pipelist);
     const uint32_t off_s = p3 ? 1 : 0, off_m = off_s + 1;
-    auto cut = [&](uint32_t j) { return (uint32_t)((uint64_t)N1 * j / Z); };
+    // Slices are whole first-pass segments (2^D[1] second-pass regions
+    // each): a segment's Table-1 span is its first-pass count, which also
+    // covers the holes a region overflow leaves after its groups, so the
+    // segments' capacity bounds the match chunks a slice owns.
+    const uint32_t N0 = 1u << P.D[0];
+    auto seg_cut = [&](uint32_t j) { return (uint32_t)((uint64_t)N0 * j / Z); };
+    auto cut = [&](uint32_t j) { return seg_cut(j) << P.D[1]; };
+    (void)N1;
     const vxk::SortArgs sa{b->t1_keys, b->t1_nonces,
                            vxk::GroupIn{Bl.out_k, Bl.out_n, at<uint32_t>(ws, L.seg_lo[last]),
                                         at<uint32_t>(ws, L.seg_hi[last])},
@@ -854,9 +860,11 @@ vx_status run_pipe_tail(const Plan &P, const Layout &L, void *ws, const vx_plot_
             M.r_lo = gst1 + a;
             M.r_hi = gst1 + e;
             M.last = j + 1 == Z;
-            // The slice's records fit its second-pass regions; its chunks are
-            // at most one more than its records fill.
-            const uint64_t maxrec = std::min<uint64_t>(P.n, (uint64_t)(e - a) * P.R[1]);
+            // The slice's Table-1 span fits its segments' first-pass regions
+            // (P.hq of R[0] records each); its chunks are at most one more
+            // than that span fills.
+            const uint64_t span = (uint64_t)(seg_cut(j + 1) - seg_cut(j)) * P.hq * P.R[0];
+            const uint64_t maxrec = std::min<uint64_t>(P.n, span);
             M.items = (uint32_t)(maxrec >> P.cb) + 2;
             W.items[3] += M.items;
         }

@@ -1437,9 +1437,57 @@ __device__ __forceinline__ void match_one_chunk(uint32_t ci, const MatchArgs &A,
     between();
     // A pair-free chunk skips the LDS writes below (it has no barrier after
     // them before the next chunk).
+    if (ctot == 0) return;
+    uint4 *out = A.t2 + base;
+    const uint64_t cap = A.cap;
+    if (ctot <= SLOTS) {
+        // One window (every chunk of BLAKE3 keys): slots fit 32 bits, and a
+        // chunk whose slots all fit Table 2 skips the per-pair check.
+        uint32_t *s_first32 = reinterpret_cast<uint32_t *>(s_first);
+        uint32_t r = (uint32_t)run;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            s_first32[e0 + i] = r;
+            for (uint32_t q = r; q < r + cnt[i]; ++q) s_slot[q] = e0 + i;
+            r += cnt[i];
+        }
+        __syncthreads();
+        const uint32_t nq = (uint32_t)ctot;
+        auto pair = [&](uint32_t qr, uint32_t &na, uint32_t &nb) {
+            const uint32_t e = s_slot[qr];
+            const uint32_t j = e + 1 + qr - s_first32[e];
+            na = s_nonces[e];
+            // The partner is almost always in this chunk's LDS copy; an
+            // out-of-line load for the rest keeps the compiler from merging
+            // the two into a generic (flat) load per pair.
+            if (__builtin_expect(j < m, 1))
+                nb = s_nonces[j];
+            else
+                nb = load_nonce_slow(A.nonces, c + j);
+        };
+        if (base + ctot <= cap) {
+#pragma unroll 1
+            for (uint32_t qr = tid; qr < nq; qr += BLOCK) {
+                uint32_t na, nb;
+                pair(qr, na, nb);
+                const uint64_t h = vxd::h2(key, na, nb);
+                out[qr] = make_uint4(na, nb, (uint32_t)h, (uint32_t)(h >> 32));
+            }
+        } else {
+#pragma unroll 1
+            for (uint32_t qr = tid; qr < nq; qr += BLOCK) {
+                uint32_t na, nb;
+                pair(qr, na, nb);
+                const uint64_t h = vxd::h2(key, na, nb);
+                if (base + qr < cap) out[qr] = make_uint4(na, nb, (uint32_t)h, (uint32_t)(h >> 32));
+            }
+        }
+        __syncthreads();
+        return;
+    }
     const uint64_t run_end = run + mine;
-    if (ctot) {
-        const uint64_t w1 = SLOTS < ctot ? SLOTS : ctot;
+    {
+        const uint64_t w1 = SLOTS;
         uint64_t r = run;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
@@ -1449,8 +1497,6 @@ __device__ __forceinline__ void match_one_chunk(uint32_t ci, const MatchArgs &A,
             r += cnt[i];
         }
     }
-    uint4 *out = A.t2 + base;
-    const uint64_t cap = A.cap;
 #pragma unroll 1
     for (uint64_t w0 = 0; w0 < ctot;) {
         const uint64_t w1 = w0 + SLOTS < ctot ? w0 + SLOTS : ctot;
@@ -1490,7 +1536,7 @@ __device__ __forceinline__ void match_one_chunk(uint32_t ci, const MatchArgs &A,
 }
 
 template <int BLOCK, int MCAP, int SLOTS>
-__global__ __launch_bounds__(BLOCK) void k_match_emit(MatchArgs A, const uint32_t *r_lo, const uint32_t *r_hi,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_match_emit(MatchArgs A, const uint32_t *r_lo, const uint32_t *r_hi,
                                                       uint32_t last, uint32_t *__restrict__ ticket) {
     constexpr int ITEMS = MCAP / BLOCK;
     __shared__ MatchLds<BLOCK, MCAP, SLOTS> S;

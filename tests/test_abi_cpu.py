@@ -159,7 +159,8 @@ def test_hash_slices_take_their_own_plan():
 def test_tail_slices_take_their_own_plan():
     """The pipelined tail is planned only where its kernel applies: region
     passes, at most 2560 records per group in LDS, a third digit of at most
-    7 bits, and no more slices than second-pass regions."""
+    7 bits, and no more slices than first-pass segments (slices are whole
+    segments)."""
     from paper_2606_14007_amd import _native as N
     p = N.make_params(bytes(range(32)), 16)
     zt = lambda **t: N.vx_tail_slices(p, N.make_tuning(**t))
@@ -171,6 +172,8 @@ def test_tail_slices_take_their_own_plan():
     assert zt(tail_slices=4, group_bits=10, fused_sort_match=1) == 1  # the fused tail
     assert zt(tail_slices=4, group_bits=1) == 1           # one pass
     assert zt(tail_slices=4, group_bits=20, pass1_bits=4, pass2_bits=7) == 1  # a 9-bit third digit
-    assert zt(tail_slices=16, group_bits=5) == 1          # four second-pass regions
+    assert zt(tail_slices=16, group_bits=5) == 1          # one pass
+    assert zt(tail_slices=16, group_bits=15, pass1_bits=3) == 1   # eight first-pass segments
+    assert zt(tail_slices=8, group_bits=15, pass1_bits=3) == 8
     assert zt(tail_slices=17) == 0                        # invalid tuning
     assert N.vx_tail_slices(p) >= 1

@@ -299,14 +299,16 @@ def test_region_overflow_is_reported(vx):
     out of Table 1 cannot make the match walk far."""
     from paper_2606_14007_amd import _native as N
     k = 16
-    small = vx.make_tuning(group_bits=12, region_pct=25)
+    # a 6-bit first digit: 64 stage regions of ~1024 records, which a quarter
+    # of their capacity cannot hold
+    small = vx.make_tuning(group_bits=12, pass1_bits=6, region_pct=25)
     b = vx.plot(KEY0, k, threshold=0, tuning=small)
     torch.cuda.synchronize()
     assert vx.device_status(b.workspace) & N.VX_DEV_STATUS_REGION_OVERFLOW
     st = vx.stage_plot(KEY0, k, 1, tuning=small)
     torch.cuda.synchronize()
     assert vx.device_status(st.data) & N.VX_DEV_STATUS_REGION_OVERFLOW
-    b = vx.plot(KEY0, k, threshold=0, tuning=vx.make_tuning(group_bits=12))
+    b = vx.plot(KEY0, k, threshold=0, tuning=vx.make_tuning(group_bits=12, pass1_bits=6))
     _assert_plot_equal(vx, b, oracle.plot(KEY0, k, threshold=0))
 
 
