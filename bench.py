@@ -49,9 +49,11 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, k: int):
-    """HBM bytes per launch of `kernel` at size k, from the committed
-    rocprofv3 counter summary, or None when absent or taken on other code."""
+def load_traffic(kernel: str, k: int, launches: int = 1):
+    """HBM bytes of `kernel` at size k, from the committed rocprofv3 counter
+    summary: per launch, or summed over the `launches` launches of one plot
+    where a stage runs the kernel several times (the record names that
+    count).  None when absent, taken on other code or on another split."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -62,8 +64,9 @@ def load_traffic(kernel: str, k: int):
             continue
         parts = ln.split()
         if len(parts) >= 5 and parts[0] == kernel and parts[1] == f"k={k}":
-            rec = {"sha": parts[2], "fetch": float(parts[3]), "write": float(parts[4])}
-    if not rec or rec["sha"] != source_digest():
+            n = int(parts[5].split("=")[1]) if len(parts) >= 6 else 1
+            rec = {"sha": parts[2], "fetch": float(parts[3]), "write": float(parts[4]), "n": n}
+    if not rec or rec["sha"] != source_digest() or rec["n"] != launches:
         return None
     return rec["fetch"] + rec["write"]
 
@@ -639,14 +642,21 @@ def main() -> int:
     tslices = vx.vx_tail_slices(params, tun)
     # With two or more passes the hash kernel also does the first pass (its
     # stage is then only the region scan); a one-pass plot hashes alone.  A
-    # plot hashed in slices also does the second pass in the hash launches.
+    # plot hashed in slices also does the second pass in the hash launches,
+    # and the third where it has one (launch i filing slice i - 2).
     fused_first = npass >= 2
-    in_hash = 0 if not fused_first else (2 if hslices > 1 else 1)
+    in_hash = vx.vx_front_passes(params, tun)
+    hlaunches = hslices + max(in_hash - 1, 1) if hslices > 1 else 1
     kernel_of = dict(KERNEL_OF_STAGE)
     if not fused_first:
         kernel_of.update(hash="k_hash_table1", partition1="k_digit_hist + k_scatter (pass 1)")
-    if hslices > 1:
-        kernel_of.update(hash=f"k_hash_pass x{hslices + 1} (hash in {hslices} slices + the second pass)",
+    if hslices > 1 and in_hash == 3:
+        kernel_of.update(hash=(f"k_hash_pass x{hlaunches} (hash in {hslices} slices + the second and "
+                               "third passes)"),
+                         partition1="k_region_scan_slices + k_region_bounds + k_colscan (passes 2-3 are in the hash)",
+                         partition2="(in the hash launches)")
+    elif hslices > 1:
+        kernel_of.update(hash=f"k_hash_pass x{hlaunches} (hash in {hslices} slices + the second pass)",
                          partition1="k_region_scan_slices + k_region_bounds + k_colscan (pass 2 is in the hash)",
                          partition2="k_scatter claiming regions + k_region_bounds + k_colscan (third pass)")
     in_tail = 1 if tslices > 1 and npass == 3 else 0
@@ -684,7 +694,8 @@ def main() -> int:
         stages[s] = ent
     dom = max(STAGES, key=lambda s: stage_ms[s])
     d = stages[dom]
-    traffic = load_traffic(kernel_of[dom], k)
+    traffic = load_traffic(kernel_of[dom].split()[0], k,
+                           hlaunches if dom == "hash" else 1)
     alu = d.get("bound") == "alu"
     roofline = {"bound": d.get("bound"), "achieved": d.get("achieved"), "peak": d.get("peak"),
                 "unit": "TOP/s" if alu else "GB/s",
@@ -721,7 +732,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"k={k} single plot", "k": k, "nonces": n, "key_seed": 0,
                    "threshold": f"2^{64 - k}", "buckets": 1 << 24, "partition_passes": npass,
-                   "hash_slices": hslices, "tail_slices": tslices, "parallelism": "single GPU"},
+                   "hash_slices": hslices, "front_passes": in_hash, "tail_slices": tslices, "parallelism": "single GPU"},
         "blake3_hashes_per_s": round((n + t2n) / plot_s, 1),
         "plots_per_hour": round(3600.0 / plot_s, 1),
         "table2_records": t2n,

@@ -140,6 +140,11 @@ typedef struct {
                                   the batch that ask for it -- one persistent launch per step over a
                                   device work list of slices of several plots; 0 (default) runs the
                                   plot on its own, on one of the batch's lanes */
+    uint32_t front_passes;     /* vx_plot: partition passes that the launches of a sliced hash file
+                                  when the plot has three: 2 = the first two (the third runs as a
+                                  separate scatter); 3 = all three, launch i also filing slice i - 2
+                                  by the third digit (a third digit of at most 7 bits, and neither
+                                  tail_slices nor batch_shared_hash); 0 = 3 where the plan allows */
 } vx_tuning;
 
 enum { VX_CALL_BUCKET_SORT = 1, VX_CALL_MATCH = 2, VX_CALL_PLOT = 3 };
@@ -163,6 +168,12 @@ uint32_t vx_partition_passes(const vx_plot_params *params, const vx_tuning *tuni
  * first two partition passes are done by then.  No device work.  Returns 0
  * for invalid params or tuning. */
 uint32_t vx_hash_slices(const vx_plot_params *params, const vx_tuning *tuning);
+
+/* Partition passes that vx_plot's hash launches file for these params and
+ * tuning (may be NULL): 0 = none (a separate hash kernel), 1 = the first, 2
+ * or 3 = that many, in nonce slices (vx_hash_slices >= 2).  No device work.
+ * Returns 0 also for invalid params or tuning. */
+uint32_t vx_front_passes(const vx_plot_params *params, const vx_tuning *tuning);
 
 /* Slices over which vx_plot pipelines the work after the first two
  * partition passes (the third pass, the sort and the match, in one

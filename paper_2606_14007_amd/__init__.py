@@ -12,7 +12,7 @@ from ._native import (VX_BUCKET_BITS, VX_CALL_BUCKET_SORT, VX_CALL_MATCH, VX_CAL
                       vx_bucket_sort, vx_default_threshold, vx_hash_table1, vx_last_error,
                       vx_match_table2, vx_plot, vx_plot_batch, vx_plot_with_events,
                       VX_PLOT_EVENTS, vx_read_status,
-                      vx_partition_passes, vx_hash_slices, vx_tail_slices, vx_t2_capacity_hint, vx_workspace_bytes,
+                      vx_partition_passes, vx_hash_slices, vx_tail_slices, vx_front_passes, vx_t2_capacity_hint, vx_workspace_bytes,
                       vx_egress_create, vx_egress_submit, vx_egress_wait, vx_egress_bytes,
                       vx_egress_destroy, vx_chunk_capacity_hint, vx_chunk_workspace_bytes,
                       vx_plot_chunk, vx_stage_bytes, vx_stage_plot, vx_staged_chunk_workspace_bytes,

@@ -52,7 +52,8 @@ class VxTuning(C.Structure):
                 ("h1_tiles", C.c_uint32), ("match_chunk_bits", C.c_uint32), ("pass2_bits", C.c_uint32),
                 ("fused_sort_match", C.c_uint32), ("pipeline_slices", C.c_uint32),
                 ("separate_hash", C.c_uint32), ("region_pct", C.c_uint32), ("hash_slices", C.c_uint32),
-                ("tail_slices", C.c_uint32), ("batch_shared_hash", C.c_uint32)]
+                ("tail_slices", C.c_uint32), ("batch_shared_hash", C.c_uint32),
+                ("front_passes", C.c_uint32)]
 
 
 class VxError(RuntimeError):
@@ -69,6 +70,7 @@ SYMBOLS = [
     ("vx_partition_passes", C.c_uint32, [C.POINTER(VxPlotParams), C.POINTER(VxTuning)]),
     ("vx_hash_slices", C.c_uint32, [C.POINTER(VxPlotParams), C.POINTER(VxTuning)]),
     ("vx_tail_slices", C.c_uint32, [C.POINTER(VxPlotParams), C.POINTER(VxTuning)]),
+    ("vx_front_passes", C.c_uint32, [C.POINTER(VxPlotParams), C.POINTER(VxTuning)]),
     ("vx_hash_table1", C.c_int, [C.POINTER(VxPlotParams), C.c_void_p, C.c_void_p]),
     ("vx_bucket_sort", C.c_int, [C.POINTER(VxPlotParams), C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(VxTuning),
@@ -147,7 +149,8 @@ def make_params(key: bytes, k: int, threshold: int | None = None) -> VxPlotParam
 
 def make_tuning(group_bits=0, pass1_bits=0, group_cap=0, h1_tiles=0, match_chunk_bits=0,
                 pass2_bits=0, fused_sort_match=0, pipeline_slices=0, separate_hash=0,
-                region_pct=0, hash_slices=0, tail_slices=0, batch_shared_hash=0) -> VxTuning:
+                region_pct=0, hash_slices=0, tail_slices=0, batch_shared_hash=0,
+                front_passes=0) -> VxTuning:
     t = VxTuning()
     t.group_bits, t.pass1_bits, t.group_cap = group_bits, pass1_bits, group_cap
     t.h1_tiles, t.match_chunk_bits, t.pass2_bits = h1_tiles, match_chunk_bits, pass2_bits
@@ -157,6 +160,7 @@ def make_tuning(group_bits=0, pass1_bits=0, group_cap=0, h1_tiles=0, match_chunk
     t.hash_slices = hash_slices
     t.tail_slices = tail_slices
     t.batch_shared_hash = batch_shared_hash
+    t.front_passes = front_passes
     return t
 
 
@@ -184,6 +188,10 @@ def vx_partition_passes(params: VxPlotParams, tuning: Optional[VxTuning] = None)
 
 def vx_hash_slices(params: VxPlotParams, tuning: Optional[VxTuning] = None) -> int:
     return int(lib().vx_hash_slices(C.byref(params), C.byref(tuning) if tuning else None))
+
+
+def vx_front_passes(params: VxPlotParams, tuning: Optional[VxTuning] = None) -> int:
+    return int(lib().vx_front_passes(C.byref(params), C.byref(tuning) if tuning else None))
 
 
 def vx_tail_slices(params: VxPlotParams, tuning: Optional[VxTuning] = None) -> int:

@@ -84,6 +84,7 @@ struct Plan {
     uint32_t R[kMaxPasses] = {};  // hs: records per region of each pass (pass 0: per hash slice)
     uint32_t hq = 1;         // plot: nonce slices of the hash (>= 2: see run_sliced_front)
     uint32_t zt = 1;         // plot: slices of the pipelined tail (>= 2: see run_pipe_tail)
+    bool deep = false;       // plot: the sliced hash launches file all three passes (run_sliced_front)
     int staged = -1;         // >= 0: one chunk (of 2^staged) of a staged plot; see vx_stage_plot
 };
 
@@ -154,6 +155,8 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     const bool hs_ok = (!records || staged >= 0) && !t->separate_hash;
     if (t->hash_slices > kMaxHashSlices) return fail(VX_ERR_UNSUPPORTED, "hash_slices must be at most 16");
     if (t->tail_slices > kMaxTailSlices) return fail(VX_ERR_UNSUPPORTED, "tail_slices must be at most 16");
+    if (t->front_passes == 1 || t->front_passes > 3)
+        return fail(VX_ERR_UNSUPPORTED, "front_passes must be 0, 2 or 3");
     // Hash slices: whole plots whose first two digits fit the sliced
     // kernel's 8 bits; the pipelined tail keeps its own split.
     uint32_t hq = t->hash_slices ? t->hash_slices : default_hash_slices(P.k);
@@ -304,6 +307,22 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
             (1u << P.D[0]) >= zt)
             P.zt = zt;
     }
+    // All three passes in the hash launches: slice i's second pass files
+    // into regions of its own (one per first two digits, R[1] records each),
+    // which launch i + 2 files by the third digit into the plot's shared
+    // third-pass regions.  The third digit takes the filing kernel's 128
+    // counters; tail_slices and batch_shared_hash keep the two-pass front.
+    if (P.hq > 1 && P.npass == 3 && t->front_passes != 2 && P.zt == 1 && !P.fused && !t->batch_shared_hash &&
+        P.D[2] <= (uint32_t)vxk::kPipeMaxBits) {
+        const uint32_t b01 = P.D[0] + P.D[1];
+        const double mean = (double)((((P.n + P.hq - 1) / P.hq) + (1ull << b01) - 1) >> b01);
+        uint32_t r1 = (uint32_t)(mean + 8.0 * std::sqrt(mean)) + 64u;
+        if (t->region_pct) r1 = std::max<uint32_t>(1, (uint32_t)((uint64_t)r1 * t->region_pct / 100));
+        if (((uint64_t)r1 << b01) < (1ull << 31)) {
+            P.deep = true;
+            P.R[1] = r1;
+        }
+    }
     if (staged >= 0 && !P.hs)
         return fail(VX_ERR_UNSUPPORTED,
                     "staged plots need two or more partition passes, a first digit of at most 8 bits and at "
@@ -343,7 +362,7 @@ constexpr uint32_t kHdrOvf = 8;          // per slice: oversized groups found
 constexpr uint32_t kHdrSortTicket = 8 + kMaxSlices;       // per slice: group ticket of the sort
 constexpr uint32_t kHdrEmitTicket = 8 + 2 * kMaxSlices;   // per slice: chunk ticket of the match
 constexpr uint32_t kHdrHashPassTicket = 8 + 3 * kMaxSlices;  // per launch of a sliced hash
-constexpr uint32_t kHdrPipeTicket = kHdrHashPassTicket + kMaxHashSlices + 1;  // per launch of a pipelined tail
+constexpr uint32_t kHdrPipeTicket = kHdrHashPassTicket + kMaxHashSlices + 2;  // per launch of a pipelined tail
 constexpr uint32_t kHdrBatchTicket = kHdrPipeTicket + kMaxTailSlices + 2;  // fused launches of a batch
 constexpr uint32_t kBatchTicketWords = kHeaderWords - kHdrBatchTicket;
 static_assert(kBatchTicketWords >= 21, "a batch round needs up to 21 launches per plot");
@@ -354,6 +373,15 @@ constexpr int kCallStagedChunk = 5;  // internal: the workspace of vx_plot_stage
 constexpr uint32_t kMaxChunkBits = 8;
 
 uint32_t match_chunks(const Plan &P) { return (uint32_t)((P.n + (1ull << P.cb) - 1) >> P.cb); }
+
+// A plan whose hash launches file all three passes (P.deep) keeps slice i's
+// first-pass regions (pass 0) and second-pass regions (pass 1) in slot
+// i % 2 of a two-slot ring each, in the scratch arrays: launch i writes the
+// first-pass regions of slice i and the second-pass regions of slice i - 1,
+// and reads those of slices i - 1 and i - 2, written by the launch before.
+uint64_t ring_slot(const Plan &P, uint32_t pass) {
+    return pass == 0 ? (uint64_t)P.R[0] << P.D[0] : (uint64_t)P.R[1] << (P.D[0] + P.D[1]);
+}
 
 uint32_t pass_tiles(const Plan &P, uint32_t i) {
     return i == 0 ? P.W : (1u << P.pre[i]) * P.Q[i];
@@ -381,16 +409,23 @@ Layout layout(const Plan &P, int which) {
     const bool hs = which == VX_CALL_PLOT && !chunk && P.hs;
     const uint32_t cbits = staged ? (uint32_t)P.staged : 0;
     uint64_t cap_even = staged ? 0 : P.n, cap_odd = staged ? 0 : P.n;
-    for (uint32_t i = staged ? 1 : 0; hs && i < P.npass; ++i) {
+    for (uint32_t i = staged ? 1 : 0; hs && !P.deep && i < P.npass; ++i) {
         const uint64_t c = ((uint64_t)P.R[i] << (P.pre[i] + P.D[i] - cbits)) * (i == 0 ? P.hq : 1);
         uint64_t &m = (i % 2 == 0) ? cap_even : cap_odd;
         m = std::max(m, c);
+    }
+    if (hs && P.deep) {
+        // The third pass's regions; the first two passes' regions of two
+        // slices at a time (ring_slot).
+        cap_even = std::max<uint64_t>(P.n, (uint64_t)P.R[2] << P.G);
+        cap_odd = 2 * (ring_slot(P, 0) + ring_slot(P, 1));
     }
     if (which == VX_CALL_PLOT) L.keys_no = take(cap_even * 8);
     if (hs) L.reg_nonces = take(cap_even * 4);
     for (uint32_t i = 0; hs && i < P.npass; ++i) {
         const size_t nr = (size_t)1 << (P.pre[i] + P.D[i]);
-        L.fill[i] = take(i == 0 && P.hq > 1 ? (size_t)slice_fill_stride(P.D[0]) * P.hq * 4 : nr * 4);
+        L.fill[i] = take(i == 0 && P.hq > 1 ? (size_t)slice_fill_stride(P.D[0]) * P.hq * 4
+                         : (i == 1 && P.deep ? nr * P.hq * 4 : nr * 4));
         L.seg_lo[i] = take(nr * 4);
         L.seg_hi[i] = take(nr * 4);
     }
@@ -575,7 +610,7 @@ vx_status run_pass(const Plan &P, const Layout &L, void *ws, const PassBufs &B, 
 // over caller keys).
 // The passes a plot's hash launches file: none (a separate hash), the first
 // (the hash kernel's own), or the first two (sliced or fused launches).
-uint32_t hash_passes(const Plan &P) { return P.hs ? (P.hq > 1 ? 2 : 1) : 0; }
+uint32_t hash_passes(const Plan &P) { return P.hs ? (P.hq > 1 ? (P.deep ? 3 : 2) : 1) : 0; }
 
 vx_status run_partition(const Plan &P, const Layout &L, void *ws, const uint64_t *keys_no,
                         bool hist_done, uint64_t *t1_keys, uint32_t *t1_nonces, uint32_t npass_run,
@@ -620,21 +655,32 @@ vx_status run_partition(const Plan &P, const Layout &L, void *ws, const uint64_t
 // and its second pass (over those regions, into the plot's second-pass
 // regions).
 bool front_fusable(const Plan &P) {
-    return P.hs && P.npass >= 2 && P.D[0] <= (uint32_t)vxk::kHashPassMaxBits &&
+    return P.hs && !P.deep && P.npass >= 2 && P.D[0] <= (uint32_t)vxk::kHashPassMaxBits &&
            P.D[1] <= (uint32_t)vxk::kHashPassMaxBits;
 }
 
 uint32_t front_fill_stride(const Plan &P) { return P.hq > 1 ? slice_fill_stride(P.D[0]) : 1u << P.D[0]; }
 
+// Where slice i's first-pass regions live: slot i of the even-pass region
+// arrays, or (P.deep) ring slot i % 2 in the scratch arrays.
+uint64_t *first_keys(const Plan &P, const Layout &L, void *ws, uint32_t i) {
+    return P.deep ? at<uint64_t>(ws, L.scr_keys) + (i % 2) * ring_slot(P, 0)
+                  : at<uint64_t>(ws, L.keys_no) + i * ring_slot(P, 0);
+}
+
+uint32_t *first_nonces(const Plan &P, const Layout &L, void *ws, uint32_t i) {
+    return P.deep ? at<uint32_t>(ws, L.scr_nonces) + (i % 2) * ring_slot(P, 0)
+                  : at<uint32_t>(ws, L.reg_nonces) + i * ring_slot(P, 0);
+}
+
 vxk::HashSliceDesc hash_slice(const Plan &P, const Layout &L, void *ws, uint32_t i) {
     vxk::HashSliceDesc H;
     memset(&H, 0, sizeof(H));
-    const uint64_t slice_recs = ((uint64_t)P.R[0]) << P.D[0];
     memcpy(H.key, P.key_words, sizeof(H.key));
     H.nonce0 = P.n * i / P.hq;
     H.n = P.n * (i + 1) / P.hq - H.nonce0;
-    H.keys = at<uint64_t>(ws, L.keys_no) + i * slice_recs;
-    H.nonces = at<uint32_t>(ws, L.reg_nonces) + i * slice_recs;
+    H.keys = first_keys(P, L, ws, i);
+    H.nonces = first_nonces(P, L, ws, i);
     H.fill = at<uint32_t>(ws, L.fill[0]) + (size_t)i * front_fill_stride(P);
     H.status = at<uint32_t>(ws, L.header) + kHdrStatus;
     H.bits = P.D[0];
@@ -646,14 +692,22 @@ vxk::HashSliceDesc hash_slice(const Plan &P, const Layout &L, void *ws, uint32_t
 vxk::PassSliceDesc pass_slice(const Plan &P, const Layout &L, void *ws, uint32_t i) {
     vxk::PassSliceDesc Q;
     memset(&Q, 0, sizeof(Q));
-    const uint64_t slice_recs = ((uint64_t)P.R[0]) << P.D[0];
     const uint32_t per = (P.R[0] + vxk::kHashScatterSub - 1) / vxk::kHashScatterSub;
-    Q.keys = at<uint64_t>(ws, L.keys_no) + i * slice_recs;
-    Q.nonces = at<uint32_t>(ws, L.reg_nonces) + i * slice_recs;
+    Q.keys = first_keys(P, L, ws, i);
+    Q.nonces = first_nonces(P, L, ws, i);
     Q.fill = at<uint32_t>(ws, L.fill[0]) + (size_t)i * front_fill_stride(P);
-    Q.out_keys = at<uint64_t>(ws, L.scr_keys);
-    Q.out_nonces = at<uint32_t>(ws, L.scr_nonces);
-    Q.out_fill = at<uint32_t>(ws, L.fill[1]);
+    if (P.deep) {
+        // The slice's own second-pass regions (ring slot i % 2, counters of
+        // its own).
+        const uint64_t o = 2 * ring_slot(P, 0) + (i % 2) * ring_slot(P, 1);
+        Q.out_keys = at<uint64_t>(ws, L.scr_keys) + o;
+        Q.out_nonces = at<uint32_t>(ws, L.scr_nonces) + o;
+        Q.out_fill = at<uint32_t>(ws, L.fill[1]) + ((size_t)i << (P.D[0] + P.D[1]));
+    } else {
+        Q.out_keys = at<uint64_t>(ws, L.scr_keys);
+        Q.out_nonces = at<uint32_t>(ws, L.scr_nonces);
+        Q.out_fill = at<uint32_t>(ws, L.fill[1]);
+    }
     Q.status = at<uint32_t>(ws, L.header) + kHdrStatus;
     Q.R_in = P.R[0];
     Q.per = per;
@@ -661,6 +715,31 @@ vxk::PassSliceDesc pass_slice(const Plan &P, const Layout &L, void *ws, uint32_t
     Q.bits = P.D[1];
     Q.R_out = P.R[1];
     Q.items = (1u << P.D[0]) * per;
+    return Q;
+}
+
+// The third pass of slice i (P.deep): its second-pass regions (ring slot
+// i % 2), filed by the third digit into the plot's third-pass regions,
+// shared by all slices, from which the group sort gathers.
+vxk::PassSliceDesc third_slice(const Plan &P, const Layout &L, void *ws, uint32_t i) {
+    vxk::PassSliceDesc Q;
+    memset(&Q, 0, sizeof(Q));
+    const uint32_t b01 = P.D[0] + P.D[1];
+    const uint32_t per = (P.R[1] + vxk::kHashScatterSub - 1) / vxk::kHashScatterSub;
+    const uint64_t o = 2 * ring_slot(P, 0) + (i % 2) * ring_slot(P, 1);
+    Q.keys = at<uint64_t>(ws, L.scr_keys) + o;
+    Q.nonces = at<uint32_t>(ws, L.scr_nonces) + o;
+    Q.fill = at<uint32_t>(ws, L.fill[1]) + ((size_t)i << b01);
+    Q.out_keys = at<uint64_t>(ws, L.keys_no);
+    Q.out_nonces = at<uint32_t>(ws, L.reg_nonces);
+    Q.out_fill = at<uint32_t>(ws, L.fill[2]);
+    Q.status = at<uint32_t>(ws, L.header) + kHdrStatus;
+    Q.R_in = P.R[1];
+    Q.per = per;
+    Q.shift = 64 - b01 - P.D[2];
+    Q.bits = P.D[2];
+    Q.R_out = P.R[2];
+    Q.items = (1u << b01) * per;
     return Q;
 }
 
@@ -681,24 +760,43 @@ vx_status finish_front(const Plan &P, const Layout &L, void *ws, hipStream_t s) 
     return claimed_regions(P, L, ws, 1, 0, nd0, s);
 }
 
+// P.deep: after every slice's third pass, the second pass's group starts
+// (summed over the slices' own regions), then the third pass's region
+// bounds and group starts on top of them.
+vx_status finish_deep_front(const Plan &P, const Layout &L, void *ws, hipStream_t s) {
+    const uint32_t nd01 = 1u << (P.D[0] + P.D[1]);
+    VX_HIP(vxk::launch_region_scan_slices(at<uint32_t>(ws, L.fill[1]), P.hq, nd01, nd01, P.R[1],
+                                          at<uint32_t>(ws, L.gstart[1]), s),
+           "region scan");
+    return claimed_regions(P, L, ws, 2, 0, nd01, s);
+}
+
+// Launch i hashes slice i and files the regions of slice i - 1 by the
+// second digit (and, P.deep, those of slice i - 2 by the third), each kind
+// reading what the launch before wrote.
 vx_status run_sliced_front(const Plan &P, const Layout &L, void *ws, hipStream_t s, hipEvent_t *ev) {
     uint32_t *hdr = at<uint32_t>(ws, L.header);
-    for (uint32_t i = 0; i <= P.hq; ++i) {
+    const uint32_t lag = P.deep ? 2 : 1;
+    for (uint32_t i = 0; i < P.hq + lag; ++i) {
         vxk::HashPassList W;
         memset(&W, 0, sizeof(W));
         if (i < P.hq) {
             W.h[W.nh++] = hash_slice(P, L, ws, i);
             W.h_items += W.h[0].items;
         }
-        if (i >= 1) {
-            W.p[W.np++] = pass_slice(P, L, ws, i - 1);
-            W.p_items += W.p[0].items;
+        if (i >= 1 && i - 1 < P.hq) {
+            W.p[W.np] = pass_slice(P, L, ws, i - 1);
+            W.p_items += W.p[W.np++].items;
+        }
+        if (P.deep && i >= 2) {
+            W.p[W.np] = third_slice(P, L, ws, i - 2);
+            W.p_items += W.p[W.np++].items;
         }
         set_frac(W);
         VX_HIP(vxk::launch_hash_pass(W, hdr + kHdrHashPassTicket + i, s), "sliced hash");
     }
     VX_HIP(mark(ev, 1, s), "event");
-    vx_status st = finish_front(P, L, ws, s);
+    vx_status st = P.deep ? finish_deep_front(P, L, ws, s) : finish_front(P, L, ws, s);
     if (st != VX_OK) return st;
     VX_HIP(mark(ev, 2, s), "event");
     return VX_OK;
@@ -1060,6 +1158,12 @@ uint32_t vx_hash_slices(const vx_plot_params *params, const vx_tuning *tuning) {
     return P.hq;
 }
 
+uint32_t vx_front_passes(const vx_plot_params *params, const vx_tuning *tuning) {
+    Plan P;
+    if (make_plan(params, tuning, &P) != VX_OK) return 0;
+    return hash_passes(P);
+}
+
 uint32_t vx_tail_slices(const vx_plot_params *params, const vx_tuning *tuning) {
     Plan P;
     if (make_plan(params, tuning, &P) != VX_OK) return 0;
@@ -1408,7 +1512,9 @@ vx_status plot_reset(const Plan &P, const Layout &L, void *ws, bool keep_status,
         VX_HIP(vxk::launch_reset(hdr, kHeaderWords, s), "reset");
     for (uint32_t i = 0; P.hs && i < P.npass; ++i)
         VX_HIP(vxk::launch_fill_u32(at<uint32_t>(ws, L.fill[i]),
-                                    i == 0 ? (uint64_t)front_fill_stride(P) * P.hq : 1ull << (P.pre[i] + P.D[i]), 0u,
+                                    i == 0 ? (uint64_t)front_fill_stride(P) * P.hq
+                                           : (uint64_t)(i == 1 && P.deep ? P.hq : 1) << (P.pre[i] + P.D[i]),
+                                    0u,
                                     s),
                "reset");
     return VX_OK;

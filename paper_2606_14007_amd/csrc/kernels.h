@@ -136,7 +136,7 @@ struct PipeList {
 hipError_t launch_pipe(const PipeList &L, PipeList *d_list, uint32_t *ticket, hipStream_t s);
 // One launch over the list; *ticket zero at launch.
 hipError_t launch_hash_pass(const HashPassList &L, uint32_t *ticket, hipStream_t s);
-// gstart[d] (d <= nd) of the first digit over a sliced hash's regions.
+// gstart[d] (d <= nd) over the per-slice regions of a sliced hash.
 hipError_t launch_region_scan_slices(const uint32_t *fill, uint32_t slices, uint32_t stride, uint32_t nd,
                                      uint32_t R, uint32_t *gstart, hipStream_t s);
 // Chunked plots: hash all n nonces, keep keys whose top pbits bits are

@@ -512,24 +512,32 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXD <= 1
     }
 }
 
-// Starts of the first digit's groups after a plot hashed in `slices`
-// slices: gstart[d] = records of digits below d over all slices, each
-// slice's region d holding min(fill[s * stride + d], R); gstart[nd] = all.
+// Group starts over regions that every slice of a sliced hash holds on its
+// own (the first digit's, or the first two digits' when the hash launches
+// also file the third pass): gstart[d] = records of digits below d over all
+// slices, each slice's region d holding min(fill[s * stride + d], R);
+// gstart[nd] = all.  Any nd: blocks of kMaxDigits digits carry their sum.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_region_scan_slices(const uint32_t *__restrict__ fill, uint32_t slices,
                                                               uint32_t stride, uint32_t nd, uint32_t R,
                                                               uint32_t *__restrict__ gstart) {
     __shared__ uint32_t s[kMaxDigits];
     __shared__ uint32_t s_wave[BLOCK / 64 + 1];
-    for (uint32_t d = threadIdx.x; d < nd; d += BLOCK) {
-        uint32_t c = 0;
-        for (uint32_t q = 0; q < slices; ++q) c += min(fill[q * stride + d], R);
-        s[d] = c;
+    uint32_t carry = 0;  // records of the digits before this block of kMaxDigits
+    for (uint32_t d0 = 0; d0 < nd; d0 += kMaxDigits) {
+        const uint32_t m = min(nd - d0, (uint32_t)kMaxDigits);
+        for (uint32_t d = threadIdx.x; d < m; d += BLOCK) {
+            uint32_t c = 0;
+            for (uint32_t q = 0; q < slices; ++q) c += min(fill[q * stride + d0 + d], R);
+            s[d] = c;
+        }
+        __syncthreads();
+        const uint32_t total = vxd::lds_exclusive_scan<BLOCK>(s, (int)m, s_wave);
+        for (uint32_t d = threadIdx.x; d < m; d += BLOCK) gstart[d0 + d] = carry + s[d];
+        carry += total;
+        __syncthreads();  // s is refilled for the next block of digits
     }
-    __syncthreads();
-    const uint32_t total = vxd::lds_exclusive_scan<BLOCK>(s, (int)nd, s_wave);
-    for (uint32_t d = threadIdx.x; d < nd; d += BLOCK) gstart[d] = s[d];
-    if (threadIdx.x == 0) gstart[nd] = total;
+    if (threadIdx.x == 0) gstart[nd] = carry;
 }
 
 // ---------------------------------------------------------------------------

@@ -94,6 +94,22 @@ def test_plot_sliced_hash(vx, k, hq):
     _assert_plot_equal(vx, b, oracle.plot(KEY0, k, threads=8))
 
 
+@pytest.mark.parametrize("k,hq,gb", [(20, 2, 18), (21, 3, 17), (22, 16, 20), (24, 16, 0), (24, 7, 18),
+                                     (26, 16, 17), (26, 4, 0)])
+def test_plot_three_pass_front(vx, k, hq, gb):
+    """Three partition passes in the sliced hash launches: launch i hashes
+    slice i, files slice i - 1 by the second digit into regions of its own
+    and slice i - 2 by the third into the shared regions that the sort
+    gathers from (24 and 26 without group bits: 13 and 15 group bits, where
+    the plan falls back to two passes)."""
+    t = vx.make_tuning(hash_slices=hq, group_bits=gb)
+    p = vx.make_params(KEY0, k)
+    assert vx.vx_hash_slices(p, t) == hq
+    assert vx.vx_front_passes(p, t) == vx.vx_partition_passes(p, t)
+    b = vx.plot(KEY0, k, tuning=t)
+    _assert_plot_equal(vx, b, oracle.plot(KEY0, k, threads=8))
+
+
 @pytest.mark.parametrize("k,hq,zt,gb", [(20, 1, 4, 12), (22, 4, 8, 0), (24, 8, 16, 0), (22, 2, 8, 18),
                                         (23, 16, 8, 20)])
 def test_plot_pipelined_tail(vx, k, hq, zt, gb):
@@ -141,9 +157,15 @@ TUNINGS = [
     dict(hash_slices=3, group_bits=12),       # uneven slices, 6-6
     dict(hash_slices=8, group_bits=15),       # 1-7-7: a claiming third pass after the slices
     dict(hash_slices=16, group_bits=14),      # sixteen slices, 7-7
-    dict(hash_slices=4, group_bits=13, pass1_bits=3),    # 3-7-3
+    dict(hash_slices=4, group_bits=13, pass1_bits=3),    # 3-7-3, three passes in the hash launches
+    dict(hash_slices=4, group_bits=13, pass1_bits=3, front_passes=2),  # 3-7-3, third pass after
+    dict(hash_slices=5, group_bits=18),       # 4-7-7 over five uneven slices, seven launches
+    dict(hash_slices=16, group_bits=17, group_cap=64),  # 3-7-7: sixteen slices, oversized groups
+    dict(hash_slices=3, group_bits=16, pass1_bits=5, pass2_bits=5, match_chunk_bits=7),  # 5-5-6
     dict(hash_slices=5, group_bits=16, fused_sort_match=1),  # sliced hash, fused tail
-    dict(hash_slices=2, group_bits=20),       # 6-7-7 (the k=31 split), tiny groups
+    dict(hash_slices=2, group_bits=20),       # 6-7-7 (the k=31 split), tiny groups, all three passes
+                                              # in the hash launches
+    dict(hash_slices=2, group_bits=20, front_passes=2),  # the same with a separate third pass
     dict(hash_slices=4, group_cap=64),        # sliced hash, oversized groups
     dict(hash_slices=6, group_bits=16),       # 8-8: the sliced kernel with 256 counters
     dict(hash_slices=3, group_bits=17, pass1_bits=8, pass2_bits=8),  # 8-8-1
@@ -314,6 +336,8 @@ def test_region_overflow_is_reported(vx):
 
 @pytest.mark.parametrize("tun", [dict(group_bits=12), dict(group_bits=14, pass1_bits=4, pass2_bits=5),
                                  dict(group_bits=12, hash_slices=4), dict(group_bits=18, hash_slices=3),
+                                 dict(group_bits=18, hash_slices=3, front_passes=2),
+                                 dict(group_bits=17, hash_slices=2),
                                  dict(group_bits=12, tail_slices=4), dict(group_bits=18, hash_slices=2, tail_slices=3)])
 @pytest.mark.parametrize("pct", [10, 25])
 def test_region_overflow_with_matching_stays_bounded(vx, tun, pct):
