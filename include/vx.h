@@ -145,6 +145,10 @@ typedef struct {
                                   separate scatter); 3 = all three, launch i also filing slice i - 2
                                   by the third digit (a third digit of at most 7 bits, and neither
                                   tail_slices nor batch_shared_hash); 0 = 3 where the plan allows */
+    uint32_t front_subtile;    /* vx_plot: records per work item of a sliced hash's launches, 2048
+                                  (256-thread work-groups) or 4096 (512 threads: each digit's run
+                                  twice as long); 0 = 4096 where the launches file three
+                                  passes, else 2048 */
 } vx_tuning;
 
 enum { VX_CALL_BUCKET_SORT = 1, VX_CALL_MATCH = 2, VX_CALL_PLOT = 3 };

@@ -53,7 +53,7 @@ class VxTuning(C.Structure):
                 ("fused_sort_match", C.c_uint32), ("pipeline_slices", C.c_uint32),
                 ("separate_hash", C.c_uint32), ("region_pct", C.c_uint32), ("hash_slices", C.c_uint32),
                 ("tail_slices", C.c_uint32), ("batch_shared_hash", C.c_uint32),
-                ("front_passes", C.c_uint32)]
+                ("front_passes", C.c_uint32), ("front_subtile", C.c_uint32)]
 
 
 class VxError(RuntimeError):
@@ -150,7 +150,7 @@ def make_params(key: bytes, k: int, threshold: int | None = None) -> VxPlotParam
 def make_tuning(group_bits=0, pass1_bits=0, group_cap=0, h1_tiles=0, match_chunk_bits=0,
                 pass2_bits=0, fused_sort_match=0, pipeline_slices=0, separate_hash=0,
                 region_pct=0, hash_slices=0, tail_slices=0, batch_shared_hash=0,
-                front_passes=0) -> VxTuning:
+                front_passes=0, front_subtile=0) -> VxTuning:
     t = VxTuning()
     t.group_bits, t.pass1_bits, t.group_cap = group_bits, pass1_bits, group_cap
     t.h1_tiles, t.match_chunk_bits, t.pass2_bits = h1_tiles, match_chunk_bits, pass2_bits
@@ -161,6 +161,7 @@ def make_tuning(group_bits=0, pass1_bits=0, group_cap=0, h1_tiles=0, match_chunk
     t.tail_slices = tail_slices
     t.batch_shared_hash = batch_shared_hash
     t.front_passes = front_passes
+    t.front_subtile = front_subtile
     return t
 
 

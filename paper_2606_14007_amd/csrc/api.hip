@@ -85,6 +85,7 @@ struct Plan {
     uint32_t hq = 1;         // plot: nonce slices of the hash (>= 2: see run_sliced_front)
     uint32_t zt = 1;         // plot: slices of the pipelined tail (>= 2: see run_pipe_tail)
     bool deep = false;       // plot: the sliced hash launches file all three passes (run_sliced_front)
+    uint32_t hsub = vxk::kHashScatterSub;  // plot: records per item of the sliced hash's launches
     int staged = -1;         // >= 0: one chunk (of 2^staged) of a staged plot; see vx_stage_plot
 };
 
@@ -157,6 +158,9 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     if (t->tail_slices > kMaxTailSlices) return fail(VX_ERR_UNSUPPORTED, "tail_slices must be at most 16");
     if (t->front_passes == 1 || t->front_passes > 3)
         return fail(VX_ERR_UNSUPPORTED, "front_passes must be 0, 2 or 3");
+    if (t->front_subtile && t->front_subtile != vxk::kHashScatterSub && t->front_subtile != vxk::kHashPassWideSub)
+        return fail(VX_ERR_UNSUPPORTED, "front_subtile must be 0, 2048 or 4096");
+
     // Hash slices: whole plots whose first two digits fit the sliced
     // kernel's 8 bits; the pipelined tail keeps its own split.
     uint32_t hq = t->hash_slices ? t->hash_slices : default_hash_slices(P.k);
@@ -323,6 +327,11 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
             P.R[1] = r1;
         }
     }
+    // Items of 4096 records (512-thread work-groups) when the launches file
+    // three passes: each digit's runs are twice as long, which the
+    // memory-bound launches need (k=31: 100.9 against 104.3 ms per plot);
+    // with two passes both sizes measured alike.
+    P.hsub = t->front_subtile ? t->front_subtile : (P.deep ? vxk::kHashPassWideSub : vxk::kHashScatterSub);
     if (staged >= 0 && !P.hs)
         return fail(VX_ERR_UNSUPPORTED,
                     "staged plots need two or more partition passes, a first digit of at most 8 bits and at "
@@ -673,7 +682,8 @@ uint32_t *first_nonces(const Plan &P, const Layout &L, void *ws, uint32_t i) {
                   : at<uint32_t>(ws, L.reg_nonces) + i * ring_slot(P, 0);
 }
 
-vxk::HashSliceDesc hash_slice(const Plan &P, const Layout &L, void *ws, uint32_t i) {
+vxk::HashSliceDesc hash_slice(const Plan &P, const Layout &L, void *ws, uint32_t i,
+                              uint32_t sub = vxk::kHashScatterSub) {
     vxk::HashSliceDesc H;
     memset(&H, 0, sizeof(H));
     memcpy(H.key, P.key_words, sizeof(H.key));
@@ -685,14 +695,15 @@ vxk::HashSliceDesc hash_slice(const Plan &P, const Layout &L, void *ws, uint32_t
     H.status = at<uint32_t>(ws, L.header) + kHdrStatus;
     H.bits = P.D[0];
     H.R = P.R[0];
-    H.items = (uint32_t)((H.n + vxk::kHashScatterSub - 1) / vxk::kHashScatterSub);
+    H.items = (uint32_t)((H.n + sub - 1) / sub);
     return H;
 }
 
-vxk::PassSliceDesc pass_slice(const Plan &P, const Layout &L, void *ws, uint32_t i) {
+vxk::PassSliceDesc pass_slice(const Plan &P, const Layout &L, void *ws, uint32_t i,
+                              uint32_t sub = vxk::kHashScatterSub) {
     vxk::PassSliceDesc Q;
     memset(&Q, 0, sizeof(Q));
-    const uint32_t per = (P.R[0] + vxk::kHashScatterSub - 1) / vxk::kHashScatterSub;
+    const uint32_t per = (P.R[0] + sub - 1) / sub;
     Q.keys = first_keys(P, L, ws, i);
     Q.nonces = first_nonces(P, L, ws, i);
     Q.fill = at<uint32_t>(ws, L.fill[0]) + (size_t)i * front_fill_stride(P);
@@ -721,11 +732,11 @@ vxk::PassSliceDesc pass_slice(const Plan &P, const Layout &L, void *ws, uint32_t
 // The third pass of slice i (P.deep): its second-pass regions (ring slot
 // i % 2), filed by the third digit into the plot's third-pass regions,
 // shared by all slices, from which the group sort gathers.
-vxk::PassSliceDesc third_slice(const Plan &P, const Layout &L, void *ws, uint32_t i) {
+vxk::PassSliceDesc third_slice(const Plan &P, const Layout &L, void *ws, uint32_t i, uint32_t sub) {
     vxk::PassSliceDesc Q;
     memset(&Q, 0, sizeof(Q));
     const uint32_t b01 = P.D[0] + P.D[1];
-    const uint32_t per = (P.R[1] + vxk::kHashScatterSub - 1) / vxk::kHashScatterSub;
+    const uint32_t per = (P.R[1] + sub - 1) / sub;
     const uint64_t o = 2 * ring_slot(P, 0) + (i % 2) * ring_slot(P, 1);
     Q.keys = at<uint64_t>(ws, L.scr_keys) + o;
     Q.nonces = at<uint32_t>(ws, L.scr_nonces) + o;
@@ -780,16 +791,17 @@ vx_status run_sliced_front(const Plan &P, const Layout &L, void *ws, hipStream_t
     for (uint32_t i = 0; i < P.hq + lag; ++i) {
         vxk::HashPassList W;
         memset(&W, 0, sizeof(W));
+        W.sub = P.hsub;
         if (i < P.hq) {
-            W.h[W.nh++] = hash_slice(P, L, ws, i);
+            W.h[W.nh++] = hash_slice(P, L, ws, i, P.hsub);
             W.h_items += W.h[0].items;
         }
         if (i >= 1 && i - 1 < P.hq) {
-            W.p[W.np] = pass_slice(P, L, ws, i - 1);
+            W.p[W.np] = pass_slice(P, L, ws, i - 1, P.hsub);
             W.p_items += W.p[W.np++].items;
         }
         if (P.deep && i >= 2) {
-            W.p[W.np] = third_slice(P, L, ws, i - 2);
+            W.p[W.np] = third_slice(P, L, ws, i - 2, P.hsub);
             W.p_items += W.p[W.np++].items;
         }
         set_frac(W);

@@ -66,7 +66,11 @@ struct HashPassList {
     uint32_t nh, np;
     uint32_t h_items, p_items;  // totals over the lists
     uint64_t h_frac;            // ceil(h_items * 2^32 / (h_items + p_items))
+    uint32_t sub;               // records per item: kHashScatterSub (0: the same; 256-thread
+                                // work-groups) or kHashPassWideSub (512 threads)
+    uint32_t pad;
 };
+constexpr uint32_t kHashPassWideSub = 512u * kHashScatterItems;
 constexpr int kHashPassMaxBits = 8;  // widest digit of a sliced hash's two passes
 constexpr int kPipeMaxBits = 7;      // widest digit of k_pipe's filing items
 

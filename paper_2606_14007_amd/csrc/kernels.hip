@@ -2174,15 +2174,28 @@ hipError_t launch_hash_pass(const HashPassList &L, uint32_t *ticket, hipStream_t
         if (L.p[i].bits < 1 || L.p[i].bits > (uint32_t)kHashPassMaxBits || L.p[i].per < 1) return hipErrorInvalidValue;
         bits = max(bits, L.p[i].bits);
     }
+    const uint32_t sub = L.sub ? L.sub : kHashScatterSub;
+    if (sub != kHashScatterSub && sub != kHashPassWideSub) return hipErrorInvalidValue;
     const uint64_t nt = (uint64_t)L.h_items + L.p_items;
     if (nt == 0) return hipSuccess;
-    // Digits up to 7 bits take the kernel whose LDS fits six work-groups on
-    // a CU; 8-bit digits the one with room for 256 counters (five).
+    // Digits up to 7 bits take the kernel whose LDS fits six 256-thread (or
+    // three 512-thread) work-groups on a CU; 8-bit digits the one with room
+    // for 256 counters.  512-thread work-groups file sub-tiles of 4096
+    // records, whose runs per digit are twice as long.
+    constexpr int WB = 2 * kHashBlock;
     static const uint32_t grid7 = resident_grid(k_hash_pass<kHashBlock, kHashScatterItems, 128>, kHashBlock);
     static const uint32_t grid8 = resident_grid(k_hash_pass<kHashBlock, kHashScatterItems, 256>, kHashBlock);
-    const uint32_t grid = bits <= 7 ? grid7 : grid8;
+    static const uint32_t gridw7 = resident_grid(k_hash_pass<WB, kHashScatterItems, 128>, WB);
+    static const uint32_t gridw8 = resident_grid(k_hash_pass<WB, kHashScatterItems, 256>, WB);
+    static_assert(WB * kHashScatterItems == (int)kHashPassWideSub, "wide sub-tile");
+    const bool wide = sub == kHashPassWideSub;
+    const uint32_t grid = wide ? (bits <= 7 ? gridw7 : gridw8) : (bits <= 7 ? grid7 : grid8);
     const uint32_t used = nt < grid ? (uint32_t)nt : grid;
-    if (bits <= 7)
+    if (wide && bits <= 7)
+        hipLaunchKernelGGL((k_hash_pass<WB, kHashScatterItems, 128>), dim3(used), dim3(WB), 0, s, L, ticket);
+    else if (wide)
+        hipLaunchKernelGGL((k_hash_pass<WB, kHashScatterItems, 256>), dim3(used), dim3(WB), 0, s, L, ticket);
+    else if (bits <= 7)
         hipLaunchKernelGGL((k_hash_pass<kHashBlock, kHashScatterItems, 128>), dim3(used), dim3(kHashBlock), 0, s, L,
                            ticket);
     else

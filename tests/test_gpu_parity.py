@@ -110,6 +110,16 @@ def test_plot_three_pass_front(vx, k, hq, gb):
     _assert_plot_equal(vx, b, oracle.plot(KEY0, k, threads=8))
 
 
+@pytest.mark.parametrize("k,hq,gb,fp", [(22, 5, 18, 3), (24, 16, 20, 3), (26, 16, 17, 3), (25, 8, 17, 2)])
+def test_plot_wide_front_items(vx, k, hq, gb, fp):
+    """The sliced hash launches with 512-thread work-groups on 4096-record
+    sub-tiles, filing two or three passes."""
+    t = vx.make_tuning(hash_slices=hq, group_bits=gb, front_passes=fp, front_subtile=4096)
+    assert vx.vx_front_passes(vx.make_params(KEY0, k), t) == fp
+    b = vx.plot(KEY0, k, tuning=t)
+    _assert_plot_equal(vx, b, oracle.plot(KEY0, k, threads=8))
+
+
 @pytest.mark.parametrize("k,hq,zt,gb", [(20, 1, 4, 12), (22, 4, 8, 0), (24, 8, 16, 0), (22, 2, 8, 18),
                                         (23, 16, 8, 20)])
 def test_plot_pipelined_tail(vx, k, hq, zt, gb):
@@ -162,6 +172,9 @@ TUNINGS = [
     dict(hash_slices=5, group_bits=18),       # 4-7-7 over five uneven slices, seven launches
     dict(hash_slices=16, group_bits=17, group_cap=64),  # 3-7-7: sixteen slices, oversized groups
     dict(hash_slices=3, group_bits=16, pass1_bits=5, pass2_bits=5, match_chunk_bits=7),  # 5-5-6
+    dict(hash_slices=4, group_bits=18, front_subtile=2048),   # 2048-record items, three passes
+    dict(hash_slices=2, group_bits=20, front_passes=2, front_subtile=4096),  # 4096, two passes
+    dict(hash_slices=6, group_bits=16, front_subtile=4096),   # 4096-record items, 8-8 digits
     dict(hash_slices=5, group_bits=16, fused_sort_match=1),  # sliced hash, fused tail
     dict(hash_slices=2, group_bits=20),       # 6-7-7 (the k=31 split), tiny groups, all three passes
                                               # in the hash launches
