@@ -706,6 +706,13 @@ def main() -> int:
                               % (opcount.ops_per_h1(), opcount.ops_per_h2()) if alu else "bytes")}
     if alu:
         roofline["instruction_form"] = dict(d["instruction_form"], unit="T VALU lane-instructions/s")
+    if traffic and stage_ms[dom] > 0:
+        # The same stage against the HBM roof, from the measured bytes: the
+        # hash launches that also file the partition passes move them at a
+        # rate that bounds them as much as their vector work does.
+        bw = traffic / (stage_ms[dom] / 1000.0)
+        roofline["hbm_side"] = {"achieved": round(bw / 1e9, 1), "peak": hbm_peak / 1e9, "unit": "GB/s",
+                                "frac": round(bw / hbm_peak, 4)}
 
     # The other two parts of the metric: Blake3 hashes/s (above) and mixed-k
     # plots/hour batched against plain, measured after the k=31 buffers are freed.
