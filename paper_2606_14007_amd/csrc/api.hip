@@ -53,12 +53,13 @@ constexpr uint32_t kMaxHashSlices = 16;
 // launch reads them, and two slices sharing a line (16 counters at k = 29)
 // made every other launch of a k=29 plot twice as slow.
 inline uint32_t slice_fill_stride(uint32_t d0) { return ((1u << d0) + 63u) & ~63u; }
-// Measured (one box, median plot time, 1 / 4 / 16 slices): k=31 114.0 /
-// 108.8 / 103.8 ms, k=30 57.8 / 55.0 / 53.4, k=29 29.2 / 27.5 / 26.9,
-// k=27 6.63 / 6.26 / 6.37, k=26 3.25 / 3.13 / 3.43, k=25 1.73 / 1.62 / 2.06;
-// at k=28 the sliced split needs a third pass (13.6 / 13.9 / 13.8), and
-// below k=25 the hash is too short to hide a pass.
-uint32_t default_hash_slices(uint32_t k) { return k >= 29 ? 16 : (k >= 25 && k <= 27 ? 4 : 1); }
+// Measured (one box, median plot time, 1 / 4 / 16 slices, the second pass
+// in the hash launches): k=31 114.0 / 108.8 / 103.8 ms, k=30 57.8 / 55.0 /
+// 53.4, k=29 29.2 / 27.5 / 26.9, k=27 6.63 / 6.26 / 6.37, k=26 3.25 / 3.13 /
+// 3.43, k=25 1.73 / 1.62 / 2.06; below k=25 the hash is too short to hide a
+// pass.  At k=28 the sliced split needs a third pass, which pays once the
+// launches also file it (16 slices: 13.2 against 13.65 ms in one launch).
+uint32_t default_hash_slices(uint32_t k) { return k >= 28 ? 16 : (k >= 25 ? 4 : 1); }
 // A plot's work after its first two partition passes can be pipelined over
 // slices (run_pipe_tail).
 constexpr uint32_t kMaxTailSlices = 16;

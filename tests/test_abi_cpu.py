@@ -81,9 +81,12 @@ def test_workspace_too_small_is_rejected_on_host():
 
 
 def test_partition_passes_follow_the_digit_split():
-    # Default groups: G = k - 11 leading bits, cut into passes of at most 9 bits.
-    for k, passes in ((12, 1), (20, 1), (21, 2), (28, 2), (29, 3), (31, 3)):
+    # Default groups: G = k - 11 leading bits, cut into passes of at most 9 bits
+    # (at most 8 bits for the first two digits of a plot hashed in slices:
+    # 17 bits at k=28 take three passes there, two in one hash launch).
+    for k, passes in ((12, 1), (20, 1), (21, 2), (27, 2), (28, 3), (29, 3), (31, 3)):
         assert vx.vx_partition_passes(vx.make_params(bytes(32), k)) == passes, k
+    assert vx.vx_partition_passes(vx.make_params(bytes(32), 28), vx.make_tuning(hash_slices=1)) == 2
     p = vx.make_params(bytes(32), 31)
     assert vx.vx_partition_passes(p, vx.make_tuning(group_bits=20, pass1_bits=10)) == 2
     assert vx.vx_partition_passes(p, vx.make_tuning(group_bits=15, pass1_bits=5, pass2_bits=5)) == 3
