@@ -317,37 +317,61 @@ __global__ __launch_bounds__(BLOCK) void k_region_scan(const uint32_t *__restric
 // contiguously.  A list may hold slices of several plots (a batch).
 // ---------------------------------------------------------------------------
 
+// The digit of a key: bits [shift, shift + bits) of the 64-bit key, where
+// shift >= 32 (every partition digit lies in the 24 bucket bits), so one
+// bit-field extract of the high word.
+__device__ __forceinline__ uint32_t key_digit(uint64_t key, uint32_t shift, uint32_t bits) {
+    return __builtin_amdgcn_ubfe((uint32_t)(key >> 32), shift - 32u, bits);
+}
+
 // Files a sub-tile of m <= BLOCK * ITEMS records, held lane-strided in k[] /
 // nv[] (item j of thread t is record j * BLOCK + t), by their digit
-// (key >> shift) & mask: ranks them with LDS atomics on cnt[], claims room
-// for each digit's run in region region0 + d (capacity R) with one global
-// atomic on fill[], lays the sub-tile out digit by digit in LDS and writes
-// every run contiguously.  cnt[] must be zero on entry and is zero again on
-// return.  before_barrier() runs between the ranking and the first barrier.
-// No barrier follows the write-out: a caller's next LDS layout must come
-// after a barrier that every thread reaches only once its reads here are
-// done.
+// key_digit(key, shift, bits), shift >= 32: ranks them with LDS atomics on
+// cnt[], claims room for each digit's run in region region0 + d (capacity
+// R) with one global atomic on fill[], lays the sub-tile out digit by digit
+// in LDS and writes every run contiguously.  A run that does not fit its
+// region is cut at the region's end and the digit's claiming thread sets
+// the overflow status bit.  Every output record index is below 2^32 (the
+// output regions hold fewer records).  cnt[] must be zero on entry and is
+// zero again on return; dst[d] receives {the output index of the record at
+// LDS position 0 of digit d's run, wrapped to 32 bits; the end of the run's
+// records that fit}.  before_barrier() runs between the ranking and the
+// first barrier.  No barrier follows the write-out: a caller's next LDS
+// layout must come after a barrier that every thread reaches only once its
+// reads here are done.  Full sub-tiles (m == BLOCK * ITEMS, nearly all)
+// take straight-line code without per-record bounds checks.
 template <int BLOCK, int ITEMS, int MAXD, typename F>
 __device__ __forceinline__ void file_records(const uint64_t (&k)[ITEMS], const uint32_t (&nv)[ITEMS], uint32_t m,
-                                             uint32_t shift, uint32_t mask, uint32_t *fill, uint32_t region0,
+                                             uint32_t shift, uint32_t bits, uint32_t *fill, uint32_t region0,
                                              uint32_t R, uint64_t *okeys, uint32_t *ononces, uint32_t *status,
                                              uint64_t *s_keys, uint32_t *s_non, uint32_t *s_cnt, uint32_t *s_pos,
-                                             uint32_t *s_claim, F before_barrier) {
+                                             uint2 *s_dst, F before_barrier) {
     constexpr int PER = (MAXD + 63) / 64;  // digits per lane of the one-wave scan
+    constexpr uint32_t SUB = BLOCK * ITEMS;
     static_assert(MAXD <= BLOCK, "one thread per digit claims its region room");
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const bool full = m == SUB;
+    // The digit width in a vector register, once: a vector instruction
+    // takes one scalar operand here, and the extract's offset is that one.
+    uint32_t vbits = bits;
+    asm volatile("" : "+v"(vbits));
     uint32_t slot[ITEMS];
+    if (full) {
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j)
-        if (j * BLOCK + tid < m) slot[j] = atomicAdd(&s_cnt[(uint32_t)(k[j] >> shift) & mask], 1u);
+        for (int j = 0; j < ITEMS; ++j) slot[j] = atomicAdd(&s_cnt[key_digit(k[j], shift, vbits)], 1u);
+    } else {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+            slot[j] = j * BLOCK + tid < m ? atomicAdd(&s_cnt[key_digit(k[j], shift, vbits)], 1u) : 0u;
+    }
     before_barrier();
     __syncthreads();
     // Claim room in the regions (thread d <-> digit d); the atomics are in
     // flight during the scan and the LDS layout.  Wave 0 scans the counts.
-    const uint32_t nd = mask + 1u;
-    uint32_t claim = 0;
+    const uint32_t nd = 1u << bits;
+    uint32_t claim = 0, c = 0;
     if (tid < nd) {
-        const uint32_t c = s_cnt[tid];
+        c = s_cnt[tid];
         if (c) claim = atomicAdd(&fill[region0 + tid], c);
     }
     if (tid < 64) {
@@ -369,28 +393,46 @@ __device__ __forceinline__ void file_records(const uint64_t (&k)[ITEMS], const u
     }
     __syncthreads();
     // The counts are consumed: clear them for the next sub-tile (its atomics
-    // come after the next barrier).
-    if (tid < nd) s_cnt[tid] = 0;
+    // come after the next barrier).  Digit d's run starts at output index
+    // (region0 + d) * R + claim and keeps the records that fit below R.
+    if (tid < nd) {
+        s_cnt[tid] = 0;
+        const uint32_t pos = s_pos[tid];
+        const uint32_t fit = claim < R ? min(c, R - claim) : 0u;
+        if (fit < c) atomicOr(status, (uint32_t)VXK_DEV_STATUS_REGION_OVERFLOW);
+        s_dst[tid] = make_uint2((region0 + tid) * R + claim - pos, pos + fit);
+    }
+    if (full) {
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j)
-        if (j * BLOCK + tid < m) {
-            const uint32_t p = s_pos[(uint32_t)(k[j] >> shift) & mask] + slot[j];
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t p = s_pos[key_digit(k[j], shift, vbits)] + slot[j];
             s_keys[p] = k[j];
             s_non[p] = nv[j];
         }
-    if (tid < nd) s_claim[tid] = claim;
+    } else {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+            if (j * BLOCK + tid < m) {
+                const uint32_t p = s_pos[key_digit(k[j], shift, vbits)] + slot[j];
+                s_keys[p] = k[j];
+                s_non[p] = nv[j];
+            }
+    }
     __syncthreads();
-    for (uint32_t e = tid; e < m; e += BLOCK) {
+    auto put = [&](uint32_t e) {
         const uint64_t kk = s_keys[e];
-        const uint32_t d = (uint32_t)(kk >> shift) & mask;
-        const uint32_t r = s_claim[d] + (e - s_pos[d]);
-        if (r < R) {
-            const uint64_t g = (uint64_t)(region0 + d) * R + r;
+        const uint64_t dd = reinterpret_cast<const uint64_t *>(s_dst)[key_digit(kk, shift, vbits)];  // one read
+        if (e < (uint32_t)(dd >> 32)) {
+            const uint32_t g = (uint32_t)dd + e;
             okeys[g] = kk;
             ononces[g] = s_non[e];
-        } else {
-            atomicOr(status, (uint32_t)VXK_DEV_STATUS_REGION_OVERFLOW);
         }
+    };
+    if (full) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) put(j * BLOCK + tid);
+    } else {
+        for (uint32_t e = tid; e < m; e += BLOCK) put(e);
     }
 }
 
@@ -458,7 +500,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXD <= 1
     __shared__ uint32_t s_non[SUB];
     __shared__ uint32_t s_cnt[MAXD];      // digit counts of the sub-tile
     __shared__ uint32_t s_pos[MAXD + 1];  // their exclusive prefix
-    __shared__ uint32_t s_claim[MAXD];
+    __shared__ uint2 s_dst[MAXD];
     __shared__ uint32_t s_tk[2];  // alternate, so a slow reader never sees the next ticket
     const uint32_t tid = threadIdx.x;
     const uint64_t NT = (uint64_t)L.h_items + L.p_items;
@@ -472,7 +514,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXD <= 1
         const bool hrole = take_first(t, L.h_frac, idx);
         uint64_t k[ITEMS];
         uint32_t nv[ITEMS];
-        uint32_t m, shift, mask, R, region0;
+        uint32_t m, shift, bits, R, region0;
         uint32_t *fill, *ononces, *status;
         uint64_t *okeys;
         if (hrole) {
@@ -481,7 +523,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXD <= 1
             const HashSliceDesc &H = L.h[s];
             m = hash_subtile<BLOCK, ITEMS>(H, x, k, nv);
             shift = 64u - H.bits;
-            mask = (1u << H.bits) - 1u;
+            bits = H.bits;
             R = H.R;
             region0 = 0;
             fill = H.fill;
@@ -495,7 +537,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXD <= 1
             uint32_t r;
             m = load_subtile<BLOCK, ITEMS>(P, x, k, nv, &r);
             shift = P.shift;
-            mask = (1u << P.bits) - 1u;
+            bits = P.bits;
             R = P.R_out;
             region0 = (P.r0 + r) << P.bits;
             fill = P.out_fill;
@@ -505,8 +547,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXD <= 1
         }
         // The next ticket is fetched before the first barrier and read after
         // the last one.
-        file_records<BLOCK, ITEMS, MAXD>(k, nv, m, shift, mask, fill, region0, R, okeys, ononces, status, s_keys,
-                                         s_non, s_cnt, s_pos, s_claim, [&]() {
+        file_records<BLOCK, ITEMS, MAXD>(k, nv, m, shift, bits, fill, region0, R, okeys, ononces, status, s_keys,
+                                         s_non, s_cnt, s_pos, s_dst, [&]() {
                                              if (tid == 0) s_tk[(it + 1) & 1] = atomicAdd(ticket, 1u);
                                          });
     }
@@ -1604,7 +1646,7 @@ struct PipeLds {
     } a;
     uint32_t cnt[1 << kPipeMaxBits];
     uint32_t pos[(1 << kPipeMaxBits) + 1];
-    uint32_t claim[1 << kPipeMaxBits];
+    uint2 dst[1 << kPipeMaxBits];
 };
 
 template <int BLOCK>
@@ -1613,9 +1655,8 @@ __device__ __noinline__ void pipe_hash(const HashSliceDesc &H, uint32_t x, PipeL
     uint64_t k[FI];
     uint32_t nv[FI];
     const uint32_t m = hash_subtile<BLOCK, FI>(H, x, k, nv);
-    file_records<BLOCK, FI, 1 << kPipeMaxBits>(k, nv, m, 64u - H.bits, (1u << H.bits) - 1u, H.fill, 0, H.R,
-                                                   H.keys, H.nonces, H.status, S.a.f.keys, S.a.f.non, S.cnt, S.pos,
-                                                   S.claim, [] {});
+    file_records<BLOCK, FI, 1 << kPipeMaxBits>(k, nv, m, 64u - H.bits, H.bits, H.fill, 0, H.R, H.keys, H.nonces,
+                                                   H.status, S.a.f.keys, S.a.f.non, S.cnt, S.pos, S.dst, [] {});
 }
 
 template <int BLOCK>
@@ -1624,9 +1665,9 @@ __device__ __noinline__ void pipe_pass(const PassSliceDesc &P, uint32_t x, PipeL
     uint64_t k[FI];
     uint32_t nv[FI], r;
     const uint32_t m = load_subtile<BLOCK, FI>(P, x, k, nv, &r);
-    file_records<BLOCK, FI, 1 << kPipeMaxBits>(k, nv, m, P.shift, (1u << P.bits) - 1u, P.out_fill,
-                                                   (P.r0 + r) << P.bits, P.R_out, P.out_keys, P.out_nonces, P.status,
-                                                   S.a.f.keys, S.a.f.non, S.cnt, S.pos, S.claim, [] {});
+    file_records<BLOCK, FI, 1 << kPipeMaxBits>(k, nv, m, P.shift, P.bits, P.out_fill, (P.r0 + r) << P.bits,
+                                                   P.R_out, P.out_keys, P.out_nonces, P.status, S.a.f.keys,
+                                                   S.a.f.non, S.cnt, S.pos, S.dst, [] {});
 }
 
 template <int BLOCK>
@@ -2171,7 +2212,9 @@ hipError_t launch_hash_pass(const HashPassList &L, uint32_t *ticket, hipStream_t
         bits = max(bits, L.h[i].bits);
     }
     for (uint32_t i = 0; i < L.np; ++i) {
-        if (L.p[i].bits < 1 || L.p[i].bits > (uint32_t)kHashPassMaxBits || L.p[i].per < 1) return hipErrorInvalidValue;
+        if (L.p[i].bits < 1 || L.p[i].bits > (uint32_t)kHashPassMaxBits || L.p[i].per < 1 || L.p[i].shift < 32 ||
+            L.p[i].shift + L.p[i].bits > 64)
+            return hipErrorInvalidValue;  // digits lie in the key's high word
         bits = max(bits, L.p[i].bits);
     }
     const uint32_t sub = L.sub ? L.sub : kHashScatterSub;
@@ -2445,7 +2488,9 @@ hipError_t launch_pipe(const PipeList &L, PipeList *d_list, uint32_t *ticket, hi
     for (uint32_t i = 0; i < L.n[0]; ++i)
         if (L.h[i].bits < 1 || L.h[i].bits > (uint32_t)kPipeMaxBits) return hipErrorInvalidValue;
     for (uint32_t i = 0; i < L.n[1]; ++i)
-        if (L.p[i].bits < 1 || L.p[i].bits > (uint32_t)kPipeMaxBits || L.p[i].per < 1) return hipErrorInvalidValue;
+        if (L.p[i].bits < 1 || L.p[i].bits > (uint32_t)kPipeMaxBits || L.p[i].per < 1 || L.p[i].shift < 32 ||
+            L.p[i].shift + L.p[i].bits > 64)
+            return hipErrorInvalidValue;  // digits lie in the key's high word
     const uint64_t nt = (uint64_t)L.items[0] + L.items[1] + L.items[2] + L.items[3];
     if (nt == 0) return hipSuccess;
     hipLaunchKernelGGL(k_store_list, dim3(1), dim3(64), 0, s, L, d_list);
