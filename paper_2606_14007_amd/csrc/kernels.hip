@@ -507,6 +507,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXD <= 1
     if (tid < MAXD) s_cnt[tid] = 0;
     if (tid == 0) s_tk[0] = atomicAdd(ticket, 1u);
     __syncthreads();
+    // Filing and pass loads issue at a raised wave priority, so that the
+    // memory-bound phases get their few instructions out ahead of the hash
+    // waves sharing the SIMD.
+    __builtin_amdgcn_s_setprio(2);
     for (uint32_t it = 0;; ++it) {
         const uint64_t t = s_tk[it & 1];
         if (t >= NT) break;
@@ -521,7 +525,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXD <= 1
             uint32_t x = (uint32_t)idx, s = 0;
             while (s + 1 < L.nh && x >= L.h[s].items) x -= L.h[s].items, ++s;
             const HashSliceDesc &H = L.h[s];
+            __builtin_amdgcn_s_setprio(0);  // the hash: vector work that any wave's idle cycles can take
             m = hash_subtile<BLOCK, ITEMS>(H, x, k, nv);
+            __builtin_amdgcn_s_setprio(2);
             shift = 64u - H.bits;
             bits = H.bits;
             R = H.R;
