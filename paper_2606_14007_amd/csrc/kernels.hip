@@ -1086,7 +1086,12 @@ __device__ __forceinline__ void sort_one_group(uint32_t g, const SortArgs &A, So
             ovf_list[i] = g;
         }
     } else {
+        // The LDS sort at the lowest wave priority, the loads before it and
+        // the write-out after it at a raised one (issued ahead of the other
+        // work-groups' LDS work).
+        __builtin_amdgcn_s_setprio(0);
         lds_sort_group<BLOCK, CAPMAX>(k, nn, n, sb_shift, s_keys, s_nonces, S.start, s_wave32);
+        __builtin_amdgcn_s_setprio(2);
         // Write the group out, with each record's pair count (one byte):
         // lane-strided records keep LDS reads and stores contiguous; a
         // record tests its next four records with independent reads (no
@@ -1166,6 +1171,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CAPMAX <=
     __shared__ SortLds<BLOCK, CAPMAX> S;
     __shared__ uint32_t s_tk[2];  // alternate, so a slow reader never sees the next ticket
     const uint32_t tid = threadIdx.x;
+    __builtin_amdgcn_s_setprio(2);
     for (uint32_t it = 0;; ++it) {
         if (tid == 0) s_tk[it & 1] = atomicAdd(ticket, 1u);
         __syncthreads();
@@ -1473,6 +1479,10 @@ __device__ __forceinline__ void match_one_chunk(uint32_t ci, const MatchArgs &A,
         const uint32_t e = tid + i * BLOCK;
         if (e < m) s_nonces[e] = pn[i];
     }
+    // The count, scan and slot expansion (barriers, LDS) at a raised wave
+    // priority, the hash loop at the lowest: a work-group between two
+    // barriers then holds the others' hashing up less.
+    __builtin_amdgcn_s_setprio(2);
     const uint32_t cw = pc;
     const uint64_t base = A.chunk_base[ci];
     uint32_t cnt[ITEMS];
@@ -1508,6 +1518,7 @@ __device__ __forceinline__ void match_one_chunk(uint32_t ci, const MatchArgs &A,
             r += cnt[i];
         }
         __syncthreads();
+        __builtin_amdgcn_s_setprio(0);
         const uint32_t nq = (uint32_t)ctot;
         auto pair = [&](uint32_t qr, uint32_t &na, uint32_t &nb) {
             const uint32_t e = s_slot[qr];
