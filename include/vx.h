@@ -125,7 +125,7 @@ typedef struct {
                                   the default (0 = 100).  The one exception to "no output
                                   changes": below 100 regions can overflow, which sets
                                   VX_DEV_STATUS_REGION_OVERFLOW (for tests of that report) */
-    uint32_t hash_slices;      /* vx_plot: 1 = hash the plot in one launch; 2..16 = hash it in that
+    uint32_t hash_slices;      /* vx_plot: 1 = hash the plot in one launch; 2..32 = hash it in that
                                   many nonce slices, each launch filing the previous slice's records
                                   by the second digit beside the next slice's hash (plots whose two
                                   leading digits fit 7 bits each); 0 = the default for k */

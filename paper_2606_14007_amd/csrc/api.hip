@@ -47,7 +47,7 @@ constexpr uint32_t kMaxSlices = 16;
 constexpr uint32_t kDefaultSlices = 1;
 // A plot hashed in slices files each slice's records by the second digit
 // beside the next slice's hash (run_sliced_front).
-constexpr uint32_t kMaxHashSlices = 16;
+constexpr uint32_t kMaxHashSlices = 32;
 // Each hash slice's first-pass fill counters start on a 256-byte line of
 // their own: a slice's hash claims room with atomics on them while the next
 // launch reads them, and two slices sharing a line (16 counters at k = 29)
@@ -155,7 +155,7 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
         P.slices = 1;
     }
     const bool hs_ok = (!records || staged >= 0) && !t->separate_hash;
-    if (t->hash_slices > kMaxHashSlices) return fail(VX_ERR_UNSUPPORTED, "hash_slices must be at most 16");
+    if (t->hash_slices > kMaxHashSlices) return fail(VX_ERR_UNSUPPORTED, "hash_slices must be at most 32");
     if (t->tail_slices > kMaxTailSlices) return fail(VX_ERR_UNSUPPORTED, "tail_slices must be at most 16");
     if (t->front_passes == 1 || t->front_passes > 3)
         return fail(VX_ERR_UNSUPPORTED, "front_passes must be 0, 2 or 3");
@@ -363,7 +363,7 @@ struct Layout {
 };
 
 // Workspace header: u32 words zeroed at the start of every call.
-constexpr uint32_t kHeaderWords = 128;
+constexpr uint32_t kHeaderWords = 160;
 constexpr uint32_t kHdrStatus = 0;       // device status bits
 constexpr uint32_t kHdrFusedTicket = 2;  // group ticket of the fused sort + match
 constexpr uint32_t kHdrAcc = 4;          // u64 (words 4, 5): Table-2 records of the slices scanned so far

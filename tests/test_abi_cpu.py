@@ -155,7 +155,7 @@ def test_hash_slices_take_their_own_plan():
         assert ws(hash_slices=4, **t) == ws(hash_slices=1, **t), t
     assert hq(hash_slices=16, group_bits=14) == 16
     assert N.vx_hash_slices(N.make_params(bytes(range(32)), 3), N.make_tuning(hash_slices=8, group_bits=2)) == 1
-    assert hq(hash_slices=17) == 0 and ws(hash_slices=17) == 0  # invalid tuning
+    assert hq(hash_slices=33) == 0 and ws(hash_slices=33) == 0  # invalid tuning
     assert N.vx_hash_slices(p) >= 1
 
 

@@ -95,7 +95,7 @@ def test_plot_sliced_hash(vx, k, hq):
 
 
 @pytest.mark.parametrize("k,hq,gb", [(20, 2, 18), (21, 3, 17), (22, 16, 20), (24, 16, 0), (24, 7, 18),
-                                     (26, 16, 17), (26, 4, 0)])
+                                     (26, 16, 17), (26, 4, 0), (22, 32, 20), (25, 24, 18), (26, 32, 17)])
 def test_plot_three_pass_front(vx, k, hq, gb):
     """Three partition passes in the sliced hash launches: launch i hashes
     slice i, files slice i - 1 by the second digit into regions of its own
