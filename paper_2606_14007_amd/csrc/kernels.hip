@@ -945,7 +945,7 @@ __device__ __forceinline__ uint64_t pairs_in_range(const uint64_t *keys, uint32_
 // group prefix (sb_shift), with two 16-bit counters per LDS word in s_start
 // (kSubBins / 2 + 1 words), then an exact rank inside each (tiny) sub-bin.
 // Every thread of the work-group calls it; it ends with a barrier, after
-// which s_start is free.
+// which s_start is free, and s_keys[n .. n + 3] hold all-ones sentinels.
 template <int BLOCK, int CAPMAX>
 __device__ __forceinline__ void lds_sort_group(const uint64_t (&k)[CAPMAX / BLOCK], const uint32_t (&nn)[CAPMAX / BLOCK],
                                                uint32_t n, uint32_t sb_shift, uint64_t *s_keys,
@@ -956,6 +956,7 @@ __device__ __forceinline__ void lds_sort_group(const uint64_t (&k)[CAPMAX / BLOC
     uint32_t slot[ITEMS];
     for (uint32_t i = tid; i < NW2; i += BLOCK) s_start[i] = 0;
     if (tid == 0) s_start[NW2] = n;  // start of the sub-bin past the last
+    if (tid < 4) s_keys[n + tid] = ~0ull;  // sentinels after the sorted records (s_keys holds n + 4)
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -1028,7 +1029,7 @@ template <int BLOCK, int CAPMAX>
 struct SortLds {
     static constexpr int NCS = CAPMAX / 64 + 2;  // match chunks a group overlaps (chunks of >= 64 records)
     static constexpr int NW2 = kSubBins / 2;     // two 16-bit sub-bin counters per word
-    uint64_t keys[CAPMAX];
+    uint64_t keys[CAPMAX + 4];  // + four all-ones sentinels after the group's records
     uint32_t nonces[CAPMAX];
     uint32_t start[NW2 + 1];
     uint64_t wave[BLOCK / 64 + 1];
@@ -1107,23 +1108,24 @@ __device__ __forceinline__ void sort_one_group(uint32_t g, const SortArgs &A, So
                 keys[lo + e] = ki;
                 nonces[lo + e] = s_nonces[e];
                 if (pcnt) {
-                    const uint32_t bi = (uint32_t)(ki >> 40);
-                    uint64_t kn[4];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) kn[r] = e + 1 + r < n ? s_keys[e + 1 + r] : ~0ull;
+                    // The partners of record e are the records after it with
+                    // a key at most ulim: in its bucket and less than T above
+                    // it.  Keys are sorted, so they form a prefix, and the
+                    // group's records are followed by all-ones sentinels, which
+                    // only a bound of all ones (keys within T of 2^64 in the
+                    // last bucket, where every later record is a partner)
+                    // would take: that bound counts records instead.
+                    const uint64_t bend = ki | ((1ull << 40) - 1u);
+                    const uint64_t tl = ki > ~0ull - (T - 1u) ? ~0ull : ki + (T - 1u);
+                    const uint64_t ulim = T == 0 ? 0 : (tl < bend ? tl : bend);
                     uint32_t c = 0;
-                    bool go = true;
+                    if (T != 0) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        go = go && e + 1 + r < n && (uint32_t)(kn[r] >> 40) == bi && kn[r] - ki < T;
-                        c += go ? 1u : 0u;
+                        for (int r = 0; r < 4; ++r) c += s_keys[e + 1 + r] <= ulim ? 1u : 0u;
+                        if (ulim == ~0ull) c = min(c, n - 1u - e);
+                        if (c == 4)
+                            for (uint32_t j = e + 5; j < n && s_keys[j] <= ulim; ++j) ++c;
                     }
-                    if (c == 4)
-                        for (uint32_t j = e + 5; j < n; ++j) {
-                            const uint64_t kj = s_keys[j];
-                            if ((uint32_t)(kj >> 40) != bi || kj - ki >= T) break;
-                            ++c;
-                        }
                     pcnt[lo + e] = (uint8_t)min(c, kPairCountEscape);
                     cnt_e = c;
                 }
