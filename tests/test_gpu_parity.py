@@ -214,6 +214,25 @@ def test_pipelined_plot_at_large_group_count(vx, T):
     _assert_plot_equal(vx, b2, ref)
 
 
+@pytest.mark.parametrize("T", [1 << 39, 1 << 40, (1 << 64) - 1])
+def test_pair_counts_at_the_top_of_the_key_space(vx, T):
+    """The key of seed 61 puts three records of its k=22 plot in the last
+    bucket.  From T = 2^40 (T >= 2^39 for its upper half) the sort's upper
+    bound on a partner's key saturates to all ones there -- the value of the
+    sentinels after a group's records -- so those records are counted by
+    position instead; the plot must still equal the oracle's."""
+    key, k = derive_key(61), 22
+    ref = oracle.plot(key, k, threshold=T, threads=8)
+    assert ref.offsets[-1] - ref.offsets[-2] >= 2  # records in bucket 2^24 - 1
+    b = vx.plot(key, k, threshold=T)
+    torch.cuda.synchronize()
+    assert vx.device_status(b.workspace) == 0
+    assert np.array_equal(vx.u64(b.t1_keys), ref.t1_keys)
+    cnt = vx.t2_count(b)
+    assert cnt == len(ref.t2)
+    assert np.array_equal(vx.t2_records(b.t2, cnt), ref.t2)
+
+
 @pytest.mark.parametrize("T", [0, 1 << 34, 1 << 37, 1 << 40, (1 << 64) - 1])
 def test_bucket_sort_and_match_crowded(vx, T):
     """Caller-supplied keys crowded into few buckets: oversized groups, long
