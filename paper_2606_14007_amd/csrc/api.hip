@@ -164,8 +164,11 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
 
     // Hash slices: whole plots whose first two digits fit the sliced
     // kernel's 8 bits; the pipelined tail keeps its own split.
+    // A staged plot (the stage and its chunks share one plan of the digits)
+    // hashes in slices only if its launches file all three passes, and with
+    // at most 4 chunks (a launch holds one third-pass descriptor per chunk).
     uint32_t hq = t->hash_slices ? t->hash_slices : default_hash_slices(P.k);
-    if (records || staged >= 0 || t->separate_hash || P.slices > 1 || P.G < 2 ||
+    if ((records && staged < 0) || staged > 2 || t->separate_hash || P.slices > 1 || P.G < 2 ||
         P.G > 2u * vxk::kHashPassMaxBits + (uint32_t)vxk::kHashPassMaxBits)
         hq = 1;
     // The digits of the passes for hq hash slices (see below).
@@ -220,7 +223,7 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     st = split(hq, d0, d1, d2);
     if (st != VX_OK) return st;
     if (hq > 1 && (!hs_ok || d0 > (uint32_t)vxk::kHashPassMaxBits || d1 == 0 ||
-                   d1 > (uint32_t)vxk::kHashPassMaxBits || (P.n >> d0) < hq)) {
+                   d1 > (uint32_t)vxk::kHashPassMaxBits || ((staged >= 0 ? 1ull << P.k : P.n) >> d0) < hq)) {
         hq = 1;  // beyond the sliced kernel: the plot hashes in one launch
         st = split(hq, d0, d1, d2);
         if (st != VX_OK) return st;
@@ -292,12 +295,16 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     // leading digits within the sliced kernel's width; otherwise the plot
     // hashes in one launch.  Slice s hashes nonces [s * n / hq, (s + 1) * n /
     // hq) into 2^D[0] regions of its own, of R[0] records each.
+    // A staged plan's slices cut the whole plot's 2^k nonces (a chunk's plan
+    // has the chunk's record count in P.n), and its first-pass regions live
+    // two slices at a time (see ring_slot).
+    const uint64_t front_n = staged >= 0 ? dens : P.n;
     if (hq > 1 && P.hs && P.npass >= 2 && P.D[0] <= (uint32_t)vxk::kHashPassMaxBits &&
-        P.D[1] <= (uint32_t)vxk::kHashPassMaxBits && (P.n >> P.D[0]) >= hq) {
-        const double mean = (double)(((P.n + hq - 1) / hq + (1ull << P.D[0]) - 1) >> P.D[0]);
+        P.D[1] <= (uint32_t)vxk::kHashPassMaxBits && (front_n >> P.D[0]) >= hq) {
+        const double mean = (double)(((front_n + hq - 1) / hq + (1ull << P.D[0]) - 1) >> P.D[0]);
         uint32_t r0 = (uint32_t)(mean + 8.0 * std::sqrt(mean)) + vxk::kHashScatterSub;
         if (t->region_pct) r0 = std::max<uint32_t>(1, (uint32_t)((uint64_t)r0 * t->region_pct / 100));
-        if (((uint64_t)r0 * hq << P.D[0]) < (1ull << 32)) {
+        if (((uint64_t)r0 * (staged >= 0 ? 1 : hq) << P.D[0]) < (1ull << 32)) {
             P.hq = hq;
             P.R[0] = r0;
         }
@@ -320,7 +327,7 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     if (P.hq > 1 && P.npass == 3 && t->front_passes != 2 && P.zt == 1 && !P.fused && !t->batch_shared_hash &&
         P.D[2] <= (uint32_t)vxk::kPipeMaxBits) {
         const uint32_t b01 = P.D[0] + P.D[1];
-        const double mean = (double)((((P.n + P.hq - 1) / P.hq) + (1ull << b01) - 1) >> b01);
+        const double mean = (double)((((front_n + P.hq - 1) / P.hq) + (1ull << b01) - 1) >> b01);
         uint32_t r1 = (uint32_t)(mean + 8.0 * std::sqrt(mean)) + 64u;
         if (t->region_pct) r1 = std::max<uint32_t>(1, (uint32_t)((uint64_t)r1 * t->region_pct / 100));
         if (((uint64_t)r1 << b01) < (1ull << 31)) {
@@ -333,6 +340,13 @@ vx_status make_plan(const vx_plot_params *p, const vx_tuning *t, Plan *pl, uint6
     // memory-bound launches need (k=31: 100.9 against 104.3 ms per plot);
     // with two passes both sizes measured alike.
     P.hsub = t->front_subtile ? t->front_subtile : (P.deep ? vxk::kHashPassWideSub : vxk::kHashScatterSub);
+    if (staged >= 0 && P.hq > 1 && !P.deep) {
+        // A staged plot that cannot file all three passes in its hash
+        // launches hashes in one (with that plan's digits).
+        vx_tuning one = *t;
+        one.hash_slices = 1;
+        return make_plan(p, &one, pl, records, max_k, staged);
+    }
     if (staged >= 0 && !P.hs)
         return fail(VX_ERR_UNSUPPORTED,
                     "staged plots need two or more partition passes, a first digit of at most 8 bits and at "
@@ -426,9 +440,10 @@ Layout layout(const Plan &P, int which) {
     }
     if (hs && P.deep) {
         // The third pass's regions; the first two passes' regions of two
-        // slices at a time (ring_slot).
-        cap_even = std::max<uint64_t>(P.n, (uint64_t)P.R[2] << P.G);
-        cap_odd = 2 * (ring_slot(P, 0) + ring_slot(P, 1));
+        // slices at a time (ring_slot).  A staged chunk reads all of them
+        // from the stage.
+        cap_even = staged ? 0 : std::max<uint64_t>(P.n, (uint64_t)P.R[2] << P.G);
+        cap_odd = staged ? 0 : 2 * (ring_slot(P, 0) + ring_slot(P, 1));
     }
     if (which == VX_CALL_PLOT) L.keys_no = take(cap_even * 8);
     if (hs) L.reg_nonces = take(cap_even * 4);
@@ -466,16 +481,23 @@ Layout layout(const Plan &P, int which) {
 }
 
 // A stage (vx_stage_plot): header words, the first pass's region fills and
-// its regions (SoA).
+// its regions (SoA).  A stage hashed in slices (P.deep) holds instead the
+// third pass's region fills and regions (chunk c's regions from record
+// c * 2^(G - chunk_bits) * R2 on), the second pass's per-slice region fills
+// (the chunks' group starts come from them), the first pass's per-slice
+// fills, and the two rings the hash launches file the first two passes
+// through.
 constexpr uint32_t kStageMagic = 0x56585354u;  // "VXST"
 constexpr uint32_t kStageIdWords = 16;  // header words [1, 16): what the stage was made for
 struct StageLayout {
     // u32[64]: [0] status; [1] magic, [2] k, [3] D0, [4] R0, [5] chunk_bits,
-    // [6, 14) key words, [14, 16) zero
+    // [6, 14) key words, [14] slices | deep << 8 | D1 << 16 | D2 << 24, [15] R2
     size_t header = 0;
-    size_t fill = 0;    // u32[2^D0]
-    size_t keys = 0;    // u64[2^D0 * R0]
-    size_t nonces = 0;  // u32[2^D0 * R0]
+    size_t fill = 0;    // u32[2^D0] (deep: u32[2^G], the third pass's)
+    size_t keys = 0;    // u64[2^D0 * R0] (deep: u64[2^G * R2])
+    size_t nonces = 0;  // u32[2^D0 * R0] (deep: u32[2^G * R2])
+    size_t fill0 = 0, fill1 = 0;            // deep: per-slice first- and second-pass fills
+    size_t ring_keys = 0, ring_nonces = 0;  // deep: two slots of each ring
     size_t total = 0;
 };
 
@@ -487,6 +509,8 @@ void stage_id(const Plan &P, uint32_t chunk_bits, uint32_t id[kStageIdWords]) {
     id[4] = P.R[0];
     id[5] = chunk_bits;
     for (int i = 0; i < 8; ++i) id[6 + i] = P.key_words[i];
+    id[14] = P.hq | (P.deep ? 1u << 8 : 0u) | (P.D[1] << 16) | (P.D[2] << 24);
+    id[15] = P.R[2];
 }
 
 StageLayout stage_layout(const Plan &P) {
@@ -497,13 +521,110 @@ StageLayout stage_layout(const Plan &P) {
         at = align_up(at + bytes, 256);
         return o;
     };
-    const uint64_t recs = (uint64_t)P.R[0] << P.D[0];
     S.header = take(kHeaderWords * 4);
-    S.fill = take((size_t)4 << P.D[0]);
-    S.keys = take(recs * 8);
-    S.nonces = take(recs * 4);
+    if (P.deep) {
+        const uint64_t recs = (uint64_t)P.R[2] << P.G;
+        const uint64_t ring = 2 * (ring_slot(P, 0) + ring_slot(P, 1));
+        S.fill = take((size_t)4 << P.G);
+        S.fill0 = take((size_t)slice_fill_stride(P.D[0]) * P.hq * 4);
+        S.fill1 = take(((size_t)P.hq << (P.D[0] + P.D[1])) * 4);
+        S.keys = take(recs * 8);
+        S.nonces = take(recs * 4);
+        S.ring_keys = take(ring * 8);
+        S.ring_nonces = take(ring * 4);
+    } else {
+        const uint64_t recs = (uint64_t)P.R[0] << P.D[0];
+        S.fill = take((size_t)4 << P.D[0]);
+        S.keys = take(recs * 8);
+        S.nonces = take(recs * 4);
+    }
     S.total = at;
     return S;
+}
+
+template <typename T>
+T *at(void *ws, size_t off);
+void set_frac(vxk::HashPassList &W);
+
+// The stage of a plot hashed in slices with all three passes in the hash
+// launches (P.deep): as run_sliced_front, in the stage's buffers, with one
+// third-pass descriptor per chunk, so that chunk c's third-pass regions are
+// its own (record indices below 2^32) and it can sort them alone.
+vx_status stage_sliced_front(const Plan &P, const StageLayout &S, uint32_t cb, void *d_stage, hipStream_t s) {
+    uint32_t *hdr = at<uint32_t>(d_stage, S.header);
+    const uint32_t b01 = P.D[0] + P.D[1], sub = P.hsub;
+    const uint32_t stride0 = slice_fill_stride(P.D[0]);
+    uint32_t *fill0 = at<uint32_t>(d_stage, S.fill0), *fill1 = at<uint32_t>(d_stage, S.fill1);
+    uint32_t *fill2 = at<uint32_t>(d_stage, S.fill);
+    uint64_t *rk = at<uint64_t>(d_stage, S.ring_keys);
+    uint32_t *rn = at<uint32_t>(d_stage, S.ring_nonces);
+    const uint64_t slot0 = ring_slot(P, 0), slot1 = ring_slot(P, 1);
+    VX_HIP(vxk::launch_fill_u32(fill0, (uint64_t)stride0 * P.hq, 0u, s), "reset");
+    VX_HIP(vxk::launch_fill_u32(fill1, (uint64_t)P.hq << b01, 0u, s), "reset");
+    VX_HIP(vxk::launch_fill_u32(fill2, 1ull << P.G, 0u, s), "reset");
+    const uint32_t nch = 1u << cb, nin_c = 1u << (b01 - cb);
+    const uint64_t creg = (uint64_t)P.R[2] << (P.G - cb);  // records of a chunk's third-pass regions
+    for (uint32_t i = 0; i < P.hq + 2; ++i) {
+        vxk::HashPassList W;
+        memset(&W, 0, sizeof(W));
+        W.sub = sub;
+        if (i < P.hq) {
+            vxk::HashSliceDesc &H = W.h[W.nh++];
+            memcpy(H.key, P.key_words, sizeof(H.key));
+            H.nonce0 = P.n * i / P.hq;
+            H.n = P.n * (i + 1) / P.hq - H.nonce0;
+            H.keys = rk + (i % 2) * slot0;
+            H.nonces = rn + (i % 2) * slot0;
+            H.fill = fill0 + (size_t)i * stride0;
+            H.status = hdr + kHdrStatus;
+            H.bits = P.D[0];
+            H.R = P.R[0];
+            H.items = (uint32_t)((H.n + sub - 1) / sub);
+            W.h_items += H.items;
+        }
+        if (i >= 1 && i - 1 < P.hq) {  // slice i - 1 by the second digit
+            const uint32_t j = i - 1, per = (P.R[0] + sub - 1) / sub;
+            vxk::PassSliceDesc &Q = W.p[W.np++];
+            Q.keys = rk + (j % 2) * slot0;
+            Q.nonces = rn + (j % 2) * slot0;
+            Q.fill = fill0 + (size_t)j * stride0;
+            Q.out_keys = rk + 2 * slot0 + (j % 2) * slot1;
+            Q.out_nonces = rn + 2 * slot0 + (j % 2) * slot1;
+            Q.out_fill = fill1 + ((size_t)j << b01);
+            Q.status = hdr + kHdrStatus;
+            Q.R_in = P.R[0];
+            Q.per = per;
+            Q.shift = 64 - b01;
+            Q.bits = P.D[1];
+            Q.R_out = P.R[1];
+            Q.items = (1u << P.D[0]) * per;
+            W.p_items += Q.items;
+        }
+        if (i >= 2) {  // slice i - 2 by the third digit, chunk by chunk
+            const uint32_t j = i - 2, per = (P.R[1] + sub - 1) / sub;
+            for (uint32_t c = 0; c < nch; ++c) {
+                vxk::PassSliceDesc &Q = W.p[W.np++];
+                const uint64_t in0 = 2 * slot0 + (j % 2) * slot1 + (uint64_t)c * nin_c * P.R[1];
+                Q.keys = rk + in0;
+                Q.nonces = rn + in0;
+                Q.fill = fill1 + ((size_t)j << b01) + (size_t)c * nin_c;
+                Q.out_keys = at<uint64_t>(d_stage, S.keys) + c * creg;
+                Q.out_nonces = at<uint32_t>(d_stage, S.nonces) + c * creg;
+                Q.out_fill = fill2 + ((size_t)c << (P.G - cb));
+                Q.status = hdr + kHdrStatus;
+                Q.R_in = P.R[1];
+                Q.per = per;
+                Q.shift = 64 - P.G;
+                Q.bits = P.D[2];
+                Q.R_out = P.R[2];
+                Q.items = nin_c * per;
+                W.p_items += Q.items;
+            }
+        }
+        set_frac(W);
+        VX_HIP(vxk::launch_hash_pass(W, hdr + kHdrHashPassTicket + i, s), "stage hash");
+    }
+    return VX_OK;
 }
 
 // Records ev[i] on s when an event array is given (stage timing).
@@ -827,7 +948,8 @@ vx_status run_sliced_front(const Plan &P, const Layout &L, void *ws, hipStream_t
 // against 12.9 + 0.8 ms; the pipelined tail uses them, the rest does not.)
 vx_status run_group_sort(const Plan &P, const Layout &L, void *ws, uint64_t *t1_keys, uint32_t *t1_nonces,
                          uint32_t *offsets, uint8_t *pcnt, uint32_t g0, uint32_t gcount, uint32_t slot,
-                         hipStream_t s, bool sums = false) {
+                         hipStream_t s, bool sums = false, const uint64_t *regions_k = nullptr,
+                         const uint32_t *regions_n = nullptr) {
     uint64_t *csum = nullptr;
     if (sums && pcnt) {
         csum = at<uint64_t>(ws, L.mcount);
@@ -841,8 +963,8 @@ vx_status run_group_sort(const Plan &P, const Layout &L, void *ws, uint64_t *t1_
     const uint32_t *in_n = nullptr, *in_lo = nullptr, *in_hi = nullptr;
     if (P.hs) {
         const PassBufs B = pass_bufs(P, L, ws, nullptr, t1_keys, t1_nonces, last);
-        in_k = B.out_k;
-        in_n = B.out_n;
+        in_k = regions_k ? regions_k : B.out_k;  // (a staged chunk's regions are in the stage)
+        in_n = regions_k ? regions_n : B.out_n;
         in_lo = at<uint32_t>(ws, L.seg_lo[last]);
         in_hi = at<uint32_t>(ws, L.seg_hi[last]);
     }
@@ -1362,6 +1484,11 @@ vx_status vx_stage_plot(const vx_plot_params *params, uint32_t chunk_bits, const
     stage_id(P, chunk_bits, id);
     VX_HIP(vxk::launch_reset(hdr, kHeaderWords, s), "reset");
     VX_HIP(vxk::launch_put_words(hdr + 1, id + 1, kStageIdWords - 1, s), "stage header");
+    if (P.deep) {
+        st = stage_sliced_front(P, S, chunk_bits, d_stage, s);
+        if (st == VX_OK) g_err[0] = 0;
+        return st;
+    }
     VX_HIP(vxk::launch_fill_u32(at<uint32_t>(d_stage, S.fill), 1ull << P.D[0], 0u, s), "reset");
     VX_HIP(vxk::launch_hash_scatter(P.key_words, P.n, P.D[0], P.R[0], at<uint64_t>(d_stage, S.keys),
                                     at<uint32_t>(d_stage, S.nonces), at<uint32_t>(d_stage, S.fill), hdr + kHdrStatus,
@@ -1379,6 +1506,71 @@ size_t vx_staged_chunk_workspace_bytes(const vx_plot_params *params, uint32_t ch
     return layout(P, kCallStagedChunk).total;
 }
 
+}  // extern "C"
+
+namespace {
+// Chunk `chunk` of a stage that holds the third pass's regions (P.deep):
+// the chunk's second-pass group starts (summed over the slices' own
+// regions), then its third-pass region bounds and group starts, from a copy
+// of its fills (the stage stays read-only), the group sort straight from
+// the stage, and the match.
+vx_status staged_chunk_sorted(const Plan &Pc, const Layout &L, const StageLayout &S, uint32_t cb, uint32_t chunk,
+                              const void *d_stage, const vx_plot_buffers *b, uint64_t t1_capacity,
+                              uint64_t *d_t1_count, hipStream_t s) {
+    void *ws = b->workspace;
+    void *stage = const_cast<void *>(d_stage);
+    uint32_t *hdr = at<uint32_t>(ws, L.header);
+    const uint32_t b01 = Pc.D[0] + Pc.D[1], D2 = Pc.D[2];
+    const uint32_t nd01c = 1u << (b01 - cb), first01 = chunk * nd01c;
+    const uint32_t g_first = first01 << D2, ng = nd01c << D2;
+    uint32_t *gst1 = at<uint32_t>(ws, L.gstart[1]);
+    VX_HIP(vxk::launch_reset(hdr, kHeaderWords, s), "reset");
+    VX_HIP(vxk::launch_region_scan_slices(at<uint32_t>(stage, S.fill1) + first01, Pc.hq, 1u << b01, nd01c,
+                                          Pc.R[1], gst1 + first01, s),
+           "chunk regions");
+    uint32_t m32 = 0, id[kStageIdWords], want[kStageIdWords];
+    VX_HIP(hipMemcpyAsync(&m32, gst1 + first01 + nd01c, sizeof(m32), hipMemcpyDeviceToHost, s), "chunk count");
+    VX_HIP(hipMemcpyAsync(id, at<const uint32_t>(stage, S.header), sizeof(id), hipMemcpyDeviceToHost, s),
+           "stage header");
+    VX_HIP(hipStreamSynchronize(s), "chunk count");
+    stage_id(Pc, cb, want);
+    if (memcmp(id + 1, want + 1, (kStageIdWords - 1) * 4) != 0)
+        return fail(VX_ERR_INVALID_ARG, "the stage was made for another key, k, chunk_bits or tuning");
+    const uint64_t m = m32;
+    bool empty = false;
+    vx_status st = publish_chunk_count(m, d_t1_count, t1_capacity, b, s, &empty);
+    if (st != VX_OK) return st;
+    if (empty) {
+        g_err[0] = 0;
+        return VX_OK;
+    }
+    Plan P = Pc;  // the stage's digits and regions, the chunk's records
+    P.n = m;
+    uint32_t *fill2 = at<uint32_t>(ws, L.fill[2]) + g_first;
+    VX_HIP(hipMemcpyAsync(fill2, at<const uint32_t>(stage, S.fill) + g_first, (size_t)ng * 4,
+                          hipMemcpyDeviceToDevice, s),
+           "chunk fills");
+    VX_HIP(vxk::launch_region_bounds(fill2, 0, ng, P.R[2], at<uint32_t>(ws, L.seg_lo[2]) + g_first,
+                                     at<uint32_t>(ws, L.seg_hi[2]) + g_first, s),
+           "chunk regions");
+    VX_HIP(vxk::launch_colscan(fill2, at<uint32_t>(ws, L.off[2]) + g_first, nd01c, 1, 1u << D2, gst1 + first01,
+                               at<uint32_t>(ws, L.gstart[2]) + g_first, ng, (uint32_t)m, s),
+           "chunk scan");
+    const uint64_t creg = (uint64_t)P.R[2] << (P.G - cb);
+    st = run_group_sort(P, L, ws, b->t1_keys, b->t1_nonces, b->bucket_offsets, at<uint8_t>(ws, L.pcnt), g_first, ng,
+                        0, s, false, at<const uint64_t>(stage, S.keys) + chunk * creg,
+                        at<const uint32_t>(stage, S.nonces) + chunk * creg);
+    if (st != VX_OK) return st;
+    if ((st = fill_outside_offsets(b->bucket_offsets, cb, chunk, m, s)) != VX_OK) return st;
+    st = run_match(P, L, ws, b->t1_keys, b->t1_nonces, b->t2, b->t2_capacity, b->t2_count, nullptr, nullptr, 1, 0,
+                   0, s);
+    if (st == VX_OK) g_err[0] = 0;
+    return st;
+}
+}  // namespace
+
+extern "C" {
+
 vx_status vx_plot_staged_chunk(const vx_plot_params *params, uint32_t chunk_bits, uint32_t chunk,
                                const void *d_stage, size_t stage_bytes, const vx_plot_buffers *b,
                                uint64_t t1_capacity, uint64_t *d_t1_count, const vx_tuning *tuning, void *stream) {
@@ -1395,6 +1587,7 @@ vx_status vx_plot_staged_chunk(const vx_plot_params *params, uint32_t chunk_bits
     hipStream_t s = (hipStream_t)stream;
     void *ws = b->workspace;
     uint32_t *hdr = at<uint32_t>(ws, L.header);
+    if (Pc.deep) return staged_chunk_sorted(Pc, L, S, chunk_bits, chunk, d_stage, b, t1_capacity, d_t1_count, s);
     // The chunk's first-pass regions in the stage, and where it starts.
     const uint32_t ndc = 1u << (Pc.D[0] - chunk_bits);
     const uint32_t d_first = chunk * ndc;

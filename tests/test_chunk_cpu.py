@@ -97,9 +97,16 @@ def test_plot_chunk_argument_checks(case, status):
 def test_stage_sizes_and_limits():
     p32 = vx.make_params(bytes(32), 32)
     st = vx.vx_stage_bytes(p32, 1)
-    # 12 bytes per record of the plot, plus slack and the header
-    assert 12 << 32 < st < (12 << 32) * 1.01
+    # Hashed in slices with all three passes (up to 4 chunks): the third
+    # pass's regions (21 % slack over 12 bytes per record) and two slices'
+    # first- and second-pass regions
+    assert (12 << 32) * 1.2 < st < (12 << 32) * 1.5
     assert vx.vx_stage_bytes(p32, 2) == st          # the stage does not depend on the chunk count
+    # in one launch: the first pass's regions, 12 bytes per record plus slack and the header
+    one = vx.vx_stage_bytes(p32, 1, vx.make_tuning(hash_slices=1))
+    assert 12 << 32 < one < (12 << 32) * 1.01
+    assert vx.vx_stage_bytes(p32, 1, vx.make_tuning(front_passes=2)) == one
+    assert vx.vx_stage_bytes(p32, 3) == one         # 8 chunks: one launch
     assert vx.vx_stage_bytes(p32, 7) == 0           # wider than the first digit (6 bits)
     assert vx.vx_stage_bytes(p32, 0) == 0           # one chunk of 2^32 records
     assert vx.vx_stage_bytes(p32, 1, vx.make_tuning(fused_sort_match=1)) == 0

@@ -126,6 +126,45 @@ def test_staged_chunk_tunings(vx, tun):
     _check_chunk(vx, b, ref, c, 1)
 
 
+@pytest.mark.parametrize("k,c,tun,T", [
+    (20, 1, dict(hash_slices=4, group_bits=18), None),
+    (22, 2, dict(hash_slices=16, group_bits=20), None),
+    (18, 2, dict(hash_slices=3, group_bits=17), 1 << 47),
+    (21, 1, dict(hash_slices=5, group_bits=17, front_subtile=2048), None),
+])
+def test_staged_chunks_sliced_front(vx, k, c, tun, T):
+    """A stage hashed in slices with all three partition passes in its
+    launches (the form a k=32 stage takes): it holds each chunk's third-pass
+    regions, and a chunk only gathers, sorts and matches them."""
+    t = vx.make_tuning(**tun)
+    p = vx.make_params(KEY0, k)
+    assert N.vx_stage_bytes(p, c, t) != N.vx_stage_bytes(p, c, vx.make_tuning(**dict(tun, hash_slices=1)))
+    ref = oracle.plot(KEY0, k, threshold=T, threads=8)
+    st = vx.stage_plot(KEY0, k, c, tuning=t)
+    b = vx.alloc_staged_chunk(k, c, threshold=T, tuning=t)
+    total1 = total2 = 0
+    for r in reversed(range(1 << c)):
+        print(f"sliced stage k={k} c={c} chunk={r}", flush=True)
+        vx.plot_staged_chunk(KEY0, st, r, b, threshold=T, tuning=t)
+        m, cnt = _check_chunk(vx, b, ref, c, r)
+        total1 += m
+        total2 += cnt
+    assert vx.device_status(st.data) == 0
+    assert total1 == 1 << k
+    assert total2 == len(ref.t2)
+    vx.plot_staged_chunk(KEY0, st, 0, b, threshold=T, tuning=t)  # again, after the others
+    _check_chunk(vx, b, ref, c, 0)
+
+
+def test_sliced_stage_region_overflow_is_reported(vx):
+    """Regions of a stage hashed in slices shrunk below their contents (a
+    test hook) set the overflow bit in the stage's status word."""
+    t = vx.make_tuning(hash_slices=4, group_bits=18, region_pct=25)
+    st = vx.stage_plot(KEY0, 18, 1, tuning=t)
+    torch.cuda.synchronize()
+    assert vx.device_status(st.data) & N.VX_DEV_STATUS_REGION_OVERFLOW
+
+
 def test_staged_chunk_checks_the_stage(vx):
     k, c = 14, 1
     st = vx.stage_plot(derive_key(5), k, c)
