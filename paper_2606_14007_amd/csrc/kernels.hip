@@ -944,20 +944,26 @@ __device__ __forceinline__ uint64_t pairs_in_range(const uint64_t *keys, uint32_
 // by (key, nonce): a counting sort on the kSubBinBits key bits below the
 // group prefix (sb_shift), with two 16-bit counters per LDS word in s_start
 // (kSubBins / 2 + 1 words), then an exact rank inside each (tiny) sub-bin.
+// A record alone in its sub-bin is in its final place after the counting
+// sort; only the records that share a sub-bin are ranked and moved again.
 // Every thread of the work-group calls it; it ends with a barrier, after
-// which s_start is free, and s_keys[n .. n + 3] hold all-ones sentinels.
+// which s_keys[n .. n + 3] hold all-ones sentinels and s_start holds each
+// sub-bin's first position (sub-bin 2w in the low half of word w, 2w + 1
+// in the high half) until the caller reuses it.
 template <int BLOCK, int CAPMAX>
 __device__ __forceinline__ void lds_sort_group(const uint64_t (&k)[CAPMAX / BLOCK], const uint32_t (&nn)[CAPMAX / BLOCK],
                                                uint32_t n, uint32_t sb_shift, uint64_t *s_keys,
                                                uint32_t *s_nonces, uint32_t *s_start, uint32_t *s_wave32) {
     constexpr int ITEMS = CAPMAX / BLOCK;
     constexpr int NW2 = kSubBins / 2;
+    constexpr uint32_t kPlaced = 0xFFFFFFFFu;  // slot[] value of a record already in its final place
     const uint32_t tid = threadIdx.x;
     uint32_t slot[ITEMS];
     for (uint32_t i = tid; i < NW2; i += BLOCK) s_start[i] = 0;
     if (tid == 0) s_start[NW2] = n;  // start of the sub-bin past the last
     if (tid < 4) s_keys[n + tid] = ~0ull;  // sentinels after the sorted records (s_keys holds n + 4)
     __syncthreads();
+    if (n == 0) return;  // uniform; k[] holds nothing
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const uint32_t e = j * BLOCK + tid;
@@ -986,26 +992,28 @@ __device__ __forceinline__ void lds_sort_group(const uint64_t (&k)[CAPMAX / BLOC
         }
     }
     __syncthreads();
+    // Scatter by sub-bin.  slot[] becomes the sub-bin's start and size
+    // (start | size << 16) for a record that shares it, else kPlaced.
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const uint32_t e = j * BLOCK + tid;
+        const uint32_t sb = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
+        const uint32_t sb1 = sb + 1;
+        const uint32_t b0 = (s_start[sb >> 1] >> ((sb & 1u) << 4)) & 0xFFFFu;
+        const uint32_t b1 = (s_start[sb1 >> 1] >> ((sb1 & 1u) << 4)) & 0xFFFFu;
         if (e < n) {
-            const uint32_t sbq = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
-            const uint32_t q = ((s_start[sbq >> 1] >> ((sbq & 1u) << 4)) & 0xFFFFu) + slot[j];
+            const uint32_t q = b0 + slot[j];
             s_keys[q] = k[j];
             s_nonces[q] = nn[j];
         }
+        slot[j] = (e < n && b1 - b0 > 1u) ? (b0 | ((b1 - b0) << 16)) : kPlaced;
     }
     __syncthreads();
-    // Exact rank inside the sub-bin; slot[] is reused for the final position.
+    // Exact rank inside a shared sub-bin; slot[] becomes the final position.
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t e = j * BLOCK + tid;
-        if (e < n) {
-            const uint32_t sb = (uint32_t)(k[j] >> sb_shift) & (kSubBins - 1);
-            const uint32_t b0 = (s_start[sb >> 1] >> ((sb & 1u) << 4)) & 0xFFFFu;
-            const uint32_t sb1 = sb + 1;
-            const uint32_t b1 = (s_start[sb1 >> 1] >> ((sb1 & 1u) << 4)) & 0xFFFFu;
+        if (slot[j] != kPlaced) {
+            const uint32_t b0 = slot[j] & 0xFFFFu, b1 = b0 + (slot[j] >> 16);
             uint32_t r = 0;
             for (uint32_t x = b0; x < b1; ++x) r += rec_less(s_keys[x], s_nonces[x], k[j], nn[j]);
             slot[j] = b0 + r;
@@ -1014,8 +1022,7 @@ __device__ __forceinline__ void lds_sort_group(const uint64_t (&k)[CAPMAX / BLOC
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t e = j * BLOCK + tid;
-        if (e < n) {
+        if (slot[j] != kPlaced) {
             s_keys[slot[j]] = k[j];
             s_nonces[slot[j]] = nn[j];
         }
@@ -1141,13 +1148,23 @@ __device__ __forceinline__ void sort_one_group(uint32_t g, const SortArgs &A, So
             }
         }
         // offsets[b] for the group's buckets: first record with bucket >= b.
-        const uint32_t bfirst = g << (VXK_BUCKET_BITS - G);
+        // With at most kSubBinBits bucket bits inside the group they are the
+        // top bits of the sub-bin, and a bucket starts where its first
+        // sub-bin does (the counting sort's starts, still in S.start);
+        // otherwise a binary search over the sorted keys.
+        const uint32_t bb = VXK_BUCKET_BITS - G, bfirst = g << bb;
         for (uint32_t bl = tid; bl < nbg; bl += BLOCK) {
             const uint32_t b = bfirst + bl;
-            uint32_t a = 0, c = n;
-            while (a < c) {
-                const uint32_t mid = (a + c) >> 1;
-                if ((uint32_t)(s_keys[mid] >> 40) < b) a = mid + 1; else c = mid;
+            uint32_t a = 0;
+            if (bb <= (uint32_t)kSubBinBits) {
+                const uint32_t sb = bl << (kSubBinBits - bb);
+                a = (S.start[sb >> 1] >> ((sb & 1u) << 4)) & 0xFFFFu;
+            } else {
+                uint32_t c = n;
+                while (a < c) {
+                    const uint32_t mid = (a + c) >> 1;
+                    if ((uint32_t)(s_keys[mid] >> 40) < b) a = mid + 1; else c = mid;
+                }
             }
             offsets[b] = lo + a;
         }

@@ -134,3 +134,40 @@ def test_batch_fused_fronts_mixed_plans(vx, refs):
         torch.cuda.synchronize()
         for b, ref in zip(bt.plots, refs):
             _check(vx, b, ref)
+
+
+def test_batch_three_pass_fronts_and_replay(vx, refs):
+    """Plans that file all three partition passes in their sliced hash
+    launches (the second pass into per-slice regions, the third into the
+    shared ones) mixed with two-pass sliced and one-launch plans, two lanes
+    sharing workspaces, eager and then under graph replay."""
+    from paper_2606_14007_amd import batch as B
+    specs = _specs()  # k = 16, 10, 18, 13, 17, 12, 15, 14
+    tun = []
+    for i, s in enumerate(specs):
+        if i % 3 == 0:
+            tun.append(vx.make_tuning(group_bits=18, hash_slices=3 + i % 2))
+        elif i % 3 == 1:
+            tun.append(vx.make_tuning(group_bits=18, hash_slices=2, front_subtile=4096))
+        else:
+            tun.append(vx.make_tuning(hash_slices=2, front_passes=2))
+    deep = [vx.vx_front_passes(vx.make_params(s.key, s.k), t) == 3 for s, t in zip(specs, tun)]
+    assert 2 <= sum(deep) < len(specs)
+    bt = B.alloc_batch(specs, tunings=tun, lanes=2)
+    B.plot_batch(bt, check_result=True)
+    torch.cuda.synchronize()
+    for b, ref in zip(bt.plots, refs):
+        _check(vx, b, ref)
+    B.capture(bt)
+    for r in range(2):
+        for b in bt.plots:
+            b.t1_keys.fill_(-1)
+            b.t1_nonces.fill_(-1)
+            b.t2_count.zero_()
+        other = vx.plot(derive_key(950 + r), 13)
+        torch.cuda.synchronize()
+        B.replay(bt, check_result=True)
+        torch.cuda.synchronize()
+        for b, ref in zip(bt.plots, refs):
+            _check(vx, b, ref)
+        assert vx.t2_count(other) >= 0
