@@ -8,22 +8,56 @@ namespace vxd {
 
 constexpr int kWave = 64;
 
+// Cross-lane moves of the GFX9 data-parallel (DPP) modifier.  A row is 16
+// lanes; lanes whose source lies outside the row, and lanes of rows left
+// out by ROW_MASK, read zero.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xF, true);
+}
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142;  // lane 15 of each row to the whole next row
+constexpr int kDppRowBcast31 = 0x143;  // lane 31 to rows 2 and 3
+
+template <int CTRL, int ROW_MASK, typename T>
+__device__ __forceinline__ T dpp_move(T x) {
+    if constexpr (sizeof(T) == 4) {
+        return (T)dpp_u32<CTRL, ROW_MASK>((uint32_t)x);
+    } else {
+        const uint64_t u = (uint64_t)x;
+        return (T)((uint64_t)dpp_u32<CTRL, ROW_MASK>((uint32_t)u) |
+                   ((uint64_t)dpp_u32<CTRL, ROW_MASK>((uint32_t)(u >> 32)) << 32));
+    }
+}
+
+// Inclusive scan over the 64 lanes of a wave, for 32- and 64-bit integers:
+// shifts by 1, 2, 4 and 8 lanes inside each row (Hillis-Steele), then row
+// 0's total added to row 1 and row 2's to row 3, then lane 31's (rows 0 and
+// 1) to rows 2 and 3.  Every lane of the wave must be active.
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T x) {
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        T y = __shfl_up(x, d, kWave);
-        if (lane >= d) x += y;
-    }
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit integers");
+    x += dpp_move<kDppRowShr1, 0xF>(x);
+    x += dpp_move<kDppRowShr2, 0xF>(x);
+    x += dpp_move<kDppRowShr4, 0xF>(x);
+    x += dpp_move<kDppRowShr8, 0xF>(x);
+    x += dpp_move<kDppRowBcast15, 0xA>(x);
+    x += dpp_move<kDppRowBcast31, 0xC>(x);
     return x;
 }
 
+// Sum over the 64 lanes of a wave (every lane active), the same in every lane.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T x) {
-#pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
-    return x;
+    x = wave_inclusive_scan(x);
+    if constexpr (sizeof(T) == 4) {
+        return (T)__builtin_amdgcn_readlane((int)x, kWave - 1);
+    } else {
+        const uint64_t u = (uint64_t)x;
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, kWave - 1);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), kWave - 1);
+        return (T)((uint64_t)lo | ((uint64_t)hi << 32));
+    }
 }
 
 // Exclusive scan of one value per thread over the work-group.  s_wave needs
