@@ -19,31 +19,53 @@ constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDp
 constexpr int kDppRowBcast15 = 0x142;  // lane 15 of each row to the whole next row
 constexpr int kDppRowBcast31 = 0x143;  // lane 31 to rows 2 and 3
 
-template <int CTRL, int ROW_MASK, typename T>
-__device__ __forceinline__ T dpp_move(T x) {
-    if constexpr (sizeof(T) == 4) {
-        return (T)dpp_u32<CTRL, ROW_MASK>((uint32_t)x);
-    } else {
-        const uint64_t u = (uint64_t)x;
-        return (T)((uint64_t)dpp_u32<CTRL, ROW_MASK>((uint32_t)u) |
-                   ((uint64_t)dpp_u32<CTRL, ROW_MASK>((uint32_t)(u >> 32)) << 32));
-    }
+// One scan step: x += the value DPP control CTRL brings in (zero where it
+// brings nothing).  64-bit values move as two halves and add with a carry.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void dpp_add(uint32_t &x) {
+    x += dpp_u32<CTRL, ROW_MASK>(x);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void dpp_add(uint32_t &lo, uint32_t &hi) {
+    const uint32_t slo = dpp_u32<CTRL, ROW_MASK>(lo), shi = dpp_u32<CTRL, ROW_MASK>(hi);
+    unsigned int carry;
+    lo = __builtin_addc(lo, slo, 0u, &carry);
+    hi = hi + shi + carry;
 }
 
-// Inclusive scan over the 64 lanes of a wave, for 32- and 64-bit integers:
-// shifts by 1, 2, 4 and 8 lanes inside each row (Hillis-Steele), then row
-// 0's total added to row 1 and row 2's to row 3, then lane 31's (rows 0 and
-// 1) to rows 2 and 3.  Every lane of the wave must be active.
-template <typename T>
+// Inclusive scan over the first N lanes of a wave (N = 64: all of them),
+// for 32- and 64-bit integers: shifts by 1, 2, 4 and 8 lanes inside each
+// row of 16 (Hillis-Steele), then row 0's total added to row 1 and row 2's
+// to row 3, then lane 31's (rows 0 and 1) to rows 2 and 3.  Steps that
+// cannot reach inside the first N lanes are left out.  Every lane of the
+// wave must be active.
+template <int N = kWave, typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T x) {
     static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit integers");
-    x += dpp_move<kDppRowShr1, 0xF>(x);
-    x += dpp_move<kDppRowShr2, 0xF>(x);
-    x += dpp_move<kDppRowShr4, 0xF>(x);
-    x += dpp_move<kDppRowShr8, 0xF>(x);
-    x += dpp_move<kDppRowBcast15, 0xA>(x);
-    x += dpp_move<kDppRowBcast31, 0xC>(x);
-    return x;
+    static_assert(N == 2 || N == 4 || N == 8 || N == 16 || N == kWave, "lane count");
+    if constexpr (sizeof(T) == 4) {
+        uint32_t v = (uint32_t)x;
+        dpp_add<kDppRowShr1, 0xF>(v);
+        if constexpr (N > 2) dpp_add<kDppRowShr2, 0xF>(v);
+        if constexpr (N > 4) dpp_add<kDppRowShr4, 0xF>(v);
+        if constexpr (N > 8) dpp_add<kDppRowShr8, 0xF>(v);
+        if constexpr (N > 16) {
+            dpp_add<kDppRowBcast15, 0xA>(v);
+            dpp_add<kDppRowBcast31, 0xC>(v);
+        }
+        return (T)v;
+    } else {
+        uint32_t lo = (uint32_t)(uint64_t)x, hi = (uint32_t)((uint64_t)x >> 32);
+        dpp_add<kDppRowShr1, 0xF>(lo, hi);
+        if constexpr (N > 2) dpp_add<kDppRowShr2, 0xF>(lo, hi);
+        if constexpr (N > 4) dpp_add<kDppRowShr4, 0xF>(lo, hi);
+        if constexpr (N > 8) dpp_add<kDppRowShr8, 0xF>(lo, hi);
+        if constexpr (N > 16) {
+            dpp_add<kDppRowBcast15, 0xA>(lo, hi);
+            dpp_add<kDppRowBcast31, 0xC>(lo, hi);
+        }
+        return (T)(((uint64_t)hi << 32) | lo);
+    }
 }
 
 // Sum over the 64 lanes of a wave (every lane active), the same in every lane.
@@ -74,7 +96,7 @@ __device__ __forceinline__ T block_exclusive_scan(T x, T *s_wave, T *total) {
     __syncthreads();
     if (wid == 0) {
         T w = lane < NW ? s_wave[lane] : T(0);
-        T wi = wave_inclusive_scan(w);
+        T wi = wave_inclusive_scan<(NW <= 2 ? 2 : NW <= 4 ? 4 : NW <= 8 ? 8 : NW <= 16 ? 16 : kWave)>(w);
         if (lane < NW) s_wave[lane] = wi - w;  // exclusive per-wave base
         if (lane == NW - 1) s_wave[NW] = wi;   // grand total
     }
