@@ -1532,9 +1532,18 @@ __device__ __forceinline__ void match_one_chunk(uint32_t ci, const MatchArgs &A,
         uint32_t r = (uint32_t)run;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
+            // A record's slots: the first four as masked stores at fixed
+            // offsets (a wave would otherwise loop as often as its largest
+            // count), a loop only for the rare record with more.
             s_first32[e0 + i] = r;
-            for (uint32_t q = r; q < r + cnt[i]; ++q) s_slot[q] = e0 + i;
-            r += cnt[i];
+            uint32_t *dst = s_slot + r;
+            const uint32_t ni = cnt[i], val = e0 + i;
+            if (ni > 0) dst[0] = val;
+            if (ni > 1) dst[1] = val;
+            if (ni > 2) dst[2] = val;
+            if (ni > 3) dst[3] = val;
+            for (uint32_t q = 4; q < ni; ++q) dst[q] = val;
+            r += ni;
         }
         __syncthreads();
         __builtin_amdgcn_s_setprio(0);
