@@ -91,7 +91,17 @@ __device__ __forceinline__ T block_exclusive_scan(T x, T *s_wave, T *total) {
     constexpr int NW = BLOCK / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
-    T inc = wave_inclusive_scan(x);
+    T inc;
+    if constexpr (sizeof(T) == 8) {
+        // A wave whose values are all below 2^26 sums below 2^32: it scans
+        // in 32 bits (a branch the whole wave takes the same way).
+        if (__ballot((uint64_t)x >= (1ull << 26)) == 0)
+            inc = (T)wave_inclusive_scan((uint32_t)(uint64_t)x);
+        else
+            inc = wave_inclusive_scan(x);
+    } else {
+        inc = wave_inclusive_scan(x);
+    }
     if (lane == kWave - 1) s_wave[wid] = inc;
     __syncthreads();
     if (wid == 0) {
