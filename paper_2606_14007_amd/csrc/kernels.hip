@@ -1365,7 +1365,7 @@ __device__ __forceinline__ void chunk_range(const uint32_t *r_lo, const uint32_t
 }
 
 // Table-2 pair count of every match chunk (of a record range) from the
-// per-record count bytes: one wave per chunk, 32-bit loads, no barriers.
+// per-record count bytes: one wave per chunk, 16-byte loads, no barriers.
 // Escaped bytes are recounted from the keys.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_chunk_sums(const uint8_t *__restrict__ pcnt,
@@ -1380,19 +1380,27 @@ __global__ __launch_bounds__(BLOCK) void k_chunk_sums(const uint8_t *__restrict_
     chunk_range(r_lo, r_hi, last, cb, nchunks, c0, c1);
     for (uint32_t ci = c0 + blockIdx.x * WPB + threadIdx.x / 64; ci < c1; ci += gridDim.x * WPB) {
         const uint32_t c = ci << cb, m = min(1u << cb, n_total - c);
-        const uint32_t nw = (m + 3) / 4;
-        const uint32_t *w32 = reinterpret_cast<const uint32_t *>(pcnt + c);
+        // 16 count bytes per lane and load (a chunk starts on a 64-byte
+        // boundary of the 256-byte aligned count array), then the chunk's
+        // last m mod 16 bytes one by one.
+        const uint32_t n16 = m >> 4;
+        const uint4 *v16 = reinterpret_cast<const uint4 *>(pcnt + c);
         uint64_t sum = 0;
-        for (uint32_t w = lane; w < nw; w += 64) {
-            const uint32_t v = w32[w];
+        for (uint32_t w = lane; w < n16; w += 64) {
+            const uint4 v = v16[w];
+            const uint32_t q[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t e = 4 * w + i;
-                if (e < m) {
-                    const uint32_t b = (v >> (8 * i)) & 0xffu;
-                    sum += b == kPairCountEscape ? pairs_after_global(keys, c + e, n_total, T) : b;
+            for (int k = 0; k < 4; ++k) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint32_t b = (q[k] >> (8 * i)) & 0xffu;
+                    sum += b == kPairCountEscape ? pairs_after_global(keys, c + 16 * w + 4 * k + i, n_total, T) : b;
                 }
             }
+        }
+        for (uint32_t e = (n16 << 4) + lane; e < m; e += 64) {
+            const uint32_t b = pcnt[c + e];
+            sum += b == kPairCountEscape ? pairs_after_global(keys, c + e, n_total, T) : b;
         }
         sum = vxd::wave_sum(sum);
         if (lane == 0) counts[ci] = sum;
