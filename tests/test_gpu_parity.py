@@ -254,6 +254,33 @@ def test_bucket_sort_and_match_crowded(vx, T):
     assert np.array_equal(vx.t2_records(t2, ref_cnt), ref_t2)
 
 
+def test_table2_count_beyond_32_bits(vx):
+    """All 2^17 records in one bucket and every pair within the threshold:
+    |Table 2| = n (n - 1) / 2 > 2^32, each chunk's count above 2^26, so the
+    64-bit scans carry across 32 bits.  Only the first records fit the
+    capacity; the count is exact (a closed form, no oracle run)."""
+    k = 17
+    keys = _crowded_keys(k, nbuckets=1, seed=11)
+    n = len(keys)
+    expect = n * (n - 1) // 2
+    assert expect > 1 << 32
+    dkeys = _to_dev(keys, np.int64)
+    t1k, t1n, off, ws = vx.bucket_sort(KEY0, k, dkeys)
+    torch.cuda.synchronize()
+    assert vx.device_status(ws) == 0
+    t2, cnt = vx.match_table2(KEY0, k, t1k, t1n, off, threshold=(1 << 64) - 1, t2_capacity=4096)
+    torch.cuda.synchronize()
+    assert vx.t2_count(cnt) == expect
+    # The first records in canonical order: Table-1 record 0 with its
+    # partners 1, 2, ..., the hashes of a few checked with the oracle's H2.
+    recs = vx.t2_records(t2, 4096)
+    nonces = vx.u32(t1n)
+    assert np.array_equal(recs["nonce_a"], np.full(4096, nonces[0], dtype=np.uint32))
+    assert np.array_equal(recs["nonce_b"], nonces[1:4097])
+    for i in (0, 1, 2047, 4095):
+        assert int(recs["hash2"][i]) == oracle.h2(KEY0, int(nonces[0]), int(nonces[i + 1]))
+
+
 @pytest.mark.parametrize("cap", [0, 2600, 3072])
 def test_group_sizes_around_the_lds_capacities(vx, cap):
     """Sort groups of exactly 2560 (the default capacity), 2561, 2800 and
